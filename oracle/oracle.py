@@ -1,0 +1,202 @@
+"""ctypes wrapper of the FP64 CPU oracle (oracle/woi_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, the smoke check and the CPU-baseline
+leg of the benchmark.  The product path never imports this module.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "woi_oracle.c")
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain C99, -O2, no fast-math)."""
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC,
+                               "-lm", "-lpthread"])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class _In(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n_regions", C.c_int),
+                ("parent", C.POINTER(C.c_int)), ("sigma", C.POINTER(C.c_double)),
+                ("shape_kind", C.POINTER(C.c_int)), ("center", C.POINTER(C.c_double)),
+                ("radius", C.POINTER(C.c_double)), ("A", C.POINTER(C.c_double)),
+                ("n_vertices", C.POINTER(C.c_int)), ("vertex_offset", C.POINTER(C.c_int64)),
+                ("vertices", C.POINTER(C.c_double)), ("data_kind", C.POINTER(C.c_int)),
+                ("data_center", C.POINTER(C.c_double)), ("n_terms", C.POINTER(C.c_int)),
+                ("coef_offset", C.POINTER(C.c_int64)), ("coef", C.POINTER(C.c_double)),
+                ("exps", C.POINTER(C.c_ubyte))]
+
+
+class _Query(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("walks", C.c_uint64), ("walk_offset", C.c_uint64),
+                ("M", C.c_int), ("estimator", C.c_int), ("schedule_mode", C.c_int),
+                ("batch_share", C.c_int), ("instance", C.c_uint32)]
+
+
+class _Counters(C.Structure):
+    _fields_ = [("walks", C.c_uint64), ("walk_steps", C.c_uint64), ("redraws", C.c_uint64),
+                ("rejections", C.c_uint64), ("cap_hits", C.c_uint64), ("zero_dist", C.c_uint64)]
+
+
+_lib = None
+
+
+def build_variant(plant: int, outdir: str) -> str:
+    """Build a deliberately wrong oracle (OR_PLANT = plant) for the tests that show the
+    pins reject it; never used for reference values."""
+    path = os.path.join(outdir, f"liboracle_plant{plant}.so")
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", f"-DOR_PLANT={plant}", "-o", path,
+                           _SRC, "-lm", "-lpthread"])
+    return path
+
+
+def load(path):
+    _l = C.CDLL(path)
+    _declare(_l)
+    return _l
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        _declare(_lib)
+    return _lib
+
+
+def _declare(_lib):
+    _lib.or_problem_create.argtypes = [C.POINTER(_In), C.POINTER(C.c_void_p)]
+    _lib.or_problem_destroy.argtypes = [C.c_void_p]
+    _lib.or_problem_info.argtypes = [C.c_void_p] + [C.POINTER(C.c_double)] * 7
+    _lib.or_trace.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int64, C.POINTER(_Query), C.c_uint64,
+                              C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_uint32)]
+    _lib.or_estimate.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int64, C.POINTER(_Query), C.c_int,
+                                 C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                 C.POINTER(C.c_double), C.POINTER(_Counters)]
+    _lib.or_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
+    _lib.or_sample_surface.argtypes = [C.c_void_p, C.c_int, C.c_uint64, C.c_uint64, C.POINTER(C.c_double)]
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct)) if a is not None else None
+
+
+def philox(ctr, key):
+    c = np.asarray(ctr, dtype=np.uint32); k = np.asarray(key, dtype=np.uint32); o = np.zeros(4, np.uint32)
+    lib().or_philox4x32_10(_p(c, C.c_uint32), _p(k, C.c_uint32), _p(o, C.c_uint32))
+    return o
+
+
+class OracleProblem:
+    """Oracle-side compiled problem (built from a workloads.Problem)."""
+
+    def __init__(self, prob, library=None):
+        self.lib = library if library is not None else lib()
+        m, N = prob.dim, prob.n_regions
+        self.dim, self.N = m, N
+        keep = {}
+        keep["parent"] = np.asarray(prob.parent, dtype=np.int32)
+        keep["sigma"] = np.asarray(prob.sigma, dtype=np.float64)
+        keep["kind"] = np.array([s.kind for s in prob.shapes], dtype=np.int32)
+        keep["center"] = np.array([s.center for s in prob.shapes], dtype=np.float64).reshape(-1)
+        keep["radius"] = np.array([s.radius for s in prob.shapes], dtype=np.float64)
+        keep["A"] = np.array([s.A if s.A is not None else np.zeros((m, m)) for s in prob.shapes],
+                             dtype=np.float64).reshape(-1)
+        nv = [len(s.vertices) if s.vertices is not None else 0 for s in prob.shapes]
+        keep["nv"] = np.asarray(nv, dtype=np.int32)
+        keep["voff"] = np.concatenate([[0], np.cumsum(nv)[:-1]]).astype(np.int64)
+        verts = [s.vertices for s in prob.shapes if s.vertices is not None]
+        keep["verts"] = np.ascontiguousarray(np.concatenate(verts, 0) if verts else np.zeros((1, 2)), dtype=np.float64).reshape(-1)
+        keep["dkind"] = np.array([d.kind for d in prob.data], dtype=np.int32)
+        keep["dcenter"] = np.array([np.asarray(d.center, dtype=np.float64).reshape(m) for d in prob.data]).reshape(-1)
+        keep["nterms"] = np.array([d.n_terms for d in prob.data], dtype=np.int32)
+        ncoef = [len(d.coef) for d in prob.data]
+        keep["coff"] = np.concatenate([[0], np.cumsum(ncoef)[:-1]]).astype(np.int64)
+        keep["coef"] = np.concatenate([np.asarray(d.coef, dtype=np.float64) for d in prob.data] + [np.zeros(1)])
+        ex = np.zeros((sum(ncoef) + 1) * m, dtype=np.uint8)
+        for d, off in zip(prob.data, keep["coff"]):
+            if d.exps is not None:
+                e = np.asarray(d.exps, dtype=np.uint8).reshape(-1)
+                ex[off * m: off * m + len(e)] = e
+        keep["exps"] = ex
+        self._keep = keep
+        s = _In(m, N, _p(keep["parent"], C.c_int), _p(keep["sigma"], C.c_double), _p(keep["kind"], C.c_int),
+                _p(keep["center"], C.c_double), _p(keep["radius"], C.c_double), _p(keep["A"], C.c_double),
+                _p(keep["nv"], C.c_int), _p(keep["voff"], C.c_int64), _p(keep["verts"], C.c_double),
+                _p(keep["dkind"], C.c_int), _p(keep["dcenter"], C.c_double), _p(keep["nterms"], C.c_int),
+                _p(keep["coff"], C.c_int64), _p(keep["coef"], C.c_double), _p(keep["exps"], C.c_ubyte))
+        h = C.c_void_p()
+        rc = self.lib.or_problem_create(C.byref(s), C.byref(h))
+        if rc != 0:
+            raise ValueError(f"oracle problem_create failed: {rc}")
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.lib.or_problem_destroy(self.h)
+            self.h = None
+
+    def info(self):
+        N = self.N
+        out = {k: np.zeros(N) for k in ("alpha", "beta_scale", "area", "area_plus", "area_minus", "flux")}
+        l1 = C.c_double()
+        self.lib.or_problem_info(self.h, *[_p(out[k], C.c_double) for k in
+                                        ("alpha", "beta_scale", "area", "area_plus", "area_minus", "flux")],
+                              C.byref(l1))
+        out["alpha_l1"] = l1.value
+        return out
+
+    def sample_surface(self, region, seed, n):
+        y = np.zeros((n, self.dim))
+        self.lib.or_sample_surface(self.h, region, seed, n, _p(y, C.c_double))
+        return y
+
+
+def _query(walks, M, seed=0, estimator=0, schedule_mode=0, batch_share=1, walk_offset=0, instance=0):
+    return _Query(int(seed), int(walks), int(walk_offset), int(M), int(estimator), int(schedule_mode),
+                  int(batch_share), int(instance))
+
+
+def estimate(op: OracleProblem, x, walks, M, seed=0, estimator=0, schedule_mode=0, batch_share=1,
+             walk_offset=0, instance=0, threads=None):
+    """Per-point mean, SE, gradient and gradient SE (Alg. 1, FP64)."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, op.dim)
+    P = len(x)
+    mean = np.zeros(P); se = np.zeros(P); g = np.zeros((P, op.dim)); gse = np.zeros((P, op.dim))
+    cnt = _Counters()
+    q = _query(walks, M, seed, estimator, schedule_mode, batch_share, walk_offset, instance)
+    rc = op.lib.or_estimate(op.h, _p(x, C.c_double), P, C.byref(q), threads or os.cpu_count() or 1,
+                           _p(mean, C.c_double), _p(se, C.c_double), _p(g, C.c_double), _p(gse, C.c_double),
+                           C.byref(cnt))
+    if rc != 0:
+        raise ValueError(f"oracle estimate failed: {rc}")
+    counters = {f: getattr(cnt, f) for f, _ in _Counters._fields_}
+    return mean, se, g, gse, counters
+
+
+def trace(op: OracleProblem, x, n_samples, M, seed=0, estimator=0, schedule_mode=0, batch_share=1,
+          walk_offset=0, instance=0, threads=None):
+    """Per-walk values: F[p, j, k] (walker k of sample j at point p, times N), G[p, j, k, :],
+    decision words T[p, j, k, i]."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, op.dim)
+    P = len(x); K = 2 if estimator else 1
+    F = np.zeros((P, n_samples, K)); G = np.zeros((P, n_samples, K, op.dim))
+    T = np.zeros((P, n_samples, K, M + 1), dtype=np.uint32)
+    walks = 2 * n_samples if estimator else n_samples
+    q = _query(walks, M, seed, estimator, schedule_mode, batch_share, walk_offset, instance)
+    rc = op.lib.or_trace(op.h, _p(x, C.c_double), P, C.byref(q), n_samples, threads or os.cpu_count() or 1,
+                        _p(F, C.c_double), _p(G, C.c_double), _p(T, C.c_uint32))
+    if rc != 0:
+        raise ValueError(f"oracle trace failed: {rc}")
+    return F, G, T
