@@ -84,6 +84,9 @@ def _declare(_lib):
     _lib.or_estimate.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int64, C.POINTER(_Query), C.c_int,
                                  C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                  C.POINTER(C.c_double), C.POINTER(_Counters)]
+    _lib.or_estimate_groups.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int64, C.POINTER(_Query),
+                                        C.POINTER(C.c_uint32), C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(_Counters)]
     _lib.or_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
     _lib.or_sample_surface.argtypes = [C.c_void_p, C.c_int, C.c_uint64, C.c_uint64, C.POINTER(C.c_double)]
 
@@ -169,16 +172,18 @@ def _query(walks, M, seed=0, estimator=0, schedule_mode=0, batch_share=1, walk_o
 
 
 def estimate(op: OracleProblem, x, walks, M, seed=0, estimator=0, schedule_mode=0, batch_share=1,
-             walk_offset=0, instance=0, threads=None):
-    """Per-point mean, SE, gradient and gradient SE (Alg. 1, FP64)."""
+             walk_offset=0, instance=0, threads=None, groups=None):
+    """Per-point mean, SE, gradient and gradient SE (Alg. 1, FP64).  `groups` optionally gives
+    each point's random-stream group explicitly (default: point index // batch_share)."""
     x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, op.dim)
     P = len(x)
     mean = np.zeros(P); se = np.zeros(P); g = np.zeros((P, op.dim)); gse = np.zeros((P, op.dim))
     cnt = _Counters()
     q = _query(walks, M, seed, estimator, schedule_mode, batch_share, walk_offset, instance)
-    rc = op.lib.or_estimate(op.h, _p(x, C.c_double), P, C.byref(q), threads or os.cpu_count() or 1,
-                           _p(mean, C.c_double), _p(se, C.c_double), _p(g, C.c_double), _p(gse, C.c_double),
-                           C.byref(cnt))
+    gr = None if groups is None else np.ascontiguousarray(groups, dtype=np.uint32)
+    rc = op.lib.or_estimate_groups(op.h, _p(x, C.c_double), P, C.byref(q), _p(gr, C.c_uint32),
+                                   threads or os.cpu_count() or 1, _p(mean, C.c_double), _p(se, C.c_double),
+                                   _p(g, C.c_double), _p(gse, C.c_double), C.byref(cnt))
     if rc != 0:
         raise ValueError(f"oracle estimate failed: {rc}")
     counters = {f: getattr(cnt, f) for f, _ in _Counters._fields_}

@@ -13,7 +13,8 @@
  *     in Sec. 3); in the "other" transition the sign is applied once:
  *     Q *= |K*| |dOmega|, T *= sign((y_i - y_{i-1}) . n(y_i));
  *   - line case: q counts intersections other than y_{i-1}; the pick among the q
- *     hits is uniform; hits are ordered by segment index (polylines);
+ *     hits is uniform; hits are ordered by segment index (polylines); a polyline hit
+ *     within |t| <= 1e-12 of y_{i-1} (a vertex shared with its segment) is y_{i-1};
  *   - "descendant" means strict descendant in the region tree;
  *   - VR halves: dOmega^+ = {beta >= 0}; an empty half contributes 0; for VR the
  *     walker count W gives W/2 two-walker samples;
@@ -354,7 +355,7 @@ static int hits_of(const region_t *g, int m, const double *y, int yseg, const do
         double t = (wx * ey - wy * ex) / den;
         double s = (wx * d[1] - wy * d[0]) / den;
         if (s < 0 || s >= 1) continue;
-        if (ray ? !(t > 0) : t == 0) continue;
+        if (ray ? !(t > 0) : fabs(t) <= 1e-12) continue;   /* |t| <= 1e-12: y_{i-1} itself */
         if (q < cap) { out[q].t = t; out[q].seg = j; }
         q++;
     }
@@ -869,8 +870,11 @@ typedef struct {
     int64_t p0, p1; uint64_t n;
     double *F, *G; uint32_t *trace;            /* trace mode */
     double *mean, *se, *grad, *grad_se;        /* estimate mode */
+    const uint32_t *groups;                    /* explicit stream group per point, or NULL */
     or_counters cnt;
 } job_t;
+
+static uint32_t group_of(const job_t *j, int64_t p, int B) { return j->groups ? j->groups[p] : (uint32_t)(p / B); }
 
 static uint64_t n_samples_of(const or_query *q) { return q->estimator ? q->walks / 2 : q->walks; }
 static uint64_t first_sample(const or_query *q) { return q->estimator ? q->walk_offset / 2 : q->walk_offset; }
@@ -885,7 +889,7 @@ static void *trace_job(void *arg)
         for (uint64_t s = 0; s < j->n; ++s) {
             size_t idx = (size_t)p * j->n + s;
             double Fk[2], Gk[2 * OR_MAX_DIM];
-            one_sample(pr, j->x + p * m, j->q, first_sample(j->q) + s, (uint32_t)(p / B), Fk, Gk,
+            one_sample(pr, j->x + p * m, j->q, first_sample(j->q) + s, group_of(j, p, B), Fk, Gk,
                        j->trace ? j->trace + idx * K * (M + 1) : NULL, &j->cnt);
             for (int k = 0; k < K; ++k) {
                 j->F[idx * K + k] = Fk[k];
@@ -906,7 +910,7 @@ static void *estimate_job(void *arg)
         double mu = 0, m2 = 0, gmu[OR_MAX_DIM] = {0}, gm2[OR_MAX_DIM] = {0};
         for (uint64_t s = 0; s < n; ++s) {
             double Fk[2], Gk[2 * OR_MAX_DIM];
-            one_sample(pr, j->x + p * m, j->q, first_sample(j->q) + s, (uint32_t)(p / B), Fk, Gk, NULL, &j->cnt);
+            one_sample(pr, j->x + p * m, j->q, first_sample(j->q) + s, group_of(j, p, B), Fk, Gk, NULL, &j->cnt);
             double f = 0, g[OR_MAX_DIM] = {0};
             for (int k = 0; k < K; ++k) { f += Fk[k]; for (int d = 0; d < m; ++d) g[d] += Gk[k * m + d]; }
             /* Welford, as in Alg. 1 */
@@ -972,9 +976,15 @@ int or_trace(const or_problem *pr, const double *x, int64_t P, const or_query *q
 int or_estimate(const or_problem *pr, const double *x, int64_t P, const or_query *q, int nth,
                 double *mean, double *se, double *grad, double *grad_se, or_counters *cnt)
 {
+    return or_estimate_groups(pr, x, P, q, NULL, nth, mean, se, grad, grad_se, cnt);
+}
+
+int or_estimate_groups(const or_problem *pr, const double *x, int64_t P, const or_query *q, const uint32_t *groups,
+                       int nth, double *mean, double *se, double *grad, double *grad_se, or_counters *cnt)
+{
     int rc = check_query(pr, q);
     if (rc) return rc;
     job_t t; memset(&t, 0, sizeof t);
-    t.mean = mean; t.se = se; t.grad = grad; t.grad_se = grad_se;
+    t.mean = mean; t.se = se; t.grad = grad; t.grad_se = grad_se; t.groups = groups;
     return run_jobs(pr, x, P, q, nth, &t, estimate_job, cnt);
 }

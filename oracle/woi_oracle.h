@@ -82,6 +82,9 @@ int  or_trace(const or_problem *p, const double *x, int64_t P, const or_query *q
    schedule per walk; Welford accumulation). */
 int  or_estimate(const or_problem *p, const double *x, int64_t P, const or_query *q, int n_threads,
                  double *mean, double *se, double *grad, double *grad_se, or_counters *cnt);
+/* as or_estimate, with an explicit random-stream group per point (groups[p]) instead of p / B */
+int  or_estimate_groups(const or_problem *p, const double *x, int64_t P, const or_query *q, const uint32_t *groups,
+                        int n_threads, double *mean, double *se, double *grad, double *grad_se, or_counters *cnt);
 /* Philox4x32-10 block, exported for the known-answer test. */
 void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 /* Uniform point on interface `region` from one attempt's words (for histogram tests). */
