@@ -1,0 +1,200 @@
+/*
+ * woi.h -- C ABI of the MI355X (gfx950) Walk-on-Interfaces library.
+ *
+ * Walk-on-Interfaces (WoI) is a Monte Carlo estimator of u(x) and grad u(x) for the
+ * Neumann elliptic interface problem div(sigma grad u) = 0 with piecewise-constant
+ * sigma over a tree of nested regions and flux-jump data b_i on every interface
+ * (Ding & Stinchcombe, arXiv 2508.16767, Sec. 1, Eq. interface_problem).
+ *
+ * Conventions shared by every entry point
+ *   - All calls return woi_status (0 = WOI_OK, negative = error).  On error, a
+ *     thread-local message is available from woi_last_error(); outputs are then
+ *     unspecified.
+ *   - Point and output arrays are DEVICE pointers (HIP global memory on the current
+ *     device) owned by the caller; the library never frees or retains them.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream) and is
+ *     stream-ordered; calls return once the work is enqueued.
+ *   - Problems are immutable after creation and may be shared across threads and
+ *     streams of the device they were created on.
+ *   - Region 0 is the root: its interface is the outer boundary dOmega (Neumann data
+ *     b_1 in the paper's 1-based numbering); every other region i has parent[i] < i.
+ */
+#ifndef WOI_H
+#define WOI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WOI_MAX_DIM 8
+#define WOI_MAX_REGIONS 32
+#define WOI_MAX_M 32
+#define WOI_COUNTERS 8
+
+typedef enum {
+    WOI_OK = 0,
+    WOI_E_INVALID_ARG = -1,   /* bad pointer, size, dimension, query field            */
+    WOI_E_GEOMETRY = -2,      /* not a tree, degenerate or non-nested shapes          */
+    WOI_E_INCOMPATIBLE = -3,  /* flux data violate the compatibility condition        */
+    WOI_E_UNSUPPORTED = -4,   /* valid request this build does not implement          */
+    WOI_E_DEVICE = -5,        /* a HIP call failed                                    */
+    WOI_E_OOM = -6            /* device allocation or workspace too small             */
+} woi_status;
+
+/* Interface geometry (Sec. 4.6: implicit surfaces with exact sampling and
+ * intersection, and 2D polylines as surface meshes). */
+typedef enum {
+    WOI_SHAPE_SPHERE = 0,     /* |y - center| = radius, any dimension                   */
+    WOI_SHAPE_ELLIPSOID = 1,  /* (y - c)^T A (y - c) = 1, A symmetric positive definite  */
+    WOI_SHAPE_POLYLINE2D = 2  /* closed counter-clockwise polygon, dimension 2 only      */
+} woi_shape_kind;
+
+typedef struct {
+    int kind;                 /* woi_shape_kind                                        */
+    int n_vertices;           /* POLYLINE2D: vertex count (>= 3)                       */
+    double center[WOI_MAX_DIM];
+    double radius;            /* SPHERE                                                */
+    const double *A;          /* ELLIPSOID: dim*dim row-major, host memory             */
+    const double *vertices;   /* POLYLINE2D: n_vertices*2 (x, y), host memory, CCW     */
+} woi_shape;
+
+/* Flux-jump / Neumann data b_i on an interface (Eq. interface_problem). */
+typedef enum {
+    WOI_DATA_ZERO = 0,
+    WOI_DATA_FOURIER2D = 1,   /* a0 + sum_k a_k cos(k th) + c_k sin(k th), th = angle about center;
+                                 coef = [a0, a1, c1, ..., aK, cK], n_terms = K           */
+    WOI_DATA_DIRPOLY = 2,     /* sum_t coef_t prod_d e_d^{exps[t*dim+d]}, e = (y-center)/|y-center|;
+                                 n_terms terms, exponents <= 15                         */
+    WOI_DATA_SOURCE_FLUX = 3, /* coef[0] (y - center).n(y) / |y - center|^dim            */
+    WOI_DATA_FIELD_FLUX = 4   /* n(y) . coef[0..dim-1] (flux of a uniform field)        */
+} woi_data_kind;
+
+typedef struct {
+    int kind;                 /* woi_data_kind                                          */
+    int n_terms;
+    double center[WOI_MAX_DIM];
+    const double *coef;       /* host memory                                            */
+    const uint8_t *exps;      /* DIRPOLY: n_terms*dim exponents, host memory            */
+} woi_data;
+
+/* Compatibility of the data (Sec. 1 requires zero flux through every interface). */
+typedef enum {
+    WOI_COMPAT_PER_INTERFACE = 0, /* |int b_i dA| <= tol * int |b_i| dA for every i      */
+    WOI_COMPAT_GLOBAL = 1,        /* int b_1 = sum_{i>1} int b_i (global flux balance)   */
+    WOI_COMPAT_NONE = 2
+} woi_compat_mode;
+
+typedef struct {
+    int dim;                  /* 2 .. WOI_MAX_DIM                                       */
+    int n_regions;            /* N, 1 .. WOI_MAX_REGIONS                                */
+    const int *parent;        /* [N], parent[0] = -1, 0 <= parent[i] < i               */
+    const double *sigma;      /* [N] conductivities, sigma_i >= 0, sigma_i + sigma_parent > 0 */
+    const woi_shape *shapes;  /* [N] shapes[i] is the interface dOmega_i               */
+    const woi_data *data;     /* [N] b_i                                                */
+    int compat_mode;          /* woi_compat_mode                                        */
+    double compat_tol;        /* relative tolerance, e.g. 1e-8                          */
+} woi_problem_desc;
+
+typedef struct woi_problem woi_problem;
+
+/* Compile a problem on the host (validation, alpha_i / beta scalings of Eq.
+ * unit_coeff_charge_density_sys, schedule distribution of Eq. scheduled_interface_pdf,
+ * region relations for the transition pdfs of Eq. naive_woi_p, surface measures,
+ * polyline arclength tables and bounding-volume trees, VR half-surface tables of
+ * Sec. 4.4, compatibility check).  Deep-copies everything it needs: the descriptor
+ * and its arrays may be freed after return.  Makes no HIP call.
+ * Errors: INVALID_ARG, GEOMETRY, INCOMPATIBLE, UNSUPPORTED, OOM. */
+woi_status woi_problem_create(const woi_problem_desc *desc, woi_problem **out);
+/* Copy the compiled tables to the current device (hipMalloc + hipMemcpy, synchronous).
+ * Called implicitly by the first woi_estimate / woi_trace; call it explicitly before
+ * capturing those calls in a HIP graph.  Idempotent; the problem is then bound to that
+ * device (INVALID_ARG if used from another).  Errors: DEVICE, OOM, INVALID_ARG. */
+woi_status woi_problem_upload(woi_problem *p);
+/* Frees host and device memory of the problem (no stream synchronisation: the caller
+ * must ensure no enqueued work still reads it). */
+void woi_problem_destroy(woi_problem *p);
+
+typedef struct {
+    int dim, n_regions;
+    double alpha_l1;                          /* ||alpha||_1                          */
+    double alpha[WOI_MAX_REGIONS];            /* alpha_i                              */
+    double beta_scale[WOI_MAX_REGIONS];       /* beta_i = beta_scale[i] * b_i         */
+    double area[WOI_MAX_REGIONS];             /* |dOmega_i|                           */
+    double area_plus[WOI_MAX_REGIONS];        /* |{beta_i >= 0}| (NaN if unsupported) */
+    double area_minus[WOI_MAX_REGIONS];       /* |{beta_i <  0}|                      */
+    double flux[WOI_MAX_REGIONS];             /* integral of b_i over dOmega_i        */
+    size_t device_bytes;                      /* size of the uploaded tables          */
+} woi_problem_info;
+woi_status woi_problem_get_info(const woi_problem *p, woi_problem_info *out);
+
+typedef enum { WOI_EST_PLAIN = 0, WOI_EST_VR = 1 } woi_estimator;      /* Alg. 2 / Alg. 3 */
+typedef enum { WOI_PREC_FP64 = 0, WOI_PREC_FP32 = 1 } woi_precision;
+typedef enum { WOI_SCHED_PER_GROUP = 0, WOI_SCHED_SHARED = 1 } woi_schedule_mode;
+
+typedef struct {
+    uint64_t seed;            /* Philox4x32-10 key                                      */
+    uint64_t walks;           /* W walkers per point; VR uses W/2 two-walker samples (W even) */
+    uint64_t walk_offset;     /* first walker index (resume; even for VR)               */
+    int M;                    /* truncation, steps 0..M, 0 <= M <= WOI_MAX_M            */
+    int estimator;            /* woi_estimator                                          */
+    int precision;            /* woi_precision: FP64 everywhere, or FP32 walks with FP64 sums */
+    int schedule_mode;        /* PER_GROUP: schedule keyed by (walk, point group);
+                                 SHARED: keyed by walk only (wave-uniform, Alg. 1)      */
+    int batch_share;          /* B >= 1: points p with equal p/B share trajectories (Sec. 4.6) */
+    uint32_t instance;        /* < 2^24, mixed into every random-number counter         */
+    int samples_per_thread;   /* 0 = automatic                                          */
+    int block_size;           /* 0 = automatic (64 or 256)                              */
+} woi_query;
+
+/* Device workspace (bytes) woi_estimate needs for P points with this query. */
+woi_status woi_workspace_size(const woi_problem *p, int64_t P, const woi_query *q, size_t *bytes);
+
+/* Estimate u, its standard error, grad u and the gradient's standard error at P points
+ * (Eq. woi_estimator / variance_reduced_woi_estimator and their gradient versions,
+ * Alg. 1 with one schedule per sample).
+ *   points   [P*dim] row-major doubles (device)
+ *   mean, se [P] doubles (device); grad, grad_se [P*dim] (device) or NULL
+ *   workspace/workspace_bytes: device scratch of at least woi_workspace_size() bytes
+ *   counters: NULL or device uint64[WOI_COUNTERS] that the call adds to:
+ *             walker-steps, redraws (q = 0), rejections, attempt-cap hits, zero distances
+ * Errors: INVALID_ARG (sizes, NULL, VR with odd walks or dim > 3), OOM (workspace), DEVICE. */
+woi_status woi_estimate(const woi_problem *p, const double *points, int64_t P, const woi_query *q,
+                        double *mean, double *se, double *grad, double *grad_se,
+                        void *workspace, size_t workspace_bytes, uint64_t *counters, void *stream);
+
+/* Per-sample values for parity checks: samples [walk_offset, walk_offset + n_samples) of
+ * every point.  F[(p*n + j)*K + k] = N * (walker k's sum), K = 1 (plain) or 2 (VR);
+ * G[((p*n + j)*K + k)*dim + d]; trace[((p*n + j)*K + k)*(M+1) + i] = decision word
+ * (bits 0-5 region, 6-7 case 0 first/1 same/2 descendant/3 other, 8-15 q,
+ * 16-23 pick, 24 negative sign, 25-31 attempts).  All device pointers; G, trace may be NULL. */
+woi_status woi_trace(const woi_problem *p, const double *points, int64_t P, const woi_query *q,
+                     uint64_t n_samples, double *F, double *G, uint32_t *trace, void *stream);
+
+/* Many independent problem instances in one launch (uneven N, P, W): a persistent kernel
+ * pulls (instance, point tile, sample chunk) items from a work-stealing queue.  All
+ * instances must share dim, precision and estimator.  Per-item arrays are host arrays
+ * of length n; their pointers are device pointers. */
+typedef struct {
+    const woi_problem *problem;
+    const double *points;     /* device [P*dim]                                         */
+    int64_t P;
+    woi_query query;
+    double *mean, *se, *grad, *grad_se;  /* device; grad/grad_se may be NULL            */
+} woi_batch_item;
+
+woi_status woi_batch_workspace_size(const woi_batch_item *items, int n, size_t *bytes);
+/* Enqueues the whole batch as one captured HIP graph (queue reset, persistent walk
+ * kernel, reduction); repeated calls with the same items replay the cached graph. */
+woi_status woi_estimate_batch(const woi_batch_item *items, int n, void *workspace, size_t workspace_bytes,
+                              uint64_t *counters, void *stream);
+
+const char *woi_status_string(woi_status s);
+const char *woi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WOI_H */

@@ -427,7 +427,7 @@ static void one_sample(const or_problem *pr, const double *x, const or_query *q,
         const region_t *g0 = &pr->r[h[0]];
         double meas = q->estimator ? g0->meas[k] : g0->area;
         if (meas == 0) { /* empty VR half: this walker contributes nothing */
-            if (tr) for (int i = 0; i <= M; ++i) tr[i] = trace_word(h[i], 0, 0, 0, 0, 0);
+            if (tr) for (int i = 0; i <= M; ++i) tr[i] = i ? 0u : trace_word(h[0], 0, 0, 0, 0, 0);
             Fk[k] = 0; for (int i = 0; i < m; ++i) Gk[k * m + i] = 0;
             continue;
         }

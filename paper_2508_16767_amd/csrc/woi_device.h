@@ -1,0 +1,47 @@
+// woi_device.h -- device-resident layout of a compiled Walk-on-Interfaces problem.
+//
+// One contiguous device blob: a DevProblem header followed by three payload arrays
+// (doubles, floats, bytes).  Every table exists in FP64 (for the FP64 path) and in
+// FP32 (for the mixed-precision path) so that neither path converts on the fly.
+// Offsets are element offsets into the payload array of the matching type.
+#pragma once
+#include <stdint.h>
+
+#include "woi.h"
+
+namespace woi {
+
+enum : int { REL_SAME = 1, REL_DESC = 2, REL_OTHER = 3 };
+
+// Geometry payload of one region (offsets g64 / g32, same layout in both types):
+//   SPHERE     : c[m], R
+//   ELLIPSOID  : c[m], A[m*m], L[m*m] (= A^{-1/2}), 1/lambda_max(A)
+//   POLYLINE2D : vertices v[2*(nv+1)] (v[nv] = v[0]), segment lengths len[nv],
+//                cumulative arclength cum[nv+1]; bounding-volume tree nodes as
+//                float4 (cx, cy, hx, hy) in the float payload at `bvh`.
+struct DevRegion {
+    int kind, dkind, nt, nv;
+    int g64, g32;              // shape parameters / polyline vertices
+    int len64, len32;          // polyline segment lengths
+    int cum64, cum32;          // polyline cumulative lengths
+    int bvh;                   // float offset of the first node (4 floats per node)
+    int nleaf, leaf;           // leaves (power of two), segments per leaf
+    int d64, d32, dexp;        // data coefficients, DIRPOLY exponents (byte offset)
+    int b64, b32, nbrk, class0;// VR (2D): sign breakpoints of beta along arclength
+    int pad0;
+    double alpha, sgn, s, area, meas[2], total;
+    float alpha_f, sgn_f, s_f, area_f, meas_f[2], total_f, pad1;
+};
+
+struct DevProblem {
+    int dim, N, vr_ok, pad0;
+    double alpha_l1, unit_area, phi_c;        // |S^{m-1}|, Phi prefactor (m >= 3)
+    float alpha_l1_f, unit_area_f, phi_c_f, pad1;
+    double cdf[WOI_MAX_REGIONS];              // schedule CDF over |alpha| / ||alpha||_1
+    unsigned char rel[WOI_MAX_REGIONS][WOI_MAX_REGIONS];
+    DevRegion reg[WOI_MAX_REGIONS];
+    uint64_t off64, off32, offb;              // byte offsets of the payload arrays
+    uint64_t bytes;
+};
+
+}  // namespace woi

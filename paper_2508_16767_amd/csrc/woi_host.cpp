@@ -1,0 +1,1101 @@
+// woi_host.cpp -- problem compiler and C ABI of the Walk-on-Interfaces library.
+//
+// Problem compile (once per problem, host FP64):
+//   alpha_i, beta scalings                      Eq. unit_coeff_charge_density_sys
+//   schedule CDF over |alpha| / ||alpha||_1     Theorem 2, Eq. scheduled_interface_pdf
+//   relation of consecutive interfaces          Eq. naive_woi_p (same / descendant / other)
+//   surface measures |dOmega_i|                 Eqs. naive_woi_p0, naive_woi_p
+//   halves {beta >= 0}, {beta < 0}              Sec. 4.4 (variance reduction)
+//   compatibility  int b_i dA = 0               Sec. 1 (after Eq. interface_problem)
+// then one device upload.  Estimation launches the walk kernel over (point tile, sample
+// chunk) and a deterministic reduction.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "woi.h"
+#include "woi_device.h"
+#include "woi_launch.h"
+
+using woi::DevProblem;
+using woi::DevRegion;
+
+namespace {
+
+thread_local std::string g_err;
+
+woi_status fail(woi_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+const double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------- small linear algebra
+// Symmetric eigen-decomposition by cyclic Jacobi rotations: A = V diag(ev) V^T.
+void sym_eig(int m, const double* A, double* ev, double* V) {
+    double a[WOI_MAX_DIM * WOI_MAX_DIM];
+    std::memcpy(a, A, sizeof(double) * m * m);
+    for (int i = 0; i < m * m; ++i) V[i] = 0.0;
+    for (int i = 0; i < m; ++i) V[i * m + i] = 1.0;
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        double off = 0.0;
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j)
+                if (i != j) off += a[i * m + j] * a[i * m + j];
+        if (off < 1e-280) break;
+        for (int p = 0; p < m - 1; ++p)
+            for (int q = p + 1; q < m; ++q) {
+                const double apq = a[p * m + q];
+                if (std::fabs(apq) < 1e-300) continue;
+                const double tau = (a[q * m + q] - a[p * m + p]) / (2.0 * apq);
+                const double t = std::copysign(1.0, tau) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+                const double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
+                for (int k = 0; k < m; ++k) {
+                    const double x = a[k * m + p], y = a[k * m + q];
+                    a[k * m + p] = c * x - s * y;
+                    a[k * m + q] = s * x + c * y;
+                }
+                for (int k = 0; k < m; ++k) {
+                    const double x = a[p * m + k], y = a[q * m + k];
+                    a[p * m + k] = c * x - s * y;
+                    a[q * m + k] = s * x + c * y;
+                }
+                for (int k = 0; k < m; ++k) {
+                    const double x = V[k * m + p], y = V[k * m + q];
+                    V[k * m + p] = c * x - s * y;
+                    V[k * m + q] = s * x + c * y;
+                }
+            }
+    }
+    for (int i = 0; i < m; ++i) ev[i] = a[i * m + i];
+}
+
+// Gauss-Legendre rule on [-1, 1] (Golub-Welsch free: Newton iteration on P_n).
+void gl_rule(int n, std::vector<double>& x, std::vector<double>& w) {
+    x.resize(n);
+    w.resize(n);
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double z = std::cos(kPi * (i + 0.75) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 60; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p1 = z; p0 = 1.0; }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-17) break;
+        }
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// ---------------------------------------------------------------------------- host geometry
+struct HostRegion {
+    int kind = 0, dkind = 0, nt = 0;
+    double c[WOI_MAX_DIM] = {0}, R = 0;
+    double A[WOI_MAX_DIM * WOI_MAX_DIM] = {0}, L[WOI_MAX_DIM * WOI_MAX_DIM] = {0};
+    double lam_max = 0, detL = 1;
+    std::vector<double> v;      // polyline vertices, closed (nv + 1)
+    std::vector<double> len, cum;
+    double total = 0, area = 0;
+    std::vector<double> coef;   // data payload: coefficients then centre / source
+    std::vector<uint8_t> exps;
+    double alpha = 0, s = 0, flux = 0, absflux = 0;
+    double meas[2] = {0, 0};
+    std::vector<double> brk;
+    int class0 = 0;
+    int nv() const { return (int)len.size(); }
+};
+
+struct Host {
+    int m = 0, N = 0;
+    int parent[WOI_MAX_REGIONS] = {0};
+    double sigma[WOI_MAX_REGIONS] = {0};
+    HostRegion r[WOI_MAX_REGIONS];
+    double alpha_l1 = 0;
+};
+
+void outward_normal(const Host& H, const HostRegion& g, const double* y, int seg, double* n) {
+    const int m = H.m;
+    if (g.kind == WOI_SHAPE_SPHERE) {
+        for (int i = 0; i < m; ++i) n[i] = (y[i] - g.c[i]) / g.R;
+    } else if (g.kind == WOI_SHAPE_ELLIPSOID) {
+        double nn = 0;
+        for (int i = 0; i < m; ++i) {
+            double t = 0;
+            for (int j = 0; j < m; ++j) t += g.A[i * m + j] * (y[j] - g.c[j]);
+            n[i] = t;
+            nn += t * t;
+        }
+        nn = std::sqrt(nn);
+        for (int i = 0; i < m; ++i) n[i] /= nn;
+    } else {
+        const double ex = g.v[2 * seg + 2] - g.v[2 * seg], ey = g.v[2 * seg + 3] - g.v[2 * seg + 1];
+        const double l = std::sqrt(ex * ex + ey * ey);
+        n[0] = ey / l;
+        n[1] = -ex / l;
+    }
+}
+
+// b_i(y): data payload layout matches the device (coefficients, then centre / source)
+double b_value(const Host& H, const HostRegion& g, const double* y, int seg) {
+    const int m = H.m;
+    switch (g.dkind) {
+        case WOI_DATA_ZERO: return 0.0;
+        case WOI_DATA_FIELD_FLUX: {
+            double n[WOI_MAX_DIM], b = 0;
+            outward_normal(H, g, y, seg, n);
+            for (int i = 0; i < m; ++i) b += g.coef[i] * n[i];
+            return b;
+        }
+        case WOI_DATA_SOURCE_FLUX: {
+            double n[WOI_MAX_DIM], dn = 0, r2 = 0;
+            outward_normal(H, g, y, seg, n);
+            for (int i = 0; i < m; ++i) {
+                const double e = y[i] - g.coef[1 + i];
+                dn += e * n[i];
+                r2 += e * e;
+            }
+            return g.coef[0] * dn / std::pow(r2, 0.5 * m);
+        }
+        default: break;
+    }
+    const int nc = g.dkind == WOI_DATA_FOURIER2D ? 2 * g.nt + 1 : g.nt;
+    const double* c = g.coef.data() + nc;
+    double e[WOI_MAX_DIM], r2 = 0;
+    for (int i = 0; i < m; ++i) {
+        e[i] = y[i] - c[i];
+        r2 += e[i] * e[i];
+    }
+    const double ir = 1.0 / std::sqrt(r2);
+    for (int i = 0; i < m; ++i) e[i] *= ir;
+    if (g.dkind == WOI_DATA_FOURIER2D) {
+        const double th = std::atan2(e[1], e[0]);
+        double b = g.coef[0];
+        for (int k = 1; k <= g.nt; ++k) b += g.coef[2 * k - 1] * std::cos(k * th) + g.coef[2 * k] * std::sin(k * th);
+        return b;
+    }
+    double b = 0;
+    for (int t = 0; t < g.nt; ++t) {
+        double term = g.coef[t];
+        for (int i = 0; i < m; ++i)
+            for (int p = 0; p < g.exps[t * m + i]; ++p) term *= e[i];
+        b += term;
+    }
+    return b;
+}
+
+// point of a sphere / ellipsoid from a unit vector u, and the surface Jacobian
+void quadric_point(const Host& H, const HostRegion& g, const double* u, double* y, double* J) {
+    const int m = H.m;
+    if (g.kind == WOI_SHAPE_SPHERE) {
+        for (int i = 0; i < m; ++i) y[i] = g.c[i] + g.R * u[i];
+        *J = std::pow(g.R, m - 1);
+        return;
+    }
+    double uAu = 0;
+    for (int i = 0; i < m; ++i) {
+        double t = 0, l = 0;
+        for (int j = 0; j < m; ++j) {
+            t += g.A[i * m + j] * u[j];
+            l += g.L[i * m + j] * u[j];
+        }
+        uAu += u[i] * t;
+        y[i] = g.c[i] + l;
+    }
+    *J = g.detL * std::sqrt(uAu);
+}
+
+// Integral over S^{m-1} in hyperspherical angles: Gauss-Legendre in each polar angle
+// (nodes np per angle), periodic trapezoid (2 np nodes) in the azimuth.
+template <class F>
+double sphere_quad(int m, int np, F&& f) {
+    if (m == 2) {
+        const int n = 8 * np;
+        double s = 0;
+        for (int j = 0; j < n; ++j) {
+            const double ph = 2 * kPi * (j + 0.5) / n;
+            const double u[2] = {std::cos(ph), std::sin(ph)};
+            s += f(u);
+        }
+        return s * 2 * kPi / n;
+    }
+    std::vector<double> gx, gw;
+    gl_rule(np, gx, gw);
+    const int npol = m - 2, naz = 2 * np;
+    std::vector<int> idx(npol, 0);
+    double total = 0;
+    while (true) {
+        double u[WOI_MAX_DIM], w = 1, sprod = 1;
+        for (int a = 0; a < npol; ++a) {
+            const double th = 0.5 * kPi * (gx[idx[a]] + 1.0);
+            u[a] = sprod * std::cos(th);
+            w *= 0.5 * kPi * gw[idx[a]] * std::pow(std::sin(th), m - 2 - a);
+            sprod *= std::sin(th);
+        }
+        for (int j = 0; j < naz; ++j) {
+            const double ph = 2 * kPi * (j + 0.5) / naz;
+            u[m - 2] = sprod * std::cos(ph);
+            u[m - 1] = sprod * std::sin(ph);
+            total += w * (2 * kPi / naz) * f(u);
+        }
+        int a = 0;
+        while (a < npol && ++idx[a] == np) idx[a++] = 0;
+        if (a == npol) break;
+    }
+    return total;
+}
+
+int quad_order(int m) { return m == 2 ? 256 : m == 3 ? 96 : m == 4 ? 48 : m == 5 ? 32 : m == 6 ? 24 : 16; }
+
+bool point_inside(const Host& H, const HostRegion& g, const double* y) {
+    const int m = H.m;
+    if (g.kind == WOI_SHAPE_SPHERE) {
+        double r2 = 0;
+        for (int i = 0; i < m; ++i) r2 += (y[i] - g.c[i]) * (y[i] - g.c[i]);
+        return r2 < g.R * g.R;
+    }
+    if (g.kind == WOI_SHAPE_ELLIPSOID) {
+        double q = 0;
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) q += (y[i] - g.c[i]) * g.A[i * m + j] * (y[j] - g.c[j]);
+        return q < 1.0;
+    }
+    bool in = false;   // crossing number
+    for (int j = 0; j < g.nv(); ++j) {
+        const double* a = &g.v[2 * j];
+        const double* b = &g.v[2 * j + 2];
+        if ((a[1] > y[1]) != (b[1] > y[1])) {
+            const double xi = a[0] + (y[1] - a[1]) / (b[1] - a[1]) * (b[0] - a[0]);
+            if (y[0] < xi) in = !in;
+        }
+    }
+    return in;
+}
+
+// deterministic sample points on an interface for validation
+void probe_points(const Host& H, const HostRegion& g, std::vector<double>& pts) {
+    const int m = H.m;
+    pts.clear();
+    if (g.kind == WOI_SHAPE_POLYLINE2D) {
+        for (int j = 0; j < g.nv(); ++j)
+            for (int s = 0; s < 2; ++s) {
+                const double f = 0.5 * s;
+                pts.push_back(g.v[2 * j] + f * (g.v[2 * j + 2] - g.v[2 * j]));
+                pts.push_back(g.v[2 * j + 1] + f * (g.v[2 * j + 3] - g.v[2 * j + 1]));
+            }
+        return;
+    }
+    // Fibonacci-like lattice on S^{m-1} via low-discrepancy Gaussian directions
+    const int n = m == 2 ? 720 : 4000;
+    uint64_t st = 0x9E3779B97F4A7C15ull;
+    for (int k = 0; k < n; ++k) {
+        double u[WOI_MAX_DIM], nn = 0;
+        for (int i = 0; i < m; ++i) {
+            st = st * 6364136223846793005ull + 1442695040888963407ull;
+            const double a = ((st >> 11) + 0.5) * 0x1p-53;
+            st = st * 6364136223846793005ull + 1442695040888963407ull;
+            const double b = ((st >> 11) + 0.5) * 0x1p-53;
+            u[i] = std::sqrt(-2 * std::log(a)) * std::cos(2 * kPi * b);
+            nn += u[i] * u[i];
+        }
+        nn = std::sqrt(nn);
+        for (int i = 0; i < m; ++i) u[i] /= nn;
+        if (m == 2) {
+            u[0] = std::cos(2 * kPi * (k + 0.5) / n);
+            u[1] = std::sin(2 * kPi * (k + 0.5) / n);
+        }
+        double y[WOI_MAX_DIM], J;
+        quadric_point(H, g, u, y, &J);
+        for (int i = 0; i < m; ++i) pts.push_back(y[i]);
+    }
+}
+
+// ---------------------------------------------------------------------------- VR halves
+double curve_beta(const Host& H, const HostRegion& g, double s) {
+    double y[2];
+    int seg = 0;
+    if (g.kind == WOI_SHAPE_POLYLINE2D) {
+        const int n = g.nv();
+        int j = (int)(std::upper_bound(g.cum.begin(), g.cum.begin() + n, s) - g.cum.begin()) - 1;
+        j = std::max(0, std::min(j, n - 1));
+        const double f = (s - g.cum[j]) / g.len[j];
+        y[0] = g.v[2 * j] + f * (g.v[2 * j + 2] - g.v[2 * j]);
+        y[1] = g.v[2 * j + 1] + f * (g.v[2 * j + 3] - g.v[2 * j + 1]);
+        seg = j;
+    } else {
+        y[0] = g.c[0] + g.R * std::cos(s / g.R);
+        y[1] = g.c[1] + g.R * std::sin(s / g.R);
+    }
+    return g.s * b_value(H, g, y, seg);
+}
+
+void vr_halves_2d(const Host& H, HostRegion& g) {
+    const int n = g.kind == WOI_SHAPE_POLYLINE2D ? 16 * g.nv() : 16384;
+    g.brk.clear();
+    auto cls = [&](double s) { return curve_beta(H, g, s) >= 0.0 ? 0 : 1; };
+    int c_prev = cls(0.0);
+    g.class0 = c_prev;
+    double s_prev = 0.0;
+    for (int j = 1; j <= n; ++j) {
+        const double s = g.total * j / n;
+        const int c = j == n ? g.class0 : cls(s);
+        if (c != c_prev) {
+            double lo = s_prev, hi = s;
+            const int clo = c_prev;
+            for (int it = 0; it < 80; ++it) {
+                const double mid = 0.5 * (lo + hi);
+                if (mid <= lo || mid >= hi) break;
+                if (cls(mid) == clo) lo = mid; else hi = mid;
+            }
+            g.brk.push_back(0.5 * (lo + hi));
+        }
+        s_prev = s;
+        c_prev = c;
+    }
+    g.meas[0] = g.meas[1] = 0.0;
+    double start = 0.0;
+    int c = g.class0;
+    for (size_t p = 0; p <= g.brk.size(); ++p) {
+        const double end = p < g.brk.size() ? g.brk[p] : g.total;
+        g.meas[c] += end - start;
+        start = end;
+        c ^= 1;
+    }
+}
+
+// 3D halves: for each polar angle th, exact breakpoints of sign(beta) along the azimuth,
+// Gauss-Legendre (5 nodes) for the surface Jacobian on every piece; adaptive
+// Gauss-Kronrod (7/15) over th.
+double ring_measure(const Host& H, const HostRegion& g, double th, int want) {
+    const int n = 192;
+    static const double x5[5] = {-0.9061798459386640, -0.5384693101056831, 0.0, 0.5384693101056831, 0.9061798459386640};
+    static const double w5[5] = {0.2369268850561891, 0.4786286704993665, 0.5688888888888889, 0.4786286704993665, 0.2369268850561891};
+    const double st = std::sin(th), ct = std::cos(th);
+    auto eval = [&](double ph, double* J) {
+        const double u[3] = {st * std::cos(ph), st * std::sin(ph), ct};
+        double y[3];
+        quadric_point(H, g, u, y, J);
+        return g.s * b_value(H, g, y, 0) >= 0.0 ? 0 : 1;
+    };
+    auto piece = [&](double a, double b) {
+        double s = 0, J;
+        for (int k = 0; k < 5; ++k) {
+            eval(0.5 * (a + b) + 0.5 * (b - a) * x5[k], &J);
+            s += 0.5 * (b - a) * w5[k] * J;
+        }
+        return s;
+    };
+    double total = 0, J;
+    int ca = eval(0.0, &J);
+    for (int j = 0; j < n; ++j) {
+        const double a = 2 * kPi * j / n, b = 2 * kPi * (j + 1) / n;
+        const int cb = eval(b, &J);
+        if (ca == cb) {
+            if (ca == want) total += piece(a, b);
+        } else {
+            double lo = a, hi = b;
+            for (int it = 0; it < 80; ++it) {
+                const double mid = 0.5 * (lo + hi);
+                if (mid <= lo || mid >= hi) break;
+                if (eval(mid, &J) == ca) lo = mid; else hi = mid;
+            }
+            const double r = 0.5 * (lo + hi);
+            total += ca == want ? piece(a, r) : piece(r, b);
+        }
+        ca = cb;
+    }
+    return total * st;
+}
+
+double gk15(const Host& H, const HostRegion& g, int want, double a, double b, double* err) {
+    static const double xk[8] = {0.991455371120812639, 0.949107912342758525, 0.864864423359769073, 0.741531185599394440,
+                                 0.586087235467691130, 0.405845151377397167, 0.207784955007898468, 0.0};
+    static const double wk[8] = {0.022935322010529225, 0.063092092629978553, 0.104790010322250184, 0.140653259715525919,
+                                 0.169004726639267903, 0.190350578064785410, 0.204432940075298892, 0.209482141084727828};
+    static const double wg[4] = {0.129484966168869693, 0.279705391489276668, 0.381830050505118945, 0.417959183673469388};
+    const double c = 0.5 * (a + b), h = 0.5 * (b - a);
+    double fc = ring_measure(H, g, c, want);
+    double rk = fc * wk[7], rg = fc * wg[3];
+    for (int j = 0; j < 7; ++j) {
+        const double f1 = ring_measure(H, g, c - h * xk[j], want), f2 = ring_measure(H, g, c + h * xk[j], want);
+        rk += wk[j] * (f1 + f2);
+        if (j % 2 == 1) rg += wg[j / 2] * (f1 + f2);
+    }
+    *err = std::fabs((rk - rg) * h);
+    return rk * h;
+}
+
+double adapt(const Host& H, const HostRegion& g, int want, double a, double b, double tol, int depth) {
+    double err;
+    const double v = gk15(H, g, want, a, b, &err);
+    if (err <= tol || depth == 0) return v;
+    const double m = 0.5 * (a + b);
+    return adapt(H, g, want, a, m, 0.5 * tol, depth - 1) + adapt(H, g, want, m, b, 0.5 * tol, depth - 1);
+}
+
+void vr_halves_3d(const Host& H, HostRegion& g) {
+    for (int want = 0; want < 2; ++want) {
+        double s = 0;
+        const int panels = 16;
+        for (int p = 0; p < panels; ++p)
+            s += adapt(H, g, want, kPi * p / panels, kPi * (p + 1) / panels, 1e-12 * g.area / panels, 24);
+        g.meas[want] = s;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------- problem object
+struct woi_problem {
+    Host H;
+    std::vector<uint8_t> blob;   // device image, uploaded on first use
+    std::mutex mu;
+    int device = -1;
+    void* dev = nullptr;
+    size_t bytes = 0;
+    woi_problem_info info{};
+};
+
+namespace {
+
+woi_status compile_shapes(const woi_problem_desc* d, Host& H) {
+    const int m = H.m;
+    for (int i = 0; i < H.N; ++i) {
+        HostRegion& g = H.r[i];
+        const woi_shape& s = d->shapes[i];
+        g.kind = s.kind;
+        for (int k = 0; k < m; ++k) g.c[k] = s.center[k];
+        if (s.kind == WOI_SHAPE_SPHERE) {
+            if (!(s.radius > 0)) return fail(WOI_E_GEOMETRY, "region %d: sphere radius must be > 0", i);
+            g.R = s.radius;
+            g.area = 2 * std::pow(kPi, 0.5 * m) / std::tgamma(0.5 * m) * std::pow(g.R, m - 1);
+            g.total = m == 2 ? 2 * kPi * g.R : 0.0;
+        } else if (s.kind == WOI_SHAPE_ELLIPSOID) {
+            if (!s.A) return fail(WOI_E_INVALID_ARG, "region %d: ellipsoid matrix is NULL", i);
+            std::memcpy(g.A, s.A, sizeof(double) * m * m);
+            for (int a = 0; a < m; ++a)
+                for (int b = 0; b < a; ++b)
+                    if (std::fabs(g.A[a * m + b] - g.A[b * m + a]) > 1e-12 * (std::fabs(g.A[a * m + b]) + 1e-300))
+                        return fail(WOI_E_GEOMETRY, "region %d: ellipsoid matrix not symmetric", i);
+            double ev[WOI_MAX_DIM], V[WOI_MAX_DIM * WOI_MAX_DIM];
+            sym_eig(m, g.A, ev, V);
+            g.lam_max = 0;
+            g.detL = 1;
+            for (int k = 0; k < m; ++k) {
+                if (!(ev[k] > 0)) return fail(WOI_E_GEOMETRY, "region %d: ellipsoid matrix not positive definite", i);
+                g.lam_max = std::max(g.lam_max, ev[k]);
+                g.detL /= std::sqrt(ev[k]);
+            }
+            for (int a = 0; a < m; ++a)
+                for (int b = 0; b < m; ++b) {
+                    double t = 0;
+                    for (int k = 0; k < m; ++k) t += V[a * m + k] * V[b * m + k] / std::sqrt(ev[k]);
+                    g.L[a * m + b] = t;
+                }
+            const HostRegion& gg = g;
+            g.area = sphere_quad(m, quad_order(m), [&](const double* u) {
+                double y[WOI_MAX_DIM], J;
+                quadric_point(H, gg, u, y, &J);
+                return J;
+            });
+            g.total = m == 2 ? g.area : 0.0;
+            if (m == 2) return fail(WOI_E_UNSUPPORTED, "region %d: 2D ellipses are not supported (use a polyline)", i);
+        } else if (s.kind == WOI_SHAPE_POLYLINE2D) {
+            if (m != 2) return fail(WOI_E_INVALID_ARG, "region %d: polylines need dim 2", i);
+            if (s.n_vertices < 3 || !s.vertices) return fail(WOI_E_INVALID_ARG, "region %d: polyline needs >= 3 vertices", i);
+            const int n = s.n_vertices;
+            g.v.assign(s.vertices, s.vertices + 2 * n);
+            g.v.push_back(s.vertices[0]);
+            g.v.push_back(s.vertices[1]);
+            g.len.resize(n);
+            g.cum.resize(n + 1);
+            g.cum[0] = 0;
+            double area2 = 0;
+            for (int j = 0; j < n; ++j) {
+                const double ex = g.v[2 * j + 2] - g.v[2 * j], ey = g.v[2 * j + 3] - g.v[2 * j + 1];
+                g.len[j] = std::sqrt(ex * ex + ey * ey);
+                if (!(g.len[j] > 0)) return fail(WOI_E_GEOMETRY, "region %d: zero-length polyline segment %d", i, j);
+                g.cum[j + 1] = g.cum[j] + g.len[j];
+                area2 += g.v[2 * j] * g.v[2 * j + 3] - g.v[2 * j + 2] * g.v[2 * j + 1];
+            }
+            if (!(area2 > 0)) return fail(WOI_E_GEOMETRY, "region %d: polyline must be counter-clockwise", i);
+            g.total = g.area = g.cum[n];
+        } else {
+            return fail(WOI_E_INVALID_ARG, "region %d: unknown shape kind %d", i, s.kind);
+        }
+    }
+    return WOI_OK;
+}
+
+woi_status compile_data(const woi_problem_desc* d, Host& H) {
+    const int m = H.m;
+    for (int i = 0; i < H.N; ++i) {
+        HostRegion& g = H.r[i];
+        const woi_data& dd = d->data[i];
+        g.dkind = dd.kind;
+        g.nt = dd.n_terms;
+        g.coef.clear();
+        switch (dd.kind) {
+            case WOI_DATA_ZERO: g.nt = 0; break;
+            case WOI_DATA_FOURIER2D:
+                if (m != 2) return fail(WOI_E_INVALID_ARG, "region %d: Fourier data needs dim 2", i);
+                if (dd.n_terms < 0 || dd.n_terms > 64 || !dd.coef) return fail(WOI_E_INVALID_ARG, "region %d: bad Fourier data", i);
+                g.coef.assign(dd.coef, dd.coef + 2 * dd.n_terms + 1);
+                for (int k = 0; k < m; ++k) g.coef.push_back(dd.center[k]);
+                break;
+            case WOI_DATA_DIRPOLY:
+                if (dd.n_terms < 1 || dd.n_terms > 4096 || !dd.coef || !dd.exps) return fail(WOI_E_INVALID_ARG, "region %d: bad DIRPOLY data", i);
+                g.coef.assign(dd.coef, dd.coef + dd.n_terms);
+                for (int k = 0; k < m; ++k) g.coef.push_back(dd.center[k]);
+                g.exps.assign(dd.exps, dd.exps + (size_t)dd.n_terms * m);
+                for (uint8_t e : g.exps)
+                    if (e > 15) return fail(WOI_E_INVALID_ARG, "region %d: DIRPOLY exponent > 15", i);
+                break;
+            case WOI_DATA_SOURCE_FLUX:
+                if (!dd.coef) return fail(WOI_E_INVALID_ARG, "region %d: SOURCE_FLUX needs coef[0]", i);
+                g.coef.push_back(dd.coef[0]);
+                for (int k = 0; k < m; ++k) g.coef.push_back(dd.center[k]);
+                g.nt = 1;
+                break;
+            case WOI_DATA_FIELD_FLUX:
+                if (!dd.coef) return fail(WOI_E_INVALID_ARG, "region %d: FIELD_FLUX needs coef[0..dim-1]", i);
+                g.coef.assign(dd.coef, dd.coef + m);
+                g.nt = m;
+                break;
+            default: return fail(WOI_E_INVALID_ARG, "region %d: unknown data kind %d", i, dd.kind);
+        }
+    }
+    return WOI_OK;
+}
+
+woi_status validate_nesting(Host& H) {
+    std::vector<double> pts;
+    const int m = H.m;
+    for (int i = 1; i < H.N; ++i) {
+        probe_points(H, H.r[i], pts);
+        const size_t np = pts.size() / m;
+        for (size_t k = 0; k < np; ++k) {
+            const double* y = &pts[k * m];
+            if (!point_inside(H, H.r[H.parent[i]], y))
+                return fail(WOI_E_GEOMETRY, "region %d: interface leaves its parent region %d", i, H.parent[i]);
+            for (int j = 1; j < H.N; ++j)
+                if (j != i && H.parent[j] == H.parent[i] && point_inside(H, H.r[j], y))
+                    return fail(WOI_E_GEOMETRY, "regions %d and %d (siblings) overlap", i, j);
+        }
+    }
+    return WOI_OK;
+}
+
+void flux_integrals(Host& H) {
+    const int m = H.m;
+    for (int i = 0; i < H.N; ++i) {
+        HostRegion& g = H.r[i];
+        if (g.kind == WOI_SHAPE_POLYLINE2D) {
+            std::vector<double> gx, gw;
+            gl_rule(6, gx, gw);
+            double s = 0, sa = 0;
+            for (int j = 0; j < g.nv(); ++j)
+                for (int k = 0; k < 6; ++k) {
+                    const double f = 0.5 * (gx[k] + 1.0);
+                    const double y[2] = {g.v[2 * j] + f * (g.v[2 * j + 2] - g.v[2 * j]),
+                                         g.v[2 * j + 1] + f * (g.v[2 * j + 3] - g.v[2 * j + 1])};
+                    const double b = b_value(H, g, y, j);
+                    s += 0.5 * gw[k] * g.len[j] * b;
+                    sa += 0.5 * gw[k] * g.len[j] * std::fabs(b);
+                }
+            g.flux = s;
+            g.absflux = sa;
+        } else {
+            const HostRegion& gg = g;
+            double sa = 0;
+            g.flux = sphere_quad(m, quad_order(m), [&](const double* u) {
+                double y[WOI_MAX_DIM], J;
+                quadric_point(H, gg, u, y, &J);
+                const double b = b_value(H, gg, y, 0);
+                sa += 0;   // absolute flux computed below
+                return J * b;
+            });
+            g.absflux = sphere_quad(m, quad_order(m), [&](const double* u) {
+                double y[WOI_MAX_DIM], J;
+                quadric_point(H, gg, u, y, &J);
+                return J * std::fabs(b_value(H, gg, y, 0));
+            });
+            (void)sa;
+        }
+    }
+}
+
+// bounding-volume tree over polyline segments: implicit complete binary tree, leaf = 8 segments
+void build_bvh(const HostRegion& g, int& nleaf, int leaf, std::vector<float>& nodes) {
+    const int n = g.nv();
+    nleaf = 1;
+    while (nleaf * leaf < n) nleaf *= 2;
+    const int nn = 2 * nleaf - 1;
+    std::vector<double> lo(2 * nn, 1e300), hi(2 * nn, -1e300);
+    for (int l = 0; l < nleaf; ++l) {
+        const int k = nleaf - 1 + l;
+        for (int j = l * leaf; j < std::min(n, (l + 1) * leaf); ++j)
+            for (int e = 0; e < 2; ++e)
+                for (int c = 0; c < 2; ++c) {
+                    lo[2 * k + c] = std::min(lo[2 * k + c], g.v[2 * (j + e) + c]);
+                    hi[2 * k + c] = std::max(hi[2 * k + c], g.v[2 * (j + e) + c]);
+                }
+    }
+    for (int k = nleaf - 2; k >= 0; --k)
+        for (int c = 0; c < 2; ++c) {
+            lo[2 * k + c] = std::min(lo[2 * (2 * k + 1) + c], lo[2 * (2 * k + 2) + c]);
+            hi[2 * k + c] = std::max(hi[2 * (2 * k + 1) + c], hi[2 * (2 * k + 2) + c]);
+        }
+    nodes.resize(4 * nn);
+    for (int k = 0; k < nn; ++k) {
+        if (lo[2 * k] > hi[2 * k]) {   // empty leaf: a box no line reaches
+            nodes[4 * k] = 1e30f; nodes[4 * k + 1] = 1e30f; nodes[4 * k + 2] = 0.f; nodes[4 * k + 3] = 0.f;
+            continue;
+        }
+        for (int c = 0; c < 2; ++c) {
+            const double mid = 0.5 * (lo[2 * k + c] + hi[2 * k + c]);
+            const double half = 0.5 * (hi[2 * k + c] - lo[2 * k + c]);
+            nodes[4 * k + c] = (float)mid;   // conservative: inflate for FP32 rounding
+            nodes[4 * k + 2 + c] = (float)(half + 1e-6 * (1.0 + std::fabs(mid)) + std::fabs(mid - (double)(float)mid));
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* woi_status_string(woi_status s) {
+    switch (s) {
+        case WOI_OK: return "WOI_OK";
+        case WOI_E_INVALID_ARG: return "WOI_E_INVALID_ARG";
+        case WOI_E_GEOMETRY: return "WOI_E_GEOMETRY";
+        case WOI_E_INCOMPATIBLE: return "WOI_E_INCOMPATIBLE";
+        case WOI_E_UNSUPPORTED: return "WOI_E_UNSUPPORTED";
+        case WOI_E_DEVICE: return "WOI_E_DEVICE";
+        case WOI_E_OOM: return "WOI_E_OOM";
+    }
+    return "WOI_E_UNKNOWN";
+}
+
+const char* woi_last_error(void) { return g_err.c_str(); }
+
+woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
+    if (!d || !out) return fail(WOI_E_INVALID_ARG, "NULL descriptor or output");
+    *out = nullptr;
+    if (d->dim < 2 || d->dim > WOI_MAX_DIM) return fail(WOI_E_INVALID_ARG, "dim %d outside [2, %d]", d->dim, WOI_MAX_DIM);
+    if (d->n_regions < 1 || d->n_regions > WOI_MAX_REGIONS)
+        return fail(WOI_E_INVALID_ARG, "n_regions %d outside [1, %d]", d->n_regions, WOI_MAX_REGIONS);
+    if (!d->parent || !d->sigma || !d->shapes || !d->data) return fail(WOI_E_INVALID_ARG, "NULL array in descriptor");
+    auto* P = new (std::nothrow) woi_problem;
+    if (!P) return fail(WOI_E_OOM, "host allocation failed");
+    Host& H = P->H;
+    H.m = d->dim;
+    H.N = d->n_regions;
+    const int m = H.m, N = H.N;
+    woi_status st = WOI_OK;
+    for (int i = 0; i < N && st == WOI_OK; ++i) {
+        H.parent[i] = d->parent[i];
+        H.sigma[i] = d->sigma[i];
+        if (i == 0 && d->parent[0] != -1) st = fail(WOI_E_GEOMETRY, "parent[0] must be -1");
+        if (i > 0 && (d->parent[i] < 0 || d->parent[i] >= i)) st = fail(WOI_E_GEOMETRY, "parent[%d] = %d must be in [0, %d)", i, d->parent[i], i);
+        if (!(d->sigma[i] >= 0) || !std::isfinite(d->sigma[i])) st = fail(WOI_E_INVALID_ARG, "sigma[%d] must be finite and >= 0", i);
+    }
+    for (int i = 1; i < N && st == WOI_OK; ++i)
+        if (!(H.sigma[i] + H.sigma[H.parent[i]] > 0)) st = fail(WOI_E_INVALID_ARG, "sigma[%d] + sigma[parent] must be > 0", i);
+    if (st == WOI_OK && !(H.sigma[0] > 0)) st = fail(WOI_E_INVALID_ARG, "sigma[0] must be > 0");
+    if (st == WOI_OK) st = compile_shapes(d, H);
+    if (st == WOI_OK) st = compile_data(d, H);
+    if (st == WOI_OK) st = validate_nesting(H);
+    if (st != WOI_OK) { delete P; return st; }
+
+    // alpha_i and beta scale s_i (Eq. unit_coeff_charge_density_sys)
+    H.alpha_l1 = 0;
+    for (int i = 0; i < N; ++i) {
+        HostRegion& g = H.r[i];
+        if (i == 0) { g.alpha = 2.0; g.s = 2.0 / H.sigma[0]; }
+        else {
+            const double sp = H.sigma[H.parent[i]], si = H.sigma[i];
+            g.alpha = 2.0 * (si - sp) / (sp + si);
+            g.s = -2.0 / (sp + si);
+        }
+        H.alpha_l1 += std::fabs(g.alpha);
+    }
+    flux_integrals(H);
+    if (d->compat_mode == WOI_COMPAT_PER_INTERFACE) {
+        for (int i = 0; i < N; ++i)
+            if (std::fabs(H.r[i].flux) > d->compat_tol * H.r[i].absflux + 1e-300) {
+                delete P;
+                return fail(WOI_E_INCOMPATIBLE, "region %d: integral of b = %.3e exceeds tol * integral |b| = %.3e", i,
+                            H.r[i].flux, d->compat_tol * H.r[i].absflux);
+            }
+    } else if (d->compat_mode == WOI_COMPAT_GLOBAL) {
+        double s = -H.r[0].flux, sa = H.r[0].absflux;
+        for (int i = 1; i < N; ++i) { s += H.r[i].flux; sa += H.r[i].absflux; }
+        if (std::fabs(s) > d->compat_tol * sa + 1e-300) {
+            delete P;
+            return fail(WOI_E_INCOMPATIBLE, "global flux balance violated by %.3e", s);
+        }
+    } else if (d->compat_mode != WOI_COMPAT_NONE) {
+        delete P;
+        return fail(WOI_E_INVALID_ARG, "unknown compat_mode %d", d->compat_mode);
+    }
+    // VR halves
+    const bool vr_ok = m <= 3;
+    for (int i = 0; i < N; ++i) {
+        HostRegion& g = H.r[i];
+        if (m == 2) vr_halves_2d(H, g);
+        else if (m == 3) vr_halves_3d(H, g);
+        else g.meas[0] = g.meas[1] = std::nan("");
+        if (m == 3)
+            for (int c = 0; c < 2; ++c)
+                if (g.meas[c] < 1e-13 * g.area) g.meas[c] = 0.0;
+    }
+
+    // ---- device layout
+    std::vector<double> p64;
+    std::vector<float> p32;
+    std::vector<uint8_t> pb;
+    auto put64 = [&](const double* x, size_t n) { const int o = (int)p64.size(); p64.insert(p64.end(), x, x + n); return o; };
+    auto put32 = [&](const double* x, size_t n) {
+        const int o = (int)p32.size();
+        for (size_t k = 0; k < n; ++k) p32.push_back((float)x[k]);
+        return o;
+    };
+    DevProblem hdr;
+    std::memset(&hdr, 0, sizeof hdr);
+    hdr.dim = m;
+    hdr.N = N;
+    hdr.vr_ok = vr_ok;
+    hdr.alpha_l1 = H.alpha_l1;
+    hdr.unit_area = 2 * std::pow(kPi, 0.5 * m) / std::tgamma(0.5 * m);
+    hdr.phi_c = m == 2 ? 1.0 / (2 * kPi) : 1.0 / ((m - 2) * hdr.unit_area);
+    hdr.alpha_l1_f = (float)hdr.alpha_l1;
+    hdr.unit_area_f = (float)hdr.unit_area;
+    hdr.phi_c_f = (float)hdr.phi_c;
+    double acc = 0;
+    for (int i = 0; i < N; ++i) {
+        acc += std::fabs(H.r[i].alpha);
+        hdr.cdf[i] = acc / H.alpha_l1;
+    }
+    for (int a = 0; a < N; ++a)
+        for (int b = 0; b < N; ++b) {
+            int rel = woi::REL_OTHER;
+            if (a == b) rel = woi::REL_SAME;
+            else
+                for (int p = H.parent[a]; p >= 0; p = H.parent[p])
+                    if (p == b) { rel = woi::REL_DESC; break; }
+            hdr.rel[a][b] = (unsigned char)rel;
+        }
+    for (int i = 0; i < N; ++i) {
+        const HostRegion& g = H.r[i];
+        DevRegion& r = hdr.reg[i];
+        r.kind = g.kind;
+        r.dkind = g.dkind;
+        r.nt = g.nt;
+        std::vector<double> geo;
+        if (g.kind == WOI_SHAPE_SPHERE) {
+            geo.assign(g.c, g.c + m);
+            geo.push_back(g.R);
+        } else if (g.kind == WOI_SHAPE_ELLIPSOID) {
+            geo.assign(g.c, g.c + m);
+            geo.insert(geo.end(), g.A, g.A + m * m);
+            geo.insert(geo.end(), g.L, g.L + m * m);
+            geo.push_back(1.0 / g.lam_max);
+        } else {
+            geo = g.v;
+            r.nv = g.nv();
+        }
+        r.g64 = put64(geo.data(), geo.size());
+        r.g32 = put32(geo.data(), geo.size());
+        if (g.kind == WOI_SHAPE_POLYLINE2D) {
+            r.len64 = put64(g.len.data(), g.len.size());
+            r.len32 = put32(g.len.data(), g.len.size());
+            r.cum64 = put64(g.cum.data(), g.cum.size());
+            r.cum32 = put32(g.cum.data(), g.cum.size());
+            std::vector<float> nodes;
+            r.leaf = 8;
+            build_bvh(g, r.nleaf, r.leaf, nodes);
+            while (p32.size() % 4) p32.push_back(0.f);
+            r.bvh = (int)p32.size();
+            p32.insert(p32.end(), nodes.begin(), nodes.end());
+        }
+        if (!g.coef.empty()) {
+            r.d64 = put64(g.coef.data(), g.coef.size());
+            r.d32 = put32(g.coef.data(), g.coef.size());
+        }
+        if (!g.exps.empty()) {
+            r.dexp = (int)pb.size();
+            pb.insert(pb.end(), g.exps.begin(), g.exps.end());
+        }
+        if (!g.brk.empty()) {
+            r.b64 = put64(g.brk.data(), g.brk.size());
+            r.b32 = put32(g.brk.data(), g.brk.size());
+        }
+        r.nbrk = (int)g.brk.size();
+        r.class0 = g.class0;
+        r.alpha = g.alpha;
+        r.sgn = g.alpha < 0 ? -1.0 : 1.0;
+        r.s = g.s;
+        r.area = g.area;
+        r.meas[0] = g.meas[0];
+        r.meas[1] = g.meas[1];
+        r.total = g.total;
+        r.alpha_f = (float)r.alpha;
+        r.sgn_f = (float)r.sgn;
+        r.s_f = (float)r.s;
+        r.area_f = (float)r.area;
+        r.meas_f[0] = (float)r.meas[0];
+        r.meas_f[1] = (float)r.meas[1];
+        r.total_f = (float)r.total;
+    }
+    auto align = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
+    hdr.off64 = align(sizeof(DevProblem));
+    hdr.off32 = align(hdr.off64 + p64.size() * sizeof(double));
+    hdr.offb = align(hdr.off32 + p32.size() * sizeof(float));
+    hdr.bytes = align(hdr.offb + pb.size() + 16);
+    std::vector<uint8_t> blob(hdr.bytes, 0);
+    std::memcpy(blob.data(), &hdr, sizeof hdr);
+    if (!p64.empty()) std::memcpy(blob.data() + hdr.off64, p64.data(), p64.size() * sizeof(double));
+    if (!p32.empty()) std::memcpy(blob.data() + hdr.off32, p32.data(), p32.size() * sizeof(float));
+    if (!pb.empty()) std::memcpy(blob.data() + hdr.offb, pb.data(), pb.size());
+    P->blob = std::move(blob);
+    P->bytes = hdr.bytes;
+    woi_problem_info& inf = P->info;
+    inf.dim = m;
+    inf.n_regions = N;
+    inf.alpha_l1 = H.alpha_l1;
+    for (int i = 0; i < N; ++i) {
+        inf.alpha[i] = H.r[i].alpha;
+        inf.beta_scale[i] = H.r[i].s;
+        inf.area[i] = H.r[i].area;
+        inf.area_plus[i] = H.r[i].meas[0];
+        inf.area_minus[i] = H.r[i].meas[1];
+        inf.flux[i] = H.r[i].flux;
+    }
+    inf.device_bytes = hdr.bytes;
+    *out = P;
+    return WOI_OK;
+}
+
+woi_status woi_problem_upload(woi_problem* p) {
+    if (!p) return fail(WOI_E_INVALID_ARG, "NULL problem");
+    std::lock_guard<std::mutex> lk(p->mu);
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(WOI_E_DEVICE, "no HIP device");
+    if (p->dev) {
+        if (cur != p->device) return fail(WOI_E_INVALID_ARG, "problem lives on device %d, current device is %d", p->device, cur);
+        return WOI_OK;
+    }
+    void* d = nullptr;
+    if (hipMalloc(&d, p->bytes) != hipSuccess) return fail(WOI_E_OOM, "hipMalloc(%zu) failed", p->bytes);
+    if (hipMemcpy(d, p->blob.data(), p->bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        return fail(WOI_E_DEVICE, "problem upload failed");
+    }
+    p->dev = d;
+    p->device = cur;
+    return WOI_OK;
+}
+
+void woi_problem_destroy(woi_problem* p) {
+    if (!p) return;
+    if (p->dev) {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(p->device);
+        (void)hipFree(p->dev);
+        (void)hipSetDevice(cur);
+    }
+    delete p;
+}
+
+woi_status woi_problem_get_info(const woi_problem* p, woi_problem_info* out) {
+    if (!p || !out) return fail(WOI_E_INVALID_ARG, "NULL argument");
+    *out = p->info;
+    return WOI_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------- estimation
+namespace {
+
+struct Plan {
+    int block;
+    uint32_t spt;
+    int chunks;
+    unsigned gx;
+    uint64_t n_samples, first;
+};
+
+woi_status check_query(const woi_problem* p, int64_t P, const woi_query* q) {
+    if (!p || !q) return fail(WOI_E_INVALID_ARG, "NULL problem or query");
+    if (P < 1) return fail(WOI_E_INVALID_ARG, "P = %lld must be >= 1", (long long)P);
+    if (q->M < 0 || q->M > WOI_MAX_M) return fail(WOI_E_INVALID_ARG, "M = %d outside [0, %d]", q->M, WOI_MAX_M);
+    if (q->walks < 1) return fail(WOI_E_INVALID_ARG, "walks must be >= 1");
+    if (q->estimator != WOI_EST_PLAIN && q->estimator != WOI_EST_VR) return fail(WOI_E_INVALID_ARG, "bad estimator");
+    if (q->precision != WOI_PREC_FP64 && q->precision != WOI_PREC_FP32) return fail(WOI_E_INVALID_ARG, "bad precision");
+    if (q->estimator == WOI_EST_VR) {
+        if (p->H.m > 3) return fail(WOI_E_UNSUPPORTED, "variance reduction needs dim <= 3");
+        if ((q->walks & 1) || (q->walk_offset & 1)) return fail(WOI_E_INVALID_ARG, "VR needs even walks and walk_offset");
+    }
+    if (q->batch_share < 1) return fail(WOI_E_INVALID_ARG, "batch_share must be >= 1");
+    if (q->instance >= (1u << 24)) return fail(WOI_E_INVALID_ARG, "instance must be < 2^24");
+    const uint64_t ns = q->estimator == WOI_EST_VR ? q->walks / 2 : q->walks;
+    const uint64_t first = q->estimator == WOI_EST_VR ? q->walk_offset / 2 : q->walk_offset;
+    if (first + ns > (1ull << 32)) return fail(WOI_E_INVALID_ARG, "walk indices must stay below 2^32");
+    return WOI_OK;
+}
+
+Plan make_plan(const woi_problem* p, int64_t P, const woi_query* q, uint64_t n_samples) {
+    Plan pl;
+    pl.n_samples = n_samples;
+    pl.first = q->estimator == WOI_EST_VR ? q->walk_offset / 2 : q->walk_offset;
+    pl.block = q->block_size > 0 ? q->block_size : (P >= 4096 ? 256 : 64);
+    pl.gx = (unsigned)((P + pl.block - 1) / pl.block);
+    uint64_t spt;
+    if (q->samples_per_thread > 0) spt = (uint64_t)q->samples_per_thread;
+    else {
+        // aim at >= 2^20 resident threads (256 CUs x 4 SIMDs x 16 waves x 64 lanes) with
+        // at least 8 samples per thread
+        const uint64_t target = 1ull << 20;
+        const uint64_t lanes = (uint64_t)pl.gx * pl.block;
+        uint64_t chunks = std::max<uint64_t>(1, (target + lanes - 1) / lanes);
+        spt = std::max<uint64_t>(8, (n_samples + chunks - 1) / chunks);
+    }
+    spt = std::min<uint64_t>(spt, n_samples);
+    uint64_t chunks = (n_samples + spt - 1) / spt;
+    while (chunks > 65535) { spt *= 2; chunks = (n_samples + spt - 1) / spt; }
+    pl.spt = (uint32_t)spt;
+    pl.chunks = (int)chunks;
+    (void)p;
+    return pl;
+}
+
+}  // namespace
+
+extern "C" {
+
+woi_status woi_workspace_size(const woi_problem* p, int64_t P, const woi_query* q, size_t* bytes) {
+    woi_status st = check_query(p, P, q);
+    if (st != WOI_OK) return st;
+    if (!bytes) return fail(WOI_E_INVALID_ARG, "NULL bytes");
+    const uint64_t ns = q->estimator == WOI_EST_VR ? q->walks / 2 : q->walks;
+    const Plan pl = make_plan(p, P, q, ns);
+    *bytes = (size_t)pl.chunks * (size_t)P * (2 + 2 * p->H.m) * sizeof(double);
+    return WOI_OK;
+}
+
+woi_status woi_estimate(const woi_problem* p, const double* points, int64_t P, const woi_query* q, double* mean,
+                        double* se, double* grad, double* grad_se, void* workspace, size_t workspace_bytes,
+                        uint64_t* counters, void* stream) {
+    woi_status st = check_query(p, P, q);
+    if (st != WOI_OK) return st;
+    if (!points || !mean || !se) return fail(WOI_E_INVALID_ARG, "NULL points/mean/se");
+    st = woi_problem_upload(const_cast<woi_problem*>(p));
+    if (st != WOI_OK) return st;
+    const uint64_t ns = q->estimator == WOI_EST_VR ? q->walks / 2 : q->walks;
+    const Plan pl = make_plan(p, P, q, ns);
+    const size_t need = (size_t)pl.chunks * (size_t)P * (2 + 2 * p->H.m) * sizeof(double);
+    if (!workspace || workspace_bytes < need)
+        return fail(WOI_E_OOM, "workspace of %zu bytes is smaller than the %zu bytes needed", workspace_bytes, need);
+    woi::KParams kp{};
+    kp.dp = static_cast<const DevProblem*>(p->dev);
+    kp.points = points;
+    kp.P = P;
+    kp.n_samples = ns;
+    kp.first_sample = pl.first;
+    kp.samples_per_thread = pl.spt;
+    kp.k0 = (uint32_t)q->seed;
+    kp.k1 = (uint32_t)(q->seed >> 32);
+    kp.M = q->M;
+    kp.batch_share = q->batch_share;
+    kp.shared_sched = q->schedule_mode == WOI_SCHED_SHARED;
+    kp.instance = q->instance;
+    kp.partials = static_cast<double*>(workspace);
+    kp.counters = counters;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = woi::launch_walk(kp, p->H.m, q->estimator == WOI_EST_VR, q->precision == WOI_PREC_FP32,
+                                    dim3(pl.gx, pl.chunks), dim3(pl.block), s);
+    if (e != hipSuccess) return fail(WOI_E_DEVICE, "walk launch failed: %s", hipGetErrorString(e));
+    woi::RParams rp{};
+    rp.partials = kp.partials;
+    rp.P = P;
+    rp.dim = p->H.m;
+    rp.n_chunks = pl.chunks;
+    rp.samples_per_thread = pl.spt;
+    rp.n_samples = ns;
+    rp.mean = mean;
+    rp.se = se;
+    rp.grad = grad;
+    rp.grad_se = grad_se;
+    e = woi::launch_reduce(rp, s);
+    if (e != hipSuccess) return fail(WOI_E_DEVICE, "reduce launch failed: %s", hipGetErrorString(e));
+    return WOI_OK;
+}
+
+woi_status woi_trace(const woi_problem* p, const double* points, int64_t P, const woi_query* q, uint64_t n_samples,
+                     double* F, double* G, uint32_t* trace, void* stream) {
+    woi_query qq = *q;
+    qq.walks = q->estimator == WOI_EST_VR ? 2 * n_samples : n_samples;
+    woi_status st = check_query(p, P, &qq);
+    if (st != WOI_OK) return st;
+    if (!points || !F) return fail(WOI_E_INVALID_ARG, "NULL points or F");
+    st = woi_problem_upload(const_cast<woi_problem*>(p));
+    if (st != WOI_OK) return st;
+    const Plan pl = make_plan(p, P, &qq, n_samples);
+    woi::KParams kp{};
+    kp.dp = static_cast<const DevProblem*>(p->dev);
+    kp.points = points;
+    kp.P = P;
+    kp.n_samples = n_samples;
+    kp.first_sample = pl.first;
+    kp.samples_per_thread = pl.spt;
+    kp.k0 = (uint32_t)q->seed;
+    kp.k1 = (uint32_t)(q->seed >> 32);
+    kp.M = q->M;
+    kp.batch_share = q->batch_share;
+    kp.shared_sched = q->schedule_mode == WOI_SCHED_SHARED;
+    kp.instance = q->instance;
+    kp.traceF = F;
+    kp.traceG = G;
+    kp.trace = trace;
+    hipError_t e = woi::launch_walk(kp, p->H.m, q->estimator == WOI_EST_VR, q->precision == WOI_PREC_FP32,
+                                    dim3(pl.gx, pl.chunks), dim3(pl.block), static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(WOI_E_DEVICE, "walk launch failed: %s", hipGetErrorString(e));
+    return WOI_OK;
+}
+
+woi_status woi_batch_workspace_size(const woi_batch_item* items, int n, size_t* bytes) {
+    (void)items; (void)n; (void)bytes;
+    return fail(WOI_E_UNSUPPORTED, "batched estimation not built yet");
+}
+
+woi_status woi_estimate_batch(const woi_batch_item* items, int n, void* workspace, size_t workspace_bytes,
+                              uint64_t* counters, void* stream) {
+    (void)items; (void)n; (void)workspace; (void)workspace_bytes; (void)counters; (void)stream;
+    return fail(WOI_E_UNSUPPORTED, "batched estimation not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,754 @@
+// woi_kernels.hip -- gfx950 kernels of the Walk-on-Interfaces estimator.
+//
+// Paper: Ding & Stinchcombe, "Walk-on-Interfaces", arXiv 2508.16767.
+//   schedule H_0 ~ U{1..N}, H_i ~ |alpha|/||alpha||_1      Theorem 2, Eq. scheduled_interface_pdf
+//   transitions (line / ray / uniform) and Q, T factors    Sec. 4.2.1-4.2.3, Eqs. naive_woi_p, _Q, _T
+//   accumulation of w_i ||alpha||^i prod sign Q T Phi      Eq. woi_estimator, Alg. 2
+//   two walkers on {beta >= 0} / {beta < 0}               Sec. 4.4, Alg. 3
+//   gradient by grad_x Phi on the same walks               Sec. 4.5
+//
+// Mapping: one lane = one evaluation point, a thread loops over a chunk of samples
+// (walk indices).  With the shared schedule the walk index -- and so the scheduled
+// interface and the transition case -- is the same for all 64 lanes of a wave, so
+// the case branch and the geometry record are wave-uniform (scalar loads/branches);
+// only positions differ.  Every lane draws its own Philox4x32-10 counters keyed by
+// (walk, point group, instance|walker|purpose, step|draw), so results do not depend
+// on the launch shape.  Per-point sums are FP64 in every precision.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "woi_device.h"
+#include "woi_launch.h"
+
+namespace woi {
+
+#define WOI_ATTEMPT_CAP 256
+
+// ----------------------------------------------------------------------------- Philox4x32-10
+// Salmon, Moraes, Dror, Shaw (SC'11): 10 rounds, multipliers 0xD2511F53 / 0xCD9E8D57,
+// Weyl key increments 0x9E3779B9 / 0xBB67AE85.
+__device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
+                       (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+    }
+    return c;
+}
+
+struct Stream {
+    uint32_t k0, k1, c0, c1, c2;
+    __device__ __forceinline__ uint4 block(uint32_t step, uint32_t draw) const {
+        return philox(make_uint4(c0, c1, c2, (step << 16) | (draw & 0xFFFFu)), k0, k1);
+    }
+};
+
+// NW consecutive words of draws [first, ...): registers only (fully unrolled).
+template <int NW>
+struct Words {
+    uint32_t w[NW];
+    __device__ __forceinline__ void fill(const Stream& s, uint32_t step, uint32_t first) {
+#pragma unroll
+        for (int b = 0; b < (NW + 3) / 4; ++b) {
+            const uint4 v = s.block(step, first + b);
+            if (4 * b + 0 < NW) w[4 * b + 0] = v.x;
+            if (4 * b + 1 < NW) w[4 * b + 1] = v.y;
+            if (4 * b + 2 < NW) w[4 * b + 2] = v.z;
+            if (4 * b + 3 < NW) w[4 * b + 3] = v.w;
+        }
+    }
+};
+
+// ----------------------------------------------------------------------------- precision
+template <typename R> struct RO;
+template <> struct RO<double> {
+    static __device__ __forceinline__ double u(uint32_t v) { return ((double)v + 0.5) * 0x1p-32; }
+    static __device__ __forceinline__ void sc2pi(double u, double& s, double& c) { sincospi(2.0 * u, &s, &c); }
+    static __device__ __forceinline__ double lg(double x) { return log(x); }
+    static __device__ __forceinline__ double sq(double x) { return sqrt(x); }
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+    static constexpr double line_eps = 1e-12;   // |t| below which a polyline hit is y itself
+    static constexpr double ray_eps = 0.0;
+};
+template <> struct RO<float> {
+    static __device__ __forceinline__ float u(uint32_t v) { return (float)((v >> 8) | 1u) * 0x1p-24f; }
+    // v_sin_f32 / v_cos_f32 take their argument in revolutions
+    static __device__ __forceinline__ void sc2pi(float u, float& s, float& c) {
+        s = __builtin_amdgcn_sinf(u); c = __builtin_amdgcn_cosf(u);
+    }
+    static __device__ __forceinline__ float lg(float x) { return __logf(x); }
+    static __device__ __forceinline__ float sq(float x) { return __builtin_sqrtf(x); }
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+    static constexpr float line_eps = 1e-5f;
+    static constexpr float ray_eps = 0.0f;
+};
+
+template <typename R> struct Pay;
+template <> struct Pay<double> {
+    static __device__ __forceinline__ const double* base(const DevProblem* dp) {
+        return reinterpret_cast<const double*>(reinterpret_cast<const char*>(dp) + dp->off64);
+    }
+    static __device__ __forceinline__ int g(const DevRegion& r) { return r.g64; }
+    static __device__ __forceinline__ int len(const DevRegion& r) { return r.len64; }
+    static __device__ __forceinline__ int cum(const DevRegion& r) { return r.cum64; }
+    static __device__ __forceinline__ int dat(const DevRegion& r) { return r.d64; }
+    static __device__ __forceinline__ int brk(const DevRegion& r) { return r.b64; }
+    static __device__ __forceinline__ double area(const DevRegion& r) { return r.area; }
+    static __device__ __forceinline__ double meas(const DevRegion& r, int k) { return r.meas[k]; }
+    static __device__ __forceinline__ double total(const DevRegion& r) { return r.total; }
+    static __device__ __forceinline__ double s(const DevRegion& r) { return r.s; }
+    static __device__ __forceinline__ double sgn(const DevRegion& r) { return r.sgn; }
+    static __device__ __forceinline__ double l1(const DevProblem* dp) { return dp->alpha_l1; }
+    static __device__ __forceinline__ double ua(const DevProblem* dp) { return dp->unit_area; }
+    static __device__ __forceinline__ double pc(const DevProblem* dp) { return dp->phi_c; }
+};
+template <> struct Pay<float> {
+    static __device__ __forceinline__ const float* base(const DevProblem* dp) {
+        return reinterpret_cast<const float*>(reinterpret_cast<const char*>(dp) + dp->off32);
+    }
+    static __device__ __forceinline__ int g(const DevRegion& r) { return r.g32; }
+    static __device__ __forceinline__ int len(const DevRegion& r) { return r.len32; }
+    static __device__ __forceinline__ int cum(const DevRegion& r) { return r.cum32; }
+    static __device__ __forceinline__ int dat(const DevRegion& r) { return r.d32; }
+    static __device__ __forceinline__ int brk(const DevRegion& r) { return r.b32; }
+    static __device__ __forceinline__ float area(const DevRegion& r) { return r.area_f; }
+    static __device__ __forceinline__ float meas(const DevRegion& r, int k) { return r.meas_f[k]; }
+    static __device__ __forceinline__ float total(const DevRegion& r) { return r.total_f; }
+    static __device__ __forceinline__ float s(const DevRegion& r) { return r.s_f; }
+    static __device__ __forceinline__ float sgn(const DevRegion& r) { return r.sgn_f; }
+    static __device__ __forceinline__ float l1(const DevProblem* dp) { return dp->alpha_l1_f; }
+    static __device__ __forceinline__ float ua(const DevProblem* dp) { return dp->unit_area_f; }
+    static __device__ __forceinline__ float pc(const DevProblem* dp) { return dp->phi_c_f; }
+};
+
+struct Counts {
+    uint32_t steps, redraws, rejections, caps, zero;
+};
+
+constexpr int dir_words(int D) { return D == 2 ? 1 : (D == 3 ? 2 : 2 * ((D + 1) / 2)); }
+
+// ----------------------------------------------------------------------------- directions
+// Uniform direction on S^{D-1} from the first dir_words(D) words.
+template <typename R, int D, int NW>
+__device__ __forceinline__ void unit_dir(const Words<NW>& W, R d[D]) {
+    if constexpr (D == 2) {
+        RO<R>::sc2pi(RO<R>::u(W.w[0]), d[1], d[0]);
+    } else if constexpr (D == 3) {
+        const R z = R(2) * RO<R>::u(W.w[0]) - R(1);
+        R s, c;
+        RO<R>::sc2pi(RO<R>::u(W.w[1]), s, c);
+        const R r = RO<R>::sq(fmax(R(0), R(1) - z * z));
+        d[0] = r * c; d[1] = r * s; d[2] = z;
+    } else {
+        R g[2 * ((D + 1) / 2)];
+#pragma unroll
+        for (int j = 0; j < (D + 1) / 2; ++j) {
+            const R rr = RO<R>::sq(R(-2) * RO<R>::lg(RO<R>::u(W.w[2 * j])));
+            R s, c;
+            RO<R>::sc2pi(RO<R>::u(W.w[2 * j + 1]), s, c);
+            g[2 * j] = rr * c; g[2 * j + 1] = rr * s;
+        }
+        R n2 = 0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) n2 += g[i] * g[i];
+        const R inv = RO<R>::rsq(n2);
+#pragma unroll
+        for (int i = 0; i < D; ++i) d[i] = g[i] * inv;
+    }
+}
+
+// ----------------------------------------------------------------------------- geometry
+template <typename R, int D>
+__device__ __forceinline__ void normal_at(const DevRegion& g, const R* __restrict__ pay, const R y[D], int seg, R n[D]) {
+    const R* q = pay + Pay<R>::g(g);
+    if (g.kind == WOI_SHAPE_SPHERE) {
+        const R iR = R(1) / q[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) n[i] = (y[i] - q[i]) * iR;
+    } else if (g.kind == WOI_SHAPE_ELLIPSOID) {
+        R s = 0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            R t = 0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) t += q[D + i * D + j] * (y[j] - q[j]);
+            n[i] = t; s += t * t;
+        }
+        const R inv = R(1) / RO<R>::sq(s);
+#pragma unroll
+        for (int i = 0; i < D; ++i) n[i] *= inv;
+    } else {
+        if constexpr (D == 2) {
+            const R* v = q + 2 * seg;
+            const R ex = v[2] - v[0], ey = v[3] - v[1];
+            const R l = RO<R>::sq(ex * ex + ey * ey);
+            n[0] = ey / l; n[1] = -ex / l;
+        }
+    }
+}
+
+// b_i(y) (Eq. interface_problem data).
+template <typename R, int D>
+__device__ __forceinline__ R data_b(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
+                                    const R y[D], int seg) {
+    const R* cf = pay + Pay<R>::dat(g);
+    if (g.dkind == WOI_DATA_ZERO) return R(0);
+    if (g.dkind == WOI_DATA_FIELD_FLUX || g.dkind == WOI_DATA_SOURCE_FLUX) {
+        R n[D];
+        normal_at<R, D>(g, pay, y, seg, n);
+        if (g.dkind == WOI_DATA_FIELD_FLUX) {
+            R b = 0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) b += cf[i] * n[i];
+            return b;
+        }
+        R dn = 0, r2 = 0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) { const R e = y[i] - cf[1 + i]; dn += e * n[i]; r2 += e * e; }
+        R rm = R(1);
+#pragma unroll
+        for (int i = 0; i < D / 2; ++i) rm *= r2;
+        if constexpr (D % 2) rm *= RO<R>::sq(r2);
+        return cf[0] * dn / rm;
+    }
+    // direction-based data: e = (y - c)/|y - c|, c stored after the coefficients
+    const R* c = cf + (g.dkind == WOI_DATA_FOURIER2D ? 2 * g.nt + 1 : g.nt);
+    R e[D], r2 = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) { e[i] = y[i] - c[i]; r2 += e[i] * e[i]; }
+    const R ir = RO<R>::rsq(r2);
+#pragma unroll
+    for (int i = 0; i < D; ++i) e[i] *= ir;
+    if (g.dkind == WOI_DATA_FOURIER2D) {
+        // cos(k th) + i sin(k th) = (e_x + i e_y)^k
+        R b = cf[0], zr = 1, zi = 0;
+        for (int k = 1; k <= g.nt; ++k) {
+            const R nr = zr * e[0] - zi * e[1], ni = zr * e[1] + zi * e[0];
+            zr = nr; zi = ni;
+            b += cf[2 * k - 1] * zr + cf[2 * k] * zi;
+        }
+        return b;
+    }
+    const unsigned char* ex = reinterpret_cast<const unsigned char*>(dp) + dp->offb + g.dexp;
+    R b = 0;
+    for (int t = 0; t < g.nt; ++t) {
+        R term = cf[t];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+            for (int p = 0; p < ex[t * D + i]; ++p) term *= e[i];
+        b += term;
+    }
+    return b;
+}
+
+// ---- uniform surface sample, one attempt: returns false when rejected
+template <typename R, int D>
+__device__ __forceinline__ bool polyline_at(const DevRegion& g, const R* __restrict__ pay, R s, R y[D], int& seg) {
+    if constexpr (D == 2) {
+        const R* cum = pay + Pay<R>::cum(g);
+        int lo = 0, hi = g.nv - 1;   // largest j with cum[j] <= s
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (cum[mid] <= s) lo = mid; else hi = mid - 1;
+        }
+        const R* v = pay + Pay<R>::g(g) + 2 * lo;
+        const R f = (s - cum[lo]) / pay[Pay<R>::len(g) + lo];
+        y[0] = v[0] + f * (v[2] - v[0]); y[1] = v[1] + f * (v[3] - v[1]);
+        seg = lo;
+    }
+    return true;
+}
+
+template <typename R, int D>
+__device__ __forceinline__ int surf_words(const DevRegion& g) {
+    return g.kind == WOI_SHAPE_POLYLINE2D ? 1 : dir_words(D) + (g.kind == WOI_SHAPE_ELLIPSOID ? 1 : 0);
+}
+
+template <typename R, int D>
+__device__ __forceinline__ bool surf_attempt(const DevRegion& g, const R* __restrict__ pay, const Stream& st,
+                                             uint32_t step, int att, R y[D], int& seg) {
+    seg = 0;
+    if (g.kind == WOI_SHAPE_POLYLINE2D) {
+        Words<1> W; W.fill(st, step, (uint32_t)att);
+        return polyline_at<R, D>(g, pay, RO<R>::u(W.w[0]) * Pay<R>::total(g), y, seg);
+    }
+    const R* q = pay + Pay<R>::g(g);
+    if (g.kind == WOI_SHAPE_SPHERE) {
+        constexpr int NW = dir_words(D), NB = (NW + 3) / 4;
+        Words<NW> W; W.fill(st, step, (uint32_t)(att * NB));
+        R u[D];
+        unit_dir<R, D>(W, u);
+#pragma unroll
+        for (int i = 0; i < D; ++i) y[i] = q[i] + q[D] * u[i];
+        return true;
+    }
+    // ellipsoid: y = c + A^{-1/2} u, accept with probability |A^{1/2} u| / sqrt(lambda_max)
+    constexpr int NW = dir_words(D) + 1, NB = (NW + 3) / 4;
+    Words<NW> W; W.fill(st, step, (uint32_t)(att * NB));
+    R u[D];
+    unit_dir<R, D>(W, u);
+    const R acc = RO<R>::u(W.w[NW - 1]);
+    R uAu = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        R t = 0, l = 0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) { t += q[D + i * D + j] * u[j]; l += q[D + D * D + i * D + j] * u[j]; }
+        uAu += u[i] * t;
+        y[i] = q[i] + l;
+    }
+    return acc < RO<R>::sq(uAu * q[D + 2 * D * D]);
+}
+
+// point at arclength s on a closed 2D curve (circle or polyline)
+template <typename R, int D>
+__device__ __forceinline__ void curve_at(const DevRegion& g, const R* __restrict__ pay, R s, R y[D], int& seg) {
+    if constexpr (D == 2) {
+        if (g.kind == WOI_SHAPE_POLYLINE2D) { polyline_at<R, D>(g, pay, s, y, seg); return; }
+        const R* q = pay + Pay<R>::g(g);
+        R sn, cs;
+        RO<R>::sc2pi(s / (R(2) * R(3.14159265358979323846) * q[2]), sn, cs);
+        y[0] = q[0] + q[2] * cs; y[1] = q[1] + q[2] * sn; seg = 0;
+    }
+}
+
+// one attempt of a uniform sample on the VR half `cls` of region h
+template <typename R, int D>
+__device__ __forceinline__ bool vr_attempt(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
+                                           int cls, const Stream& st, int att, R y[D], int& seg) {
+    if constexpr (D == 2) {
+        Words<1> W; W.fill(st, 0, (uint32_t)att);
+        const R t = RO<R>::u(W.w[0]) * Pay<R>::meas(g, cls);
+        const R* br = pay + Pay<R>::brk(g);
+        R start = 0, acc = 0;
+        int c = g.class0;
+        for (int p = 0; p <= g.nbrk; ++p) {
+            const R end = p < g.nbrk ? br[p] : Pay<R>::total(g);
+            if (c == cls) {
+                const R l = end - start;
+                if (t < acc + l || p == g.nbrk) {
+                    curve_at<R, D>(g, pay, fmin(start + (t - acc), end), y, seg);
+                    return true;
+                }
+                acc += l;
+            }
+            start = end; c ^= 1;
+        }
+        curve_at<R, D>(g, pay, start, y, seg);
+        return true;
+    } else {
+        if (!surf_attempt<R, D>(g, pay, st, 0, att, y, seg)) return false;
+        return (Pay<R>::s(g) * data_b<R, D>(dp, g, pay, y, seg) >= R(0)) == (cls == 0);
+    }
+}
+
+// ---- line / ray intersections
+// Quadric (sphere, ellipsoid): returns q in {0, 1} and t.
+template <typename R, int D>
+__device__ __forceinline__ int quadric_hit(const DevRegion& g, const R* __restrict__ pay, const R y[D], const R d[D],
+                                           bool ray, R& t) {
+    const R* q = pay + Pay<R>::g(g);
+    R yc[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) yc[i] = y[i] - q[i];
+    R a, b, cc;
+    if (g.kind == WOI_SHAPE_SPHERE) {
+        a = 1; b = 0; cc = -q[D] * q[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) { b += yc[i] * d[i]; cc += yc[i] * yc[i]; }
+    } else {
+        a = 0; b = 0; cc = -1;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            R s1 = 0, s2 = 0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) { s1 += q[D + i * D + j] * d[j]; s2 += q[D + i * D + j] * yc[j]; }
+            a += d[i] * s1; b += d[i] * s2; cc += yc[i] * s2;
+        }
+    }
+    if (!ray) {   // y on the quadric: other root of t (a t + 2 b) = 0
+        t = R(-2) * b / a;
+        return t != R(0) ? 1 : 0;
+    }
+    const R disc = b * b - a * cc;
+    if (disc < R(0)) return 0;
+    t = (-b + RO<R>::sq(disc)) / a;
+    return t > R(0) ? 1 : 0;
+}
+
+// Polyline: hits in segment order via a stackless walk of the implicit binary tree of
+// leaf boxes (left to right).  want < 0: count all hits, remembering the first two;
+// want >= 0: stop at hit number `want`.
+template <typename R>
+struct PolyHit { int q; int seg0, seg1; };
+
+template <typename R>
+__device__ __forceinline__ bool seg_hit(const R* v, const R y[2], const R d[2], bool ray, R eps) {
+    const R ex = v[2] - v[0], ey = v[3] - v[1];
+    const R den = d[0] * ey - d[1] * ex;
+    if (den == R(0)) return false;
+    const R wx = v[0] - y[0], wy = v[1] - y[1];
+    const R t = (wx * ey - wy * ex) / den;
+    const R s = (wx * d[1] - wy * d[0]) / den;
+    if (s < R(0) || s >= R(1)) return false;
+    return ray ? (t > R(0)) : (fabs(t) > eps);
+}
+
+template <typename R>
+__device__ __noinline__ int poly_walk(const DevRegion& g, const R* __restrict__ pay, const float4* __restrict__ nodes,
+                                      const R y[2], const R d[2], bool ray, int yseg, int want, int& s0, int& s1) {
+    const R* v = pay + Pay<R>::g(g);
+    const float fy0 = (float)y[0], fy1 = (float)y[1], fd0 = (float)d[0], fd1 = (float)d[1];
+    const float ad0 = fabsf(fd0), ad1 = fabsf(fd1);
+    const int first_leaf = g.nleaf - 1;
+    int k = 0, q = 0;
+    s0 = s1 = -1;
+    while (true) {
+        const float4 b = nodes[k];
+        const float cx = b.x - fy0, cy = b.y - fy1;
+        bool hit = fabsf(fd0 * cy - fd1 * cx) <= ad1 * b.z + ad0 * b.w;
+        if (ray) hit = hit && (fd0 * cx + fd1 * cy + ad0 * b.z + ad1 * b.w >= 0.f);
+        if (hit && k < first_leaf) { k = 2 * k + 1; continue; }
+        if (hit) {
+            const int j0 = (k - first_leaf) * g.leaf;
+            const int j1 = min(j0 + g.leaf, g.nv);
+            for (int j = j0; j < j1; ++j) {
+                if (!ray && j == yseg) continue;
+                if (seg_hit<R>(v + 2 * j, y, d, ray, RO<R>::line_eps)) {
+                    if (q == want) { s0 = j; return q + 1; }
+                    if (q == 0) s0 = j; else if (q == 1) s1 = j;
+                    ++q;
+                }
+            }
+        }
+        while (k > 0 && (k & 1) == 0) k = (k - 1) >> 1;
+        if (k == 0) break;
+        ++k;
+    }
+    return q;
+}
+
+// ----------------------------------------------------------------------------- accumulation
+template <typename R, int D>
+__device__ __forceinline__ void add_term(const DevProblem* dp, const R xh[D], const R xl[D], const R y[D], R c,
+                                         R& F, R G[D], Counts& cnt) {
+    R d[D], r2 = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) { d[i] = (xh[i] - y[i]) + xl[i]; r2 += d[i] * d[i]; }
+    if (r2 == R(0)) { cnt.zero++; return; }
+    R phi, irm;   // Phi(x, y), |x - y|^{-m}
+    if constexpr (D == 2) {
+        phi = -RO<R>::lg(r2) * R(0.0795774715459476678844418816863);   // 1/(4 pi)
+        irm = RO<R>::rcp(r2);
+    } else {
+        const R ir = RO<R>::rsq(r2);
+        R ir2 = ir * ir, p = R(1);
+#pragma unroll
+        for (int i = 0; i < (D - 2) / 2; ++i) p *= ir2;
+        if constexpr (D % 2) p *= ir;   // p = r^{2-m}
+        phi = Pay<R>::pc(dp) * p;
+        irm = p * ir2;
+    }
+    F += c * phi;
+    const R gs = -c * irm / Pay<R>::ua(dp);
+#pragma unroll
+    for (int i = 0; i < D; ++i) G[i] += gs * d[i];
+}
+
+__device__ __forceinline__ uint32_t trace_word(int h, int cs, int q, int pick, int neg, int att) {
+    q = min(q, 255); pick = min(pick, 255); att = min(att, 127);
+    return (uint32_t)h | ((uint32_t)cs << 6) | ((uint32_t)q << 8) | ((uint32_t)pick << 16) |
+           ((uint32_t)(neg ? 1 : 0) << 24) | ((uint32_t)att << 25);
+}
+
+// ----------------------------------------------------------------------------- one sample
+// Walker k of sample `w` at point x: F = N sum_i c_i Phi(x, y_i), G = N sum_i c_i grad_x Phi.
+template <typename R, int D, bool VR>
+__device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const R* __restrict__ pay,
+                                       const float4* __restrict__ nodes, const R xh[D], const R xl[D],
+                                       const KParams& kp, uint32_t w, uint32_t group, int k, R& F, R G[D],
+                                       uint32_t* __restrict__ tr, Counts& cnt) {
+    const int N = dp->N, M = kp.M;
+    const uint32_t inst = (kp.instance & 0xFFFFFFu) << 8;
+    const Stream sched{kp.k0, kp.k1, w, kp.shared_sched ? 0xFFFFFFFFu : group, inst};
+    const Stream st{kp.k0, kp.k1, w, group, inst | ((uint32_t)k << 4) | 1u};
+    F = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) G[i] = 0;
+
+    // schedule H_0 (Theorem 2): uniform over regions
+    uint4 sb = sched.block(0, 0);
+    int h;
+    {
+        int t = (int)floor(RO<double>::u(sb.x) * N);
+        h = t < N ? t : N - 1;
+        if (kp.shared_sched) h = __builtin_amdgcn_readfirstlane(h);
+    }
+    const DevRegion* g = &dp->reg[h];
+    const R meas = VR ? Pay<R>::meas(*g, k) : Pay<R>::area(*g);
+    if (meas == R(0)) {   // empty VR half: the walker contributes nothing
+        if (tr) for (int i = 0; i <= M; ++i) tr[i] = i ? 0u : trace_word(h, 0, 0, 0, 0, 0);
+        return;
+    }
+    R y[D];
+    int seg = 0, att;
+    for (att = 0; att < WOI_ATTEMPT_CAP; ++att) {
+        bool ok;
+        if constexpr (VR) ok = vr_attempt<R, D>(dp, *g, pay, k, st, att, y, seg);
+        else ok = surf_attempt<R, D>(*g, pay, st, 0, att, y, seg);
+        if (ok) break;
+        cnt.rejections++;
+    }
+    if (att == WOI_ATTEMPT_CAP) cnt.caps++;
+    R Q = Pay<R>::s(*g) * data_b<R, D>(dp, *g, pay, y, seg) * meas, T = 1;
+    add_term<R, D>(dp, xh, xl, y, (M == 0 ? R(0.5) : R(1)) * Q * T, F, G, cnt);
+    cnt.steps++;
+    if (tr) tr[0] = trace_word(h, 0, 1, 0, 0, att);
+    R S = 1, pw = 1;
+    const R l1 = Pay<R>::l1(dp);
+    for (int i = 1; i <= M; ++i) {
+        if ((i & 3) == 0) sb = sched.block(0, (uint32_t)(i >> 2));
+        const uint32_t wv = (i & 3) == 0 ? sb.x : (i & 3) == 1 ? sb.y : (i & 3) == 2 ? sb.z : sb.w;
+        const double uu = RO<double>::u(wv);
+        int hn = 0;
+        while (hn < N - 1 && !(uu < dp->cdf[hn])) ++hn;
+        if (kp.shared_sched) hn = __builtin_amdgcn_readfirstlane(hn);
+        const int rel = dp->rel[h][hn];
+        h = hn;
+        g = &dp->reg[h];
+        S *= Pay<R>::sgn(*g);
+        pw *= l1;
+        R yn[D], nn[D];
+        int segn = 0, qn = 1, pick = 0;
+        if (rel == REL_OTHER) {
+            // y_i uniform on dOmega_{h_i}: Q *= |K*(y_i, y_{i-1})| |dOmega_{h_i}|
+            for (att = 0; att < WOI_ATTEMPT_CAP; ++att) {
+                if (surf_attempt<R, D>(*g, pay, st, (uint32_t)i, att, yn, segn)) break;
+                cnt.rejections++;
+            }
+            if (att == WOI_ATTEMPT_CAP) cnt.caps++;
+            normal_at<R, D>(*g, pay, yn, segn, nn);
+            R dn = 0, r2 = 0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) { const R e = yn[j] - y[j]; dn += e * nn[j]; r2 += e * e; }
+            R rm = R(1);
+#pragma unroll
+            for (int j = 0; j < D / 2; ++j) rm *= r2;
+            if constexpr (D % 2) rm *= RO<R>::sq(r2);
+            Q *= fabs(dn / (Pay<R>::ua(dp) * rm)) * Pay<R>::area(*g);
+        } else {
+            // isotropic line (same interface) or ray (descendant to ancestor); uniform pick among q hits
+            const bool ray = rel == REL_DESC;
+            constexpr int NW = dir_words(D) + 1, NB = (NW + 3) / 4;
+            bool found = false;
+            for (att = 0; att < WOI_ATTEMPT_CAP; ++att) {
+                Words<NW> W; W.fill(st, (uint32_t)i, (uint32_t)(att * NB));
+                R d[D];
+                unit_dir<R, D>(W, d);
+                const R up = RO<R>::u(W.w[NW - 1]);
+                if (g->kind == WOI_SHAPE_POLYLINE2D) {
+                    if constexpr (D == 2) {
+                        const float4* nd = nodes + g->bvh / 4;
+                        int s0, s1;
+                        qn = poly_walk<R>(*g, pay, nd, y, d, ray, seg, -1, s0, s1);
+                        if (qn == 0) { cnt.redraws++; continue; }
+                        pick = min((int)(up * (R)qn), qn - 1);
+                        int j = pick == 0 ? s0 : s1;
+                        if (pick >= 2) { int a, b; poly_walk<R>(*g, pay, nd, y, d, ray, seg, pick, a, b); j = a; }
+                        const R* v = pay + Pay<R>::g(*g) + 2 * j;
+                        const R ex = v[2] - v[0], ey = v[3] - v[1];
+                        const R den = d[0] * ey - d[1] * ex;
+                        const R s = ((v[0] - y[0]) * d[1] - (v[1] - y[1]) * d[0]) / den;
+                        yn[0] = v[0] + s * ex; yn[1] = v[1] + s * ey; segn = j;
+                    }
+                } else {
+                    R t;
+                    qn = quadric_hit<R, D>(*g, pay, y, d, ray, t);
+                    if (qn == 0) { cnt.redraws++; continue; }
+                    pick = 0;
+#pragma unroll
+                    for (int j = 0; j < D; ++j) yn[j] = y[j] + t * d[j];
+                }
+                found = true;
+                break;
+            }
+            if (!found) {   // no hit after the attempt cap: the walker stops here
+                cnt.caps++;
+                if (tr) for (int j = i; j <= M; ++j) tr[j] = trace_word(h, rel, 0, 0, 0, att);
+                break;
+            }
+            if (!ray) Q *= R(0.5);
+            normal_at<R, D>(*g, pay, yn, segn, nn);
+        }
+        R dn = 0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) dn += (yn[j] - y[j]) * nn[j];
+        const R sg = dn < R(0) ? R(-1) : R(1);
+        T *= (R)qn * sg;
+#pragma unroll
+        for (int j = 0; j < D; ++j) y[j] = yn[j];
+        seg = segn;
+        add_term<R, D>(dp, xh, xl, y, (i == M ? R(0.5) : R(1)) * pw * S * Q * T, F, G, cnt);
+        cnt.steps++;
+        if (tr) tr[i] = trace_word(h, rel, qn, pick, sg < R(0), att);
+    }
+    F *= (R)N;
+#pragma unroll
+    for (int i = 0; i < D; ++i) G[i] *= (R)N;
+}
+
+// ----------------------------------------------------------------------------- kernels
+template <typename R, int D>
+__device__ __forceinline__ void load_point(const double* __restrict__ pts, int64_t p, R xh[D], R xl[D]) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        const double v = pts[p * D + i];
+        xh[i] = (R)v;
+        xl[i] = (R)(v - (double)xh[i]);
+    }
+}
+
+__device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <typename R, int D, bool VR>
+__global__ __launch_bounds__(256) void walk_kernel(KParams kp) {
+    const DevProblem* __restrict__ dp = kp.dp;
+    const R* __restrict__ pay = Pay<R>::base(dp);
+    const float4* __restrict__ nodes = reinterpret_cast<const float4*>(Pay<float>::base(dp));
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = p < kp.P;
+    const int64_t pc = active ? p : kp.P - 1;
+    R xh[D], xl[D];
+    load_point<R, D>(kp.points, pc, xh, xl);
+    const uint32_t group = (uint32_t)(pc / kp.batch_share);
+    const uint64_t s0 = (uint64_t)blockIdx.y * kp.samples_per_thread;
+    const uint64_t s1 = min(s0 + (uint64_t)kp.samples_per_thread, kp.n_samples);
+    double S1 = 0, S2 = 0, G1[D], G2[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) { G1[i] = 0; G2[i] = 0; }
+    Counts cnt{0, 0, 0, 0, 0};
+    constexpr int K = VR ? 2 : 1;
+    for (uint64_t s = s0; s < s1; ++s) {
+        const uint32_t w = (uint32_t)(kp.first_sample + s);
+        double F = 0, Gs[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) Gs[i] = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            R Fk, Gk[D];
+            uint32_t* tr = nullptr;
+            const size_t idx = ((size_t)pc * kp.n_samples + s) * K + k;
+            if (kp.trace && active) tr = kp.trace + idx * (kp.M + 1);
+            walker<R, D, VR>(dp, pay, nodes, xh, xl, kp, w, group, k, Fk, Gk, tr, cnt);
+            F += (double)Fk;
+#pragma unroll
+            for (int i = 0; i < D; ++i) Gs[i] += (double)Gk[i];
+            if (kp.traceF && active) {
+                kp.traceF[idx] = (double)Fk;
+                if (kp.traceG)
+#pragma unroll
+                    for (int i = 0; i < D; ++i) kp.traceG[idx * D + i] = (double)Gk[i];
+            }
+        }
+        S1 += F; S2 += F * F;
+#pragma unroll
+        for (int i = 0; i < D; ++i) { G1[i] += Gs[i]; G2[i] += Gs[i] * Gs[i]; }
+    }
+    if (active && kp.partials) {
+        double* o = kp.partials + ((size_t)blockIdx.y * kp.P + p) * (2 + 2 * D);
+        o[0] = S1; o[1] = S2;
+#pragma unroll
+        for (int i = 0; i < D; ++i) { o[2 + i] = G1[i]; o[2 + D + i] = G2[i]; }
+    }
+    if (kp.counters) {
+        const uint64_t a = wave_sum(active ? cnt.steps : 0), b = wave_sum(active ? cnt.redraws : 0);
+        const uint64_t c = wave_sum(active ? cnt.rejections : 0), d = wave_sum(active ? cnt.caps : 0);
+        const uint64_t e = wave_sum(active ? cnt.zero : 0);
+        if ((threadIdx.x & 63) == 0) {
+            atomicAdd((unsigned long long*)&kp.counters[0], (unsigned long long)a);
+            atomicAdd((unsigned long long*)&kp.counters[1], (unsigned long long)b);
+            atomicAdd((unsigned long long*)&kp.counters[2], (unsigned long long)c);
+            atomicAdd((unsigned long long*)&kp.counters[3], (unsigned long long)d);
+            atomicAdd((unsigned long long*)&kp.counters[4], (unsigned long long)e);
+        }
+    }
+}
+
+// Chan et al. merge of per-chunk (n, sum, sum of squares) in chunk order: deterministic.
+__global__ void reduce_kernel(RParams rp) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= rp.P) return;
+    const int D = rp.dim, W = 2 + 2 * D;
+    double n = 0, mu = 0, m2 = 0, gmu[WOI_MAX_DIM], gm2[WOI_MAX_DIM];
+    for (int i = 0; i < D; ++i) { gmu[i] = 0; gm2[i] = 0; }
+    for (int c = 0; c < rp.n_chunks; ++c) {
+        const uint64_t lo = (uint64_t)c * rp.samples_per_thread;
+        const uint64_t hi = min(lo + (uint64_t)rp.samples_per_thread, rp.n_samples);
+        const double nc = (double)(hi - lo);
+        const double* o = rp.partials + ((size_t)c * rp.P + p) * W;
+        const double mc = o[0] / nc, m2c = o[1] - o[0] * mc;
+        const double nt = n + nc, dl = mc - mu;
+        mu += dl * nc / nt; m2 += m2c + dl * dl * n * nc / nt;
+        for (int i = 0; i < D; ++i) {
+            const double gc = o[2 + i] / nc, g2c = o[2 + D + i] - o[2 + i] * gc, e = gc - gmu[i];
+            gmu[i] += e * nc / nt; gm2[i] += g2c + e * e * n * nc / nt;
+        }
+        n = nt;
+    }
+    rp.mean[p] = mu;
+    rp.se[p] = n > 1 ? sqrt(fmax(m2, 0.0) / (n - 1) / n) : 0.0;
+    for (int i = 0; i < D; ++i) {
+        if (rp.grad) rp.grad[p * D + i] = gmu[i];
+        if (rp.grad_se) rp.grad_se[p * D + i] = n > 1 ? sqrt(fmax(gm2[i], 0.0) / (n - 1) / n) : 0.0;
+    }
+}
+
+// ----------------------------------------------------------------------------- launchers
+template <typename R, int D, bool VR>
+static hipError_t launch_walk_t(const KParams& kp, dim3 grid, dim3 block, hipStream_t s) {
+    hipLaunchKernelGGL((walk_kernel<R, D, VR>), grid, block, 0, s, kp);
+    return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t launch_walk_r(const KParams& kp, int dim, bool vr, dim3 grid, dim3 block, hipStream_t s) {
+    if (vr) {
+        switch (dim) {
+            case 2: return launch_walk_t<R, 2, true>(kp, grid, block, s);
+            case 3: return launch_walk_t<R, 3, true>(kp, grid, block, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    switch (dim) {
+        case 2: return launch_walk_t<R, 2, false>(kp, grid, block, s);
+        case 3: return launch_walk_t<R, 3, false>(kp, grid, block, s);
+        case 4: return launch_walk_t<R, 4, false>(kp, grid, block, s);
+        case 5: return launch_walk_t<R, 5, false>(kp, grid, block, s);
+        case 6: return launch_walk_t<R, 6, false>(kp, grid, block, s);
+        case 7: return launch_walk_t<R, 7, false>(kp, grid, block, s);
+        case 8: return launch_walk_t<R, 8, false>(kp, grid, block, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_walk(const KParams& kp, int dim, bool vr, bool fp32, dim3 grid, dim3 block, hipStream_t s) {
+    return fp32 ? launch_walk_r<float>(kp, dim, vr, grid, block, s) : launch_walk_r<double>(kp, dim, vr, grid, block, s);
+}
+
+hipError_t launch_reduce(const RParams& rp, hipStream_t s) {
+    const int bs = 256;
+    hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)((rp.P + bs - 1) / bs)), dim3(bs), 0, s, rp);
+    return hipGetLastError();
+}
+
+}  // namespace woi

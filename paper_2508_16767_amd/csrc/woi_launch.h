@@ -1,0 +1,45 @@
+// woi_launch.h -- kernel parameter blocks and launchers (host <-> device boundary inside
+// the library; not part of the public C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "woi_device.h"
+
+namespace woi {
+
+// One estimation launch: grid.x covers points (one lane per point), grid.y covers
+// chunks of `samples_per_thread` consecutive samples.
+struct KParams {
+    const DevProblem* dp;
+    const double* points;          // [P*dim]
+    int64_t P;
+    uint64_t n_samples;            // samples per point (walkers, or walker pairs for VR)
+    uint64_t first_sample;         // index of the first sample
+    uint32_t samples_per_thread;
+    uint32_t k0, k1;               // Philox key (seed)
+    int M;
+    int batch_share;
+    int shared_sched;
+    uint32_t instance;
+    double* partials;              // [chunks][P][2 + 2 dim] or null
+    double* traceF;                // per-walker values (trace mode) or null
+    double* traceG;
+    uint32_t* trace;
+    uint64_t* counters;
+};
+
+struct RParams {
+    const double* partials;
+    int64_t P;
+    int dim;
+    int n_chunks;
+    uint32_t samples_per_thread;
+    uint64_t n_samples;
+    double *mean, *se, *grad, *grad_se;
+};
+
+hipError_t launch_walk(const KParams& kp, int dim, bool vr, bool fp32, dim3 grid, dim3 block, hipStream_t s);
+hipError_t launch_reduce(const RParams& rp, hipStream_t s);
+
+}  // namespace woi

@@ -1,0 +1,243 @@
+"""Python binding of libwoi.so (include/woi.h): argument marshalling only.
+
+Every step of the estimator runs in the HIP kernels behind the C ABI; this module
+only converts problem descriptions to the C structs, allocates device buffers with
+PyTorch (device memory and streams are PyTorch's job here) and passes pointers.
+If the native library is missing the import fails: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libwoi.so")
+
+MAX_DIM, MAX_REGIONS, MAX_M, N_COUNTERS = 8, 32, 32, 8
+PLAIN, VR = 0, 1
+FP64, FP32 = 0, 1
+SCHED_PER_GROUP, SCHED_SHARED = 0, 1
+COUNTER_NAMES = ("walker_steps", "redraws", "rejections", "cap_hits", "zero_distance")
+
+
+class WoiError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{status}: {msg}")
+        self.status = status
+
+
+class _Shape(C.Structure):
+    _fields_ = [("kind", C.c_int), ("n_vertices", C.c_int), ("center", C.c_double * MAX_DIM),
+                ("radius", C.c_double), ("A", C.POINTER(C.c_double)), ("vertices", C.POINTER(C.c_double))]
+
+
+class _Data(C.Structure):
+    _fields_ = [("kind", C.c_int), ("n_terms", C.c_int), ("center", C.c_double * MAX_DIM),
+                ("coef", C.POINTER(C.c_double)), ("exps", C.POINTER(C.c_uint8))]
+
+
+class _Desc(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n_regions", C.c_int), ("parent", C.POINTER(C.c_int)),
+                ("sigma", C.POINTER(C.c_double)), ("shapes", C.POINTER(_Shape)), ("data", C.POINTER(_Data)),
+                ("compat_mode", C.c_int), ("compat_tol", C.c_double)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n_regions", C.c_int), ("alpha_l1", C.c_double),
+                ("alpha", C.c_double * MAX_REGIONS), ("beta_scale", C.c_double * MAX_REGIONS),
+                ("area", C.c_double * MAX_REGIONS), ("area_plus", C.c_double * MAX_REGIONS),
+                ("area_minus", C.c_double * MAX_REGIONS), ("flux", C.c_double * MAX_REGIONS),
+                ("device_bytes", C.c_size_t)]
+
+
+class Query(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("walks", C.c_uint64), ("walk_offset", C.c_uint64), ("M", C.c_int),
+                ("estimator", C.c_int), ("precision", C.c_int), ("schedule_mode", C.c_int),
+                ("batch_share", C.c_int), ("instance", C.c_uint32), ("samples_per_thread", C.c_int),
+                ("block_size", C.c_int)]
+
+
+class _BatchItem(C.Structure):
+    _fields_ = [("problem", C.c_void_p), ("points", C.c_void_p), ("P", C.c_int64), ("query", Query),
+                ("mean", C.c_void_p), ("se", C.c_void_p), ("grad", C.c_void_p), ("grad_se", C.c_void_p)]
+
+
+EXPORTS = ("woi_problem_create", "woi_problem_upload", "woi_problem_destroy", "woi_problem_get_info", "woi_workspace_size",
+           "woi_estimate", "woi_trace", "woi_batch_workspace_size", "woi_estimate_batch",
+           "woi_status_string", "woi_last_error")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2508_16767_amd.build.build()")
+    lib = C.CDLL(LIB_PATH)
+    lib.woi_problem_create.argtypes = [C.POINTER(_Desc), C.POINTER(C.c_void_p)]
+    lib.woi_problem_destroy.argtypes = [C.c_void_p]
+    lib.woi_problem_destroy.restype = None
+    lib.woi_problem_get_info.argtypes = [C.c_void_p, C.POINTER(_Info)]
+    lib.woi_workspace_size.argtypes = [C.c_void_p, C.c_int64, C.POINTER(Query), C.POINTER(C.c_size_t)]
+    lib.woi_estimate.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(Query), C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]
+    lib.woi_trace.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(Query), C.c_uint64, C.c_void_p,
+                              C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.woi_batch_workspace_size.argtypes = [C.POINTER(_BatchItem), C.c_int, C.POINTER(C.c_size_t)]
+    lib.woi_estimate_batch.argtypes = [C.POINTER(_BatchItem), C.c_int, C.c_void_p, C.c_size_t, C.c_void_p,
+                                       C.c_void_p]
+    lib.woi_status_string.restype = C.c_char_p
+    lib.woi_status_string.argtypes = [C.c_int]
+    lib.woi_last_error.restype = C.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def _check(rc):
+    if rc != 0:
+        raise WoiError(_lib.woi_status_string(rc).decode(), _lib.woi_last_error().decode())
+
+
+def _dptr(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+class Problem:
+    """A compiled problem on the current device.
+
+    `desc` is any object with attributes dim, parent, sigma, shapes, data, compat_mode:
+    shapes[i] has kind (0 sphere, 1 ellipsoid, 2 polyline), center, radius, A, vertices;
+    data[i] has kind (0 zero, 1 Fourier, 2 direction polynomial, 3 source flux,
+    4 field flux), center, coef, exps -- the fields of woi_shape / woi_data in woi.h.
+    """
+
+    def __init__(self, desc, compat_tol=1e-8):
+        m, N = int(desc.dim), len(desc.parent)
+        self.dim, self.N = m, N
+        keep = []
+        parent = np.ascontiguousarray(desc.parent, dtype=np.int32)
+        sigma = np.ascontiguousarray(desc.sigma, dtype=np.float64)
+        keep += [parent, sigma]
+        shapes = (_Shape * N)()
+        datas = (_Data * N)()
+        for i, (s, d) in enumerate(zip(desc.shapes, desc.data)):
+            shapes[i].kind = int(s.kind)
+            c = np.zeros(MAX_DIM); c[:m] = np.asarray(s.center, dtype=np.float64)[:m]
+            shapes[i].center[:] = list(c)
+            shapes[i].radius = float(getattr(s, "radius", 0.0) or 0.0)
+            A = getattr(s, "A", None)
+            if A is not None:
+                A = np.ascontiguousarray(A, dtype=np.float64).reshape(-1); keep.append(A)
+                shapes[i].A = _dptr(A, C.c_double)
+            v = getattr(s, "vertices", None)
+            if v is not None:
+                v = np.ascontiguousarray(v, dtype=np.float64).reshape(-1); keep.append(v)
+                shapes[i].vertices = _dptr(v, C.c_double)
+                shapes[i].n_vertices = len(v) // 2
+            datas[i].kind = int(d.kind)
+            dc = np.zeros(MAX_DIM); dc[:m] = np.asarray(d.center, dtype=np.float64).reshape(-1)[:m]
+            datas[i].center[:] = list(dc)
+            coef = np.ascontiguousarray(d.coef, dtype=np.float64).reshape(-1)
+            keep.append(coef)
+            if coef.size:
+                datas[i].coef = _dptr(coef, C.c_double)
+            if int(d.kind) == 1:
+                datas[i].n_terms = (coef.size - 1) // 2
+            else:
+                datas[i].n_terms = coef.size
+            ex = getattr(d, "exps", None)
+            if ex is not None:
+                ex = np.ascontiguousarray(ex, dtype=np.uint8).reshape(-1); keep.append(ex)
+                datas[i].exps = _dptr(ex, C.c_uint8)
+        desc_c = _Desc(m, N, _dptr(parent, C.c_int), _dptr(sigma, C.c_double), shapes, datas,
+                       int(getattr(desc, "compat_mode", 0)), float(compat_tol))
+        h = C.c_void_p()
+        _check(_lib.woi_problem_create(C.byref(desc_c), C.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            try:
+                _lib.woi_problem_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    def info(self):
+        inf = _Info()
+        _check(_lib.woi_problem_get_info(self.handle, C.byref(inf)))
+        N = self.N
+        out = {k: np.array(getattr(inf, k)[:N]) for k in
+               ("alpha", "beta_scale", "area", "area_plus", "area_minus", "flux")}
+        out["alpha_l1"] = inf.alpha_l1
+        out["device_bytes"] = inf.device_bytes
+        return out
+
+
+def make_query(walks, M, seed=0, estimator=PLAIN, precision=FP64, schedule_mode=SCHED_PER_GROUP,
+               batch_share=1, walk_offset=0, instance=0, samples_per_thread=0, block_size=0):
+    return Query(int(seed), int(walks), int(walk_offset), int(M), int(estimator), int(precision),
+                 int(schedule_mode), int(batch_share), int(instance), int(samples_per_thread), int(block_size))
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _points(points, dim):
+    x = torch.as_tensor(points, dtype=torch.float64)
+    if not x.is_cuda:
+        x = x.cuda()
+    return x.reshape(-1, dim).contiguous()
+
+
+def workspace_size(problem, P, q):
+    n = C.c_size_t()
+    _check(_lib.woi_workspace_size(problem.handle, int(P), C.byref(q), C.byref(n)))
+    return n.value
+
+
+def estimate(problem, points, walks, M, seed=0, estimator=PLAIN, precision=FP64, schedule_mode=SCHED_PER_GROUP,
+             batch_share=1, walk_offset=0, instance=0, samples_per_thread=0, block_size=0, counters=None,
+             out=None, workspace=None):
+    """Per-point mean, SE, gradient, gradient SE as CUDA float64 tensors (asynchronous)."""
+    x = _points(points, problem.dim)
+    P = x.shape[0]
+    q = make_query(walks, M, seed, estimator, precision, schedule_mode, batch_share, walk_offset, instance,
+                   samples_per_thread, block_size)
+    if out is None:
+        out = (torch.empty(P, dtype=torch.float64, device=x.device), torch.empty(P, dtype=torch.float64, device=x.device),
+               torch.empty(P, problem.dim, dtype=torch.float64, device=x.device),
+               torch.empty(P, problem.dim, dtype=torch.float64, device=x.device))
+    nbytes = workspace_size(problem, P, q)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(max(nbytes, 8), dtype=torch.uint8, device=x.device)
+    mean, se, g, gse = out
+    _check(_lib.woi_estimate(problem.handle, C.c_void_p(x.data_ptr()), P, C.byref(q), C.c_void_p(mean.data_ptr()),
+                             C.c_void_p(se.data_ptr()), C.c_void_p(g.data_ptr()), C.c_void_p(gse.data_ptr()),
+                             C.c_void_p(workspace.data_ptr()), workspace.numel(),
+                             C.c_void_p(counters.data_ptr()) if counters is not None else None, _stream()))
+    return mean, se, g, gse
+
+
+def trace(problem, points, n_samples, M, seed=0, estimator=PLAIN, precision=FP64, schedule_mode=SCHED_PER_GROUP,
+          batch_share=1, walk_offset=0, instance=0):
+    """Per-walker values F[P, n, K], gradients G[P, n, K, dim] and decision words T[P, n, K, M+1]."""
+    x = _points(points, problem.dim)
+    P = x.shape[0]
+    K = 2 if estimator == VR else 1
+    F = torch.zeros(P, n_samples, K, dtype=torch.float64, device=x.device)
+    G = torch.zeros(P, n_samples, K, problem.dim, dtype=torch.float64, device=x.device)
+    T = torch.zeros(P, n_samples, K, M + 1, dtype=torch.int32, device=x.device)
+    q = make_query(2 * n_samples if estimator == VR else n_samples, M, seed, estimator, precision, schedule_mode,
+                   batch_share, walk_offset, instance)
+    _check(_lib.woi_trace(problem.handle, C.c_void_p(x.data_ptr()), P, C.byref(q), int(n_samples),
+                          C.c_void_p(F.data_ptr()), C.c_void_p(G.data_ptr()), C.c_void_p(T.data_ptr()), _stream()))
+    return F, G, T
+
+
+def new_counters(device="cuda"):
+    return torch.zeros(N_COUNTERS, dtype=torch.int64, device=device)

@@ -1,0 +1,103 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol that
+include/woi.h declares, and its host-side problem compiler validates inputs and
+agrees with the oracle's independent computation of the problem constants."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def woi():
+    from paper_2508_16767_amd import woi as mod
+    return mod
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "woi.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(woi_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_abi():
+    names = declared_functions()
+    for n in ("woi_problem_create", "woi_problem_upload", "woi_problem_destroy", "woi_estimate", "woi_trace",
+              "woi_estimate_batch", "woi_workspace_size"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(woi):
+    out = subprocess.run(["nm", "-D", "--defined-only", woi.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (woi_[a-z_0-9]+)\b", out))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    for n in declared_functions():
+        getattr(woi._lib, n)
+    assert set(woi.EXPORTS) <= set(declared_functions())
+
+
+def _err(woi, prob, status, **kw):
+    with pytest.raises(woi.WoiError) as e:
+        woi.Problem(prob, **kw)
+    assert e.value.status == status, str(e.value)
+
+
+def test_validation_errors(woi):
+    p, _ = W.config1()
+    bad = W.Problem(2, [-1, 1], p.sigma, p.shapes, p.data)
+    _err(woi, bad, "WOI_E_GEOMETRY")                           # parent must precede child
+    outside = W.Problem(2, [-1, 0], [1.0, 2.0], [W.sphere([0, 0], 1.0), W.sphere([0.9, 0], 0.3)], p.data)
+    _err(woi, outside, "WOI_E_GEOMETRY")                       # child pokes out of its parent
+    sib = W.Problem(2, [-1, 0, 0], [1.0, 2.0, 3.0],
+                    [W.sphere([0, 0], 1.0), W.sphere([0.2, 0], 0.3), W.sphere([-0.2, 0], 0.3)], p.data + [W.zero_data(2)])
+    _err(woi, sib, "WOI_E_GEOMETRY")                           # overlapping siblings
+    inc = W.Problem(2, [-1], [1.0], [W.sphere([0, 0], 1.0)], [W.fourier([0, 0], 0.3, [1.0], [0.0])])
+    _err(woi, inc, "WOI_E_INCOMPATIBLE")                       # nonzero net flux
+    inc.compat_mode = 2
+    woi.Problem(inc)                                           # accepted without the check
+    cw = W.star_polyline([0, 0], 0.5, 0.1, 3, 64)
+    cw.vertices = cw.vertices[::-1].copy()
+    _err(woi, W.Problem(2, [-1, 0], [1.0, 2.0], [W.sphere([0, 0], 1.0), cw], p.data), "WOI_E_GEOMETRY")
+    neg = W.Problem(2, [-1, 0], [1.0, -3.0], p.shapes, p.data)
+    _err(woi, neg, "WOI_E_INVALID_ARG")
+
+
+def test_query_validation_without_gpu(woi):
+    p5, _ = W.config5()
+    prob = woi.Problem(p5)
+    with pytest.raises(woi.WoiError) as e:
+        woi.workspace_size(prob, 16, woi.make_query(100, 4, estimator=woi.VR))
+    assert e.value.status == "WOI_E_UNSUPPORTED"
+    p1, _ = W.config1()
+    prob = woi.Problem(p1)
+    for q in (woi.make_query(101, 4, estimator=woi.VR), woi.make_query(100, 99), woi.make_query(0, 4),
+              woi.make_query(100, 4, batch_share=0), woi.make_query(100, 4, instance=1 << 24)):
+        with pytest.raises(woi.WoiError):
+            woi.workspace_size(prob, 16, q)
+    assert woi.workspace_size(prob, 64, woi.make_query(10000, 4)) > 0
+
+
+@pytest.mark.parametrize("make", [lambda: W.config1()[0], lambda: W.config2(n_points=8)[0], lambda: W.config5()[0],
+                                  lambda: W.zheng_ex3_3d(),
+                                  lambda: W.single_ellipsoid_linear(3, [0.9, 0.6, 0.4])[0]])
+def test_host_compile_matches_oracle(woi, oracle_mod, make):
+    p = make()
+    a = woi.Problem(p).info()
+    b = oracle_mod.OracleProblem(p).info()
+    for k in ("alpha", "beta_scale"):
+        assert np.array_equal(a[k], b[k])
+    assert a["alpha_l1"] == pytest.approx(b["alpha_l1"], rel=1e-15)
+    assert np.allclose(a["area"], b["area"], rtol=1e-12)
+    scale = np.abs(a["area"]).max()
+    assert np.allclose(a["flux"], b["flux"], atol=1e-10 * scale)
+    if p.dim <= 3:
+        assert np.allclose(a["area_plus"], b["area_plus"], rtol=1e-6, atol=1e-12 * scale)
+        assert np.allclose(a["area_minus"], b["area_minus"], rtol=1e-6, atol=1e-12 * scale)
+    else:
+        assert np.all(np.isnan(a["area_plus"]))

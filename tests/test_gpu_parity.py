@@ -1,0 +1,237 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Per walk (FP64 on identical Philox streams): values agree to 1e-10 relative and the
+decision traces agree; a walker whose trace differs is a "flip" (a rounding-level
+difference changed a discrete choice) and is counted against a small budget; a walker
+with an identical trace but different value is a bug.  Per point: same-seed means
+agree to 1e-9 relative (FP64) and independent-seed means within 4 combined standard
+errors.  FP32 walks: paired against FP64 on identical streams.
+"""
+import numpy as np
+import pytest
+
+import closed_forms as CF
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from oracle import oracle as O  # noqa: E402
+from paper_2508_16767_amd import woi  # noqa: E402
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def walk_parity(prob, pts, n, M, estimator=0, sched=0, B=1, seed=7, flip_budget=1e-6, offset=0):
+    """Run both sides' traces; return (n_walkers, n_flips) after asserting there is no bug."""
+    op = O.OracleProblem(prob)
+    Fo, Go, To = O.trace(op, pts, n, M, seed=seed, estimator=estimator, schedule_mode=sched, batch_share=B,
+                         walk_offset=offset)
+    gp = woi.Problem(prob)
+    Fg, Gg, Tg = woi.trace(gp, pts, n, M, seed=seed, estimator=estimator, precision=woi.FP64, schedule_mode=sched,
+                           batch_share=B, walk_offset=offset)
+    torch.cuda.synchronize()
+    Fg, Gg, Tg = _np(Fg), _np(Gg), _np(Tg).astype(np.uint32)
+    if estimator == 1 and prob.dim == 3:
+        # the first factor |dOmega^+-| comes from each side's own quadrature: compare per unit measure
+        h0 = (To[..., 0] & 0x3F).astype(int)
+        k = np.arange(Fo.shape[2])[None, None, :]
+        io, ig = op.info(), gp.info()
+        mo = np.where(k == 0, io["area_plus"][h0], io["area_minus"][h0])
+        mg = np.where(k == 0, ig["area_plus"][h0], ig["area_minus"][h0])
+        assert np.all(np.abs(mo - mg) <= 1e-6 * np.abs(mo) + 1e-300)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            Fo = np.where(mo > 0, Fo / mo, 0.0); Fg = np.where(mg > 0, Fg / mg, 0.0)
+            Go = np.where(mo[..., None] > 0, Go / mo[..., None], 0.0); Gg = np.where(mg[..., None] > 0, Gg / mg[..., None], 0.0)
+    same = np.all(To == Tg, axis=-1)
+    rms = np.sqrt(np.mean(Fo ** 2, axis=(1, 2), keepdims=True)) + 1e-300
+    tol = 1e-10 * np.maximum(np.abs(Fo), 1e-3 * rms)
+    okF = np.abs(Fg - Fo) <= tol
+    grms = np.sqrt(np.mean(Go ** 2, axis=(1, 2, 3), keepdims=True)) + 1e-300
+    okG = np.all(np.abs(Gg - Go) <= 1e-10 * np.maximum(np.abs(Go), 1e-3 * grms), axis=-1)
+    bugs = same & ~(okF & okG)
+    n_walkers, n_flips = same.size, int((~same).sum())
+    assert bugs.sum() == 0, f"{bugs.sum()} walkers with identical decisions but different values; " \
+                            f"max |dF| = {np.max(np.abs(Fg - Fo)[bugs]):.3e}"
+    assert n_flips <= max(1, flip_budget * n_walkers), f"{n_flips} decision flips in {n_walkers} walkers"
+    return n_walkers, n_flips
+
+
+# ----------------------------------------------------------------------------- per-walk parity
+@pytest.mark.parametrize("estimator", [0, 1])
+@pytest.mark.parametrize("sched", [0, 1])
+def test_walk_parity_concentric_2d(estimator, sched):
+    p, xs = W.config1()
+    walk_parity(p, xs[::4], 2000, 4, estimator=estimator, sched=sched)
+
+
+def test_walk_parity_six_ball():
+    p, xs = W.config5()
+    walk_parity(p, xs[:8], 1000, 8)
+
+
+@pytest.mark.parametrize("estimator", [0, 1])
+def test_walk_parity_spheres_3d(estimator):
+    p = W.zheng_ex3_3d()
+    pts = W.ball_points(np.random.default_rng(1), 8, 3, 0.95)
+    walk_parity(p, pts, 1000, 6, estimator=estimator)
+
+
+@pytest.mark.parametrize("estimator", [0, 1])
+def test_walk_parity_star_tree(estimator):
+    from test_oracle_pins import STAR_PTS, _star_tree
+    p, _, _ = _star_tree()
+    walk_parity(p, STAR_PTS, 2000, 4, estimator=estimator, flip_budget=1e-4)
+
+
+def test_walk_parity_nonconvex_boundary():
+    from test_oracle_pins import NC_PTS, _nonconvex_root
+    p, _, _ = _nonconvex_root()
+    walk_parity(p, NC_PTS, 2000, 3, flip_budget=1e-4)
+
+
+def test_walk_parity_config2_small():
+    p, xs = W.config2(n_points=64)
+    walk_parity(p, xs, 300, 4, flip_budget=1e-4)
+    walk_parity(p, xs[:16], 300, 4, estimator=1, sched=1, flip_budget=1e-4)
+
+
+def test_walk_parity_ellipsoids_vr_3d():
+    p, xs = W.config4(n_points=24)
+    walk_parity(p, xs, 300, 6, estimator=1, flip_budget=1e-4)
+    walk_parity(p, xs[:8], 300, 4, estimator=0, sched=1, flip_budget=1e-4)
+
+
+@pytest.mark.parametrize("dim,axes", [(3, [0.9, 0.6, 0.4]), (4, [0.8, 0.6, 0.5, 0.4])])
+def test_walk_parity_single_ellipsoid(dim, axes):
+    p, A, Q = W.single_ellipsoid_linear(dim, axes)
+    pts = np.random.default_rng(0).standard_normal((8, dim)) * 0.1
+    walk_parity(p, pts, 1000, 3, flip_budget=1e-4)
+
+
+def test_walk_parity_shared_trajectories_and_offset():
+    p, xs = W.config1()
+    walk_parity(p, xs[:12], 500, 4, B=4)
+    walk_parity(p, xs[:12], 500, 4, offset=123456)
+
+
+# ----------------------------------------------------------------------------- per-point parity
+def test_estimate_same_streams_match_oracle_fp64():
+    from test_oracle_pins import STAR_PTS, _star_tree
+    cases = [(W.config1()[0], W.config1()[1][::3], 4, 0), (_star_tree()[0], STAR_PTS, 3, 0),
+             (W.zheng_ex3_3d(), W.ball_points(np.random.default_rng(2), 6, 3, 0.9), 5, 0),
+             (W.config1()[0], W.config1()[1][::5], 4, 1)]
+    for prob, pts, M, est in cases:
+        op = O.OracleProblem(prob)
+        mo, so, go, gso, _ = O.estimate(op, pts, 20000, M, seed=3, estimator=est)
+        gp = woi.Problem(prob)
+        mg, sg, gg, gsg = [_np(t) for t in woi.estimate(gp, pts, 20000, M, seed=3, estimator=est)]
+        assert np.allclose(mg, mo, rtol=1e-9, atol=1e-9 * so.max())
+        assert np.allclose(sg, so, rtol=1e-7)
+        assert np.allclose(gg, go, rtol=1e-9, atol=1e-9 * gso.max())
+        assert np.allclose(gsg, gso, rtol=1e-7)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_estimate_matches_exact_expectation(precision):
+    p, xs = W.config1()
+    H, gH = CF.harmonic_2d(1, "cos")
+    gp = woi.Problem(p)
+    for M, est in ((4, 0), (2, 1)):
+        mean, se, g, gse = [_np(t) for t in woi.estimate(gp, xs, 400000, M, seed=21, estimator=est,
+                                                          precision=precision, schedule_mode=1)]
+        ref = [CF.concentric_uM([1, .5], [10, 1], [1, 1], 1, 2, M, x, H, gH) for x in xs]
+        z = (mean - np.array([r[0] for r in ref])) / se
+        zg = (g - np.array([r[1] for r in ref])) / gse
+        assert np.max(np.abs(z)) < 4.5 and np.max(np.abs(zg)) < 4.5
+        assert 0.5 < np.mean(z ** 2) < 1.6
+
+
+def test_estimate_six_ball_exact_expectation_fp32():
+    p, xs = W.config5()
+    dirs = np.random.default_rng(1).standard_normal((32, 6))
+    pts = dirs / np.linalg.norm(dirs, axis=1, keepdims=True) * np.linspace(0.1, 0.85, 32)[:, None]
+    c1 = 0.7 ** 5 - 0.5 * 0.35 ** 5
+    H0, g0 = CF.harmonic_const(6); H1, g1 = CF.harmonic_x1(6)
+    gp = woi.Problem(p)
+    M = 4
+    mean, se, g, gse = [_np(t) for t in woi.estimate(gp, pts, 200000, M, seed=5, precision=woi.FP32, schedule_mode=1)]
+    ref = [CF.concentric_uM([1, .7, .35], [1, 5, .2], [c1, 1, -.5], 0, 6, M, x, H0, g0)[0] +
+           CF.concentric_uM([1, .7, .35], [1, 5, .2], [1, .5, -.3], 1, 6, M, x, H1, g1)[0] for x in pts]
+    assert np.max(np.abs((mean - ref) / se)) < 4.5
+
+
+def test_fp32_paired_with_fp64():
+    """FP32 walks against FP64 walks on identical streams: most decisions agree, the
+    paired difference is far below the statistical error, and its mean is consistent with 0."""
+    p, xs = W.config2(n_points=64)
+    gp = woi.Problem(p)
+    F64, _, T64 = woi.trace(gp, xs, 2000, 4, seed=9, schedule_mode=1)
+    F32, _, T32 = woi.trace(gp, xs, 2000, 4, seed=9, precision=woi.FP32, schedule_mode=1)
+    F64, F32 = _np(F64)[..., 0], _np(F32)[..., 0]
+    same = np.all(_np(T64) == _np(T32), axis=-1)[..., 0]
+    assert same.mean() > 0.99
+    d = (F32 - F64)[same]
+    sd = F64.std()
+    assert np.median(np.abs(d)) < 1e-4 * sd
+    assert abs(d.mean()) < 4 * d.std() / np.sqrt(d.size) + 1e-6 * sd
+
+
+# ----------------------------------------------------------------------------- edge cases
+def test_edge_cases():
+    p, xs = W.config1()
+    gp = woi.Problem(p)
+    op = O.OracleProblem(p)
+    # one point, one walk, M = 0; ragged point count (65 = 64 + 1)
+    for pts, walks, M in ((xs[:1], 1, 0), (np.concatenate([xs, xs[:1]]), 37, 2), (xs[:3], 5, 0)):
+        mg, sg, gg, _ = [_np(t) for t in woi.estimate(gp, pts, walks, M, seed=1)]
+        mo, so, go, _, _ = O.estimate(op, pts, walks, M, seed=1)
+        assert np.allclose(mg, mo, rtol=1e-9, atol=1e-12)
+        if walks == 1:
+            assert np.all(sg == 0)
+    # explicit launch shapes give the same numbers (results do not depend on the decomposition)
+    base = _np(woi.estimate(gp, xs, 1000, 4, seed=2)[0])
+    for spt, bs in ((1, 64), (7, 256), (1000, 64)):
+        alt = _np(woi.estimate(gp, xs, 1000, 4, seed=2, samples_per_thread=spt, block_size=bs)[0])
+        assert np.allclose(alt, base, rtol=1e-12, atol=1e-15)
+
+
+def test_counters_and_errors():
+    p, xs = W.config1()
+    gp = woi.Problem(p)
+    c = woi.new_counters()
+    woi.estimate(gp, xs, 1000, 4, seed=2, counters=c)
+    torch.cuda.synchronize()
+    c = _np(c)
+    assert c[0] == len(xs) * 1000 * 5
+    assert c[3] == 0
+    with pytest.raises(woi.WoiError):
+        woi.estimate(gp, xs, 1001, 4, estimator=woi.VR)     # odd walker count for VR
+    with pytest.raises(woi.WoiError):
+        woi.estimate(gp, xs, 100, 40)                       # M above the maximum
+
+
+# ----------------------------------------------------------------------------- full size, bench launch
+def test_config2_full_size_sampled():
+    """Config 2 at its full size (4096 points, W = 1e5) in the benchmark's launch configuration;
+    sampled points checked against the oracle on identical streams."""
+    p, xs = W.config2()
+    gp = woi.Problem(p)
+    idx = np.array([0, 1, 777, 2048, 3071, 3072, 3500, 4095])
+    mean32, se32, _, _ = [_np(t) for t in woi.estimate(gp, xs, 100000, 4, seed=2024, precision=woi.FP32,
+                                                        schedule_mode=1)]
+    mean64, se64, _, _ = [_np(t) for t in woi.estimate(gp, xs, 100000, 4, seed=2024, precision=woi.FP64,
+                                                        schedule_mode=1)]
+    # FP64 GPU against the oracle on the same streams (the oracle keys each sampled point by its index)
+    op = O.OracleProblem(p)
+    mo, so, _, _, _ = O.estimate(op, xs[idx], 100000, 4, seed=2024, schedule_mode=1, groups=idx)
+    assert np.allclose(mean64[idx], mo, rtol=1e-9, atol=1e-9 * so.max())
+    assert np.allclose(se64[idx], so, rtol=1e-7)
+    # FP32 walks on the same streams: differences far below the statistical error
+    z = (mean32 - mean64) / se64
+    assert np.all(np.isfinite(mean32)) and np.median(np.abs(z)) < 0.05 and np.max(np.abs(z)) < 1.0
