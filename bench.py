@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Walk-on-Interfaces benchmark on one MI355X.
+
+Workload (the 2D tree configuration): unit disk containing 3 nested star interfaces
+r0 (1 + 0.2 cos k t) with (r0, k) = (0.7, 3), (0.4, 5), (0.2, 7) as 2048-vertex polylines
+and 5 circular inclusions (N = 9 regions, depth 3), sigma = 10^U(-1, 2), 5-mode random
+Fourier flux data with zero mean; 4096 evaluation points (25 % within 1e-3 of an
+interface); W = 1e5 walkers per point, M = 4; values and gradients.
+
+One step = one full estimate of all points: the walk kernel plus the per-point reduction,
+inputs resident in HBM.  The headline path is FP32 walks with FP64 per-point sums and the
+wave-uniform shared schedule; the FP64 plain path (same kernel in FP64) is measured for the
+equal-standard-error comparison.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "walk-steps/s and eval-points/s at fixed std. error, FP32-batched vs FP64 plain"
+
+# Algorithmic FP work per event of the walk kernel (2D, counted from the kernel source; a
+# transcendental counts as one flop, an FMA as two).  See DESIGN.md, "Roofline".
+FLOPS_PER_WALKER_STEP = 29      # Phi + grad Phi + accumulation (19) and the Q/T/sign update (10)
+FLOPS_PER_OTHER = 18            # uniform re-sample + |K*| |dOmega| factor
+FLOPS_PER_NODE_TEST = 9         # line / ray against one bounding box
+FLOPS_PER_SEGMENT_TEST = 15     # line / ray against one polyline segment
+FLOPS_PER_WALKER = 57           # step-0 datum b(y_0) (5-mode Fourier) and Q_0
+PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 (packed) peak
+PEAK_HBM_GBS = 8000.0
+
+
+class HipEvents:
+    """hipEvent_t handles from libamdhip64 (events on the stream the kernels run on)."""
+
+    def __init__(self):
+        self.hip = ctypes.CDLL("libamdhip64.so")
+        self.hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+
+    def create(self):
+        e = ctypes.c_void_p()
+        assert self.hip.hipEventCreate(ctypes.byref(e)) == 0
+        return e.value
+
+    def ms(self, a, b):
+        t = ctypes.c_float()
+        assert self.hip.hipEventElapsedTime(ctypes.byref(t), ctypes.c_void_p(a), ctypes.c_void_p(b)) == 0
+        return t.value
+
+
+def flops_of(counts):
+    walker_steps, other, nodes, segs = counts[0], counts[7], counts[5], counts[6]
+    walkers = walker_steps / 5.0
+    return (FLOPS_PER_WALKER_STEP * walker_steps + FLOPS_PER_OTHER * other + FLOPS_PER_NODE_TEST * nodes +
+            FLOPS_PER_SEGMENT_TEST * segs + FLOPS_PER_WALKER * walkers)
+
+
+def run_path(woi, torch, prob, pts, walks, M, precision, steps, warmup, ev, seed0):
+    P = pts.shape[0]
+    out = (torch.empty(P, dtype=torch.float64, device="cuda"), torch.empty(P, dtype=torch.float64, device="cuda"),
+           torch.empty(P, 2, dtype=torch.float64, device="cuda"), torch.empty(P, 2, dtype=torch.float64, device="cuda"))
+    q = woi.make_query(walks, M, precision=precision, schedule_mode=woi.SCHED_SHARED)
+    ws = torch.empty(woi.workspace_size(prob, P, q), dtype=torch.uint8, device="cuda")
+    cnt = woi.new_counters()
+    for w in range(warmup):
+        woi.estimate(prob, pts, walks, M, seed=seed0 + 1000 + w, precision=precision, schedule_mode=woi.SCHED_SHARED,
+                     out=out, workspace=ws)
+    evs = [(ev.create(), ev.create()) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        woi.estimate(prob, pts, walks, M, seed=seed0 + k, precision=precision, schedule_mode=woi.SCHED_SHARED,
+                     out=out, workspace=ws, counters=cnt, events=evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = [ev.ms(a, b) for a, b in evs]
+    se = out[1].cpu().numpy()
+    return wall, kern_ms, cnt.cpu().numpy().astype(float), se, out[0].cpu().numpy()
+
+
+def cpu_baseline(prob, pts, walks, M, budget_s):
+    import numpy as np
+    from oracle import oracle as O
+    threads = min(16, os.cpu_count() or 1)
+    op = O.OracleProblem(prob)
+    idx = np.linspace(0, len(pts) - 1, 64).astype(int)          # 64 points spread over the set
+    t = time.perf_counter()
+    _, _, _, _, c = O.estimate(op, pts[idx], 400, M, seed=5, schedule_mode=1, threads=threads, groups=idx)
+    dt = time.perf_counter() - t
+    rate = c["walk_steps"] / dt
+    n = int(max(400, min(walks, budget_s * rate / (len(idx) * (M + 1)))))
+    t = time.perf_counter()
+    _, _, _, _, c = O.estimate(op, pts[idx], n, M, seed=6, schedule_mode=1, threads=threads, groups=idx)
+    dt = time.perf_counter() - t
+    return {"value": c["walk_steps"] / dt, "unit": "walk-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"64 of the 4096 points, {n} walkers each (W = {walks} in the full workload), FP64, "
+                      f"{c['walk_steps']} walker-steps in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--walks", type=int, default=100000)
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the walk ranges would shard with one all-reduce of per-point sums)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2508_16767_amd import woi
+
+    torch.cuda.set_device(0)
+    prob_desc, pts_np = W.config2()
+    M = 4
+    prob = woi.Problem(prob_desc)
+    woi._lib.woi_problem_upload(prob.handle)
+    pts = torch.tensor(pts_np, dtype=torch.float64, device="cuda")
+    P = pts.shape[0]
+    ev = HipEvents()
+
+    wall32, k32, c32, se32, _ = run_path(woi, torch, prob, pts, args.walks, M, woi.FP32, args.steps, args.warmup, ev, 1)
+    wall64, k64, c64, se64, _ = run_path(woi, torch, prob, pts, args.walks, M, woi.FP64, args.fp64_steps,
+                                         min(args.warmup, 1), ev, 101)
+
+    steps32 = c32[0] / args.steps                     # walker-steps per step
+    value = c32[0] / wall32
+    value64 = c64[0] / wall64
+    t32, t64 = wall32 / args.steps, wall64 / args.fp64_steps
+    eps = float(np.median(se64))                      # fixed SE: median per-point SE of FP64 plain
+    t32_eps = t32 * float(np.mean(se32 ** 2)) / eps ** 2
+    t64_eps = t64 * float(np.mean(se64 ** 2)) / eps ** 2
+    kern_ms = float(np.mean(k32))
+    flops = flops_of(c32 / args.steps)
+    achieved = flops / (kern_ms * 1e-3) / 1e12
+    kern64_ms = float(np.mean(k64))
+    flops64 = flops_of(c64 / args.fp64_steps)
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "walk-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t32 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2D tree: unit disk, 3 nested 2048-vertex star polylines (k=3,5,7) + 5 circles, "
+                               "sigma 10^U(-1,2), 5-mode Fourier jump data; 4096 points (25% within 1e-3 of an "
+                               "interface); W=1e5 walkers, M=4; values + gradients",
+                   "points": P, "walkers": args.walks, "M": M, "estimator": "plain", "schedule": "shared",
+                   "precision": "FP32 walks, FP64 per-point sums"},
+        "eval_points_per_s_fixed_se": P / t32_eps,
+        "fixed_se": eps,
+        "fp64_plain": {"walk_steps_per_s": value64, "ms_per_step": t64 * 1e3,
+                       "eval_points_per_s_fixed_se": P / t64_eps, "walk_kernel_ms": kern64_ms,
+                       "fp64_tflops": flops64 / (kern64_ms * 1e-3) / 1e12},
+        "speedup_fp32_vs_fp64_fixed_se": t64_eps / t32_eps,
+        "walk_kernel_ms": kern_ms,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "walk_kernel<float, 2, false>",
+                     "flops_per_launch": flops,
+                     "counts_per_launch": {n: float(v / args.steps) for n, v in zip(woi.COUNTER_NAMES, c32)}},
+    }
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_baseline(prob_desc, pts_np, args.walks, M, args.cpu_seconds)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

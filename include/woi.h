@@ -147,6 +147,9 @@ typedef struct {
     uint32_t instance;        /* < 2^24, mixed into every random-number counter         */
     int samples_per_thread;   /* 0 = automatic                                          */
     int block_size;           /* 0 = automatic (64 or 256)                              */
+    void *event_begin;        /* optional hipEvent_t recorded on `stream` right before the walk
+                                 kernel, and event_end right after it (NULL = none)     */
+    void *event_end;
 } woi_query;
 
 /* Device workspace (bytes) woi_estimate needs for P points with this query. */
@@ -158,8 +161,10 @@ woi_status woi_workspace_size(const woi_problem *p, int64_t P, const woi_query *
  *   points   [P*dim] row-major doubles (device)
  *   mean, se [P] doubles (device); grad, grad_se [P*dim] (device) or NULL
  *   workspace/workspace_bytes: device scratch of at least woi_workspace_size() bytes
- *   counters: NULL or device uint64[WOI_COUNTERS] that the call adds to:
- *             walker-steps, redraws (q = 0), rejections, attempt-cap hits, zero distances
+ *   counters: NULL or device uint64[WOI_COUNTERS] that the call adds to: [0] walker-steps,
+ *             [1] redraws (q = 0), [2] rejections, [3] attempt-cap hits, [4] zero distances,
+ *             [5] polyline tree-node tests, [6] polyline segment tests, [7] uniform ("other")
+ *             transitions
  * Errors: INVALID_ARG (sizes, NULL, VR with odd walks or dim > 3), OOM (workspace), DEVICE. */
 woi_status woi_estimate(const woi_problem *p, const double *points, int64_t P, const woi_query *q,
                         double *mean, double *se, double *grad, double *grad_se,

@@ -17,30 +17,39 @@ enum : int { REL_SAME = 1, REL_DESC = 2, REL_OTHER = 3 };
 //   SPHERE     : c[m], R
 //   ELLIPSOID  : c[m], A[m*m], L[m*m] (= A^{-1/2}), 1/lambda_max(A)
 //   POLYLINE2D : vertices v[2*(nv+1)] (v[nv] = v[0]), segment lengths len[nv],
-//                cumulative arclength cum[nv+1]; bounding-volume tree nodes as
-//                float4 (cx, cy, hx, hy) in the float payload at `bvh`.
+//                cumulative arclength cum[nv+1], outward unit normals nrm[2*nv].
+// Polyline search tables (float payload, shared by both precisions):
+//   for every level l >= 1 and aligned block b (vertices [b 2^l, min((b+1) 2^l, nv)]),
+//   bnd[base_l + b] bounds the distance of the block's vertices from its chord, with
+//   base_l = N2 - (N2 >> (l - 1)) and N2 = nv rounded up to a power of two; the walk
+//   starts at level top.  Guide table (int payload): gd[k] = largest j with
+//   cum[j] <= k L / nv.
 struct DevRegion {
     int kind, dkind, nt, nv;
     int g64, g32;              // shape parameters / polyline vertices
     int len64, len32;          // polyline segment lengths
     int cum64, cum32;          // polyline cumulative lengths
-    int bvh;                   // float offset of the first node (4 floats per node)
-    int nleaf, leaf;           // leaves (power of two), segments per leaf
+    int nrm64, nrm32;          // polyline segment normals
+    int bnd;                   // float offset of the block bounds
+    int n2, top;               // nv rounded up to a power of two, first walk level
+    int guide;                 // int offset of the guide table (nv entries)
     int d64, d32, dexp;        // data coefficients, DIRPOLY exponents (byte offset)
     int b64, b32, nbrk, class0;// VR (2D): sign breakpoints of beta along arclength
-    int pad0;
+    int lds_v, lds_b;          // byte offsets of the LDS copies (FP32 vertices, FP16 bounds), -1 if none
     double alpha, sgn, s, area, meas[2], total;
     float alpha_f, sgn_f, s_f, area_f, meas_f[2], total_f, pad1;
 };
 
+constexpr int LDS_BUDGET = 64 * 1024;   // bytes of polyline tables a workgroup may stage
+
 struct DevProblem {
-    int dim, N, vr_ok, pad0;
+    int dim, N, vr_ok, lds_bytes;             // lds_bytes: polyline tables staged per workgroup
     double alpha_l1, unit_area, phi_c;        // |S^{m-1}|, Phi prefactor (m >= 3)
     float alpha_l1_f, unit_area_f, phi_c_f, pad1;
     double cdf[WOI_MAX_REGIONS];              // schedule CDF over |alpha| / ||alpha||_1
     unsigned char rel[WOI_MAX_REGIONS][WOI_MAX_REGIONS];
     DevRegion reg[WOI_MAX_REGIONS];
-    uint64_t off64, off32, offb;              // byte offsets of the payload arrays
+    uint64_t off64, off32, offb, offi;        // byte offsets of the payload arrays
     uint64_t bytes;
 };
 

@@ -645,38 +645,37 @@ void flux_integrals(Host& H) {
     }
 }
 
-// bounding-volume tree over polyline segments: implicit complete binary tree, leaf = 8 segments
-void build_bvh(const HostRegion& g, int& nleaf, int leaf, std::vector<float>& nodes) {
+// Distance from point p to the segment [a, b].
+double seg_dist(const double* p, const double* a, const double* b) {
+    const double ex = b[0] - a[0], ey = b[1] - a[1], wx = p[0] - a[0], wy = p[1] - a[1];
+    const double ee = ex * ex + ey * ey;
+    double t = ee > 0 ? (wx * ex + wy * ey) / ee : 0.0;
+    t = std::min(1.0, std::max(0.0, t));
+    return std::hypot(wx - t * ex, wy - t * ey);
+}
+
+// Block bounds of the polyline search: every vertex of the aligned block
+// [b 2^l, min((b+1) 2^l, n)] lies within bnd of the block's chord segment, so its signed
+// distance to any line lies within [min(h_first, h_last) - bnd, max(...) + bnd].
+// Inflated to stay conservative under FP32 rounding.
+void block_bounds(const HostRegion& g, std::vector<float>& bnd, int& n2, int& top) {
     const int n = g.nv();
-    nleaf = 1;
-    while (nleaf * leaf < n) nleaf *= 2;
-    const int nn = 2 * nleaf - 1;
-    std::vector<double> lo(2 * nn, 1e300), hi(2 * nn, -1e300);
-    for (int l = 0; l < nleaf; ++l) {
-        const int k = nleaf - 1 + l;
-        for (int j = l * leaf; j < std::min(n, (l + 1) * leaf); ++j)
-            for (int e = 0; e < 2; ++e)
-                for (int c = 0; c < 2; ++c) {
-                    lo[2 * k + c] = std::min(lo[2 * k + c], g.v[2 * (j + e) + c]);
-                    hi[2 * k + c] = std::max(hi[2 * k + c], g.v[2 * (j + e) + c]);
-                }
-    }
-    for (int k = nleaf - 2; k >= 0; --k)
-        for (int c = 0; c < 2; ++c) {
-            lo[2 * k + c] = std::min(lo[2 * (2 * k + 1) + c], lo[2 * (2 * k + 2) + c]);
-            hi[2 * k + c] = std::max(hi[2 * (2 * k + 1) + c], hi[2 * (2 * k + 2) + c]);
-        }
-    nodes.resize(4 * nn);
-    for (int k = 0; k < nn; ++k) {
-        if (lo[2 * k] > hi[2 * k]) {   // empty leaf: a box no line reaches
-            nodes[4 * k] = 1e30f; nodes[4 * k + 1] = 1e30f; nodes[4 * k + 2] = 0.f; nodes[4 * k + 3] = 0.f;
-            continue;
-        }
-        for (int c = 0; c < 2; ++c) {
-            const double mid = 0.5 * (lo[2 * k + c] + hi[2 * k + c]);
-            const double half = 0.5 * (hi[2 * k + c] - lo[2 * k + c]);
-            nodes[4 * k + c] = (float)mid;   // conservative: inflate for FP32 rounding
-            nodes[4 * k + 2 + c] = (float)(half + 1e-6 * (1.0 + std::fabs(mid)) + std::fabs(mid - (double)(float)mid));
+    n2 = 1;
+    int L = 0;
+    while (n2 < n) { n2 *= 2; ++L; }
+    top = std::max(1, L - 4);
+    double scale = 0;
+    for (double x : g.v) scale = std::max(scale, std::fabs(x));
+    const double pad = 4e-6 * (1.0 + scale);
+    bnd.assign(n2, 0.0f);
+    for (int l = 1; l <= L; ++l) {
+        const int base = n2 - (n2 >> (l - 1));
+        for (int j0 = 0, blk = 0; j0 < n; j0 += 1 << l, ++blk) {
+            const int j1 = std::min(n, j0 + (1 << l));
+            double dmax = 0;
+            for (int j = j0; j <= j1; ++j) dmax = std::max(dmax, seg_dist(&g.v[2 * j], &g.v[2 * j0], &g.v[2 * j1]));
+            // 1e-3 relative headroom keeps the bound conservative after rounding to FP16
+            bnd[base + blk] = (float)(dmax * (1.0 + 2e-3) + pad);
         }
     }
 }
@@ -776,6 +775,7 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
     std::vector<double> p64;
     std::vector<float> p32;
     std::vector<uint8_t> pb;
+    std::vector<int32_t> pi;
     auto put64 = [&](const double* x, size_t n) { const int o = (int)p64.size(); p64.insert(p64.end(), x, x + n); return o; };
     auto put32 = [&](const double* x, size_t n) {
         const int o = (int)p32.size();
@@ -829,16 +829,30 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
         r.g64 = put64(geo.data(), geo.size());
         r.g32 = put32(geo.data(), geo.size());
         if (g.kind == WOI_SHAPE_POLYLINE2D) {
+            const int n = g.nv();
             r.len64 = put64(g.len.data(), g.len.size());
             r.len32 = put32(g.len.data(), g.len.size());
             r.cum64 = put64(g.cum.data(), g.cum.size());
             r.cum32 = put32(g.cum.data(), g.cum.size());
-            std::vector<float> nodes;
-            r.leaf = 8;
-            build_bvh(g, r.nleaf, r.leaf, nodes);
-            while (p32.size() % 4) p32.push_back(0.f);
-            r.bvh = (int)p32.size();
-            p32.insert(p32.end(), nodes.begin(), nodes.end());
+            std::vector<double> nrm(2 * n);
+            for (int j = 0; j < n; ++j) {   // outward normal of a counter-clockwise segment
+                const double ex = g.v[2 * j + 2] - g.v[2 * j], ey = g.v[2 * j + 3] - g.v[2 * j + 1];
+                const double l = std::sqrt(ex * ex + ey * ey);
+                nrm[2 * j] = ey / l;
+                nrm[2 * j + 1] = -ex / l;
+            }
+            r.nrm64 = put64(nrm.data(), nrm.size());
+            r.nrm32 = put32(nrm.data(), nrm.size());
+            std::vector<float> bnd;
+            block_bounds(g, bnd, r.n2, r.top);
+            r.bnd = (int)p32.size();
+            p32.insert(p32.end(), bnd.begin(), bnd.end());
+            r.guide = (int)pi.size();
+            for (int k = 0; k < n; ++k) {
+                const double s0 = g.cum[n] * k / n;
+                int j = (int)(std::upper_bound(g.cum.begin(), g.cum.begin() + n, s0) - g.cum.begin()) - 1;
+                pi.push_back(std::max(0, std::min(j, n - 1)));
+            }
         }
         if (!g.coef.empty()) {
             r.d64 = put64(g.coef.data(), g.coef.size());
@@ -869,16 +883,36 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
         r.meas_f[1] = (float)r.meas[1];
         r.total_f = (float)r.total;
     }
+    // LDS staging plan: FP32 vertices (8 B each, n + 1) and FP16 bounds (2 B each, n2) of
+    // every polyline, if they fit in one workgroup's budget together
+    {
+        int off = 0;
+        for (int i = 0; i < N; ++i) {
+            DevRegion& r = hdr.reg[i];
+            r.lds_v = r.lds_b = -1;
+            if (r.kind != WOI_SHAPE_POLYLINE2D) continue;
+            r.lds_v = off;
+            off += 8 * (r.nv + 1);
+            r.lds_b = off;
+            off += 2 * r.n2;
+            off = (off + 15) & ~15;
+        }
+        hdr.lds_bytes = off <= woi::LDS_BUDGET ? off : 0;
+        if (hdr.lds_bytes == 0)
+            for (int i = 0; i < N; ++i) hdr.reg[i].lds_v = hdr.reg[i].lds_b = -1;
+    }
     auto align = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
     hdr.off64 = align(sizeof(DevProblem));
     hdr.off32 = align(hdr.off64 + p64.size() * sizeof(double));
     hdr.offb = align(hdr.off32 + p32.size() * sizeof(float));
-    hdr.bytes = align(hdr.offb + pb.size() + 16);
+    hdr.offi = align(hdr.offb + pb.size());
+    hdr.bytes = align(hdr.offi + pi.size() * sizeof(int32_t) + 16);
     std::vector<uint8_t> blob(hdr.bytes, 0);
     std::memcpy(blob.data(), &hdr, sizeof hdr);
     if (!p64.empty()) std::memcpy(blob.data() + hdr.off64, p64.data(), p64.size() * sizeof(double));
     if (!p32.empty()) std::memcpy(blob.data() + hdr.off32, p32.data(), p32.size() * sizeof(float));
     if (!pb.empty()) std::memcpy(blob.data() + hdr.offb, pb.data(), pb.size());
+    if (!pi.empty()) std::memcpy(blob.data() + hdr.offi, pi.data(), pi.size() * sizeof(int32_t));
     P->blob = std::move(blob);
     P->bytes = hdr.bytes;
     woi_problem_info& inf = P->info;
@@ -942,6 +976,7 @@ woi_status woi_problem_get_info(const woi_problem* p, woi_problem_info* out) {
 namespace {
 
 struct Plan {
+    unsigned lds;
     int block;
     uint32_t spt;
     int chunks;
@@ -972,7 +1007,9 @@ Plan make_plan(const woi_problem* p, int64_t P, const woi_query* q, uint64_t n_s
     Plan pl;
     pl.n_samples = n_samples;
     pl.first = q->estimator == WOI_EST_VR ? q->walk_offset / 2 : q->walk_offset;
-    pl.block = q->block_size > 0 ? q->block_size : (P >= 4096 ? 256 : 64);
+    const DevProblem* hdr = reinterpret_cast<const DevProblem*>(p->blob.data());
+    pl.lds = hdr->lds_bytes > 0 && p->H.m == 2 ? (unsigned)hdr->lds_bytes : 0u;
+    pl.block = pl.lds ? 512 : (q->block_size > 0 ? q->block_size : (P >= 4096 ? 256 : 64));
     pl.gx = (unsigned)((P + pl.block - 1) / pl.block);
     uint64_t spt;
     if (q->samples_per_thread > 0) spt = (uint64_t)q->samples_per_thread;
@@ -1036,9 +1073,13 @@ woi_status woi_estimate(const woi_problem* p, const double* points, int64_t P, c
     kp.partials = static_cast<double*>(workspace);
     kp.counters = counters;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = woi::launch_walk(kp, p->H.m, q->estimator == WOI_EST_VR, q->precision == WOI_PREC_FP32,
+    if (q->event_begin && hipEventRecord(static_cast<hipEvent_t>(q->event_begin), s) != hipSuccess)
+        return fail(WOI_E_DEVICE, "hipEventRecord(begin) failed");
+    hipError_t e = woi::launch_walk(kp, p->H.m, q->estimator == WOI_EST_VR, q->precision == WOI_PREC_FP32, pl.lds,
                                     dim3(pl.gx, pl.chunks), dim3(pl.block), s);
     if (e != hipSuccess) return fail(WOI_E_DEVICE, "walk launch failed: %s", hipGetErrorString(e));
+    if (q->event_end && hipEventRecord(static_cast<hipEvent_t>(q->event_end), s) != hipSuccess)
+        return fail(WOI_E_DEVICE, "hipEventRecord(end) failed");
     woi::RParams rp{};
     rp.partials = kp.partials;
     rp.P = P;
@@ -1081,7 +1122,7 @@ woi_status woi_trace(const woi_problem* p, const double* points, int64_t P, cons
     kp.traceF = F;
     kp.traceG = G;
     kp.trace = trace;
-    hipError_t e = woi::launch_walk(kp, p->H.m, q->estimator == WOI_EST_VR, q->precision == WOI_PREC_FP32,
+    hipError_t e = woi::launch_walk(kp, p->H.m, q->estimator == WOI_EST_VR, q->precision == WOI_PREC_FP32, pl.lds,
                                     dim3(pl.gx, pl.chunks), dim3(pl.block), static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return fail(WOI_E_DEVICE, "walk launch failed: %s", hipGetErrorString(e));
     return WOI_OK;

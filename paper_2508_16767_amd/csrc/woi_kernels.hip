@@ -14,9 +14,11 @@
 // only positions differ.  Every lane draws its own Philox4x32-10 counters keyed by
 // (walk, point group, instance|walker|purpose, step|draw), so results do not depend
 // on the launch shape.  Per-point sums are FP64 in every precision.
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "woi_device.h"
 #include "woi_launch.h"
@@ -97,6 +99,7 @@ template <> struct Pay<double> {
     static __device__ __forceinline__ int g(const DevRegion& r) { return r.g64; }
     static __device__ __forceinline__ int len(const DevRegion& r) { return r.len64; }
     static __device__ __forceinline__ int cum(const DevRegion& r) { return r.cum64; }
+    static __device__ __forceinline__ int nrm(const DevRegion& r) { return r.nrm64; }
     static __device__ __forceinline__ int dat(const DevRegion& r) { return r.d64; }
     static __device__ __forceinline__ int brk(const DevRegion& r) { return r.b64; }
     static __device__ __forceinline__ double area(const DevRegion& r) { return r.area; }
@@ -115,6 +118,7 @@ template <> struct Pay<float> {
     static __device__ __forceinline__ int g(const DevRegion& r) { return r.g32; }
     static __device__ __forceinline__ int len(const DevRegion& r) { return r.len32; }
     static __device__ __forceinline__ int cum(const DevRegion& r) { return r.cum32; }
+    static __device__ __forceinline__ int nrm(const DevRegion& r) { return r.nrm32; }
     static __device__ __forceinline__ int dat(const DevRegion& r) { return r.d32; }
     static __device__ __forceinline__ int brk(const DevRegion& r) { return r.b32; }
     static __device__ __forceinline__ float area(const DevRegion& r) { return r.area_f; }
@@ -128,7 +132,7 @@ template <> struct Pay<float> {
 };
 
 struct Counts {
-    uint32_t steps, redraws, rejections, caps, zero;
+    uint32_t steps, redraws, rejections, caps, zero, nodes, segs, other;
 };
 
 constexpr int dir_words(int D) { return D == 2 ? 1 : (D == 3 ? 2 : 2 * ((D + 1) / 2)); }
@@ -185,10 +189,8 @@ __device__ __forceinline__ void normal_at(const DevRegion& g, const R* __restric
         for (int i = 0; i < D; ++i) n[i] *= inv;
     } else {
         if constexpr (D == 2) {
-            const R* v = q + 2 * seg;
-            const R ex = v[2] - v[0], ey = v[3] - v[1];
-            const R l = RO<R>::sq(ex * ex + ey * ey);
-            n[0] = ey / l; n[1] = -ex / l;
+            const R* nr = pay + Pay<R>::nrm(g) + 2 * seg;
+            n[0] = nr[0]; n[1] = nr[1];
         }
     }
 }
@@ -248,19 +250,27 @@ __device__ __forceinline__ R data_b(const DevProblem* dp, const DevRegion& g, co
 }
 
 // ---- uniform surface sample, one attempt: returns false when rejected
+__device__ __forceinline__ const int* int_payload(const DevProblem* dp) {
+    return reinterpret_cast<const int*>(reinterpret_cast<const char*>(dp) + dp->offi);
+}
+
+// Point at arclength s on a polyline: the segment is the largest j with cum[j] <= s, found
+// from the guide table entry for s in O(1) expected probes.
 template <typename R, int D>
-__device__ __forceinline__ bool polyline_at(const DevRegion& g, const R* __restrict__ pay, R s, R y[D], int& seg) {
+__device__ __forceinline__ bool polyline_at(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay, R s,
+                                            R y[D], int& seg) {
     if constexpr (D == 2) {
         const R* cum = pay + Pay<R>::cum(g);
-        int lo = 0, hi = g.nv - 1;   // largest j with cum[j] <= s
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (cum[mid] <= s) lo = mid; else hi = mid - 1;
-        }
-        const R* v = pay + Pay<R>::g(g) + 2 * lo;
-        const R f = (s - cum[lo]) / pay[Pay<R>::len(g) + lo];
+        const int n = g.nv;
+        int k = (int)(s * ((R)n / Pay<R>::total(g)));
+        k = min(max(k, 0), n - 1);
+        int j = int_payload(dp)[g.guide + k];
+        while (j < n - 1 && cum[j + 1] <= s) ++j;
+        while (j > 0 && cum[j] > s) --j;
+        const R* v = pay + Pay<R>::g(g) + 2 * j;
+        const R f = (s - cum[j]) / pay[Pay<R>::len(g) + j];
         y[0] = v[0] + f * (v[2] - v[0]); y[1] = v[1] + f * (v[3] - v[1]);
-        seg = lo;
+        seg = j;
     }
     return true;
 }
@@ -271,12 +281,12 @@ __device__ __forceinline__ int surf_words(const DevRegion& g) {
 }
 
 template <typename R, int D>
-__device__ __forceinline__ bool surf_attempt(const DevRegion& g, const R* __restrict__ pay, const Stream& st,
-                                             uint32_t step, int att, R y[D], int& seg) {
+__device__ __forceinline__ bool surf_attempt(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
+                                             const Stream& st, uint32_t step, int att, R y[D], int& seg) {
     seg = 0;
     if (g.kind == WOI_SHAPE_POLYLINE2D) {
         Words<1> W; W.fill(st, step, (uint32_t)att);
-        return polyline_at<R, D>(g, pay, RO<R>::u(W.w[0]) * Pay<R>::total(g), y, seg);
+        return polyline_at<R, D>(dp, g, pay, RO<R>::u(W.w[0]) * Pay<R>::total(g), y, seg);
     }
     const R* q = pay + Pay<R>::g(g);
     if (g.kind == WOI_SHAPE_SPHERE) {
@@ -308,9 +318,10 @@ __device__ __forceinline__ bool surf_attempt(const DevRegion& g, const R* __rest
 
 // point at arclength s on a closed 2D curve (circle or polyline)
 template <typename R, int D>
-__device__ __forceinline__ void curve_at(const DevRegion& g, const R* __restrict__ pay, R s, R y[D], int& seg) {
+__device__ __forceinline__ void curve_at(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay, R s,
+                                         R y[D], int& seg) {
     if constexpr (D == 2) {
-        if (g.kind == WOI_SHAPE_POLYLINE2D) { polyline_at<R, D>(g, pay, s, y, seg); return; }
+        if (g.kind == WOI_SHAPE_POLYLINE2D) { polyline_at<R, D>(dp, g, pay, s, y, seg); return; }
         const R* q = pay + Pay<R>::g(g);
         R sn, cs;
         RO<R>::sc2pi(s / (R(2) * R(3.14159265358979323846) * q[2]), sn, cs);
@@ -333,17 +344,17 @@ __device__ __forceinline__ bool vr_attempt(const DevProblem* dp, const DevRegion
             if (c == cls) {
                 const R l = end - start;
                 if (t < acc + l || p == g.nbrk) {
-                    curve_at<R, D>(g, pay, fmin(start + (t - acc), end), y, seg);
+                    curve_at<R, D>(dp, g, pay, fmin(start + (t - acc), end), y, seg);
                     return true;
                 }
                 acc += l;
             }
             start = end; c ^= 1;
         }
-        curve_at<R, D>(g, pay, start, y, seg);
+        curve_at<R, D>(dp, g, pay, start, y, seg);
         return true;
     } else {
-        if (!surf_attempt<R, D>(g, pay, st, 0, att, y, seg)) return false;
+        if (!surf_attempt<R, D>(dp, g, pay, st, 0, att, y, seg)) return false;
         return (Pay<R>::s(g) * data_b<R, D>(dp, g, pay, y, seg) >= R(0)) == (cls == 0);
     }
 }
@@ -382,56 +393,70 @@ __device__ __forceinline__ int quadric_hit(const DevRegion& g, const R* __restri
     return t > R(0) ? 1 : 0;
 }
 
-// Polyline: hits in segment order via a stackless walk of the implicit binary tree of
-// leaf boxes (left to right).  want < 0: count all hits, remembering the first two;
-// want >= 0: stop at hit number `want`.
-template <typename R>
-struct PolyHit { int q; int seg0, seg1; };
+// Polyline: hits of the line / ray y + t d in segment order.  The signed distance of
+// vertex j from the line is h_j = d x (v_j - y); segment j is hit iff h_j = 0 != h_{j+1}
+// or the signs differ (the half-open segment [v_j, v_{j+1})).  One flat loop per lane
+// walks the vertex index with an adaptive aligned stride 2^l: a block whose chord bound
+// keeps all its vertices strictly on one side of the line is skipped, otherwise it is
+// halved; at stride 1 the segment is tested exactly.  Every iteration costs the same
+// (one vertex, one bound), so lanes of a wave stay in step.
+// want < 0: count all hits (q) remembering the first two; want >= 0: stop at hit `want`.
+struct PolyHits { int q, j0, j1; };
 
-template <typename R>
-__device__ __forceinline__ bool seg_hit(const R* v, const R y[2], const R d[2], bool ray, R eps) {
-    const R ex = v[2] - v[0], ey = v[3] - v[1];
-    const R den = d[0] * ey - d[1] * ex;
-    if (den == R(0)) return false;
-    const R wx = v[0] - y[0], wy = v[1] - y[1];
-    const R t = (wx * ey - wy * ex) / den;
-    const R s = (wx * d[1] - wy * d[0]) / den;
-    if (s < R(0) || s >= R(1)) return false;
-    return ray ? (t > R(0)) : (fabs(t) > eps);
-}
+// Polyline tables staged by the workgroup (FP32 vertices, FP16 block bounds).
+extern __shared__ __align__(16) char woi_smem[];
 
-template <typename R>
-__device__ __noinline__ int poly_walk(const DevRegion& g, const R* __restrict__ pay, const float4* __restrict__ nodes,
-                                      const R y[2], const R d[2], bool ray, int yseg, int want, int& s0, int& s1) {
-    const R* v = pay + Pay<R>::g(g);
-    const float fy0 = (float)y[0], fy1 = (float)y[1], fd0 = (float)d[0], fd1 = (float)d[1];
-    const float ad0 = fabsf(fd0), ad1 = fabsf(fd1);
-    const int first_leaf = g.nleaf - 1;
-    int k = 0, q = 0;
-    s0 = s1 = -1;
-    while (true) {
-        const float4 b = nodes[k];
-        const float cx = b.x - fy0, cy = b.y - fy1;
-        bool hit = fabsf(fd0 * cy - fd1 * cx) <= ad1 * b.z + ad0 * b.w;
-        if (ray) hit = hit && (fd0 * cx + fd1 * cy + ad0 * b.z + ad1 * b.w >= 0.f);
-        if (hit && k < first_leaf) { k = 2 * k + 1; continue; }
-        if (hit) {
-            const int j0 = (k - first_leaf) * g.leaf;
-            const int j1 = min(j0 + g.leaf, g.nv);
-            for (int j = j0; j < j1; ++j) {
-                if (!ray && j == yseg) continue;
-                if (seg_hit<R>(v + 2 * j, y, d, ray, RO<R>::line_eps)) {
-                    if (q == want) { s0 = j; return q + 1; }
-                    if (q == 0) s0 = j; else if (q == 1) s1 = j;
-                    ++q;
-                }
+constexpr bool COUNT_POLY = true;   // dead code unless the counting kernel reads the counters
+
+template <typename R, bool LDS>
+__device__ __forceinline__ PolyHits poly_hits(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
+                                              const R y[2], const R d[2], bool ray, int yseg, int want, Counts& cnt) {
+    const R* __restrict__ v = pay + Pay<R>::g(g);            // exact tests, precision R
+    const int n = g.nv, n2 = g.n2, top = g.top;
+    // block tests run in FP32 on the staged (or global) FP32 copy; bounds absorb the rounding
+    const float* __restrict__ vf;
+    if constexpr (LDS) vf = reinterpret_cast<const float*>(woi_smem + g.lds_v);
+    else vf = Pay<float>::base(dp) + g.g32;
+    const float yf0 = (float)y[0], yf1 = (float)y[1], df0 = (float)d[0], df1 = (float)d[1];
+    auto hf = [&](int j) -> float { return df0 * (vf[2 * j + 1] - yf1) - df1 * (vf[2 * j] - yf0); };
+    auto bound = [&](int idx) -> float {
+        if constexpr (LDS) return __half2float(reinterpret_cast<const __half*>(woi_smem + g.lds_b)[idx]);
+        else return Pay<float>::base(dp)[g.bnd + idx];
+    };
+    PolyHits r{0, -1, -1};
+    int j = 0, lvl = top;
+    float hj = hf(0);
+    // Branch-free body: every lane evaluates the block test and the segment crossing with
+    // selects; only a lane that actually crosses a segment enters the (rare) hit branch.
+    while (j < n) {
+        const int je = min(j + (1 << lvl), n);
+        const float he = hf(je);
+        const bool seg_level = lvl == 0;
+        const float b = bound(seg_level ? 0 : n2 - (n2 >> (lvl - 1)) + (j >> lvl));
+        const bool skip = fminf(hj, he) - b > 0.f || fmaxf(hj, he) + b < 0.f;
+        const R* a = v + 2 * j;
+        R ha, hb;
+        if constexpr (std::is_same<R, float>::value) { ha = hj; hb = he; }
+        else { ha = d[0] * (a[1] - y[1]) - d[1] * (a[0] - y[0]); hb = d[0] * (a[3] - y[1]) - d[1] * (a[2] - y[0]); }
+        const bool cross = hb != R(0) && (ha == R(0) || ((ha > R(0)) != (hb > R(0))));
+        if (seg_level && cross && (ray || j != yseg)) {
+            const R ex = a[2] - a[0], ey = a[3] - a[1];
+            const R den = d[0] * ey - d[1] * ex;
+            const R t = ((a[0] - y[0]) * ey - (a[1] - y[1]) * ex) / den;
+            if (den != R(0) && (ray ? (t > R(0)) : (fabs(t) > RO<R>::line_eps))) {
+                r.j0 = (r.q == 0 || r.q == want) ? j : r.j0;
+                r.j1 = r.q == 1 ? j : r.j1;
+                if (r.q == want) { r.q++; return r; }
+                r.q++;
             }
         }
-        while (k > 0 && (k & 1) == 0) k = (k - 1) >> 1;
-        if (k == 0) break;
-        ++k;
+        if (COUNT_POLY) { cnt.nodes += seg_level ? 0 : 1; cnt.segs += seg_level ? 1 : 0; }
+        const bool advance = seg_level || skip;
+        j = advance ? je : j;
+        hj = advance ? he : hj;
+        lvl = advance ? min(top, (int)__builtin_ctz((unsigned)je | (1u << top))) : lvl - 1;
     }
-    return q;
+    return r;
 }
 
 // ----------------------------------------------------------------------------- accumulation
@@ -469,9 +494,9 @@ __device__ __forceinline__ uint32_t trace_word(int h, int cs, int q, int pick, i
 
 // ----------------------------------------------------------------------------- one sample
 // Walker k of sample `w` at point x: F = N sum_i c_i Phi(x, y_i), G = N sum_i c_i grad_x Phi.
-template <typename R, int D, bool VR>
+template <typename R, int D, bool VR, bool LDS>
 __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const R* __restrict__ pay,
-                                       const float4* __restrict__ nodes, const R xh[D], const R xl[D],
+                                       const R xh[D], const R xl[D],
                                        const KParams& kp, uint32_t w, uint32_t group, int k, R& F, R G[D],
                                        uint32_t* __restrict__ tr, Counts& cnt) {
     const int N = dp->N, M = kp.M;
@@ -501,7 +526,7 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
     for (att = 0; att < WOI_ATTEMPT_CAP; ++att) {
         bool ok;
         if constexpr (VR) ok = vr_attempt<R, D>(dp, *g, pay, k, st, att, y, seg);
-        else ok = surf_attempt<R, D>(*g, pay, st, 0, att, y, seg);
+        else ok = surf_attempt<R, D>(dp, *g, pay, st, 0, att, y, seg);
         if (ok) break;
         cnt.rejections++;
     }
@@ -528,8 +553,9 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
         int segn = 0, qn = 1, pick = 0;
         if (rel == REL_OTHER) {
             // y_i uniform on dOmega_{h_i}: Q *= |K*(y_i, y_{i-1})| |dOmega_{h_i}|
+            cnt.other++;
             for (att = 0; att < WOI_ATTEMPT_CAP; ++att) {
-                if (surf_attempt<R, D>(*g, pay, st, (uint32_t)i, att, yn, segn)) break;
+                if (surf_attempt<R, D>(dp, *g, pay, st, (uint32_t)i, att, yn, segn)) break;
                 cnt.rejections++;
             }
             if (att == WOI_ATTEMPT_CAP) cnt.caps++;
@@ -554,13 +580,12 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
                 const R up = RO<R>::u(W.w[NW - 1]);
                 if (g->kind == WOI_SHAPE_POLYLINE2D) {
                     if constexpr (D == 2) {
-                        const float4* nd = nodes + g->bvh / 4;
-                        int s0, s1;
-                        qn = poly_walk<R>(*g, pay, nd, y, d, ray, seg, -1, s0, s1);
+                        const PolyHits ph = poly_hits<R, LDS>(dp, *g, pay, y, d, ray, seg, -1, cnt);
+                        qn = ph.q;
                         if (qn == 0) { cnt.redraws++; continue; }
                         pick = min((int)(up * (R)qn), qn - 1);
-                        int j = pick == 0 ? s0 : s1;
-                        if (pick >= 2) { int a, b; poly_walk<R>(*g, pay, nd, y, d, ray, seg, pick, a, b); j = a; }
+                        int j = pick == 0 ? ph.j0 : ph.j1;
+                        if (pick >= 2) j = poly_hits<R, LDS>(dp, *g, pay, y, d, ray, seg, pick, cnt).j0;
                         const R* v = pay + Pay<R>::g(*g) + 2 * j;
                         const R ex = v[2] - v[0], ey = v[3] - v[1];
                         const R den = d[0] * ey - d[1] * ex;
@@ -620,11 +645,26 @@ __device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
     return v;
 }
 
-template <typename R, int D, bool VR>
-__global__ __launch_bounds__(256) void walk_kernel(KParams kp) {
+// Stage every polyline's FP32 vertices and FP16 block bounds into LDS (LDS variant).
+__device__ __forceinline__ void stage_polylines(const DevProblem* __restrict__ dp) {
+    const float* __restrict__ f32 = Pay<float>::base(dp);
+    for (int i = 0; i < dp->N; ++i) {
+        const DevRegion& g = dp->reg[i];
+        if (g.lds_v < 0) continue;
+        float2* dv = reinterpret_cast<float2*>(woi_smem + g.lds_v);
+        const float2* sv = reinterpret_cast<const float2*>(f32 + g.g32);
+        for (int t = threadIdx.x; t <= g.nv; t += blockDim.x) dv[t] = sv[t];
+        __half* db = reinterpret_cast<__half*>(woi_smem + g.lds_b);
+        for (int t = threadIdx.x; t < g.n2; t += blockDim.x) db[t] = __float2half_ru(f32[g.bnd + t]);
+    }
+    __syncthreads();
+}
+
+template <typename R, int D, bool VR, bool COUNT, bool LDS>
+__global__ __launch_bounds__(LDS ? 512 : 256) void walk_kernel(KParams kp) {
     const DevProblem* __restrict__ dp = kp.dp;
     const R* __restrict__ pay = Pay<R>::base(dp);
-    const float4* __restrict__ nodes = reinterpret_cast<const float4*>(Pay<float>::base(dp));
+    if constexpr (LDS) stage_polylines(dp);
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = p < kp.P;
     const int64_t pc = active ? p : kp.P - 1;
@@ -636,7 +676,7 @@ __global__ __launch_bounds__(256) void walk_kernel(KParams kp) {
     double S1 = 0, S2 = 0, G1[D], G2[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) { G1[i] = 0; G2[i] = 0; }
-    Counts cnt{0, 0, 0, 0, 0};
+    Counts cnt{0, 0, 0, 0, 0, 0, 0, 0};
     constexpr int K = VR ? 2 : 1;
     for (uint64_t s = s0; s < s1; ++s) {
         const uint32_t w = (uint32_t)(kp.first_sample + s);
@@ -649,7 +689,7 @@ __global__ __launch_bounds__(256) void walk_kernel(KParams kp) {
             uint32_t* tr = nullptr;
             const size_t idx = ((size_t)pc * kp.n_samples + s) * K + k;
             if (kp.trace && active) tr = kp.trace + idx * (kp.M + 1);
-            walker<R, D, VR>(dp, pay, nodes, xh, xl, kp, w, group, k, Fk, Gk, tr, cnt);
+            walker<R, D, VR, LDS>(dp, pay, xh, xl, kp, w, group, k, Fk, Gk, tr, cnt);
             F += (double)Fk;
 #pragma unroll
             for (int i = 0; i < D; ++i) Gs[i] += (double)Gk[i];
@@ -670,16 +710,13 @@ __global__ __launch_bounds__(256) void walk_kernel(KParams kp) {
 #pragma unroll
         for (int i = 0; i < D; ++i) { o[2 + i] = G1[i]; o[2 + D + i] = G2[i]; }
     }
-    if (kp.counters) {
-        const uint64_t a = wave_sum(active ? cnt.steps : 0), b = wave_sum(active ? cnt.redraws : 0);
-        const uint64_t c = wave_sum(active ? cnt.rejections : 0), d = wave_sum(active ? cnt.caps : 0);
-        const uint64_t e = wave_sum(active ? cnt.zero : 0);
-        if ((threadIdx.x & 63) == 0) {
-            atomicAdd((unsigned long long*)&kp.counters[0], (unsigned long long)a);
-            atomicAdd((unsigned long long*)&kp.counters[1], (unsigned long long)b);
-            atomicAdd((unsigned long long*)&kp.counters[2], (unsigned long long)c);
-            atomicAdd((unsigned long long*)&kp.counters[3], (unsigned long long)d);
-            atomicAdd((unsigned long long*)&kp.counters[4], (unsigned long long)e);
+    if constexpr (COUNT) {
+        const uint32_t v[WOI_COUNTERS] = {cnt.steps, cnt.redraws, cnt.rejections, cnt.caps,
+                                          cnt.zero, cnt.nodes, cnt.segs, cnt.other};
+#pragma unroll
+        for (int i = 0; i < WOI_COUNTERS; ++i) {
+            const uint64_t s = wave_sum(active ? (uint64_t)v[i] : 0);
+            if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long*)&kp.counters[i], (unsigned long long)s);
         }
     }
 }
@@ -714,35 +751,58 @@ __global__ void reduce_kernel(RParams rp) {
 }
 
 // ----------------------------------------------------------------------------- launchers
-template <typename R, int D, bool VR>
-static hipError_t launch_walk_t(const KParams& kp, dim3 grid, dim3 block, hipStream_t s) {
-    hipLaunchKernelGGL((walk_kernel<R, D, VR>), grid, block, 0, s, kp);
+template <typename R, int D, bool VR, bool COUNT, bool LDS>
+static hipError_t launch_walk_t(const KParams& kp, dim3 grid, dim3 block, unsigned smem, hipStream_t s) {
+    if constexpr (LDS) {
+        if (D != 2) return hipErrorInvalidValue;
+        static bool attr = false;
+        if (!attr) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&walk_kernel<R, D, VR, COUNT, LDS>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BUDGET);
+            if (e != hipSuccess) return e;
+            attr = true;
+        }
+    }
+    hipLaunchKernelGGL((walk_kernel<R, D, VR, COUNT, LDS>), grid, block, smem, s, kp);
     return hipGetLastError();
 }
 
-template <typename R>
-static hipError_t launch_walk_r(const KParams& kp, int dim, bool vr, dim3 grid, dim3 block, hipStream_t s) {
+template <typename R, bool COUNT>
+static hipError_t launch_walk_c(const KParams& kp, int dim, bool vr, bool lds, dim3 grid, dim3 block, unsigned smem,
+                                hipStream_t s) {
+    if (lds) {
+        if (dim != 2) return hipErrorInvalidValue;
+        return vr ? launch_walk_t<R, 2, true, COUNT, true>(kp, grid, block, smem, s)
+                  : launch_walk_t<R, 2, false, COUNT, true>(kp, grid, block, smem, s);
+    }
     if (vr) {
         switch (dim) {
-            case 2: return launch_walk_t<R, 2, true>(kp, grid, block, s);
-            case 3: return launch_walk_t<R, 3, true>(kp, grid, block, s);
+            case 2: return launch_walk_t<R, 2, true, COUNT, false>(kp, grid, block, 0, s);
+            case 3: return launch_walk_t<R, 3, true, COUNT, false>(kp, grid, block, 0, s);
             default: return hipErrorInvalidValue;
         }
     }
     switch (dim) {
-        case 2: return launch_walk_t<R, 2, false>(kp, grid, block, s);
-        case 3: return launch_walk_t<R, 3, false>(kp, grid, block, s);
-        case 4: return launch_walk_t<R, 4, false>(kp, grid, block, s);
-        case 5: return launch_walk_t<R, 5, false>(kp, grid, block, s);
-        case 6: return launch_walk_t<R, 6, false>(kp, grid, block, s);
-        case 7: return launch_walk_t<R, 7, false>(kp, grid, block, s);
-        case 8: return launch_walk_t<R, 8, false>(kp, grid, block, s);
+        case 2: return launch_walk_t<R, 2, false, COUNT, false>(kp, grid, block, 0, s);
+        case 3: return launch_walk_t<R, 3, false, COUNT, false>(kp, grid, block, 0, s);
+        case 4: return launch_walk_t<R, 4, false, COUNT, false>(kp, grid, block, 0, s);
+        case 5: return launch_walk_t<R, 5, false, COUNT, false>(kp, grid, block, 0, s);
+        case 6: return launch_walk_t<R, 6, false, COUNT, false>(kp, grid, block, 0, s);
+        case 7: return launch_walk_t<R, 7, false, COUNT, false>(kp, grid, block, 0, s);
+        case 8: return launch_walk_t<R, 8, false, COUNT, false>(kp, grid, block, 0, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_walk(const KParams& kp, int dim, bool vr, bool fp32, dim3 grid, dim3 block, hipStream_t s) {
-    return fp32 ? launch_walk_r<float>(kp, dim, vr, grid, block, s) : launch_walk_r<double>(kp, dim, vr, grid, block, s);
+hipError_t launch_walk(const KParams& kp, int dim, bool vr, bool fp32, unsigned lds_bytes, dim3 grid, dim3 block,
+                       hipStream_t s) {
+    const bool lds = lds_bytes > 0 && dim == 2;
+    if (kp.counters) {
+        return fp32 ? launch_walk_c<float, true>(kp, dim, vr, lds, grid, block, lds_bytes, s)
+                    : launch_walk_c<double, true>(kp, dim, vr, lds, grid, block, lds_bytes, s);
+    }
+    return fp32 ? launch_walk_c<float, false>(kp, dim, vr, lds, grid, block, lds_bytes, s)
+                : launch_walk_c<double, false>(kp, dim, vr, lds, grid, block, lds_bytes, s);
 }
 
 hipError_t launch_reduce(const RParams& rp, hipStream_t s) {

@@ -39,7 +39,9 @@ struct RParams {
     double *mean, *se, *grad, *grad_se;
 };
 
-hipError_t launch_walk(const KParams& kp, int dim, bool vr, bool fp32, dim3 grid, dim3 block, hipStream_t s);
+// lds_bytes > 0 (dimension 2): polyline tables are staged in LDS; block must then be 512 threads
+hipError_t launch_walk(const KParams& kp, int dim, bool vr, bool fp32, unsigned lds_bytes, dim3 grid, dim3 block,
+                       hipStream_t s);
 hipError_t launch_reduce(const RParams& rp, hipStream_t s);
 
 }  // namespace woi

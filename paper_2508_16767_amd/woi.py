@@ -20,7 +20,8 @@ MAX_DIM, MAX_REGIONS, MAX_M, N_COUNTERS = 8, 32, 32, 8
 PLAIN, VR = 0, 1
 FP64, FP32 = 0, 1
 SCHED_PER_GROUP, SCHED_SHARED = 0, 1
-COUNTER_NAMES = ("walker_steps", "redraws", "rejections", "cap_hits", "zero_distance")
+COUNTER_NAMES = ("walker_steps", "redraws", "rejections", "cap_hits", "zero_distance", "node_tests",
+                 "segment_tests", "other_transitions")
 
 
 class WoiError(RuntimeError):
@@ -57,7 +58,7 @@ class Query(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("walks", C.c_uint64), ("walk_offset", C.c_uint64), ("M", C.c_int),
                 ("estimator", C.c_int), ("precision", C.c_int), ("schedule_mode", C.c_int),
                 ("batch_share", C.c_int), ("instance", C.c_uint32), ("samples_per_thread", C.c_int),
-                ("block_size", C.c_int)]
+                ("block_size", C.c_int), ("event_begin", C.c_void_p), ("event_end", C.c_void_p)]
 
 
 class _BatchItem(C.Structure):
@@ -178,9 +179,11 @@ class Problem:
 
 
 def make_query(walks, M, seed=0, estimator=PLAIN, precision=FP64, schedule_mode=SCHED_PER_GROUP,
-               batch_share=1, walk_offset=0, instance=0, samples_per_thread=0, block_size=0):
+               batch_share=1, walk_offset=0, instance=0, samples_per_thread=0, block_size=0, events=None):
+    ev = events if events is not None else (None, None)
     return Query(int(seed), int(walks), int(walk_offset), int(M), int(estimator), int(precision),
-                 int(schedule_mode), int(batch_share), int(instance), int(samples_per_thread), int(block_size))
+                 int(schedule_mode), int(batch_share), int(instance), int(samples_per_thread), int(block_size),
+                 ev[0], ev[1])
 
 
 def _stream():
@@ -202,12 +205,13 @@ def workspace_size(problem, P, q):
 
 def estimate(problem, points, walks, M, seed=0, estimator=PLAIN, precision=FP64, schedule_mode=SCHED_PER_GROUP,
              batch_share=1, walk_offset=0, instance=0, samples_per_thread=0, block_size=0, counters=None,
-             out=None, workspace=None):
-    """Per-point mean, SE, gradient, gradient SE as CUDA float64 tensors (asynchronous)."""
+             out=None, workspace=None, events=None):
+    """Per-point mean, SE, gradient, gradient SE as CUDA float64 tensors (asynchronous).
+    events: optional (hipEvent_t, hipEvent_t) handles recorded around the walk kernel."""
     x = _points(points, problem.dim)
     P = x.shape[0]
     q = make_query(walks, M, seed, estimator, precision, schedule_mode, batch_share, walk_offset, instance,
-                   samples_per_thread, block_size)
+                   samples_per_thread, block_size, events)
     if out is None:
         out = (torch.empty(P, dtype=torch.float64, device=x.device), torch.empty(P, dtype=torch.float64, device=x.device),
                torch.empty(P, problem.dim, dtype=torch.float64, device=x.device),
