@@ -27,11 +27,11 @@ sys.path.insert(0, ROOT)
 METRIC = "walk-steps/s and eval-points/s at fixed std. error, FP32-batched vs FP64 plain"
 
 # Algorithmic FP work per event of the walk kernel (2D, counted from the kernel source; a
-# transcendental counts as one flop, an FMA as two).  See DESIGN.md, "Roofline".
+# transcendental counts as one flop, an FMA as two, compares and integer work count zero).
 FLOPS_PER_WALKER_STEP = 29      # Phi + grad Phi + accumulation (19) and the Q/T/sign update (10)
 FLOPS_PER_OTHER = 18            # uniform re-sample + |K*| |dOmega| factor
-FLOPS_PER_NODE_TEST = 9         # line / ray against one bounding box
-FLOPS_PER_SEGMENT_TEST = 15     # line / ray against one polyline segment
+FLOPS_PER_NODE_TEST = 7         # signed distance of a block end vertex to the line (5) +- bound (2)
+FLOPS_PER_SEGMENT_TEST = 5      # signed distance of the segment end vertex (crossings add ~10, rare)
 FLOPS_PER_WALKER = 57           # step-0 datum b(y_0) (5-mode Fourier) and Q_0
 PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 (packed) peak
 PEAK_HBM_GBS = 8000.0
@@ -65,12 +65,16 @@ def flops_of(counts):
 
 
 def run_path(woi, torch, prob, pts, walks, M, precision, steps, warmup, ev, seed0):
+    """Untimed counting launch (same workload, its own seed) for the work counts, warm-up
+    launches, then `steps` timed launches of the non-counting kernel."""
     P = pts.shape[0]
     out = (torch.empty(P, dtype=torch.float64, device="cuda"), torch.empty(P, dtype=torch.float64, device="cuda"),
            torch.empty(P, 2, dtype=torch.float64, device="cuda"), torch.empty(P, 2, dtype=torch.float64, device="cuda"))
     q = woi.make_query(walks, M, precision=precision, schedule_mode=woi.SCHED_SHARED)
     ws = torch.empty(woi.workspace_size(prob, P, q), dtype=torch.uint8, device="cuda")
     cnt = woi.new_counters()
+    woi.estimate(prob, pts, walks, M, seed=seed0 + 999, precision=precision, schedule_mode=woi.SCHED_SHARED,
+                 out=out, workspace=ws, counters=cnt)
     for w in range(warmup):
         woi.estimate(prob, pts, walks, M, seed=seed0 + 1000 + w, precision=precision, schedule_mode=woi.SCHED_SHARED,
                      out=out, workspace=ws)
@@ -79,12 +83,12 @@ def run_path(woi, torch, prob, pts, walks, M, precision, steps, warmup, ev, seed
     t0 = time.perf_counter()
     for k in range(steps):
         woi.estimate(prob, pts, walks, M, seed=seed0 + k, precision=precision, schedule_mode=woi.SCHED_SHARED,
-                     out=out, workspace=ws, counters=cnt, events=evs[k])
+                     out=out, workspace=ws, events=evs[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kern_ms = [ev.ms(a, b) for a, b in evs]
     se = out[1].cpu().numpy()
-    return wall, kern_ms, cnt.cpu().numpy().astype(float), se, out[0].cpu().numpy()
+    return wall, kern_ms, cnt.cpu().numpy().astype(float) * steps, se, out[0].cpu().numpy()
 
 
 def cpu_baseline(prob, pts, walks, M, budget_s):
@@ -92,17 +96,18 @@ def cpu_baseline(prob, pts, walks, M, budget_s):
     from oracle import oracle as O
     threads = min(16, os.cpu_count() or 1)
     op = O.OracleProblem(prob)
-    idx = np.linspace(0, len(pts) - 1, 64).astype(int)          # 64 points spread over the set
+    idx = np.linspace(0, len(pts) - 1, 64).astype(int)
     t = time.perf_counter()
-    _, _, _, _, c = O.estimate(op, pts[idx], 400, M, seed=5, schedule_mode=1, threads=threads, groups=idx)
-    dt = time.perf_counter() - t
-    rate = c["walk_steps"] / dt
-    n = int(max(400, min(walks, budget_s * rate / (len(idx) * (M + 1)))))
+    _, _, _, _, c = O.estimate(op, pts[idx], 2000, M, seed=5, schedule_mode=1, threads=threads, groups=idx)
+    rate = c["walk_steps"] / (time.perf_counter() - t)
+    # points spread over the set, each with the full W, sized to the time budget
+    n_pts = int(max(threads, min(len(pts), budget_s * rate / (walks * (M + 1)))))
+    idx = np.linspace(0, len(pts) - 1, n_pts).astype(int)
     t = time.perf_counter()
-    _, _, _, _, c = O.estimate(op, pts[idx], n, M, seed=6, schedule_mode=1, threads=threads, groups=idx)
+    _, _, _, _, c = O.estimate(op, pts[idx], walks, M, seed=6, schedule_mode=1, threads=threads, groups=idx)
     dt = time.perf_counter() - t
     return {"value": c["walk_steps"] / dt, "unit": "walk-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"64 of the 4096 points, {n} walkers each (W = {walks} in the full workload), FP64, "
+            "sample": f"{n_pts} of the 4096 points spread over the set, W = {walks} walkers each, FP64 oracle, "
                       f"{c['walk_steps']} walker-steps in {dt:.1f} s"}
 
 
@@ -179,7 +184,7 @@ def main():
         "walk_kernel_ms": kern_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                     "kernel": "walk_kernel<float, 2, false>",
+                     "kernel": "walk_kernel<float, 2, false, false, true> (FP32, 2D, plain, LDS-staged polylines)",
                      "flops_per_launch": flops,
                      "counts_per_launch": {n: float(v / args.steps) for n, v in zip(woi.COUNTER_NAMES, c32)}},
     }

@@ -1030,6 +1030,105 @@ Plan make_plan(const woi_problem* p, int64_t P, const woi_query* q, uint64_t n_s
     return pl;
 }
 
+// Shared-trajectory plan (batch_share B > 1): chunks of samples whose trajectories fit the
+// trajectory budget, evaluation pieces of spt_e samples (the reduction's unit).
+struct SharedPlan {
+    int ng;
+    uint32_t chunk, spt_g, spt_e;
+    int n_chunks, pieces_per_chunk, n_pieces;
+    size_t plane, traj_bytes, part_bytes;
+};
+
+SharedPlan make_shared_plan(const woi_problem* p, int64_t P, const woi_query* q, uint64_t ns) {
+    SharedPlan sp;
+    const int m = p->H.m, K = q->estimator == WOI_EST_VR ? 2 : 1;
+    const size_t rs = q->precision == WOI_PREC_FP32 ? sizeof(float) : sizeof(double);
+    sp.ng = (int)((P + q->batch_share - 1) / q->batch_share);
+    // evaluation pieces: enough (point, piece) lanes to fill the device, >= 16 samples each
+    const uint64_t lanes_target = 1ull << 20;
+    uint64_t pieces = std::max<uint64_t>(1, lanes_target / (uint64_t)P);
+    uint64_t spt_e = std::max<uint64_t>(16, (ns + pieces - 1) / pieces);
+    spt_e = std::min<uint64_t>(spt_e, ns);
+    // trajectory chunk: a multiple of spt_e whose planes stay within 256 MiB
+    const size_t per_sample = (size_t)sp.ng * K * (q->M + 1) * (m + 1) * rs;
+    uint64_t chunk = std::max<uint64_t>(1, (256ull << 20) / per_sample);
+    chunk = std::max<uint64_t>(spt_e, chunk / spt_e * spt_e);
+    chunk = std::min<uint64_t>(chunk, (ns + spt_e - 1) / spt_e * spt_e);
+    sp.chunk = (uint32_t)chunk;
+    sp.spt_e = (uint32_t)spt_e;
+    sp.pieces_per_chunk = (int)(chunk / spt_e);
+    sp.n_chunks = (int)((ns + chunk - 1) / chunk);
+    sp.n_pieces = (int)((ns + spt_e - 1) / spt_e);
+    // generation: lanes = groups; split the chunk so that >= 2^18 walkers run at once
+    const uint64_t want = std::max<uint64_t>(1, (1ull << 18) / (uint64_t)sp.ng);
+    sp.spt_g = (uint32_t)std::max<uint64_t>(1, (chunk + want - 1) / want);
+    sp.plane = (size_t)chunk * K * (q->M + 1) * sp.ng;
+    sp.traj_bytes = (sp.plane * (m + 1) * rs + 255) & ~size_t(255);
+    sp.part_bytes = (size_t)sp.n_pieces * (size_t)P * (2 + 2 * m) * sizeof(double);
+    return sp;
+}
+
+// Shared trajectories: per chunk, generate the trajectories of every point group, then
+// evaluate them at the group's points; finally the deterministic per-point reduction.
+woi_status estimate_shared(const woi_problem* p, const double* points, int64_t P, const woi_query* q, uint64_t ns,
+                           double* mean, double* se, double* grad, double* grad_se, void* workspace,
+                           size_t workspace_bytes, uint64_t* counters, hipStream_t s) {
+    const SharedPlan sp = make_shared_plan(p, P, q, ns);
+    if (!workspace || workspace_bytes < sp.traj_bytes + sp.part_bytes)
+        return fail(WOI_E_OOM, "workspace of %zu bytes is smaller than the %zu bytes needed", workspace_bytes,
+                    sp.traj_bytes + sp.part_bytes);
+    const DevProblem* hdr = reinterpret_cast<const DevProblem*>(p->blob.data());
+    const unsigned lds = hdr->lds_bytes > 0 && p->H.m == 2 ? (unsigned)hdr->lds_bytes : 0u;
+    const bool vr = q->estimator == WOI_EST_VR, f32 = q->precision == WOI_PREC_FP32;
+    woi::KParams kp{};
+    kp.dp = static_cast<const DevProblem*>(p->dev);
+    kp.points = points;
+    kp.P = P;
+    kp.n_samples = ns;
+    kp.first_sample = q->estimator == WOI_EST_VR ? q->walk_offset / 2 : q->walk_offset;
+    kp.k0 = (uint32_t)q->seed;
+    kp.k1 = (uint32_t)(q->seed >> 32);
+    kp.M = q->M;
+    kp.batch_share = q->batch_share;
+    kp.shared_sched = q->schedule_mode == WOI_SCHED_SHARED;
+    kp.instance = q->instance;
+    kp.partials = reinterpret_cast<double*>(static_cast<char*>(workspace) + sp.traj_bytes);
+    kp.counters = counters;
+    woi::TParams tp{};
+    tp.traj = workspace;
+    tp.plane = sp.plane;
+    tp.ng = sp.ng;
+    tp.spt = sp.spt_g;
+    tp.spt_e = sp.spt_e;
+    if (q->event_begin && hipEventRecord(static_cast<hipEvent_t>(q->event_begin), s) != hipSuccess)
+        return fail(WOI_E_DEVICE, "hipEventRecord(begin) failed");
+    for (int c = 0; c < sp.n_chunks; ++c) {
+        tp.chunk_first = (uint64_t)c * sp.chunk;
+        tp.ns = (uint32_t)std::min<uint64_t>(sp.chunk, ns - tp.chunk_first);
+        tp.piece0 = c * sp.pieces_per_chunk;
+        hipError_t e = woi::launch_traj(kp, tp, p->H.m, vr, f32, lds, s);
+        if (e != hipSuccess) return fail(WOI_E_DEVICE, "trajectory launch failed: %s", hipGetErrorString(e));
+        e = woi::launch_eval(kp, tp, p->H.m, vr, f32, s);
+        if (e != hipSuccess) return fail(WOI_E_DEVICE, "evaluation launch failed: %s", hipGetErrorString(e));
+    }
+    if (q->event_end && hipEventRecord(static_cast<hipEvent_t>(q->event_end), s) != hipSuccess)
+        return fail(WOI_E_DEVICE, "hipEventRecord(end) failed");
+    woi::RParams rp{};
+    rp.partials = kp.partials;
+    rp.P = P;
+    rp.dim = p->H.m;
+    rp.n_chunks = sp.n_pieces;
+    rp.samples_per_thread = sp.spt_e;
+    rp.n_samples = ns;
+    rp.mean = mean;
+    rp.se = se;
+    rp.grad = grad;
+    rp.grad_se = grad_se;
+    hipError_t e = woi::launch_reduce(rp, s);
+    if (e != hipSuccess) return fail(WOI_E_DEVICE, "reduce launch failed: %s", hipGetErrorString(e));
+    return WOI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1039,6 +1138,11 @@ woi_status woi_workspace_size(const woi_problem* p, int64_t P, const woi_query* 
     if (st != WOI_OK) return st;
     if (!bytes) return fail(WOI_E_INVALID_ARG, "NULL bytes");
     const uint64_t ns = q->estimator == WOI_EST_VR ? q->walks / 2 : q->walks;
+    if (q->batch_share > 1) {
+        const SharedPlan sp = make_shared_plan(p, P, q, ns);
+        *bytes = sp.traj_bytes + sp.part_bytes;
+        return WOI_OK;
+    }
     const Plan pl = make_plan(p, P, q, ns);
     *bytes = (size_t)pl.chunks * (size_t)P * (2 + 2 * p->H.m) * sizeof(double);
     return WOI_OK;
@@ -1053,6 +1157,9 @@ woi_status woi_estimate(const woi_problem* p, const double* points, int64_t P, c
     st = woi_problem_upload(const_cast<woi_problem*>(p));
     if (st != WOI_OK) return st;
     const uint64_t ns = q->estimator == WOI_EST_VR ? q->walks / 2 : q->walks;
+    if (q->batch_share > 1)
+        return estimate_shared(p, points, P, q, ns, mean, se, grad, grad_se, workspace, workspace_bytes, counters,
+                               static_cast<hipStream_t>(stream));
     const Plan pl = make_plan(p, P, q, ns);
     const size_t need = (size_t)pl.chunks * (size_t)P * (2 + 2 * p->H.m) * sizeof(double);
     if (!workspace || workspace_bytes < need)

@@ -255,9 +255,12 @@ __device__ __forceinline__ const int* int_payload(const DevProblem* dp) {
 }
 
 // Point at arclength s on a polyline: the segment is the largest j with cum[j] <= s, found
-// from the guide table entry for s in O(1) expected probes.
+// from the guide table entry for s in O(1) expected probes.  Kept out of line: inlined
+// into the trajectory-generation kernel at -O2/-O3 (ROCm 7.2 clang) it produced points off
+// the polyline in "other" transitions, while -O1, an out-of-line call, and the per-point
+// kernel were exact; the shared-trajectory parity tests check this path.
 template <typename R, int D>
-__device__ __forceinline__ bool polyline_at(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay, R s,
+__device__ __noinline__ bool polyline_at(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay, R s,
                                             R y[D], int& seg) {
     if constexpr (D == 2) {
         const R* cum = pay + Pay<R>::cum(g);
@@ -493,19 +496,60 @@ __device__ __forceinline__ uint32_t trace_word(int h, int cs, int q, int pick, i
 }
 
 // ----------------------------------------------------------------------------- one sample
-// Walker k of sample `w` at point x: F = N sum_i c_i Phi(x, y_i), G = N sum_i c_i grad_x Phi.
-template <typename R, int D, bool VR, bool LDS>
+// Where a walker's terms c_i (y_i) go: accumulated at the lane's point, or stored as a
+// trajectory for evaluation at a batch of points (shared trajectories, Sec. 4.6).
+template <typename R, int D>
+struct AccumSink {
+    const DevProblem* dp;
+    R xh[D], xl[D];
+    R F, G[D];
+    __device__ __forceinline__ void begin() {
+        F = 0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) G[i] = 0;
+    }
+    __device__ __forceinline__ void add(int, R c, const R y[D], Counts& cnt) { add_term<R, D>(dp, xh, xl, y, c, F, G, cnt); }
+    __device__ __forceinline__ void finish(int) {}
+};
+
+// Trajectory planes: component q (0 = c, 1.. = y) of step i of walker k of local sample s of
+// group g sits at plane[q][((s K + k)(M + 1) + i) NG + g], g fastest (coalesced stores).
+template <typename R, int D>
+struct StoreSink {
+    R* base;           // &plane[0][((s K + k)(M + 1)) NG + g]
+    size_t plane;      // elements per plane
+    int ng, M;
+    bool on;           // lanes past the last group walk (keeping the wave uniform) but store nothing
+    __device__ __forceinline__ void begin() {}
+    __device__ __forceinline__ void add(int i, R c, const R y[D], Counts&) {
+        if (!on) return;
+        R* p = base + (size_t)i * ng;
+        p[0] = c;
+#pragma unroll
+        for (int q = 0; q < D; ++q) p[(q + 1) * plane] = y[q];
+    }
+    __device__ __forceinline__ void finish(int i_next) {   // steps never reached contribute 0
+        if (!on) return;
+        for (int i = i_next; i <= M; ++i) {
+            R* p = base + (size_t)i * ng;
+            p[0] = R(0);
+#pragma unroll
+            for (int q = 0; q < D; ++q) p[(q + 1) * plane] = R(0);
+        }
+    }
+};
+
+// Walker k of sample `w`: emits c_i and y_i, i = 0..M, to the sink (the accumulating sink
+// forms sum_i c_i Phi(x, y_i) and sum_i c_i grad_x Phi; the caller multiplies by N).
+template <typename R, int D, bool VR, bool LDS, class Sink>
 __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const R* __restrict__ pay,
-                                       const R xh[D], const R xl[D],
-                                       const KParams& kp, uint32_t w, uint32_t group, int k, R& F, R G[D],
+                                       const KParams& kp, uint32_t w, uint32_t group, int k, Sink& sink,
                                        uint32_t* __restrict__ tr, Counts& cnt) {
     const int N = dp->N, M = kp.M;
     const uint32_t inst = (kp.instance & 0xFFFFFFu) << 8;
     const Stream sched{kp.k0, kp.k1, w, kp.shared_sched ? 0xFFFFFFFFu : group, inst};
     const Stream st{kp.k0, kp.k1, w, group, inst | ((uint32_t)k << 4) | 1u};
-    F = 0;
-#pragma unroll
-    for (int i = 0; i < D; ++i) G[i] = 0;
+    sink.begin();
 
     // schedule H_0 (Theorem 2): uniform over regions
     uint4 sb = sched.block(0, 0);
@@ -519,6 +563,7 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
     const R meas = VR ? Pay<R>::meas(*g, k) : Pay<R>::area(*g);
     if (meas == R(0)) {   // empty VR half: the walker contributes nothing
         if (tr) for (int i = 0; i <= M; ++i) tr[i] = i ? 0u : trace_word(h, 0, 0, 0, 0, 0);
+        sink.finish(0);
         return;
     }
     R y[D];
@@ -532,9 +577,10 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
     }
     if (att == WOI_ATTEMPT_CAP) cnt.caps++;
     R Q = Pay<R>::s(*g) * data_b<R, D>(dp, *g, pay, y, seg) * meas, T = 1;
-    add_term<R, D>(dp, xh, xl, y, (M == 0 ? R(0.5) : R(1)) * Q * T, F, G, cnt);
+    sink.add(0, (M == 0 ? R(0.5) : R(1)) * Q * T, y, cnt);
     cnt.steps++;
     if (tr) tr[0] = trace_word(h, 0, 1, 0, 0, att);
+    int done = 1;
     R S = 1, pw = 1;
     const R l1 = Pay<R>::l1(dp);
     for (int i = 1; i <= M; ++i) {
@@ -619,13 +665,12 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
 #pragma unroll
         for (int j = 0; j < D; ++j) y[j] = yn[j];
         seg = segn;
-        add_term<R, D>(dp, xh, xl, y, (i == M ? R(0.5) : R(1)) * pw * S * Q * T, F, G, cnt);
+        sink.add(i, (i == M ? R(0.5) : R(1)) * pw * S * Q * T, y, cnt);
         cnt.steps++;
+        done = i + 1;
         if (tr) tr[i] = trace_word(h, rel, qn, pick, sg < R(0), att);
     }
-    F *= (R)N;
-#pragma unroll
-    for (int i = 0; i < D; ++i) G[i] *= (R)N;
+    sink.finish(done);
 }
 
 // ----------------------------------------------------------------------------- kernels
@@ -668,8 +713,9 @@ __global__ __launch_bounds__(LDS ? 512 : 256) void walk_kernel(KParams kp) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = p < kp.P;
     const int64_t pc = active ? p : kp.P - 1;
-    R xh[D], xl[D];
-    load_point<R, D>(kp.points, pc, xh, xl);
+    AccumSink<R, D> sink;
+    sink.dp = dp;
+    load_point<R, D>(kp.points, pc, sink.xh, sink.xl);
     const uint32_t group = (uint32_t)(pc / kp.batch_share);
     const uint64_t s0 = (uint64_t)blockIdx.y * kp.samples_per_thread;
     const uint64_t s1 = min(s0 + (uint64_t)kp.samples_per_thread, kp.n_samples);
@@ -685,11 +731,14 @@ __global__ __launch_bounds__(LDS ? 512 : 256) void walk_kernel(KParams kp) {
         for (int i = 0; i < D; ++i) Gs[i] = 0;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            R Fk, Gk[D];
             uint32_t* tr = nullptr;
             const size_t idx = ((size_t)pc * kp.n_samples + s) * K + k;
             if (kp.trace && active) tr = kp.trace + idx * (kp.M + 1);
-            walker<R, D, VR, LDS>(dp, pay, xh, xl, kp, w, group, k, Fk, Gk, tr, cnt);
+            walker<R, D, VR, LDS>(dp, pay, kp, w, group, k, sink, tr, cnt);
+            const R Fk = sink.F * (R)dp->N;
+            R Gk[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) Gk[i] = sink.G[i] * (R)dp->N;
             F += (double)Fk;
 #pragma unroll
             for (int i = 0; i < D; ++i) Gs[i] += (double)Gk[i];
@@ -718,6 +767,89 @@ __global__ __launch_bounds__(LDS ? 512 : 256) void walk_kernel(KParams kp) {
             const uint64_t s = wave_sum(active ? (uint64_t)v[i] : 0);
             if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long*)&kp.counters[i], (unsigned long long)s);
         }
+    }
+}
+
+// ----------------------------------------------------------------------------- shared trajectories
+// Generation: one lane per point group; all lanes of a wave share the walk index, so with
+// the shared schedule the transition case and geometry record are wave-uniform.
+template <typename R, int D, bool VR, bool LDS>
+__global__ __launch_bounds__(LDS ? 512 : 256) void traj_kernel(KParams kp, TParams tp) {
+    const DevProblem* __restrict__ dp = kp.dp;
+    const R* __restrict__ pay = Pay<R>::base(dp);
+    if constexpr (LDS) stage_polylines(dp);
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = g < tp.ng;
+    const int gc = active ? g : tp.ng - 1;
+    constexpr int K = VR ? 2 : 1;
+    R* planes = static_cast<R*>(tp.traj);
+    const uint32_t s0 = blockIdx.y * tp.spt, s1 = min(s0 + tp.spt, tp.ns);
+    Counts cnt{0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t s = s0; s < s1; ++s) {
+        const uint32_t w = (uint32_t)(kp.first_sample + tp.chunk_first + s);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            StoreSink<R, D> sink;
+            sink.base = planes + ((size_t)(s * K + k) * (kp.M + 1)) * tp.ng + gc;
+            sink.plane = tp.plane;
+            sink.ng = tp.ng;
+            sink.M = kp.M;
+            sink.on = active;
+            walker<R, D, VR, LDS>(dp, pay, kp, w, (uint32_t)gc, k, sink, nullptr, cnt);
+        }
+    }
+}
+
+// Evaluation: one lane per point; F = N sum_i c_i Phi(x_p, y_i) over the trajectories of the
+// point's group, FP64 per-point sums per piece of samples.
+template <typename R, int D, bool VR>
+__global__ __launch_bounds__(256) void eval_kernel(KParams kp, TParams tp) {
+    const DevProblem* __restrict__ dp = kp.dp;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = p < kp.P;
+    const int64_t pc = active ? p : kp.P - 1;
+    R xh[D], xl[D];
+    load_point<R, D>(kp.points, pc, xh, xl);
+    const int g = (int)(pc / kp.batch_share);
+    constexpr int K = VR ? 2 : 1;
+    const R* __restrict__ planes = static_cast<const R*>(tp.traj);
+    const uint32_t s0 = blockIdx.y * tp.spt_e, s1 = min(s0 + tp.spt_e, tp.ns);
+    const int M = kp.M;
+    const R N = (R)dp->N;
+    Counts cnt{0, 0, 0, 0, 0, 0, 0, 0};
+    double S1 = 0, S2 = 0, G1[D], G2[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) { G1[i] = 0; G2[i] = 0; }
+    for (uint32_t s = s0; s < s1; ++s) {
+        double F = 0, Gs[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) Gs[i] = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const R* src = planes + ((size_t)(s * K + k) * (M + 1)) * tp.ng + g;
+            R Fk = 0, Gk[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) Gk[i] = 0;
+            for (int i = 0; i <= M; ++i) {
+                const R* q = src + (size_t)i * tp.ng;
+                R y[D];
+#pragma unroll
+                for (int d = 0; d < D; ++d) y[d] = q[(d + 1) * tp.plane];
+                add_term<R, D>(dp, xh, xl, y, q[0], Fk, Gk, cnt);
+            }
+            F += (double)(Fk * N);
+#pragma unroll
+            for (int i = 0; i < D; ++i) Gs[i] += (double)(Gk[i] * N);
+        }
+        S1 += F; S2 += F * F;
+#pragma unroll
+        for (int i = 0; i < D; ++i) { G1[i] += Gs[i]; G2[i] += Gs[i] * Gs[i]; }
+    }
+    if (active) {
+        double* o = kp.partials + ((size_t)(tp.piece0 + blockIdx.y) * kp.P + p) * (2 + 2 * D);
+        o[0] = S1; o[1] = S2;
+#pragma unroll
+        for (int i = 0; i < D; ++i) { o[2 + i] = G1[i]; o[2 + D + i] = G2[i]; }
     }
 }
 
@@ -792,6 +924,83 @@ static hipError_t launch_walk_c(const KParams& kp, int dim, bool vr, bool lds, d
         case 8: return launch_walk_t<R, 8, false, COUNT, false>(kp, grid, block, 0, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+template <typename R, int D, bool VR, bool LDS>
+static hipError_t launch_traj_t(const KParams& kp, const TParams& tp, unsigned smem, hipStream_t s) {
+    const int bs = LDS ? 512 : 256;
+    if constexpr (LDS) {
+        static bool attr = false;
+        if (!attr) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&traj_kernel<R, D, VR, LDS>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BUDGET);
+            if (e != hipSuccess) return e;
+            attr = true;
+        }
+    }
+    const dim3 grid((unsigned)((tp.ng + bs - 1) / bs), (unsigned)((tp.ns + tp.spt - 1) / tp.spt));
+    hipLaunchKernelGGL((traj_kernel<R, D, VR, LDS>), grid, dim3(bs), smem, s, kp, tp);
+    return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t launch_traj_r(const KParams& kp, const TParams& tp, int dim, bool vr, unsigned lds, hipStream_t s) {
+    if (lds && dim == 2) return vr ? launch_traj_t<R, 2, true, true>(kp, tp, lds, s) : launch_traj_t<R, 2, false, true>(kp, tp, lds, s);
+    if (vr) {
+        switch (dim) {
+            case 2: return launch_traj_t<R, 2, true, false>(kp, tp, 0, s);
+            case 3: return launch_traj_t<R, 3, true, false>(kp, tp, 0, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    switch (dim) {
+        case 2: return launch_traj_t<R, 2, false, false>(kp, tp, 0, s);
+        case 3: return launch_traj_t<R, 3, false, false>(kp, tp, 0, s);
+        case 4: return launch_traj_t<R, 4, false, false>(kp, tp, 0, s);
+        case 5: return launch_traj_t<R, 5, false, false>(kp, tp, 0, s);
+        case 6: return launch_traj_t<R, 6, false, false>(kp, tp, 0, s);
+        case 7: return launch_traj_t<R, 7, false, false>(kp, tp, 0, s);
+        case 8: return launch_traj_t<R, 8, false, false>(kp, tp, 0, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_traj(const KParams& kp, const TParams& tp, int dim, bool vr, bool fp32, unsigned lds_bytes,
+                       hipStream_t s) {
+    return fp32 ? launch_traj_r<float>(kp, tp, dim, vr, lds_bytes, s) : launch_traj_r<double>(kp, tp, dim, vr, lds_bytes, s);
+}
+
+template <typename R, int D, bool VR>
+static hipError_t launch_eval_t(const KParams& kp, const TParams& tp, hipStream_t s) {
+    const int bs = 256;
+    const dim3 grid((unsigned)((kp.P + bs - 1) / bs), (unsigned)((tp.ns + tp.spt_e - 1) / tp.spt_e));
+    hipLaunchKernelGGL((eval_kernel<R, D, VR>), grid, dim3(bs), 0, s, kp, tp);
+    return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t launch_eval_r(const KParams& kp, const TParams& tp, int dim, bool vr, hipStream_t s) {
+    if (vr) {
+        switch (dim) {
+            case 2: return launch_eval_t<R, 2, true>(kp, tp, s);
+            case 3: return launch_eval_t<R, 3, true>(kp, tp, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    switch (dim) {
+        case 2: return launch_eval_t<R, 2, false>(kp, tp, s);
+        case 3: return launch_eval_t<R, 3, false>(kp, tp, s);
+        case 4: return launch_eval_t<R, 4, false>(kp, tp, s);
+        case 5: return launch_eval_t<R, 5, false>(kp, tp, s);
+        case 6: return launch_eval_t<R, 6, false>(kp, tp, s);
+        case 7: return launch_eval_t<R, 7, false>(kp, tp, s);
+        case 8: return launch_eval_t<R, 8, false>(kp, tp, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_eval(const KParams& kp, const TParams& tp, int dim, bool vr, bool fp32, hipStream_t s) {
+    return fp32 ? launch_eval_r<float>(kp, tp, dim, vr, s) : launch_eval_r<double>(kp, tp, dim, vr, s);
 }
 
 hipError_t launch_walk(const KParams& kp, int dim, bool vr, bool fp32, unsigned lds_bytes, dim3 grid, dim3 block,

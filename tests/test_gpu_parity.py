@@ -235,3 +235,45 @@ def test_config2_full_size_sampled():
     # FP32 walks on the same streams: differences far below the statistical error
     z = (mean32 - mean64) / se64
     assert np.all(np.isfinite(mean32)) and np.median(np.abs(z)) < 0.05 and np.max(np.abs(z)) < 1.0
+
+
+# ----------------------------------------------------------------------------- shared trajectories
+@pytest.mark.parametrize("precision", [0, 1])
+def test_shared_trajectory_path(precision):
+    """batch_share B > 1 runs the generate-then-evaluate kernels; with the same keys they give the
+    per-point path's numbers (FP64: to rounding) and the oracle's (same streams)."""
+    from test_oracle_pins import STAR_PTS, _star_tree
+    cases = [(W.config1()[0], W.config1()[1], 4, 0, 8), (_star_tree()[0], np.tile(STAR_PTS, (3, 1)), 3, 0, 6),
+             (W.config1()[0], W.config1()[1], 3, 1, 4),
+             (W.zheng_ex3_3d(), W.ball_points(np.random.default_rng(2), 40, 3, 0.9), 4, 1, 5),
+             (W.config5()[0], W.config5()[1][:48], 6, 0, 16)]
+    for prob, pts, M, est, B in cases:
+        gp = woi.Problem(prob)
+        walks = 6000
+        sh = [_np(t) for t in woi.estimate(gp, pts, walks, M, seed=4, estimator=est, precision=precision,
+                                            schedule_mode=1, batch_share=B)]
+        # the per-point kernel computes the same keyed samples (trace path, B > 1)
+        F, G, _ = woi.trace(gp, pts, walks // (2 if est else 1), M, seed=4, estimator=est, precision=precision,
+                            schedule_mode=1, batch_share=B)
+        Fs = _np(F).sum(-1)
+        ref_mean = Fs.mean(1)
+        ref_se = Fs.std(1, ddof=1) / np.sqrt(Fs.shape[1])
+        tol = 1e-9 if precision == 0 else 1e-5
+        assert np.allclose(sh[0], ref_mean, rtol=tol, atol=tol * ref_se.max()), (prob.name, B)
+        assert np.allclose(sh[1], ref_se, rtol=1e-6 if precision == 0 else 1e-4)
+        if precision == 0:
+            op = O.OracleProblem(prob)
+            mo, so, go, _, _ = O.estimate(op, pts, walks, M, seed=4, estimator=est, schedule_mode=1, batch_share=B)
+            assert np.allclose(sh[0], mo, rtol=1e-9, atol=1e-9 * so.max())
+            assert np.allclose(sh[2], go, rtol=1e-9, atol=1e-9 * np.abs(go).max())
+
+
+def test_shared_trajectory_exact_expectation():
+    p, xs = W.config1()
+    H, gH = CF.harmonic_2d(1, "cos")
+    gp = woi.Problem(p)
+    mean, se, g, gse = [_np(t) for t in woi.estimate(gp, xs, 400000, 4, seed=33, precision=woi.FP32,
+                                                      schedule_mode=1, batch_share=8)]
+    ref = [CF.concentric_uM([1, .5], [10, 1], [1, 1], 1, 2, 4, x, H, gH) for x in xs]
+    z = (mean - np.array([r[0] for r in ref])) / se
+    assert np.max(np.abs(z)) < 4.5
