@@ -35,6 +35,11 @@ FLOPS_PER_SEGMENT_TEST = 5      # signed distance of the segment end vertex (cro
 FLOPS_PER_WALKER = 57           # step-0 datum b(y_0) (5-mode Fourier) and Q_0
 PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 (packed) peak
 PEAK_HBM_GBS = 8000.0
+# HBM bytes per launch of the timed FP32 walk kernel at W = 1e5, from the FETCH_SIZE and
+# WRITE_SIZE passes in profiles/walk_kernel_config2_hbm_counters.md, scaled by what the same
+# counters read for a 1 GiB device copy (factors 2.0 and 1.0).  None whenever the kernel has
+# changed since those passes.
+TRAFFIC_BYTES = 3306 * 1024 * 2.0 + 55432 * 1024 * 1.0
 
 
 class HipEvents:
@@ -120,6 +125,9 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="after the run, copy this many bytes device-to-device three times (a plain copy "
+                         "kernel of known size, to scale the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -183,7 +191,8 @@ def main():
         "speedup_fp32_vs_fp64_fixed_se": t64_eps / t32_eps,
         "walk_kernel_ms": kern_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": TRAFFIC_BYTES if args.walks == 100000 else None,
                      "kernel": "walk_kernel<float, 2, false, false, true> (FP32, 2D, plain, LDS-staged polylines)",
                      "flops_per_launch": flops,
                      "counts_per_launch": {n: float(v / args.steps) for n, v in zip(woi.COUNTER_NAMES, c32)}},
@@ -191,6 +200,12 @@ def main():
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(prob_desc, pts_np, args.walks, M, args.cpu_seconds)
     print(json.dumps(rec), flush=True)
+    if args.copy_bytes:
+        src = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":
