@@ -178,10 +178,21 @@ woi_status woi_estimate(const woi_problem *p, const double *points, int64_t P, c
 woi_status woi_trace(const woi_problem *p, const double *points, int64_t P, const woi_query *q,
                      uint64_t n_samples, double *F, double *G, uint32_t *trace, void *stream);
 
-/* Many independent problem instances in one launch (uneven N, P, W): a persistent kernel
- * pulls (instance, point tile, sample chunk) items from a work-stealing queue.  All
- * instances must share dim, precision and estimator.  Per-item arrays are host arrays
- * of length n; their pointers are device pointers. */
+/* Many independent problem instances in one persistent launch (uneven N, P, W; the
+ * batching of Sec. 4.6 taken across problems).  Every sample is the sample woi_estimate
+ * draws for the same query (same Philox keys), so an instance's results match a
+ * woi_estimate call up to the summation order of the per-point sums.
+ *
+ * Work: items (instance, tile of 64 points, chunk of samples), largest first, pulled by a
+ * grid of resident workgroups from one atomic queue; each item writes its own partial
+ * slots, and the reduction merges them in sample order (deterministic results).
+ *
+ * Requirements: all items share dim, estimator and precision; batch_share = 1; fewer than
+ * 2^32 samples per point; samples_per_thread is ignored; block_size is the same for all
+ * items: 0 (tuned) or 256 / 512 (64 x waves per workgroup).  Per-item arrays are host
+ * arrays of length n; the pointers inside are device pointers.
+ * Events: items[0].query.event_begin / event_end, if set, are recorded on `stream` around
+ * the graph launch. */
 typedef struct {
     const woi_problem *problem;
     const double *points;     /* device [P*dim]                                         */
@@ -190,9 +201,23 @@ typedef struct {
     double *mean, *se, *grad, *grad_se;  /* device; grad/grad_se may be NULL            */
 } woi_batch_item;
 
+/* Device workspace (bytes) woi_estimate_batch needs: 256 bytes of queue head, then the
+ * partial slots of the largest plan the tuner may choose.  Uploads the problems and
+ * queries the current device.  Errors: INVALID_ARG, UNSUPPORTED, DEVICE. */
 woi_status woi_batch_workspace_size(const woi_batch_item *items, int n, size_t *bytes);
-/* Enqueues the whole batch as one captured HIP graph (queue reset, persistent walk
- * kernel, reduction); repeated calls with the same items replay the cached graph. */
+
+/* Enqueue the whole batch on `stream` as one HIP graph: a fill kernel zeroes the queue
+ * head, the persistent walk kernel drains the queue, the reduction writes every item's
+ * mean / se / grad / grad_se.
+ * The first call with a given (items, workspace, counters, device) builds the plan in
+ * library-owned device memory and captures the graph; with block_size 0 it also times the
+ * candidate launch shapes on a scaled-down copy of the batch, which synchronizes `stream`
+ * and the device.  Later calls with identical arguments only launch the cached graph (up
+ * to 8 cached batches per process, least recently used evicted).  A cached graph reads
+ * the current contents of the points and problems; a problem must stay alive while a
+ * batch that uses it can run.  Calls that share a workspace must be ordered on one stream.
+ * counters: NULL or device uint64[WOI_COUNTERS], added to as in woi_estimate.
+ * Errors: INVALID_ARG, UNSUPPORTED, OOM (workspace too small or plan allocation), DEVICE. */
 woi_status woi_estimate_batch(const woi_batch_item *items, int n, void *workspace, size_t workspace_bytes,
                               uint64_t *counters, void *stream);
 

@@ -1,0 +1,212 @@
+// woi_batch.hip -- many Walk-on-Interfaces instances in one persistent launch.
+//
+// The walks are those of the per-point kernel (Alg. 2, Alg. 3 with one schedule per
+// sample, same Philox keys), so every sample of a batched instance equals the sample of
+// a woi_estimate call with the same query.  What differs is the work distribution:
+// uneven instances (N, P, W all vary) are cut into items (instance, 64-point tile,
+// chunk of samples) listed largest-first, and a grid of resident workgroups pulls items
+// from one atomic queue head until the list is exhausted.  Each item's results go to
+// its own partial slots, and the reduction merges them in sample order, so the result
+// does not depend on which workgroup ran which item.
+#include "woi_walk.h"
+
+namespace woi {
+
+template <typename R, int D, bool VR, bool COUNT, int WV, bool LDS>
+__global__ __launch_bounds__(64 * WV) void batch_kernel(BParams bp) {
+    __shared__ uint32_t s_item;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    constexpr int K = VR ? 2 : 1;
+    uint32_t staged = 0xFFFFFFFFu;   // instance whose polylines are in LDS (workgroup-uniform)
+    Counts tot{0, 0, 0, 0, 0, 0, 0, 0};
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(bp.head, 1u);
+        __syncthreads();
+        const uint32_t it = s_item;
+        __syncthreads();             // every wave has read s_item (and left the previous item)
+        if (it >= bp.n_items) break;
+        const BItem item = bp.items[it];
+        const BInst& in = bp.inst[item.inst];
+        const DevProblem* __restrict__ dp = in.dp;
+        const R* __restrict__ pay = Pay<R>::base(dp);
+        if constexpr (LDS) {
+            if (in.lds && item.inst != staged) {
+                stage_polylines(dp);
+                staged = item.inst;
+            }
+        }
+        KParams kp{};
+        kp.dp = dp;
+        kp.k0 = in.k0;
+        kp.k1 = in.k1;
+        kp.M = in.M;
+        kp.batch_share = 1;
+        kp.shared_sched = in.shared_sched;
+        kp.instance = in.instance;
+        // this wave's share of the chunk
+        const uint32_t a = bp.ctab[in.c0 + item.chunk], len = bp.ctab[in.c0 + item.chunk + 1] - a;
+        const uint32_t s0 = a + (uint32_t)(((uint64_t)len * wv) / WV);
+        const uint32_t s1 = a + (uint32_t)(((uint64_t)len * (wv + 1)) / WV);
+        const int64_t p = (int64_t)item.tile * 64 + lane;
+        const bool active = p < in.P;
+        const int64_t pc = active ? p : in.P - 1;
+        AccumSink<R, D> sink;
+        sink.dp = dp;
+        load_point<R, D>(in.points, pc, sink.xh, sink.xl);
+        double S1 = 0, S2 = 0, G1[D], G2[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) { G1[i] = 0; G2[i] = 0; }
+        Counts cnt{0, 0, 0, 0, 0, 0, 0, 0};
+        for (uint32_t s = s0; s < s1; ++s) {
+            const uint32_t w = (uint32_t)(in.first_sample + s);
+            double F = 0, Gs[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) Gs[i] = 0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                walker<R, D, VR, LDS>(dp, pay, kp, w, (uint32_t)pc, k, sink, nullptr, cnt);
+                F += (double)(sink.F * (R)dp->N);
+#pragma unroll
+                for (int i = 0; i < D; ++i) Gs[i] += (double)(sink.G[i] * (R)dp->N);
+            }
+            S1 += F; S2 += F * F;
+#pragma unroll
+            for (int i = 0; i < D; ++i) { G1[i] += Gs[i]; G2[i] += Gs[i] * Gs[i]; }
+        }
+        if (active) {
+            const uint64_t slot = in.slot0 + ((uint64_t)item.tile * in.n_chunks + item.chunk) * WV + wv;
+            double* o = bp.partials + (slot * 64 + lane) * (2 + 2 * D);
+            o[0] = S1; o[1] = S2;
+#pragma unroll
+            for (int i = 0; i < D; ++i) { o[2 + i] = G1[i]; o[2 + D + i] = G2[i]; }
+        }
+        if (COUNT && active) {   // idle lanes of a ragged tile walk too, but are not counted
+            tot.steps += cnt.steps; tot.redraws += cnt.redraws; tot.rejections += cnt.rejections;
+            tot.caps += cnt.caps; tot.zero += cnt.zero; tot.nodes += cnt.nodes; tot.segs += cnt.segs;
+            tot.other += cnt.other;
+        }
+    }
+    if constexpr (COUNT) {
+        const uint32_t v[WOI_COUNTERS] = {tot.steps, tot.redraws, tot.rejections, tot.caps,
+                                          tot.zero, tot.nodes, tot.segs, tot.other};
+#pragma unroll
+        for (int i = 0; i < WOI_COUNTERS; ++i) {
+            const uint64_t s = wave_sum((uint64_t)v[i]);
+            if (lane == 0 && s) atomicAdd((unsigned long long*)&bp.counters[i], (unsigned long long)s);
+        }
+    }
+}
+
+// One thread per (instance, point) of the flattened point list: merge the point's partial
+// slots in chunk order, and within a chunk in wave order (= sample order).
+__global__ void batch_reduce_kernel(BRParams rp) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= rp.n_points) return;
+    int lo = 0, hi = rp.n_inst - 1;           // last instance with out0 <= q
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (rp.inst[mid].out0 <= q) lo = mid;
+        else hi = mid - 1;
+    }
+    const BInst& in = rp.inst[lo];
+    const int64_t p = q - in.out0;
+    const int D = rp.dim, W = 2 + 2 * D, WV = rp.waves;
+    const uint64_t tile = (uint64_t)(p >> 6), lane = (uint64_t)(p & 63);
+    Moments f{0, 0, 0}, g[WOI_MAX_DIM];
+    for (int i = 0; i < D; ++i) g[i] = Moments{0, 0, 0};
+    for (uint32_t c = 0; c < in.n_chunks; ++c) {
+        const uint32_t a = rp.ctab[in.c0 + c], len = rp.ctab[in.c0 + c + 1] - a;
+        for (int w = 0; w < WV; ++w) {
+            const uint32_t s0 = (uint32_t)(((uint64_t)len * w) / WV), s1 = (uint32_t)(((uint64_t)len * (w + 1)) / WV);
+            if (s1 == s0) continue;
+            const uint64_t slot = in.slot0 + (tile * in.n_chunks + c) * WV + w;
+            merge_partial(f, g, D, (double)(s1 - s0), rp.partials + (slot * 64 + lane) * W);
+        }
+    }
+    store_moments(f, g, D, p, in.mean, in.se, in.grad, in.grad_se);
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t n, uint32_t v) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ----------------------------------------------------------------------------- launchers
+template <typename R, int D, bool VR, bool COUNT, int WV, bool LDS>
+static const void* batch_fn() {
+    return reinterpret_cast<const void*>(&batch_kernel<R, D, VR, COUNT, WV, LDS>);
+}
+
+// Function pointer of the instantiation for (dim, vr, fp32, count, waves, lds); null if none.
+template <typename R, bool COUNT, int WV>
+static const void* pick_r(int dim, bool vr, bool lds) {
+    if (lds) {
+        if (dim != 2) return nullptr;
+        return vr ? batch_fn<R, 2, true, COUNT, WV, true>() : batch_fn<R, 2, false, COUNT, WV, true>();
+    }
+    if (vr) {
+        switch (dim) {
+            case 2: return batch_fn<R, 2, true, COUNT, WV, false>();
+            case 3: return batch_fn<R, 3, true, COUNT, WV, false>();
+            default: return nullptr;
+        }
+    }
+    switch (dim) {
+        case 2: return batch_fn<R, 2, false, COUNT, WV, false>();
+        case 3: return batch_fn<R, 3, false, COUNT, WV, false>();
+        case 4: return batch_fn<R, 4, false, COUNT, WV, false>();
+        case 5: return batch_fn<R, 5, false, COUNT, WV, false>();
+        case 6: return batch_fn<R, 6, false, COUNT, WV, false>();
+        case 7: return batch_fn<R, 7, false, COUNT, WV, false>();
+        case 8: return batch_fn<R, 8, false, COUNT, WV, false>();
+        default: return nullptr;
+    }
+}
+
+template <bool COUNT>
+static const void* pick_c(int dim, bool vr, bool fp32, int waves, bool lds) {
+    if (waves == 4) return fp32 ? pick_r<float, COUNT, 4>(dim, vr, lds) : pick_r<double, COUNT, 4>(dim, vr, lds);
+    if (waves == 8) return fp32 ? pick_r<float, COUNT, 8>(dim, vr, lds) : pick_r<double, COUNT, 8>(dim, vr, lds);
+    return nullptr;
+}
+
+static const void* pick(int dim, bool vr, bool fp32, bool count, int waves, bool lds) {
+    return count ? pick_c<true>(dim, vr, fp32, waves, lds) : pick_c<false>(dim, vr, fp32, waves, lds);
+}
+
+hipError_t launch_batch(const BParams& bp, int dim, bool vr, bool fp32, int waves, unsigned grid, unsigned smem,
+                        hipStream_t s) {
+    const bool lds = smem > 0;
+    const void* fn = pick(dim, vr, fp32, bp.counters != nullptr, waves, lds);
+    if (!fn) return hipErrorInvalidValue;
+    if (lds) {
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        if (e != hipSuccess) return e;
+    }
+    BParams arg = bp;
+    void* args[] = {&arg};
+    return hipLaunchKernel(fn, dim3(grid), dim3(64 * waves), args, smem, s);
+}
+
+int batch_blocks_per_cu(int dim, bool vr, bool fp32, int waves, unsigned smem) {
+    const bool lds = smem > 0;
+    const void* fn = pick(dim, vr, fp32, false, waves, lds);
+    if (!fn) return 0;
+    if (lds && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess) return 0;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64 * waves, smem) != hipSuccess) return 0;
+    return nb;
+}
+
+hipError_t launch_batch_reduce(const BRParams& rp, hipStream_t s) {
+    const int bs = 256;
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3((unsigned)((rp.n_points + bs - 1) / bs)), dim3(bs), 0, s, rp);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s) {
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace woi

@@ -40,10 +40,12 @@ struct DevRegion {
     float alpha_f, sgn_f, s_f, area_f, meas_f[2], total_f, pad1;
 };
 
-constexpr int LDS_BUDGET = 64 * 1024;   // bytes of polyline tables a workgroup may stage
+// Largest LDS staging area per workgroup: two 512-thread workgroups per CU share its
+// 160 KB of LDS on gfx950 (256 bytes left for a kernel's own static LDS).
+constexpr int LDS_BUDGET_MAX = 80 * 1024 - 256;
 
 struct DevProblem {
-    int dim, N, vr_ok, lds_bytes;             // lds_bytes: polyline tables staged per workgroup
+    int dim, N, vr_ok, lds_bytes;             // lds_bytes: LDS needed to stage every polyline (0: none)
     double alpha_l1, unit_area, phi_c;        // |S^{m-1}|, Phi prefactor (m >= 3)
     float alpha_l1_f, unit_area_f, phi_c_f, pad1;
     double cdf[WOI_MAX_REGIONS];              // schedule CDF over |alpha| / ||alpha||_1

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <cmath>
 #include <cstdarg>
@@ -22,6 +23,7 @@
 
 #include "woi.h"
 #include "woi_device.h"
+#include "woi_internal.h"
 #include "woi_launch.h"
 
 using woi::DevProblem;
@@ -468,6 +470,7 @@ void vr_halves_3d(const Host& H, HostRegion& g) {
 // ---------------------------------------------------------------------------- problem object
 struct woi_problem {
     Host H;
+    uint64_t serial = 0;
     std::vector<uint8_t> blob;   // device image, uploaded on first use
     std::mutex mu;
     int device = -1;
@@ -708,6 +711,8 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
     if (!d->parent || !d->sigma || !d->shapes || !d->data) return fail(WOI_E_INVALID_ARG, "NULL array in descriptor");
     auto* P = new (std::nothrow) woi_problem;
     if (!P) return fail(WOI_E_OOM, "host allocation failed");
+    static std::atomic<uint64_t> next_serial{1};
+    P->serial = next_serial++;
     Host& H = P->H;
     H.m = d->dim;
     H.N = d->n_regions;
@@ -883,8 +888,8 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
         r.meas_f[1] = (float)r.meas[1];
         r.total_f = (float)r.total;
     }
-    // LDS staging plan: FP32 vertices (8 B each, n + 1) and FP16 bounds (2 B each, n2) of
-    // every polyline, if they fit in one workgroup's budget together
+    // LDS staging layout: FP32 vertices (8 B each, n + 1) and FP16 bounds (2 B each, n2) of
+    // every polyline
     {
         int off = 0;
         for (int i = 0; i < N; ++i) {
@@ -897,9 +902,7 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
             off += 2 * r.n2;
             off = (off + 15) & ~15;
         }
-        hdr.lds_bytes = off <= woi::LDS_BUDGET ? off : 0;
-        if (hdr.lds_bytes == 0)
-            for (int i = 0; i < N; ++i) hdr.reg[i].lds_v = hdr.reg[i].lds_b = -1;
+        hdr.lds_bytes = off;   // staged only if the device's workgroup limit allows (decided at launch)
     }
     auto align = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
     hdr.off64 = align(sizeof(DevProblem));
@@ -984,7 +987,7 @@ struct Plan {
     uint64_t n_samples, first;
 };
 
-woi_status check_query(const woi_problem* p, int64_t P, const woi_query* q) {
+woi_status check_query_impl(const woi_problem* p, int64_t P, const woi_query* q) {
     if (!p || !q) return fail(WOI_E_INVALID_ARG, "NULL problem or query");
     if (P < 1) return fail(WOI_E_INVALID_ARG, "P = %lld must be >= 1", (long long)P);
     if (q->M < 0 || q->M > WOI_MAX_M) return fail(WOI_E_INVALID_ARG, "M = %d outside [0, %d]", q->M, WOI_MAX_M);
@@ -1008,7 +1011,7 @@ Plan make_plan(const woi_problem* p, int64_t P, const woi_query* q, uint64_t n_s
     pl.n_samples = n_samples;
     pl.first = q->estimator == WOI_EST_VR ? q->walk_offset / 2 : q->walk_offset;
     const DevProblem* hdr = reinterpret_cast<const DevProblem*>(p->blob.data());
-    pl.lds = hdr->lds_bytes > 0 && p->H.m == 2 ? (unsigned)hdr->lds_bytes : 0u;
+    pl.lds = hdr->lds_bytes > 0 && p->H.m == 2 && hdr->lds_bytes <= woi::lds_budget() ? (unsigned)hdr->lds_bytes : 0u;
     pl.block = pl.lds ? 512 : (q->block_size > 0 ? q->block_size : (P >= 4096 ? 256 : 64));
     pl.gx = (unsigned)((P + pl.block - 1) / pl.block);
     uint64_t spt;
@@ -1078,7 +1081,8 @@ woi_status estimate_shared(const woi_problem* p, const double* points, int64_t P
         return fail(WOI_E_OOM, "workspace of %zu bytes is smaller than the %zu bytes needed", workspace_bytes,
                     sp.traj_bytes + sp.part_bytes);
     const DevProblem* hdr = reinterpret_cast<const DevProblem*>(p->blob.data());
-    const unsigned lds = hdr->lds_bytes > 0 && p->H.m == 2 ? (unsigned)hdr->lds_bytes : 0u;
+    const unsigned lds =
+        hdr->lds_bytes > 0 && p->H.m == 2 && hdr->lds_bytes <= woi::lds_budget() ? (unsigned)hdr->lds_bytes : 0u;
     const bool vr = q->estimator == WOI_EST_VR, f32 = q->precision == WOI_PREC_FP32;
     woi::KParams kp{};
     kp.dp = static_cast<const DevProblem*>(p->dev);
@@ -1134,7 +1138,7 @@ woi_status estimate_shared(const woi_problem* p, const double* points, int64_t P
 extern "C" {
 
 woi_status woi_workspace_size(const woi_problem* p, int64_t P, const woi_query* q, size_t* bytes) {
-    woi_status st = check_query(p, P, q);
+    woi_status st = check_query_impl(p, P, q);
     if (st != WOI_OK) return st;
     if (!bytes) return fail(WOI_E_INVALID_ARG, "NULL bytes");
     const uint64_t ns = q->estimator == WOI_EST_VR ? q->walks / 2 : q->walks;
@@ -1151,7 +1155,7 @@ woi_status woi_workspace_size(const woi_problem* p, int64_t P, const woi_query* 
 woi_status woi_estimate(const woi_problem* p, const double* points, int64_t P, const woi_query* q, double* mean,
                         double* se, double* grad, double* grad_se, void* workspace, size_t workspace_bytes,
                         uint64_t* counters, void* stream) {
-    woi_status st = check_query(p, P, q);
+    woi_status st = check_query_impl(p, P, q);
     if (st != WOI_OK) return st;
     if (!points || !mean || !se) return fail(WOI_E_INVALID_ARG, "NULL points/mean/se");
     st = woi_problem_upload(const_cast<woi_problem*>(p));
@@ -1207,7 +1211,7 @@ woi_status woi_trace(const woi_problem* p, const double* points, int64_t P, cons
                      double* F, double* G, uint32_t* trace, void* stream) {
     woi_query qq = *q;
     qq.walks = q->estimator == WOI_EST_VR ? 2 * n_samples : n_samples;
-    woi_status st = check_query(p, P, &qq);
+    woi_status st = check_query_impl(p, P, &qq);
     if (st != WOI_OK) return st;
     if (!points || !F) return fail(WOI_E_INVALID_ARG, "NULL points or F");
     st = woi_problem_upload(const_cast<woi_problem*>(p));
@@ -1235,15 +1239,31 @@ woi_status woi_trace(const woi_problem* p, const double* points, int64_t P, cons
     return WOI_OK;
 }
 
-woi_status woi_batch_workspace_size(const woi_batch_item* items, int n, size_t* bytes) {
-    (void)items; (void)n; (void)bytes;
-    return fail(WOI_E_UNSUPPORTED, "batched estimation not built yet");
-}
-
-woi_status woi_estimate_batch(const woi_batch_item* items, int n, void* workspace, size_t workspace_bytes,
-                              uint64_t* counters, void* stream) {
-    (void)items; (void)n; (void)workspace; (void)workspace_bytes; (void)counters; (void)stream;
-    return fail(WOI_E_UNSUPPORTED, "batched estimation not built yet");
-}
-
 }  // extern "C"
+
+// ---------------------------------------------------------------------------- internal helpers
+namespace woi {
+
+woi_status set_error(woi_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+woi_status check_query(const woi_problem* p, int64_t P, const woi_query* q) { return check_query_impl(p, P, q); }
+
+woi_status problem_ref(woi_problem* p, ProblemRef* out) {
+    const woi_status st = woi_problem_upload(p);
+    if (st != WOI_OK) return st;
+    out->dev = static_cast<const DevProblem*>(p->dev);
+    out->host = reinterpret_cast<const DevProblem*>(p->blob.data());
+    out->dim = p->H.m;
+    out->serial = p->serial;
+    return WOI_OK;
+}
+
+}  // namespace woi

@@ -58,9 +58,68 @@ hipError_t launch_traj(const KParams& kp, const TParams& tp, int dim, bool vr, b
                        hipStream_t s);
 hipError_t launch_eval(const KParams& kp, const TParams& tp, int dim, bool vr, bool fp32, hipStream_t s);
 
-// lds_bytes > 0 (dimension 2): polyline tables are staged in LDS; block must then be 512 threads
+// lds_bytes > 0 (dimension 2, at most lds_budget()): polyline tables are staged in LDS;
+// block must then be 512 threads
 hipError_t launch_walk(const KParams& kp, int dim, bool vr, bool fp32, unsigned lds_bytes, dim3 grid, dim3 block,
                        hipStream_t s);
 hipError_t launch_reduce(const RParams& rp, hipStream_t s);
+
+// ----------------------------------------------------------------------------- batches
+// Many instances in one persistent launch.  A work item is (instance, tile of 64 points,
+// chunk of samples); the workgroup that pulls it splits the chunk's samples evenly over
+// its WV waves, and wave w writes partial slot slot0 + (tile * n_chunks + chunk) * WV + w
+// (64 lanes x (2 + 2 dim) doubles).  Chunk k of an instance covers samples
+// [ctab[c0 + k], ctab[c0 + k + 1]) counted from first_sample; every tile of the instance
+// has the same chunks.
+struct BInst {
+    const DevProblem* dp;
+    const double* points;
+    int64_t P;
+    uint64_t first_sample;
+    uint64_t slot0;
+    int64_t out0;              // index of the instance's first point in the flattened point list
+    double *mean, *se, *grad, *grad_se;
+    uint32_t k0, k1;
+    int M, shared_sched;
+    uint32_t instance;
+    uint32_t lds;              // bytes of polyline tables staged in LDS (0: read from global memory)
+    uint32_t c0, n_chunks;
+};
+
+struct BItem {                 // 16 bytes
+    uint32_t inst, tile, chunk, cost;
+};
+
+struct BParams {
+    const BInst* inst;
+    const BItem* items;
+    const uint32_t* ctab;
+    uint32_t n_items;
+    uint32_t* head;            // queue head, zeroed before the launch
+    double* partials;
+    uint64_t* counters;
+};
+
+struct BRParams {
+    const BInst* inst;
+    const uint32_t* ctab;
+    const double* partials;
+    int n_inst;
+    int64_t n_points;          // total points over all instances
+    int dim, waves;
+};
+
+// Persistent walk kernel: grid = resident workgroups, 64 * waves threads each (waves 4 or 8).
+// smem > 0: polyline tables are staged in LDS (dimension 2; every instance with polylines
+// then needs lds <= smem bytes).
+hipError_t launch_batch(const BParams& bp, int dim, bool vr, bool fp32, int waves, unsigned grid, unsigned smem,
+                        hipStream_t s);
+hipError_t launch_batch_reduce(const BRParams& rp, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s);
+// Resident workgroups per CU of the batch kernel for this configuration (0 on error).
+int batch_blocks_per_cu(int dim, bool vr, bool fp32, int waves, unsigned smem);
+// Bytes of LDS one workgroup may stage on the current device: the device's per-workgroup
+// limit, at most LDS_BUDGET_MAX.
+int lds_budget();
 
 }  // namespace woi

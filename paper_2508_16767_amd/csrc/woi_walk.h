@@ -1,0 +1,740 @@
+// woi_walk.h -- device code of one Walk-on-Interfaces walker (Philox streams, geometry,
+// transitions, kernel evaluation), shared by the kernel translation units.
+//
+// Paper: Ding & Stinchcombe, "Walk-on-Interfaces", arXiv 2508.16767.
+//   schedule H_0 ~ U{1..N}, H_i ~ |alpha|/||alpha||_1      Theorem 2, Eq. scheduled_interface_pdf
+//   transitions (line / ray / uniform) and Q, T factors    Sec. 4.2.1-4.2.3, Eqs. naive_woi_p, _Q, _T
+//   accumulation of w_i ||alpha||^i prod sign Q T Phi      Eq. woi_estimator, Alg. 2
+//   two walkers on {beta >= 0} / {beta < 0}               Sec. 4.4, Alg. 3
+//   gradient by grad_x Phi on the same walks               Sec. 4.5
+//
+// Mapping: one lane = one evaluation point, a thread loops over a chunk of samples
+// (walk indices).  With the shared schedule the walk index -- and so the scheduled
+// interface and the transition case -- is the same for all 64 lanes of a wave, so
+// the case branch and the geometry record are wave-uniform (scalar loads/branches);
+// only positions differ.  Every lane draws its own Philox4x32-10 counters keyed by
+// (walk, point group, instance|walker|purpose, step|draw), so results do not depend
+// on the launch shape.  Per-point sums are FP64 in every precision.
+#pragma once
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "woi_device.h"
+#include "woi_launch.h"
+
+namespace woi {
+
+#define WOI_ATTEMPT_CAP 256
+
+// ----------------------------------------------------------------------------- Philox4x32-10
+// Salmon, Moraes, Dror, Shaw (SC'11): 10 rounds, multipliers 0xD2511F53 / 0xCD9E8D57,
+// Weyl key increments 0x9E3779B9 / 0xBB67AE85.
+__device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
+                       (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+    }
+    return c;
+}
+
+struct Stream {
+    uint32_t k0, k1, c0, c1, c2;
+    __device__ __forceinline__ uint4 block(uint32_t step, uint32_t draw) const {
+        return philox(make_uint4(c0, c1, c2, (step << 16) | (draw & 0xFFFFu)), k0, k1);
+    }
+};
+
+// NW consecutive words of draws [first, ...): registers only (fully unrolled).
+template <int NW>
+struct Words {
+    uint32_t w[NW];
+    __device__ __forceinline__ void fill(const Stream& s, uint32_t step, uint32_t first) {
+#pragma unroll
+        for (int b = 0; b < (NW + 3) / 4; ++b) {
+            const uint4 v = s.block(step, first + b);
+            if (4 * b + 0 < NW) w[4 * b + 0] = v.x;
+            if (4 * b + 1 < NW) w[4 * b + 1] = v.y;
+            if (4 * b + 2 < NW) w[4 * b + 2] = v.z;
+            if (4 * b + 3 < NW) w[4 * b + 3] = v.w;
+        }
+    }
+};
+
+// ----------------------------------------------------------------------------- precision
+template <typename R> struct RO;
+template <> struct RO<double> {
+    static __device__ __forceinline__ double u(uint32_t v) { return ((double)v + 0.5) * 0x1p-32; }
+    static __device__ __forceinline__ void sc2pi(double u, double& s, double& c) { sincospi(2.0 * u, &s, &c); }
+    static __device__ __forceinline__ double lg(double x) { return log(x); }
+    static __device__ __forceinline__ double sq(double x) { return sqrt(x); }
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+    static constexpr double line_eps = 1e-12;   // |t| below which a polyline hit is y itself
+    static constexpr double ray_eps = 0.0;
+};
+template <> struct RO<float> {
+    static __device__ __forceinline__ float u(uint32_t v) { return (float)((v >> 8) | 1u) * 0x1p-24f; }
+    // v_sin_f32 / v_cos_f32 take their argument in revolutions
+    static __device__ __forceinline__ void sc2pi(float u, float& s, float& c) {
+        s = __builtin_amdgcn_sinf(u); c = __builtin_amdgcn_cosf(u);
+    }
+    static __device__ __forceinline__ float lg(float x) { return __logf(x); }
+    static __device__ __forceinline__ float sq(float x) { return __builtin_sqrtf(x); }
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+    static constexpr float line_eps = 1e-5f;
+    static constexpr float ray_eps = 0.0f;
+};
+
+template <typename R> struct Pay;
+template <> struct Pay<double> {
+    static __device__ __forceinline__ const double* base(const DevProblem* dp) {
+        return reinterpret_cast<const double*>(reinterpret_cast<const char*>(dp) + dp->off64);
+    }
+    static __device__ __forceinline__ int g(const DevRegion& r) { return r.g64; }
+    static __device__ __forceinline__ int len(const DevRegion& r) { return r.len64; }
+    static __device__ __forceinline__ int cum(const DevRegion& r) { return r.cum64; }
+    static __device__ __forceinline__ int nrm(const DevRegion& r) { return r.nrm64; }
+    static __device__ __forceinline__ int dat(const DevRegion& r) { return r.d64; }
+    static __device__ __forceinline__ int brk(const DevRegion& r) { return r.b64; }
+    static __device__ __forceinline__ double area(const DevRegion& r) { return r.area; }
+    static __device__ __forceinline__ double meas(const DevRegion& r, int k) { return r.meas[k]; }
+    static __device__ __forceinline__ double total(const DevRegion& r) { return r.total; }
+    static __device__ __forceinline__ double s(const DevRegion& r) { return r.s; }
+    static __device__ __forceinline__ double sgn(const DevRegion& r) { return r.sgn; }
+    static __device__ __forceinline__ double l1(const DevProblem* dp) { return dp->alpha_l1; }
+    static __device__ __forceinline__ double ua(const DevProblem* dp) { return dp->unit_area; }
+    static __device__ __forceinline__ double pc(const DevProblem* dp) { return dp->phi_c; }
+};
+template <> struct Pay<float> {
+    static __device__ __forceinline__ const float* base(const DevProblem* dp) {
+        return reinterpret_cast<const float*>(reinterpret_cast<const char*>(dp) + dp->off32);
+    }
+    static __device__ __forceinline__ int g(const DevRegion& r) { return r.g32; }
+    static __device__ __forceinline__ int len(const DevRegion& r) { return r.len32; }
+    static __device__ __forceinline__ int cum(const DevRegion& r) { return r.cum32; }
+    static __device__ __forceinline__ int nrm(const DevRegion& r) { return r.nrm32; }
+    static __device__ __forceinline__ int dat(const DevRegion& r) { return r.d32; }
+    static __device__ __forceinline__ int brk(const DevRegion& r) { return r.b32; }
+    static __device__ __forceinline__ float area(const DevRegion& r) { return r.area_f; }
+    static __device__ __forceinline__ float meas(const DevRegion& r, int k) { return r.meas_f[k]; }
+    static __device__ __forceinline__ float total(const DevRegion& r) { return r.total_f; }
+    static __device__ __forceinline__ float s(const DevRegion& r) { return r.s_f; }
+    static __device__ __forceinline__ float sgn(const DevRegion& r) { return r.sgn_f; }
+    static __device__ __forceinline__ float l1(const DevProblem* dp) { return dp->alpha_l1_f; }
+    static __device__ __forceinline__ float ua(const DevProblem* dp) { return dp->unit_area_f; }
+    static __device__ __forceinline__ float pc(const DevProblem* dp) { return dp->phi_c_f; }
+};
+
+struct Counts {
+    uint32_t steps, redraws, rejections, caps, zero, nodes, segs, other;
+};
+
+constexpr int dir_words(int D) { return D == 2 ? 1 : (D == 3 ? 2 : 2 * ((D + 1) / 2)); }
+
+// ----------------------------------------------------------------------------- directions
+// Uniform direction on S^{D-1} from the first dir_words(D) words.
+template <typename R, int D, int NW>
+__device__ __forceinline__ void unit_dir(const Words<NW>& W, R d[D]) {
+    if constexpr (D == 2) {
+        RO<R>::sc2pi(RO<R>::u(W.w[0]), d[1], d[0]);
+    } else if constexpr (D == 3) {
+        const R z = R(2) * RO<R>::u(W.w[0]) - R(1);
+        R s, c;
+        RO<R>::sc2pi(RO<R>::u(W.w[1]), s, c);
+        const R r = RO<R>::sq(fmax(R(0), R(1) - z * z));
+        d[0] = r * c; d[1] = r * s; d[2] = z;
+    } else {
+        R g[2 * ((D + 1) / 2)];
+#pragma unroll
+        for (int j = 0; j < (D + 1) / 2; ++j) {
+            const R rr = RO<R>::sq(R(-2) * RO<R>::lg(RO<R>::u(W.w[2 * j])));
+            R s, c;
+            RO<R>::sc2pi(RO<R>::u(W.w[2 * j + 1]), s, c);
+            g[2 * j] = rr * c; g[2 * j + 1] = rr * s;
+        }
+        R n2 = 0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) n2 += g[i] * g[i];
+        const R inv = RO<R>::rsq(n2);
+#pragma unroll
+        for (int i = 0; i < D; ++i) d[i] = g[i] * inv;
+    }
+}
+
+// ----------------------------------------------------------------------------- geometry
+template <typename R, int D>
+__device__ __forceinline__ void normal_at(const DevRegion& g, const R* __restrict__ pay, const R y[D], int seg, R n[D]) {
+    const R* q = pay + Pay<R>::g(g);
+    if (g.kind == WOI_SHAPE_SPHERE) {
+        const R iR = R(1) / q[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) n[i] = (y[i] - q[i]) * iR;
+    } else if (g.kind == WOI_SHAPE_ELLIPSOID) {
+        R s = 0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            R t = 0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) t += q[D + i * D + j] * (y[j] - q[j]);
+            n[i] = t; s += t * t;
+        }
+        const R inv = R(1) / RO<R>::sq(s);
+#pragma unroll
+        for (int i = 0; i < D; ++i) n[i] *= inv;
+    } else {
+        if constexpr (D == 2) {
+            const R* nr = pay + Pay<R>::nrm(g) + 2 * seg;
+            n[0] = nr[0]; n[1] = nr[1];
+        }
+    }
+}
+
+// b_i(y) (Eq. interface_problem data).
+template <typename R, int D>
+__device__ __forceinline__ R data_b(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
+                                    const R y[D], int seg) {
+    const R* cf = pay + Pay<R>::dat(g);
+    if (g.dkind == WOI_DATA_ZERO) return R(0);
+    if (g.dkind == WOI_DATA_FIELD_FLUX || g.dkind == WOI_DATA_SOURCE_FLUX) {
+        R n[D];
+        normal_at<R, D>(g, pay, y, seg, n);
+        if (g.dkind == WOI_DATA_FIELD_FLUX) {
+            R b = 0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) b += cf[i] * n[i];
+            return b;
+        }
+        R dn = 0, r2 = 0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) { const R e = y[i] - cf[1 + i]; dn += e * n[i]; r2 += e * e; }
+        R rm = R(1);
+#pragma unroll
+        for (int i = 0; i < D / 2; ++i) rm *= r2;
+        if constexpr (D % 2) rm *= RO<R>::sq(r2);
+        return cf[0] * dn / rm;
+    }
+    // direction-based data: e = (y - c)/|y - c|, c stored after the coefficients
+    const R* c = cf + (g.dkind == WOI_DATA_FOURIER2D ? 2 * g.nt + 1 : g.nt);
+    R e[D], r2 = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) { e[i] = y[i] - c[i]; r2 += e[i] * e[i]; }
+    const R ir = RO<R>::rsq(r2);
+#pragma unroll
+    for (int i = 0; i < D; ++i) e[i] *= ir;
+    if (g.dkind == WOI_DATA_FOURIER2D) {
+        // cos(k th) + i sin(k th) = (e_x + i e_y)^k
+        R b = cf[0], zr = 1, zi = 0;
+        for (int k = 1; k <= g.nt; ++k) {
+            const R nr = zr * e[0] - zi * e[1], ni = zr * e[1] + zi * e[0];
+            zr = nr; zi = ni;
+            b += cf[2 * k - 1] * zr + cf[2 * k] * zi;
+        }
+        return b;
+    }
+    const unsigned char* ex = reinterpret_cast<const unsigned char*>(dp) + dp->offb + g.dexp;
+    R b = 0;
+    for (int t = 0; t < g.nt; ++t) {
+        R term = cf[t];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+            for (int p = 0; p < ex[t * D + i]; ++p) term *= e[i];
+        b += term;
+    }
+    return b;
+}
+
+// ---- uniform surface sample, one attempt: returns false when rejected
+__device__ __forceinline__ const int* int_payload(const DevProblem* dp) {
+    return reinterpret_cast<const int*>(reinterpret_cast<const char*>(dp) + dp->offi);
+}
+
+// Point at arclength s on a polyline: the segment is the largest j with cum[j] <= s, found
+// from the guide table entry for s in O(1) expected probes.  Kept out of line: inlined
+// into the trajectory-generation kernel at -O2/-O3 (ROCm 7.2 clang) it produced points off
+// the polyline in "other" transitions, while -O1, an out-of-line call, and the per-point
+// kernel were exact; the shared-trajectory parity tests check this path.
+template <typename R, int D>
+__device__ __noinline__ bool polyline_at(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay, R s,
+                                            R y[D], int& seg) {
+    if constexpr (D == 2) {
+        const R* cum = pay + Pay<R>::cum(g);
+        const int n = g.nv;
+        int k = (int)(s * ((R)n / Pay<R>::total(g)));
+        k = min(max(k, 0), n - 1);
+        int j = int_payload(dp)[g.guide + k];
+        while (j < n - 1 && cum[j + 1] <= s) ++j;
+        while (j > 0 && cum[j] > s) --j;
+        const R* v = pay + Pay<R>::g(g) + 2 * j;
+        const R f = (s - cum[j]) / pay[Pay<R>::len(g) + j];
+        y[0] = v[0] + f * (v[2] - v[0]); y[1] = v[1] + f * (v[3] - v[1]);
+        seg = j;
+    }
+    return true;
+}
+
+template <typename R, int D>
+__device__ __forceinline__ int surf_words(const DevRegion& g) {
+    return g.kind == WOI_SHAPE_POLYLINE2D ? 1 : dir_words(D) + (g.kind == WOI_SHAPE_ELLIPSOID ? 1 : 0);
+}
+
+template <typename R, int D>
+__device__ __forceinline__ bool surf_attempt(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
+                                             const Stream& st, uint32_t step, int att, R y[D], int& seg) {
+    seg = 0;
+    if (g.kind == WOI_SHAPE_POLYLINE2D) {
+        Words<1> W; W.fill(st, step, (uint32_t)att);
+        return polyline_at<R, D>(dp, g, pay, RO<R>::u(W.w[0]) * Pay<R>::total(g), y, seg);
+    }
+    const R* q = pay + Pay<R>::g(g);
+    if (g.kind == WOI_SHAPE_SPHERE) {
+        constexpr int NW = dir_words(D), NB = (NW + 3) / 4;
+        Words<NW> W; W.fill(st, step, (uint32_t)(att * NB));
+        R u[D];
+        unit_dir<R, D>(W, u);
+#pragma unroll
+        for (int i = 0; i < D; ++i) y[i] = q[i] + q[D] * u[i];
+        return true;
+    }
+    // ellipsoid: y = c + A^{-1/2} u, accept with probability |A^{1/2} u| / sqrt(lambda_max)
+    constexpr int NW = dir_words(D) + 1, NB = (NW + 3) / 4;
+    Words<NW> W; W.fill(st, step, (uint32_t)(att * NB));
+    R u[D];
+    unit_dir<R, D>(W, u);
+    const R acc = RO<R>::u(W.w[NW - 1]);
+    R uAu = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        R t = 0, l = 0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) { t += q[D + i * D + j] * u[j]; l += q[D + D * D + i * D + j] * u[j]; }
+        uAu += u[i] * t;
+        y[i] = q[i] + l;
+    }
+    return acc < RO<R>::sq(uAu * q[D + 2 * D * D]);
+}
+
+// point at arclength s on a closed 2D curve (circle or polyline)
+template <typename R, int D>
+__device__ __forceinline__ void curve_at(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay, R s,
+                                         R y[D], int& seg) {
+    if constexpr (D == 2) {
+        if (g.kind == WOI_SHAPE_POLYLINE2D) { polyline_at<R, D>(dp, g, pay, s, y, seg); return; }
+        const R* q = pay + Pay<R>::g(g);
+        R sn, cs;
+        RO<R>::sc2pi(s / (R(2) * R(3.14159265358979323846) * q[2]), sn, cs);
+        y[0] = q[0] + q[2] * cs; y[1] = q[1] + q[2] * sn; seg = 0;
+    }
+}
+
+// one attempt of a uniform sample on the VR half `cls` of region h
+template <typename R, int D>
+__device__ __forceinline__ bool vr_attempt(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
+                                           int cls, const Stream& st, int att, R y[D], int& seg) {
+    if constexpr (D == 2) {
+        Words<1> W; W.fill(st, 0, (uint32_t)att);
+        const R t = RO<R>::u(W.w[0]) * Pay<R>::meas(g, cls);
+        const R* br = pay + Pay<R>::brk(g);
+        R start = 0, acc = 0;
+        int c = g.class0;
+        for (int p = 0; p <= g.nbrk; ++p) {
+            const R end = p < g.nbrk ? br[p] : Pay<R>::total(g);
+            if (c == cls) {
+                const R l = end - start;
+                if (t < acc + l || p == g.nbrk) {
+                    curve_at<R, D>(dp, g, pay, fmin(start + (t - acc), end), y, seg);
+                    return true;
+                }
+                acc += l;
+            }
+            start = end; c ^= 1;
+        }
+        curve_at<R, D>(dp, g, pay, start, y, seg);
+        return true;
+    } else {
+        if (!surf_attempt<R, D>(dp, g, pay, st, 0, att, y, seg)) return false;
+        return (Pay<R>::s(g) * data_b<R, D>(dp, g, pay, y, seg) >= R(0)) == (cls == 0);
+    }
+}
+
+// ---- line / ray intersections
+// Quadric (sphere, ellipsoid): returns q in {0, 1} and t.
+template <typename R, int D>
+__device__ __forceinline__ int quadric_hit(const DevRegion& g, const R* __restrict__ pay, const R y[D], const R d[D],
+                                           bool ray, R& t) {
+    const R* q = pay + Pay<R>::g(g);
+    R yc[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) yc[i] = y[i] - q[i];
+    R a, b, cc;
+    if (g.kind == WOI_SHAPE_SPHERE) {
+        a = 1; b = 0; cc = -q[D] * q[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) { b += yc[i] * d[i]; cc += yc[i] * yc[i]; }
+    } else {
+        a = 0; b = 0; cc = -1;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            R s1 = 0, s2 = 0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) { s1 += q[D + i * D + j] * d[j]; s2 += q[D + i * D + j] * yc[j]; }
+            a += d[i] * s1; b += d[i] * s2; cc += yc[i] * s2;
+        }
+    }
+    if (!ray) {   // y on the quadric: other root of t (a t + 2 b) = 0
+        t = R(-2) * b / a;
+        return t != R(0) ? 1 : 0;
+    }
+    const R disc = b * b - a * cc;
+    if (disc < R(0)) return 0;
+    t = (-b + RO<R>::sq(disc)) / a;
+    return t > R(0) ? 1 : 0;
+}
+
+// Polyline: hits of the line / ray y + t d in segment order.  The signed distance of
+// vertex j from the line is h_j = d x (v_j - y); segment j is hit iff h_j = 0 != h_{j+1}
+// or the signs differ (the half-open segment [v_j, v_{j+1})).  One flat loop per lane
+// walks the vertex index with an adaptive aligned stride 2^l: a block whose chord bound
+// keeps all its vertices strictly on one side of the line is skipped, otherwise it is
+// halved; at stride 1 the segment is tested exactly.  Every iteration costs the same
+// (one vertex, one bound), so lanes of a wave stay in step.
+// want < 0: count all hits (q) remembering the first two; want >= 0: stop at hit `want`.
+struct PolyHits { int q, j0, j1; };
+
+// Polyline tables staged by the workgroup (FP32 vertices, FP16 block bounds).
+extern __shared__ __align__(16) char woi_smem[];
+
+constexpr bool COUNT_POLY = true;   // dead code unless the counting kernel reads the counters
+
+template <typename R, bool LDS>
+__device__ __forceinline__ PolyHits poly_hits(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
+                                              const R y[2], const R d[2], bool ray, int yseg, int want, Counts& cnt) {
+    const R* __restrict__ v = pay + Pay<R>::g(g);            // exact tests, precision R
+    const int n = g.nv, n2 = g.n2, top = g.top;
+    // block tests run in FP32 on the staged (or global) FP32 copy; bounds absorb the rounding
+    const float* __restrict__ vf;
+    if constexpr (LDS) vf = reinterpret_cast<const float*>(woi_smem + g.lds_v);
+    else vf = Pay<float>::base(dp) + g.g32;
+    const float yf0 = (float)y[0], yf1 = (float)y[1], df0 = (float)d[0], df1 = (float)d[1];
+    auto hf = [&](int j) -> float { return df0 * (vf[2 * j + 1] - yf1) - df1 * (vf[2 * j] - yf0); };
+    auto bound = [&](int idx) -> float {
+        if constexpr (LDS) return __half2float(reinterpret_cast<const __half*>(woi_smem + g.lds_b)[idx]);
+        else return Pay<float>::base(dp)[g.bnd + idx];
+    };
+    PolyHits r{0, -1, -1};
+    int j = 0, lvl = top;
+    float hj = hf(0);
+    // Branch-free body: every lane evaluates the block test and the segment crossing with
+    // selects; only a lane that actually crosses a segment enters the (rare) hit branch.
+    while (j < n) {
+        const int je = min(j + (1 << lvl), n);
+        const float he = hf(je);
+        const bool seg_level = lvl == 0;
+        const float b = bound(seg_level ? 0 : n2 - (n2 >> (lvl - 1)) + (j >> lvl));
+        const bool skip = fminf(hj, he) - b > 0.f || fmaxf(hj, he) + b < 0.f;
+        const R* a = v + 2 * j;
+        R ha, hb;
+        if constexpr (std::is_same<R, float>::value) { ha = hj; hb = he; }
+        else { ha = d[0] * (a[1] - y[1]) - d[1] * (a[0] - y[0]); hb = d[0] * (a[3] - y[1]) - d[1] * (a[2] - y[0]); }
+        const bool cross = hb != R(0) && (ha == R(0) || ((ha > R(0)) != (hb > R(0))));
+        if (seg_level && cross && (ray || j != yseg)) {
+            const R ex = a[2] - a[0], ey = a[3] - a[1];
+            const R den = d[0] * ey - d[1] * ex;
+            const R t = ((a[0] - y[0]) * ey - (a[1] - y[1]) * ex) / den;
+            if (den != R(0) && (ray ? (t > R(0)) : (fabs(t) > RO<R>::line_eps))) {
+                r.j0 = (r.q == 0 || r.q == want) ? j : r.j0;
+                r.j1 = r.q == 1 ? j : r.j1;
+                if (r.q == want) { r.q++; return r; }
+                r.q++;
+            }
+        }
+        if (COUNT_POLY) { cnt.nodes += seg_level ? 0 : 1; cnt.segs += seg_level ? 1 : 0; }
+        const bool advance = seg_level || skip;
+        j = advance ? je : j;
+        hj = advance ? he : hj;
+        lvl = advance ? min(top, (int)__builtin_ctz((unsigned)je | (1u << top))) : lvl - 1;
+    }
+    return r;
+}
+
+// ----------------------------------------------------------------------------- accumulation
+template <typename R, int D>
+__device__ __forceinline__ void add_term(const DevProblem* dp, const R xh[D], const R xl[D], const R y[D], R c,
+                                         R& F, R G[D], Counts& cnt) {
+    R d[D], r2 = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) { d[i] = (xh[i] - y[i]) + xl[i]; r2 += d[i] * d[i]; }
+    if (r2 == R(0)) { cnt.zero++; return; }
+    R phi, irm;   // Phi(x, y), |x - y|^{-m}
+    if constexpr (D == 2) {
+        phi = -RO<R>::lg(r2) * R(0.0795774715459476678844418816863);   // 1/(4 pi)
+        irm = RO<R>::rcp(r2);
+    } else {
+        const R ir = RO<R>::rsq(r2);
+        R ir2 = ir * ir, p = R(1);
+#pragma unroll
+        for (int i = 0; i < (D - 2) / 2; ++i) p *= ir2;
+        if constexpr (D % 2) p *= ir;   // p = r^{2-m}
+        phi = Pay<R>::pc(dp) * p;
+        irm = p * ir2;
+    }
+    F += c * phi;
+    const R gs = -c * irm / Pay<R>::ua(dp);
+#pragma unroll
+    for (int i = 0; i < D; ++i) G[i] += gs * d[i];
+}
+
+__device__ __forceinline__ uint32_t trace_word(int h, int cs, int q, int pick, int neg, int att) {
+    q = min(q, 255); pick = min(pick, 255); att = min(att, 127);
+    return (uint32_t)h | ((uint32_t)cs << 6) | ((uint32_t)q << 8) | ((uint32_t)pick << 16) |
+           ((uint32_t)(neg ? 1 : 0) << 24) | ((uint32_t)att << 25);
+}
+
+// ----------------------------------------------------------------------------- one sample
+// Where a walker's terms c_i (y_i) go: accumulated at the lane's point, or stored as a
+// trajectory for evaluation at a batch of points (shared trajectories, Sec. 4.6).
+template <typename R, int D>
+struct AccumSink {
+    const DevProblem* dp;
+    R xh[D], xl[D];
+    R F, G[D];
+    __device__ __forceinline__ void begin() {
+        F = 0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) G[i] = 0;
+    }
+    __device__ __forceinline__ void add(int, R c, const R y[D], Counts& cnt) { add_term<R, D>(dp, xh, xl, y, c, F, G, cnt); }
+    __device__ __forceinline__ void finish(int) {}
+};
+
+// Trajectory planes: component q (0 = c, 1.. = y) of step i of walker k of local sample s of
+// group g sits at plane[q][((s K + k)(M + 1) + i) NG + g], g fastest (coalesced stores).
+template <typename R, int D>
+struct StoreSink {
+    R* base;           // &plane[0][((s K + k)(M + 1)) NG + g]
+    size_t plane;      // elements per plane
+    int ng, M;
+    bool on;           // lanes past the last group walk (keeping the wave uniform) but store nothing
+    __device__ __forceinline__ void begin() {}
+    __device__ __forceinline__ void add(int i, R c, const R y[D], Counts&) {
+        if (!on) return;
+        R* p = base + (size_t)i * ng;
+        p[0] = c;
+#pragma unroll
+        for (int q = 0; q < D; ++q) p[(q + 1) * plane] = y[q];
+    }
+    __device__ __forceinline__ void finish(int i_next) {   // steps never reached contribute 0
+        if (!on) return;
+        for (int i = i_next; i <= M; ++i) {
+            R* p = base + (size_t)i * ng;
+            p[0] = R(0);
+#pragma unroll
+            for (int q = 0; q < D; ++q) p[(q + 1) * plane] = R(0);
+        }
+    }
+};
+
+// Walker k of sample `w`: emits c_i and y_i, i = 0..M, to the sink (the accumulating sink
+// forms sum_i c_i Phi(x, y_i) and sum_i c_i grad_x Phi; the caller multiplies by N).
+template <typename R, int D, bool VR, bool LDS, class Sink>
+__device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const R* __restrict__ pay,
+                                       const KParams& kp, uint32_t w, uint32_t group, int k, Sink& sink,
+                                       uint32_t* __restrict__ tr, Counts& cnt) {
+    const int N = dp->N, M = kp.M;
+    const uint32_t inst = (kp.instance & 0xFFFFFFu) << 8;
+    const Stream sched{kp.k0, kp.k1, w, kp.shared_sched ? 0xFFFFFFFFu : group, inst};
+    const Stream st{kp.k0, kp.k1, w, group, inst | ((uint32_t)k << 4) | 1u};
+    sink.begin();
+
+    // schedule H_0 (Theorem 2): uniform over regions
+    uint4 sb = sched.block(0, 0);
+    int h;
+    {
+        int t = (int)floor(RO<double>::u(sb.x) * N);
+        h = t < N ? t : N - 1;
+        if (kp.shared_sched) h = __builtin_amdgcn_readfirstlane(h);
+    }
+    const DevRegion* g = &dp->reg[h];
+    const R meas = VR ? Pay<R>::meas(*g, k) : Pay<R>::area(*g);
+    if (meas == R(0)) {   // empty VR half: the walker contributes nothing
+        if (tr) for (int i = 0; i <= M; ++i) tr[i] = i ? 0u : trace_word(h, 0, 0, 0, 0, 0);
+        sink.finish(0);
+        return;
+    }
+    R y[D];
+    int seg = 0, att;
+    for (att = 0; att < WOI_ATTEMPT_CAP; ++att) {
+        bool ok;
+        if constexpr (VR) ok = vr_attempt<R, D>(dp, *g, pay, k, st, att, y, seg);
+        else ok = surf_attempt<R, D>(dp, *g, pay, st, 0, att, y, seg);
+        if (ok) break;
+        cnt.rejections++;
+    }
+    if (att == WOI_ATTEMPT_CAP) cnt.caps++;
+    R Q = Pay<R>::s(*g) * data_b<R, D>(dp, *g, pay, y, seg) * meas, T = 1;
+    sink.add(0, (M == 0 ? R(0.5) : R(1)) * Q * T, y, cnt);
+    cnt.steps++;
+    if (tr) tr[0] = trace_word(h, 0, 1, 0, 0, att);
+    int done = 1;
+    R S = 1, pw = 1;
+    const R l1 = Pay<R>::l1(dp);
+    for (int i = 1; i <= M; ++i) {
+        if ((i & 3) == 0) sb = sched.block(0, (uint32_t)(i >> 2));
+        const uint32_t wv = (i & 3) == 0 ? sb.x : (i & 3) == 1 ? sb.y : (i & 3) == 2 ? sb.z : sb.w;
+        const double uu = RO<double>::u(wv);
+        int hn = 0;
+        while (hn < N - 1 && !(uu < dp->cdf[hn])) ++hn;
+        if (kp.shared_sched) hn = __builtin_amdgcn_readfirstlane(hn);
+        const int rel = dp->rel[h][hn];
+        h = hn;
+        g = &dp->reg[h];
+        S *= Pay<R>::sgn(*g);
+        pw *= l1;
+        R yn[D], nn[D];
+        int segn = 0, qn = 1, pick = 0;
+        if (rel == REL_OTHER) {
+            // y_i uniform on dOmega_{h_i}: Q *= |K*(y_i, y_{i-1})| |dOmega_{h_i}|
+            cnt.other++;
+            for (att = 0; att < WOI_ATTEMPT_CAP; ++att) {
+                if (surf_attempt<R, D>(dp, *g, pay, st, (uint32_t)i, att, yn, segn)) break;
+                cnt.rejections++;
+            }
+            if (att == WOI_ATTEMPT_CAP) cnt.caps++;
+            normal_at<R, D>(*g, pay, yn, segn, nn);
+            R dn = 0, r2 = 0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) { const R e = yn[j] - y[j]; dn += e * nn[j]; r2 += e * e; }
+            R rm = R(1);
+#pragma unroll
+            for (int j = 0; j < D / 2; ++j) rm *= r2;
+            if constexpr (D % 2) rm *= RO<R>::sq(r2);
+            Q *= fabs(dn / (Pay<R>::ua(dp) * rm)) * Pay<R>::area(*g);
+        } else {
+            // isotropic line (same interface) or ray (descendant to ancestor); uniform pick among q hits
+            const bool ray = rel == REL_DESC;
+            constexpr int NW = dir_words(D) + 1, NB = (NW + 3) / 4;
+            bool found = false;
+            for (att = 0; att < WOI_ATTEMPT_CAP; ++att) {
+                Words<NW> W; W.fill(st, (uint32_t)i, (uint32_t)(att * NB));
+                R d[D];
+                unit_dir<R, D>(W, d);
+                const R up = RO<R>::u(W.w[NW - 1]);
+                if (g->kind == WOI_SHAPE_POLYLINE2D) {
+                    if constexpr (D == 2) {
+                        const PolyHits ph = poly_hits<R, LDS>(dp, *g, pay, y, d, ray, seg, -1, cnt);
+                        qn = ph.q;
+                        if (qn == 0) { cnt.redraws++; continue; }
+                        pick = min((int)(up * (R)qn), qn - 1);
+                        int j = pick == 0 ? ph.j0 : ph.j1;
+                        if (pick >= 2) j = poly_hits<R, LDS>(dp, *g, pay, y, d, ray, seg, pick, cnt).j0;
+                        const R* v = pay + Pay<R>::g(*g) + 2 * j;
+                        const R ex = v[2] - v[0], ey = v[3] - v[1];
+                        const R den = d[0] * ey - d[1] * ex;
+                        const R s = ((v[0] - y[0]) * d[1] - (v[1] - y[1]) * d[0]) / den;
+                        yn[0] = v[0] + s * ex; yn[1] = v[1] + s * ey; segn = j;
+                    }
+                } else {
+                    R t;
+                    qn = quadric_hit<R, D>(*g, pay, y, d, ray, t);
+                    if (qn == 0) { cnt.redraws++; continue; }
+                    pick = 0;
+#pragma unroll
+                    for (int j = 0; j < D; ++j) yn[j] = y[j] + t * d[j];
+                }
+                found = true;
+                break;
+            }
+            if (!found) {   // no hit after the attempt cap: the walker stops here
+                cnt.caps++;
+                if (tr) for (int j = i; j <= M; ++j) tr[j] = trace_word(h, rel, 0, 0, 0, att);
+                break;
+            }
+            if (!ray) Q *= R(0.5);
+            normal_at<R, D>(*g, pay, yn, segn, nn);
+        }
+        R dn = 0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) dn += (yn[j] - y[j]) * nn[j];
+        const R sg = dn < R(0) ? R(-1) : R(1);
+        T *= (R)qn * sg;
+#pragma unroll
+        for (int j = 0; j < D; ++j) y[j] = yn[j];
+        seg = segn;
+        sink.add(i, (i == M ? R(0.5) : R(1)) * pw * S * Q * T, y, cnt);
+        cnt.steps++;
+        done = i + 1;
+        if (tr) tr[i] = trace_word(h, rel, qn, pick, sg < R(0), att);
+    }
+    sink.finish(done);
+}
+
+// ----------------------------------------------------------------------------- kernels
+template <typename R, int D>
+__device__ __forceinline__ void load_point(const double* __restrict__ pts, int64_t p, R xh[D], R xl[D]) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        const double v = pts[p * D + i];
+        xh[i] = (R)v;
+        xl[i] = (R)(v - (double)xh[i]);
+    }
+}
+
+__device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Stage every polyline's FP32 vertices and FP16 block bounds into LDS (LDS variant).
+__device__ __forceinline__ void stage_polylines(const DevProblem* __restrict__ dp) {
+    const float* __restrict__ f32 = Pay<float>::base(dp);
+    for (int i = 0; i < dp->N; ++i) {
+        const DevRegion& g = dp->reg[i];
+        if (g.lds_v < 0) continue;
+        float2* dv = reinterpret_cast<float2*>(woi_smem + g.lds_v);
+        const float2* sv = reinterpret_cast<const float2*>(f32 + g.g32);
+        for (int t = threadIdx.x; t <= g.nv; t += blockDim.x) dv[t] = sv[t];
+        __half* db = reinterpret_cast<__half*>(woi_smem + g.lds_b);
+        for (int t = threadIdx.x; t < g.n2; t += blockDim.x) db[t] = __float2half_ru(f32[g.bnd + t]);
+    }
+    __syncthreads();
+}
+
+// Running (n, mean, M2) of per-sample values, merged chunk by chunk from the chunk's sample
+// count and FP64 sums of values and squares (Chan, Golub & LeVeque's pairwise update).
+struct Moments {
+    double n, mu, m2;
+    __device__ __forceinline__ void merge(double nc, double s1, double s2) {
+        const double mc = s1 / nc, m2c = s2 - s1 * mc, nt = n + nc, dl = mc - mu;
+        mu += dl * nc / nt;
+        m2 += m2c + dl * dl * n * nc / nt;
+        n = nt;
+    }
+    // standard error of the mean
+    __device__ __forceinline__ double se() const { return n > 1 ? sqrt(fmax(m2, 0.0) / (n - 1) / n) : 0.0; }
+};
+
+// Merge one partial record (sum F, sum F^2, sum G[D], sum G^2[D]) of nc samples.
+__device__ __forceinline__ void merge_partial(Moments& f, Moments* g, int D, double nc, const double* __restrict__ o) {
+    f.merge(nc, o[0], o[1]);
+    for (int i = 0; i < D; ++i) g[i].merge(nc, o[2 + i], o[2 + D + i]);
+}
+
+__device__ __forceinline__ void store_moments(const Moments& f, const Moments* g, int D, int64_t p, double* mean,
+                                              double* se, double* grad, double* grad_se) {
+    mean[p] = f.mu;
+    se[p] = f.se();
+    for (int i = 0; i < D; ++i) {
+        if (grad) grad[p * D + i] = g[i].mu;
+        if (grad_se) grad_se[p * D + i] = g[i].se();
+    }
+}
+
+}  // namespace woi

@@ -243,5 +243,52 @@ def trace(problem, points, n_samples, M, seed=0, estimator=PLAIN, precision=FP64
     return F, G, T
 
 
+class Batch:
+    """Instances estimated together by woi_estimate_batch (one persistent launch, replayed
+    as a cached HIP graph).  `entries` is a list of dicts with keys problem, points, walks,
+    M and optionally seed, estimator, precision, schedule_mode, walk_offset, instance.  The
+    object keeps the points, the outputs and the workspace alive: the graph reads and
+    writes them on every run()."""
+
+    def __init__(self, entries, block_size=0, counters=None):
+        n = len(entries)
+        self.items = (_BatchItem * n)()
+        self.points, self.outputs = [], []
+        self.counters = counters
+        for i, e in enumerate(entries):
+            prob = e["problem"]
+            x = _points(e["points"], prob.dim)
+            P = x.shape[0]
+            out = (torch.empty(P, dtype=torch.float64, device=x.device), torch.empty(P, dtype=torch.float64, device=x.device),
+                   torch.empty(P, prob.dim, dtype=torch.float64, device=x.device),
+                   torch.empty(P, prob.dim, dtype=torch.float64, device=x.device))
+            q = make_query(e["walks"], e["M"], e.get("seed", 0), e.get("estimator", PLAIN), e.get("precision", FP64),
+                           e.get("schedule_mode", SCHED_SHARED), 1, e.get("walk_offset", 0), e.get("instance", 0),
+                           0, block_size)
+            it = self.items[i]
+            it.problem, it.points, it.P, it.query = prob.handle, x.data_ptr(), P, q
+            it.mean, it.se, it.grad, it.grad_se = (t.data_ptr() for t in out)
+            self.points.append(x)
+            self.outputs.append(out)
+        self.problems = [e["problem"] for e in entries]
+        nbytes = C.c_size_t()
+        _check(_lib.woi_batch_workspace_size(self.items, n, C.byref(nbytes)))
+        self.workspace = torch.empty(max(nbytes.value, 8), dtype=torch.uint8, device="cuda")
+
+    def run(self, events=None):
+        """Enqueue the batch on the current stream; returns the list of (mean, se, grad, grad_se)."""
+        q0 = self.items[0].query
+        q0.event_begin, q0.event_end = events if events is not None else (None, None)
+        cnt = C.c_void_p(self.counters.data_ptr()) if self.counters is not None else None
+        _check(_lib.woi_estimate_batch(self.items, len(self.items), C.c_void_p(self.workspace.data_ptr()),
+                                       self.workspace.numel(), cnt, _stream()))
+        return self.outputs
+
+
+def estimate_batch(entries, block_size=0, counters=None):
+    """One batched estimate of every entry (see Batch)."""
+    return Batch(entries, block_size, counters).run()
+
+
 def new_counters(device="cuda"):
     return torch.zeros(N_COUNTERS, dtype=torch.int64, device=device)

@@ -101,3 +101,38 @@ def test_host_compile_matches_oracle(woi, oracle_mod, make):
         assert np.allclose(a["area_minus"], b["area_minus"], rtol=1e-6, atol=1e-12 * scale)
     else:
         assert np.all(np.isnan(a["area_plus"]))
+
+
+def test_batch_validation_without_gpu(woi):
+    """woi_estimate_batch rejects malformed batches before touching a device."""
+    import ctypes as C
+    p1, _ = W.config1()
+    prob = woi.Problem(p1)
+    p5 = woi.Problem(W.config5()[0])
+
+    def items(*queries, problems=None):
+        arr = (woi._BatchItem * len(queries))()
+        for i, q in enumerate(queries):
+            it = arr[i]
+            it.problem = (problems[i] if problems else prob).handle
+            it.points, it.P, it.query = 16, 8, q              # never dereferenced on these paths
+            it.mean, it.se = 16, 16
+        return arr
+
+    def status(arr, n=None):
+        rc = woi._lib.woi_estimate_batch(arr, len(arr) if n is None else n, C.c_void_p(16), 1 << 20, None, None)
+        return woi._lib.woi_status_string(rc).decode()
+
+    q = woi.make_query(100, 4)
+    assert status(items(q), n=0) == "WOI_E_INVALID_ARG"                                  # empty batch
+    assert status(items(q, woi.make_query(100, 4, precision=woi.FP32))) == "WOI_E_INVALID_ARG"   # mixed precision
+    assert status(items(q, woi.make_query(100, 4, estimator=woi.VR))) == "WOI_E_INVALID_ARG"     # mixed estimator
+    assert status(items(woi.make_query(100, 4, batch_share=4))) == "WOI_E_UNSUPPORTED"   # shared trajectories
+    assert status(items(woi.make_query(100, 4, block_size=128))) == "WOI_E_INVALID_ARG"  # launch shape
+    assert status(items(q, woi.make_query(100, 4, block_size=256))) == "WOI_E_INVALID_ARG"
+    assert status(items(woi.make_query(100, 99))) == "WOI_E_INVALID_ARG"                 # M above the maximum
+    assert status(items(woi.make_query(1 << 33, 4))) == "WOI_E_INVALID_ARG"              # samples per point
+    bad = items(q)
+    bad[0].mean = None
+    assert status(bad) == "WOI_E_INVALID_ARG"
+    assert status(items(woi.make_query(100, 4, estimator=woi.VR), problems=[p5])) == "WOI_E_UNSUPPORTED"

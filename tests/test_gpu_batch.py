@@ -1,0 +1,175 @@
+"""GPU parity of batched estimation (woi_estimate_batch: persistent kernel, work queue,
+cached HIP graph) against the per-instance path and the FP64 oracle.
+
+Every sample of a batched instance is the sample woi_estimate draws for the same query
+(same Philox keys: walk, point, instance), so per-point means and SEs agree with
+woi_estimate up to the summation order of the FP64 sums, and with the oracle on the same
+streams to the per-point parity bar (1e-9 relative in FP64).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from oracle import oracle as O  # noqa: E402
+from paper_2508_16767_amd import woi  # noqa: E402
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _small_instances(n=10, seed=4, even=False):
+    """Config-3 style instances shrunk for parity runs: P in [2, 102], W in [5, 5000]."""
+    out = []
+    for k, (p, x, w) in enumerate(W.config3_instances(n_inst=n, seed=seed, scale_points=0.1, scale_walks=0.005)):
+        w = max(4, w + (w & 1 if even else 0))
+        out.append((p, x, w))
+    return out
+
+
+def _entries(inst, probs, precision=woi.FP64, estimator=woi.PLAIN, M=4, seed=11, sched=woi.SCHED_SHARED):
+    return [dict(problem=g, points=x, walks=w, M=M if np.isscalar(M) else M[i], seed=seed, precision=precision,
+                 estimator=estimator, schedule_mode=sched, instance=i)
+            for i, (g, (_, x, w)) in enumerate(zip(probs, inst))]
+
+
+def _close_to_rounding(a, b, n):
+    """Two FP64 estimates of the same samples summed in different orders."""
+    ma, sa, ga, gsa = a
+    mb, sb, gb, gsb = b
+    scale = np.abs(mb) + sb * np.sqrt(n)                   # |mean| + std of one sample
+    assert np.all(np.abs(ma - mb) <= 1e-10 * scale + 1e-300)
+    assert np.allclose(sa, sb, rtol=1e-8, atol=1e-12 * scale.max())
+    gscale = np.abs(gb) + gsb * np.sqrt(n)
+    assert np.all(np.abs(ga - gb) <= 1e-10 * gscale + 1e-300)
+    assert np.allclose(gsa, gsb, rtol=1e-8, atol=1e-12 * gscale.max())
+
+
+@pytest.mark.parametrize("precision", [woi.FP64, woi.FP32])
+def test_batch_matches_per_instance_estimate(precision):
+    inst = _small_instances()
+    probs = [woi.Problem(p) for p, _, _ in inst]
+    M = [4, 4, 0, 3, 4, 6, 4, 1, 4, 4]                   # uneven truncation too
+    outs = woi.estimate_batch(_entries(inst, probs, precision, M=M))
+    for i, (g, (p, x, w)) in enumerate(zip(probs, inst)):
+        ref = woi.estimate(g, x, w, M[i], seed=11, precision=precision, schedule_mode=woi.SCHED_SHARED, instance=i)
+        _close_to_rounding([_np(t) for t in outs[i]], [_np(t) for t in ref], w)
+
+
+def test_batch_same_streams_match_oracle_fp64():
+    inst = _small_instances(n=6, seed=9)
+    probs = [woi.Problem(p) for p, _, _ in inst]
+    outs = woi.estimate_batch(_entries(inst, probs, seed=5))
+    for i, (p, x, w) in enumerate(inst):
+        op = O.OracleProblem(p)
+        mo, so, go, gso, _ = O.estimate(op, x, w, 4, seed=5, schedule_mode=1, instance=i)
+        mg, sg, gg, gsg = [_np(t) for t in outs[i]]
+        assert np.allclose(mg, mo, rtol=1e-9, atol=1e-9 * so.max())
+        assert np.allclose(sg, so, rtol=1e-7)
+        assert np.allclose(gg, go, rtol=1e-9, atol=1e-9 * gso.max())
+        assert np.allclose(gsg, gso, rtol=1e-7)
+
+
+def test_batch_variance_reduced_2d_and_3d():
+    inst = _small_instances(n=5, seed=13, even=True)
+    probs = [woi.Problem(p) for p, _, _ in inst]
+    outs = woi.estimate_batch(_entries(inst, probs, estimator=woi.VR))
+    for i, (g, (p, x, w)) in enumerate(zip(probs, inst)):
+        ref = woi.estimate(g, x, w, 4, seed=11, estimator=woi.VR, schedule_mode=woi.SCHED_SHARED, instance=i)
+        _close_to_rounding([_np(t) for t in outs[i]], [_np(t) for t in ref], w // 2)
+    # 3D: spheres and an ellipsoid, with the oracle on the same streams
+    rng = np.random.default_rng(3)
+    p3 = [W.zheng_ex3_3d(), W.single_ellipsoid_linear(3, [0.9, 0.6, 0.4])[0]]
+    pts = [W.ball_points(rng, 70, 3, 0.8), W.ball_points(rng, 5, 3, 0.5)]
+    g3 = [woi.Problem(p) for p in p3]
+    ent = [dict(problem=g, points=x, walks=4000, M=5, seed=2, estimator=woi.VR, instance=7 + i)
+           for i, (g, x) in enumerate(zip(g3, pts))]
+    outs = woi.estimate_batch(ent)
+    for i, (p, x) in enumerate(zip(p3, pts)):
+        ref = woi.estimate(g3[i], x, 4000, 5, seed=2, estimator=woi.VR, schedule_mode=woi.SCHED_SHARED,
+                           instance=7 + i)
+        _close_to_rounding([_np(t) for t in outs[i]], [_np(t) for t in ref], 2000)
+        mo, so, _, _, _ = O.estimate(O.OracleProblem(p), x, 4000, 5, seed=2, estimator=1, schedule_mode=1,
+                                     instance=7 + i)
+        # each side integrates |dOmega^+-| by its own quadrature (agree to 1e-6)
+        assert np.allclose(_np(outs[i][0]), mo, rtol=1e-5, atol=1e-5 * so.max())
+
+
+def test_batch_graph_replay_is_deterministic():
+    """Replays of the cached graph, with unrelated eager work in between, give bitwise
+    identical results; counters add up per replay."""
+    inst = _small_instances(n=8, seed=21)
+    probs = [woi.Problem(p) for p, _, _ in inst]
+    cnt = woi.new_counters()
+    b = woi.Batch(_entries(inst, probs, precision=woi.FP32), counters=cnt)
+    first = [[t.clone() for t in o] for o in b.run()]
+    torch.cuda.synchronize()
+    c1 = _np(cnt).copy()
+    for rep in range(3):
+        a = torch.randn(512, 512, device="cuda")
+        (a @ a).sum().item()                               # eager work between replays
+        again = b.run()
+        torch.cuda.synchronize()
+        for o1, o2 in zip(first, again):
+            for t1, t2 in zip(o1, o2):
+                assert torch.equal(t1, t2)
+        assert np.array_equal(_np(cnt), c1 * (rep + 2))
+    expected = sum(x.shape[0] * w * 5 for _, x, w in inst)
+    assert 0.999 * expected <= c1[0] <= expected           # walker-steps (a walker stops early only at a cap)
+
+
+def test_batch_launch_shapes_agree():
+    """Explicit 256- and 512-thread workgroups (and the tuned shape) cut the work differently
+    but compute the same samples."""
+    inst = _small_instances(n=7, seed=33)
+    probs = [woi.Problem(p) for p, _, _ in inst]
+    res = [woi.estimate_batch(_entries(inst, probs), block_size=bs) for bs in (0, 256, 512)]
+    for i, (_, x, w) in enumerate(inst):
+        for r in res[1:]:
+            _close_to_rounding([_np(t) for t in r[i]], [_np(t) for t in res[0][i]], w)
+
+
+def test_batch_edge_cases():
+    """One point, one walker, a 65-point ragged tile, resumed walk ranges, a single item."""
+    p1, xs = W.config1()
+    g = woi.Problem(p1)
+    ent = [dict(problem=g, points=xs[:1], walks=1, M=4, seed=3, instance=0),
+           dict(problem=g, points=np.concatenate([xs, xs[:1]]), walks=33, M=4, seed=3, instance=1),   # 65 points
+           dict(problem=g, points=xs[:5], walks=700, M=4, seed=3, walk_offset=1000, instance=2)]
+    outs = woi.estimate_batch(ent)
+    for i, e in enumerate(ent):
+        ref = woi.estimate(g, e["points"], e["walks"], 4, seed=3, schedule_mode=woi.SCHED_SHARED,
+                           walk_offset=e.get("walk_offset", 0), instance=i)
+        _close_to_rounding([_np(t) for t in outs[i]], [_np(t) for t in ref], e["walks"])
+    assert _np(outs[0][1])[0] == 0.0                       # one walker: no standard error
+    single = woi.estimate_batch(ent[2:])
+    _close_to_rounding([_np(t) for t in single[0]], [_np(t) for t in outs[2]], 700)
+
+
+def test_config3_full_size_sampled():
+    """All 512 config-3 instances at full size, FP32 walks, one tuned persistent graph launch;
+    sampled points against the FP64 oracle on identical streams."""
+    inst = W.config3_instances()
+    probs = [woi.Problem(p) for p, _, _ in inst]
+    outs = woi.estimate_batch(_entries(inst, probs, precision=woi.FP32, seed=2024))
+    torch.cuda.synchronize()
+    for o in outs:
+        assert all(np.all(np.isfinite(_np(t))) for t in o)
+    # instances of moderate W, first and last point of each
+    pick = [i for i, (_, x, w) in enumerate(inst) if 2000 <= w <= 100000][:6]
+    z = []
+    for i in pick:
+        p, x, w = inst[i]
+        idx = np.array([0, len(x) - 1])
+        mo, so, _, _, _ = O.estimate(O.OracleProblem(p), x[idx], w, 4, seed=2024, schedule_mode=1, instance=i,
+                                     groups=idx)
+        z.extend((_np(outs[i][0])[idx] - mo) / so)
+    z = np.abs(np.array(z))
+    assert np.median(z) < 0.05 and np.max(z) < 1.0, z
