@@ -96,6 +96,53 @@ def run_path(woi, torch, prob, pts, walks, M, precision, steps, warmup, ev, seed
     return wall, kern_ms, cnt.cpu().numpy().astype(float) * steps, se, out[0].cpu().numpy()
 
 
+def timed(torch, ev, fn, steps, warmup):
+    """Warm-up calls, then `steps` timed calls of fn(events); returns wall seconds and the
+    per-call HIP-event milliseconds (events recorded by the library on the launch stream)."""
+    for _ in range(warmup):
+        fn(None)
+    evs = [(ev.create(), ev.create()) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        fn(evs[k])
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, [ev.ms(a, b) for a, b in evs]
+
+
+def run_shared(woi, torch, prob, pts, walks, M, B, steps, warmup, ev):
+    """Config 2 with shared trajectories (Sec. 4.6): points p with equal p // B share one
+    trajectory set.  Walk-steps here are (point, walk, step) contributions, as for the
+    per-point path."""
+    P = pts.shape[0]
+    out = (torch.empty(P, dtype=torch.float64, device="cuda"), torch.empty(P, dtype=torch.float64, device="cuda"),
+           torch.empty(P, 2, dtype=torch.float64, device="cuda"), torch.empty(P, 2, dtype=torch.float64, device="cuda"))
+    q = woi.make_query(walks, M, precision=woi.FP32, schedule_mode=woi.SCHED_SHARED, batch_share=B)
+    ws = torch.empty(woi.workspace_size(prob, P, q), dtype=torch.uint8, device="cuda")
+    fn = lambda e: woi.estimate(prob, pts, walks, M, seed=77, precision=woi.FP32, schedule_mode=woi.SCHED_SHARED,
+                                batch_share=B, out=out, workspace=ws, events=e)
+    wall, ms = timed(torch, ev, fn, steps, warmup)
+    return wall / steps, ms, out[1].cpu().numpy()
+
+
+def run_batch(woi, torch, W, precision, steps, warmup, ev):
+    """Config 3: 512 instances in one persistent graph launch (tuned launch shape).  An
+    untimed graph of the counting kernel gives the event counts; the timed graph replays
+    the non-counting kernel (same seed: the whole batch is recomputed every replay)."""
+    inst = W.config3_instances()
+    probs = [woi.Problem(p) for p, _, _ in inst]
+    entries = [dict(problem=g, points=x, walks=w, M=4, seed=4242, precision=precision, schedule_mode=woi.SCHED_SHARED,
+                    instance=i) for i, (g, (_, x, w)) in enumerate(zip(probs, inst))]
+    cnt = woi.new_counters()
+    woi.Batch(entries, counters=cnt).run()
+    b = woi.Batch(entries)
+    wall, ms = timed(torch, ev, lambda e: b.run(events=e), steps, warmup)
+    counts = cnt.cpu().numpy().astype(float)
+    se = [o[1].cpu().numpy() for o in b.outputs]
+    return {"wall": wall / steps, "ms": ms, "counts": counts, "se": se,
+            "points": sum(x.shape[0] for _, x, _ in inst), "walkers": sum(x.shape[0] * w for _, x, w in inst)}
+
+
 def cpu_baseline(prob, pts, walks, M, budget_s):
     import numpy as np
     from oracle import oracle as O
@@ -124,6 +171,9 @@ def main():
     ap.add_argument("--walks", type=int, default=100000)
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="measure only the headline path (skip config 3 batched and shared trajectories)")
+    ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after the run, copy this many bytes device-to-device three times (a plain copy "
@@ -197,6 +247,33 @@ def main():
                      "flops_per_launch": flops,
                      "counts_per_launch": {n: float(v / args.steps) for n, v in zip(woi.COUNTER_NAMES, c32)}},
     }
+    if not args.no_extra:
+        B = 16                                            # <= 0.5 % of the 4096 points
+        t_sh, ms_sh, se_sh = run_shared(woi, torch, prob, pts, args.walks, M, B, args.steps, args.warmup, ev)
+        t_sh_eps = t_sh * float(np.mean(se_sh ** 2)) / eps ** 2
+        rec["shared_trajectories"] = {
+            "batch_share": B, "walk_steps_per_s": P * args.walks * (M + 1) / t_sh, "ms_per_step": t_sh * 1e3,
+            "traj_plus_eval_ms": float(np.mean(ms_sh)), "eval_points_per_s_fixed_se": P / t_sh_eps,
+            "speedup_vs_fp64_plain_fixed_se": t64_eps / t_sh_eps}
+        b32 = run_batch(woi, torch, W, woi.FP32, args.batch_steps, 1, ev)
+        b64 = run_batch(woi, torch, W, woi.FP64, 1, 0, ev)
+        # fixed SE per instance: median SE of the FP64 batch; points/s at that SE summed over instances
+        bt32 = b32["wall"] * np.mean([np.mean(a ** 2) / np.median(c) ** 2 for a, c in zip(b32["se"], b64["se"])])
+        bt64 = b64["wall"] * np.mean([np.mean(c ** 2) / np.median(c) ** 2 for c in b64["se"]])
+        kms = float(np.mean(b32["ms"]))
+        bfl = flops_of(b32["counts"])
+        rec["batched_config3"] = {
+            "workload": "512 independent 2D instances: 1-16 circle/512-vertex star interfaces in random nesting "
+                        "trees, sigma 10^U(-1,3), P = 2^U(4,10), W = 10^U(3,6), M = 4; one persistent graph launch",
+            "points": b32["points"], "walkers": b32["walkers"],
+            "walk_steps_per_s": b32["counts"][0] / b32["wall"], "ms_per_step": b32["wall"] * 1e3,
+            "graph_ms": kms, "fp64_walk_steps_per_s": b64["counts"][0] / b64["wall"],
+            "fp64_ms_per_step": b64["wall"] * 1e3,
+            "speedup_fp32_vs_fp64_fixed_se": bt64 / bt32,
+            "roofline": {"bound": "alu", "achieved": bfl / (kms * 1e-3) / 1e12, "peak": PEAK_FP32_TFLOPS,
+                         "unit": "TFLOP/s", "frac": bfl / (kms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, "traffic": None,
+                         "kernel": "batch_kernel<float, 2, false, false, WV, true> + fill + reduce (graph)",
+                         "counts_per_launch": {n: float(v) for n, v in zip(woi.COUNTER_NAMES, b32["counts"])}}}
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(prob_desc, pts_np, args.walks, M, args.cpu_seconds)
     print(json.dumps(rec), flush=True)
