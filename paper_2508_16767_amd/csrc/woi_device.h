@@ -20,9 +20,9 @@ enum : int { REL_SAME = 1, REL_DESC = 2, REL_OTHER = 3 };
 //                cumulative arclength cum[nv+1], outward unit normals nrm[2*nv].
 // Polyline search tables (float payload, shared by both precisions):
 //   for every level l >= 1 and aligned block b (vertices [b 2^l, min((b+1) 2^l, nv)]),
-//   bnd[base_l + b] bounds the distance of the block's vertices from its chord, with
-//   base_l = N2 - (N2 >> (l - 1)) and N2 = nv rounded up to a power of two; the walk
-//   starts at level top.  Guide table (int payload): gd[k] = largest j with
+//   bnd[(N2 >> l) + b] bounds the distance of the block's vertices from its chord (heap
+//   layout, N2 = nv rounded up to a power of two, entry 0 unused); the walk starts at
+//   level top.  Guide table (int payload): gd[k] = largest j with
 //   cum[j] <= k L / nv.
 struct DevRegion {
     int kind, dkind, nt, nv;

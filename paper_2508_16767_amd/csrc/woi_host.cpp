@@ -672,7 +672,7 @@ void block_bounds(const HostRegion& g, std::vector<float>& bnd, int& n2, int& to
     const double pad = 4e-6 * (1.0 + scale);
     bnd.assign(n2, 0.0f);
     for (int l = 1; l <= L; ++l) {
-        const int base = n2 - (n2 >> (l - 1));
+        const int base = n2 >> l;   // heap layout: level l occupies [n2 >> l, 2 (n2 >> l))
         for (int j0 = 0, blk = 0; j0 < n; j0 += 1 << l, ++blk) {
             const int j1 = std::min(n, j0 + (1 << l));
             double dmax = 0;

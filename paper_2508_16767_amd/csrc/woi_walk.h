@@ -405,7 +405,7 @@ __device__ __forceinline__ int quadric_hit(const DevRegion& g, const R* __restri
 // keeps all its vertices strictly on one side of the line is skipped, otherwise it is
 // halved; at stride 1 the segment is tested exactly.  Every iteration costs the same
 // (one vertex, one bound), so lanes of a wave stay in step.
-// want < 0: count all hits (q) remembering the first two; want >= 0: stop at hit `want`.
+// FIND = false: count all hits (q) remembering the first two; FIND: stop at hit `want`.
 struct PolyHits { int q, j0, j1; };
 
 // Polyline tables staged by the workgroup (FP32 vertices, FP16 block bounds).
@@ -413,9 +413,10 @@ extern __shared__ __align__(16) char woi_smem[];
 
 constexpr bool COUNT_POLY = true;   // dead code unless the counting kernel reads the counters
 
-template <typename R, bool LDS>
+template <typename R, bool LDS, bool FIND>
 __device__ __forceinline__ PolyHits poly_hits(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
                                               const R y[2], const R d[2], bool ray, int yseg, int want, Counts& cnt) {
+    constexpr bool F32 = std::is_same<R, float>::value;
     const R* __restrict__ v = pay + Pay<R>::g(g);            // exact tests, precision R
     const int n = g.nv, n2 = g.n2, top = g.top;
     // block tests run in FP32 on the staged (or global) FP32 copy; bounds absorb the rounding
@@ -423,7 +424,9 @@ __device__ __forceinline__ PolyHits poly_hits(const DevProblem* dp, const DevReg
     if constexpr (LDS) vf = reinterpret_cast<const float*>(woi_smem + g.lds_v);
     else vf = Pay<float>::base(dp) + g.g32;
     const float yf0 = (float)y[0], yf1 = (float)y[1], df0 = (float)d[0], df1 = (float)d[1];
-    auto hf = [&](int j) -> float { return df0 * (vf[2 * j + 1] - yf1) - df1 * (vf[2 * j] - yf0); };
+    // h(v) = d x (v - y) = d0 v1 - d1 v0 - (d0 y1 - d1 y0): two FMAs per vertex
+    const float hc = df0 * yf1 - df1 * yf0;
+    auto hf = [&](int j) -> float { return fmaf(df0, vf[2 * j + 1], fmaf(-df1, vf[2 * j], -hc)); };
     auto bound = [&](int idx) -> float {
         if constexpr (LDS) return __half2float(reinterpret_cast<const __half*>(woi_smem + g.lds_b)[idx]);
         else return Pay<float>::base(dp)[g.bnd + idx];
@@ -431,35 +434,54 @@ __device__ __forceinline__ PolyHits poly_hits(const DevProblem* dp, const DevReg
     PolyHits r{0, -1, -1};
     int j = 0, lvl = top;
     float hj = hf(0);
-    // Branch-free body: every lane evaluates the block test and the segment crossing with
-    // selects; only a lane that actually crosses a segment enters the (rare) hit branch.
+    const unsigned topbit = 1u << top;
+    const int hmask = n2 - 1;
+    // Straight-line body: the block test, the segment crossing and the next (j, level) are
+    // computed with bitwise logic and selects by every lane; only a lane that crosses a
+    // segment enters the (rare) hit branch.
     while (j < n) {
         const int je = min(j + (1 << lvl), n);
         const float he = hf(je);
-        const bool seg_level = lvl == 0;
-        const float b = bound(seg_level ? 0 : n2 - (n2 >> (lvl - 1)) + (j >> lvl));
-        const bool skip = fminf(hj, he) - b > 0.f || fmaxf(hj, he) + b < 0.f;
-        const R* a = v + 2 * j;
+        const bool seg = lvl == 0;
+        // block (j, lvl) sits at (n2 >> lvl) + (j >> lvl); at stride 1 the mask keeps the
+        // (unused) read inside the table
+        const float b = bound(((n2 >> lvl) + (j >> lvl)) & hmask);
+        const bool skip = ((hj > b) & (he > b)) | ((hj < -b) & (he < -b));
         R ha, hb;
-        if constexpr (std::is_same<R, float>::value) { ha = hj; hb = he; }
-        else { ha = d[0] * (a[1] - y[1]) - d[1] * (a[0] - y[0]); hb = d[0] * (a[3] - y[1]) - d[1] * (a[2] - y[0]); }
-        const bool cross = hb != R(0) && (ha == R(0) || ((ha > R(0)) != (hb > R(0))));
-        if (seg_level && cross && (ray || j != yseg)) {
+        if constexpr (F32) {
+            ha = hj;
+            hb = he;
+        } else {                                              // FP64 exact values at stride 1 only
+            ha = R(0);
+            hb = R(0);
+            if (seg) {
+                const R* a = v + 2 * j;
+                ha = d[0] * (a[1] - y[1]) - d[1] * (a[0] - y[0]);
+                hb = d[0] * (a[3] - y[1]) - d[1] * (a[2] - y[0]);
+            }
+        }
+        const bool cross = (hb != R(0)) & ((ha == R(0)) | ((ha > R(0)) != (hb > R(0))));
+        if (seg & cross & (ray | (j != yseg))) {
+            const R* a = v + 2 * j;
             const R ex = a[2] - a[0], ey = a[3] - a[1];
             const R den = d[0] * ey - d[1] * ex;
             const R t = ((a[0] - y[0]) * ey - (a[1] - y[1]) * ex) / den;
-            if (den != R(0) && (ray ? (t > R(0)) : (fabs(t) > RO<R>::line_eps))) {
-                r.j0 = (r.q == 0 || r.q == want) ? j : r.j0;
-                r.j1 = r.q == 1 ? j : r.j1;
-                if (r.q == want) { r.q++; return r; }
+            if ((den != R(0)) & (ray ? (t > R(0)) : (fabs(t) > RO<R>::line_eps))) {
+                if constexpr (FIND) {
+                    if (r.q == want) { r.j0 = j; r.q++; return r; }
+                } else {
+                    r.j0 = r.q == 0 ? j : r.j0;
+                    r.j1 = r.q == 1 ? j : r.j1;
+                }
                 r.q++;
             }
         }
-        if (COUNT_POLY) { cnt.nodes += seg_level ? 0 : 1; cnt.segs += seg_level ? 1 : 0; }
-        const bool advance = seg_level || skip;
-        j = advance ? je : j;
-        hj = advance ? he : hj;
-        lvl = advance ? min(top, (int)__builtin_ctz((unsigned)je | (1u << top))) : lvl - 1;
+        if (COUNT_POLY) { cnt.nodes += seg ? 0 : 1; cnt.segs += seg ? 1 : 0; }
+        const bool adv = seg | skip;
+        const int lz = (int)__builtin_ctz((unsigned)je | topbit);   // <= top
+        j = adv ? je : j;
+        hj = adv ? he : hj;
+        lvl = adv ? lz : lvl - 1;
     }
     return r;
 }
@@ -549,12 +571,17 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
                                        uint32_t* __restrict__ tr, Counts& cnt) {
     const int N = dp->N, M = kp.M;
     const uint32_t inst = (kp.instance & 0xFFFFFFu) << 8;
-    const Stream sched{kp.k0, kp.k1, w, kp.shared_sched ? 0xFFFFFFFFu : group, inst};
+    // Schedule words: counter (w, group or all-ones, instance, draw).  With the shared schedule
+    // every input is wave-uniform and the block runs on the scalar unit.
+    auto sched_block = [&](uint32_t draw) -> uint4 {
+        if (kp.shared_sched) return philox(make_uint4(w, 0xFFFFFFFFu, inst, draw), kp.k0, kp.k1);
+        return philox(make_uint4(w, group, inst, draw), kp.k0, kp.k1);
+    };
     const Stream st{kp.k0, kp.k1, w, group, inst | ((uint32_t)k << 4) | 1u};
     sink.begin();
 
     // schedule H_0 (Theorem 2): uniform over regions
-    uint4 sb = sched.block(0, 0);
+    uint4 sb = sched_block(0);
     int h;
     {
         int t = (int)floor(RO<double>::u(sb.x) * N);
@@ -586,7 +613,7 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
     R S = 1, pw = 1;
     const R l1 = Pay<R>::l1(dp);
     for (int i = 1; i <= M; ++i) {
-        if ((i & 3) == 0) sb = sched.block(0, (uint32_t)(i >> 2));
+        if ((i & 3) == 0) sb = sched_block((uint32_t)(i >> 2));
         const uint32_t wv = (i & 3) == 0 ? sb.x : (i & 3) == 1 ? sb.y : (i & 3) == 2 ? sb.z : sb.w;
         const double uu = RO<double>::u(wv);
         int hn = 0;
@@ -628,12 +655,12 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
                 const R up = RO<R>::u(W.w[NW - 1]);
                 if (g->kind == WOI_SHAPE_POLYLINE2D) {
                     if constexpr (D == 2) {
-                        const PolyHits ph = poly_hits<R, LDS>(dp, *g, pay, y, d, ray, seg, -1, cnt);
+                        const PolyHits ph = poly_hits<R, LDS, false>(dp, *g, pay, y, d, ray, seg, -1, cnt);
                         qn = ph.q;
                         if (qn == 0) { cnt.redraws++; continue; }
                         pick = min((int)(up * (R)qn), qn - 1);
                         int j = pick == 0 ? ph.j0 : ph.j1;
-                        if (pick >= 2) j = poly_hits<R, LDS>(dp, *g, pay, y, d, ray, seg, pick, cnt).j0;
+                        if (pick >= 2) j = poly_hits<R, LDS, true>(dp, *g, pay, y, d, ray, seg, pick, cnt).j0;
                         const R* v = pay + Pay<R>::g(*g) + 2 * j;
                         const R ex = v[2] - v[0], ey = v[3] - v[1];
                         const R den = d[0] * ey - d[1] * ex;
