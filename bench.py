@@ -37,9 +37,9 @@ PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 (packed) peak
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the timed FP32 walk kernel at W = 1e5, from the FETCH_SIZE and
 # WRITE_SIZE passes in profiles/walk_kernel_config2_hbm_counters.md, scaled by what the same
-# counters read for a 1 GiB device copy (factors 2.0 and 1.0).  None whenever the kernel has
-# changed since those passes.
-TRAFFIC_BYTES = 3306 * 1024 * 2.0 + 55432 * 1024 * 1.0
+# counters read for a 1 GiB device copy.  None whenever the kernel has changed since those
+# passes were taken.
+TRAFFIC_BYTES = None
 
 
 class HipEvents:
