@@ -1036,7 +1036,8 @@ Plan make_plan(const woi_problem* p, int64_t P, const woi_query* q, uint64_t n_s
 // Shared-trajectory plan (batch_share B > 1): chunks of samples whose trajectories fit the
 // trajectory budget, evaluation pieces of spt_e samples (the reduction's unit).
 struct SharedPlan {
-    int ng;
+    int ng, lg, tile_rows;
+    unsigned lds;
     uint32_t chunk, spt_g, spt_e;
     int n_chunks, pieces_per_chunk, n_pieces;
     size_t plane, traj_bytes, part_bytes;
@@ -1047,8 +1048,10 @@ SharedPlan make_shared_plan(const woi_problem* p, int64_t P, const woi_query* q,
     const int m = p->H.m, K = q->estimator == WOI_EST_VR ? 2 : 1;
     const size_t rs = q->precision == WOI_PREC_FP32 ? sizeof(float) : sizeof(double);
     sp.ng = (int)((P + q->batch_share - 1) / q->batch_share);
+    const DevProblem* hdr = reinterpret_cast<const DevProblem*>(p->blob.data());
+    sp.lds = hdr->lds_bytes > 0 && m == 2 && hdr->lds_bytes <= woi::lds_budget() ? (unsigned)hdr->lds_bytes : 0u;
     // evaluation pieces: enough (point, piece) lanes to fill the device, >= 16 samples each
-    const uint64_t lanes_target = 1ull << 20;
+    const uint64_t lanes_target = 1ull << 22;
     uint64_t pieces = std::max<uint64_t>(1, lanes_target / (uint64_t)P);
     uint64_t spt_e = std::max<uint64_t>(16, (ns + pieces - 1) / pieces);
     spt_e = std::min<uint64_t>(spt_e, ns);
@@ -1062,9 +1065,16 @@ SharedPlan make_shared_plan(const woi_problem* p, int64_t P, const woi_query* q,
     sp.pieces_per_chunk = (int)(chunk / spt_e);
     sp.n_chunks = (int)((ns + chunk - 1) / chunk);
     sp.n_pieces = (int)((ns + spt_e - 1) / spt_e);
-    // generation: lanes = groups; split the chunk so that >= 2^18 walkers run at once
-    const uint64_t want = std::max<uint64_t>(1, (1ull << 18) / (uint64_t)sp.ng);
+    // generation: lanes = groups in rows of lg lanes; split the chunk so that >= 2^19
+    // walkers run at once
+    const int bs = sp.lds ? 512 : 256;
+    sp.lg = 64;
+    while (sp.lg < sp.ng && sp.lg < bs) sp.lg *= 2;
+    const uint64_t want = std::max<uint64_t>(1, (1ull << 19) / (uint64_t)sp.ng);
     sp.spt_g = (uint32_t)std::max<uint64_t>(1, (chunk + want - 1) / want);
+    // evaluation tiles: as many (sample, walker, step) rows as the LDS budget holds
+    const size_t row_bytes = woi::eval_lds_bytes(q->batch_share, P, m, 1, rs);
+    sp.tile_rows = (int)std::max<size_t>(1, (size_t)woi::EVAL_LDS / row_bytes);
     sp.plane = (size_t)chunk * K * (q->M + 1) * sp.ng;
     sp.traj_bytes = (sp.plane * (m + 1) * rs + 255) & ~size_t(255);
     sp.part_bytes = (size_t)sp.n_pieces * (size_t)P * (2 + 2 * m) * sizeof(double);
@@ -1080,9 +1090,7 @@ woi_status estimate_shared(const woi_problem* p, const double* points, int64_t P
     if (!workspace || workspace_bytes < sp.traj_bytes + sp.part_bytes)
         return fail(WOI_E_OOM, "workspace of %zu bytes is smaller than the %zu bytes needed", workspace_bytes,
                     sp.traj_bytes + sp.part_bytes);
-    const DevProblem* hdr = reinterpret_cast<const DevProblem*>(p->blob.data());
-    const unsigned lds =
-        hdr->lds_bytes > 0 && p->H.m == 2 && hdr->lds_bytes <= woi::lds_budget() ? (unsigned)hdr->lds_bytes : 0u;
+    const unsigned lds = sp.lds;
     const bool vr = q->estimator == WOI_EST_VR, f32 = q->precision == WOI_PREC_FP32;
     woi::KParams kp{};
     kp.dp = static_cast<const DevProblem*>(p->dev);
@@ -1103,7 +1111,9 @@ woi_status estimate_shared(const woi_problem* p, const double* points, int64_t P
     tp.plane = sp.plane;
     tp.ng = sp.ng;
     tp.spt = sp.spt_g;
+    tp.lg = sp.lg;
     tp.spt_e = sp.spt_e;
+    tp.tile_rows = sp.tile_rows;
     if (q->event_begin && hipEventRecord(static_cast<hipEvent_t>(q->event_begin), s) != hipSuccess)
         return fail(WOI_E_DEVICE, "hipEventRecord(begin) failed");
     for (int c = 0; c < sp.n_chunks; ++c) {

@@ -72,19 +72,24 @@ __global__ __launch_bounds__(LDS ? 512 : 256) void walk_kernel(KParams kp) {
 }
 
 // ----------------------------------------------------------------------------- shared trajectories
-// Generation: one lane per point group; all lanes of a wave share the walk index, so with
-// the shared schedule the transition case and geometry record are wave-uniform.
+// Generation: lane = point group.  A workgroup row of tp.lg lanes (a multiple of 64, so a
+// wave never leaves its row) walks one run of tp.spt consecutive samples; a workgroup holds
+// blockDim.x / tp.lg rows.  All lanes of a wave share the walk index, so with the shared
+// schedule the transition case and geometry record are wave-uniform.
 template <typename R, int D, bool VR, bool LDS>
 __global__ __launch_bounds__(LDS ? 512 : 256) void traj_kernel(KParams kp, TParams tp) {
     const DevProblem* __restrict__ dp = kp.dp;
     const R* __restrict__ pay = Pay<R>::base(dp);
     if constexpr (LDS) stage_polylines(dp);
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lg = tp.lg;
+    const int row = __builtin_amdgcn_readfirstlane((int)threadIdx.x / lg);
+    const int g = blockIdx.x * lg + (int)threadIdx.x % lg;
     const bool active = g < tp.ng;
     const int gc = active ? g : tp.ng - 1;
     constexpr int K = VR ? 2 : 1;
     R* planes = static_cast<R*>(tp.traj);
-    const uint32_t s0 = blockIdx.y * tp.spt, s1 = min(s0 + tp.spt, tp.ns);
+    const uint64_t first = ((uint64_t)blockIdx.y * (blockDim.x / lg) + row) * tp.spt;
+    const uint32_t s0 = (uint32_t)min(first, (uint64_t)tp.ns), s1 = (uint32_t)min(first + tp.spt, (uint64_t)tp.ns);
     Counts cnt{0, 0, 0, 0, 0, 0, 0, 0};
     for (uint32_t s = s0; s < s1; ++s) {
         const uint32_t w = (uint32_t)(kp.first_sample + tp.chunk_first + s);
@@ -101,50 +106,104 @@ __global__ __launch_bounds__(LDS ? 512 : 256) void traj_kernel(KParams kp, TPara
     }
 }
 
-// Evaluation: one lane per point; F = N sum_i c_i Phi(x_p, y_i) over the trajectories of the
-// point's group, FP64 per-point sums per piece of samples.
+// Natural log scaled: lnk(x) * ln_scale = ln x.  FP32 uses the hardware log2.
+template <typename R> struct LnK;
+template <> struct LnK<double> {
+    static __device__ __forceinline__ double lnk(double x) { return log(x); }
+    static constexpr double scale = 1.0;
+};
+template <> struct LnK<float> {
+    static __device__ __forceinline__ float lnk(float x) { return __log2f(x); }
+    static constexpr float scale = 0.693147180559945309417232121458f;
+};
+
+// Evaluation: lane = point, workgroup = 256 consecutive points (groups g_lo..g_hi).  The
+// workgroup's piece of tp.spt_e samples is a sequence of rows (sample, walker, step); tiles
+// of tp.tile_rows rows are copied into LDS as records {c_F, c_G, y_0 .. y_{m-1}} per group,
+// with c_F = N c times the Phi prefactor and c_G = -N c / |S^{m-1}|, and every lane then
+// forms F = sum_i c_F phi_i and G = sum_i c_G (x - y_i) / r_i^m from LDS (records of one
+// group are read by all its lanes at once).  Per-sample sums and squares are FP64.
 template <typename R, int D, bool VR>
 __global__ __launch_bounds__(256) void eval_kernel(KParams kp, TParams tp) {
+    constexpr int K = VR ? 2 : 1;
+    constexpr int S = (D + 2 + 3) & ~3;                 // record stride (elements)
     const DevProblem* __restrict__ dp = kp.dp;
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t p = p0 + threadIdx.x;
     const bool active = p < kp.P;
     const int64_t pc = active ? p : kp.P - 1;
+    const int B = kp.batch_share;
+    const int g_lo = (int)(p0 / B);
+    const int nb = (int)((min(p0 + (int64_t)blockDim.x, kp.P) - 1) / B) - g_lo + 1;
+    const int gl = (int)(pc / B) - g_lo;
     R xh[D], xl[D];
     load_point<R, D>(kp.points, pc, xh, xl);
-    const int g = (int)(pc / kp.batch_share);
-    constexpr int K = VR ? 2 : 1;
+    const int M1 = kp.M + 1;
     const R* __restrict__ planes = static_cast<const R*>(tp.traj);
-    const uint32_t s0 = blockIdx.y * tp.spt_e, s1 = min(s0 + tp.spt_e, tp.ns);
-    const int M = kp.M;
+    R* rec = reinterpret_cast<R*>(woi_smem);
     const R N = (R)dp->N;
-    Counts cnt{0, 0, 0, 0, 0, 0, 0, 0};
-    double S1 = 0, S2 = 0, G1[D], G2[D];
+    const R cf = (D == 2 ? R(-0.0795774715459476678844418816863) * LnK<R>::scale : Pay<R>::pc(dp)) * N;
+    const R cg = -N / Pay<R>::ua(dp);
+    const uint32_t s0 = blockIdx.y * tp.spt_e, s1 = min(s0 + tp.spt_e, tp.ns);
+    const int rows = (int)(s1 - s0) * K * M1;
+    const size_t row0 = (size_t)s0 * K * M1;           // first row of the piece in the planes
+    double S1 = 0, S2 = 0, G1[D], G2[D], F = 0, Gs[D];
+    R Fk = 0, Gk[D];
 #pragma unroll
-    for (int i = 0; i < D; ++i) { G1[i] = 0; G2[i] = 0; }
-    for (uint32_t s = s0; s < s1; ++s) {
-        double F = 0, Gs[D];
+    for (int i = 0; i < D; ++i) { G1[i] = 0; G2[i] = 0; Gs[i] = 0; Gk[i] = 0; }
+    int step = 0, walker = 0;                          // position of the current row
+    for (int r0 = 0; r0 < rows; r0 += tp.tile_rows) {
+        const int rn = min(tp.tile_rows, rows - r0);
+        __syncthreads();                                // the previous tile is consumed
+        for (int e = threadIdx.x; e < rn * nb; e += blockDim.x) {
+            const int r = e / nb, gg = e - r * nb;
+            const size_t src = (row0 + r0 + r) * tp.ng + g_lo + gg;
+            const R c = planes[src];
+            R* o = rec + (size_t)e * S;
+            o[0] = c * cf;
+            o[1] = c * cg;
 #pragma unroll
-        for (int i = 0; i < D; ++i) Gs[i] = 0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const R* src = planes + ((size_t)(s * K + k) * (M + 1)) * tp.ng + g;
-            R Fk = 0, Gk[D];
-#pragma unroll
-            for (int i = 0; i < D; ++i) Gk[i] = 0;
-            for (int i = 0; i <= M; ++i) {
-                const R* q = src + (size_t)i * tp.ng;
-                R y[D];
-#pragma unroll
-                for (int d = 0; d < D; ++d) y[d] = q[(d + 1) * tp.plane];
-                add_term<R, D>(dp, xh, xl, y, q[0], Fk, Gk, cnt);
-            }
-            F += (double)(Fk * N);
-#pragma unroll
-            for (int i = 0; i < D; ++i) Gs[i] += (double)(Gk[i] * N);
+            for (int d = 0; d < D; ++d) o[2 + d] = planes[(d + 1) * tp.plane + src];
         }
-        S1 += F; S2 += F * F;
+        __syncthreads();
+        const R* q = rec + (size_t)gl * S;
+        for (int r = 0; r < rn; ++r, q += (size_t)nb * S) {
+            R dv[D], r2 = 0;
 #pragma unroll
-        for (int i = 0; i < D; ++i) { G1[i] += Gs[i]; G2[i] += Gs[i] * Gs[i]; }
+            for (int d = 0; d < D; ++d) { dv[d] = (xh[d] - q[2 + d]) + xl[d]; r2 += dv[d] * dv[d]; }
+            const bool nz = r2 > R(0);                  // |x - y| = 0: the term is skipped
+            R tf, tg;
+            if constexpr (D == 2) {
+                tf = q[0] * LnK<R>::lnk(r2);
+                tg = q[1] * RO<R>::rcp(r2);
+            } else {
+                const R ir = RO<R>::rsq(r2);
+                R ir2 = ir * ir, pw = R(1);
+#pragma unroll
+                for (int i = 0; i < (D - 2) / 2; ++i) pw *= ir2;
+                if constexpr (D % 2) pw *= ir;          // r^{2-m}
+                tf = q[0] * pw;
+                tg = q[1] * pw * ir2;
+            }
+            Fk += nz ? tf : R(0);
+            tg = nz ? tg : R(0);
+#pragma unroll
+            for (int d = 0; d < D; ++d) Gk[d] += tg * dv[d];
+            if (++step == M1) {                         // walker done (uniform branch)
+                step = 0;
+                F += (double)Fk;
+                Fk = 0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) { Gs[d] += (double)Gk[d]; Gk[d] = 0; }
+                if (++walker == K) {                    // sample done
+                    walker = 0;
+                    S1 += F; S2 += F * F;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) { G1[d] += Gs[d]; G2[d] += Gs[d] * Gs[d]; Gs[d] = 0; }
+                    F = 0;
+                }
+            }
+        }
     }
     if (active) {
         double* o = kp.partials + ((size_t)(tp.piece0 + blockIdx.y) * kp.P + p) * (2 + 2 * D);
@@ -225,7 +284,9 @@ static hipError_t launch_traj_t(const KParams& kp, const TParams& tp, unsigned s
             attr = true;
         }
     }
-    const dim3 grid((unsigned)((tp.ng + bs - 1) / bs), (unsigned)((tp.ns + tp.spt - 1) / tp.spt));
+    if (tp.lg < 64 || tp.lg % 64 || bs % tp.lg) return hipErrorInvalidValue;
+    const unsigned rows = (unsigned)(bs / tp.lg), runs = (unsigned)((tp.ns + tp.spt - 1) / tp.spt);
+    const dim3 grid((unsigned)((tp.ng + tp.lg - 1) / tp.lg), (runs + rows - 1) / rows);
     hipLaunchKernelGGL((traj_kernel<R, D, VR, LDS>), grid, dim3(bs), smem, s, kp, tp);
     return hipGetLastError();
 }
@@ -259,9 +320,11 @@ hipError_t launch_traj(const KParams& kp, const TParams& tp, int dim, bool vr, b
 
 template <typename R, int D, bool VR>
 static hipError_t launch_eval_t(const KParams& kp, const TParams& tp, hipStream_t s) {
-    const int bs = 256;
+    const int bs = EVAL_BLOCK;
     const dim3 grid((unsigned)((kp.P + bs - 1) / bs), (unsigned)((tp.ns + tp.spt_e - 1) / tp.spt_e));
-    hipLaunchKernelGGL((eval_kernel<R, D, VR>), grid, dim3(bs), 0, s, kp, tp);
+    const unsigned smem = (unsigned)eval_lds_bytes(kp.batch_share, kp.P, D, tp.tile_rows, sizeof(R));
+    if (smem > (unsigned)EVAL_LDS) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((eval_kernel<R, D, VR>), grid, dim3(bs), smem, s, kp, tp);
     return hipGetLastError();
 }
 

@@ -39,10 +39,11 @@ struct RParams {
     double *mean, *se, *grad, *grad_se;
 };
 
-// Shared trajectories (batch_share B > 1).  Generation: lane = point group g < ng, grid.y
-// splits the chunk's `ns` samples into runs of `spt`; trajectories go to `traj`
+// Shared trajectories (batch_share B > 1).  Generation: lane = point group g < ng; rows of
+// `lg` lanes walk runs of `spt` samples of the chunk's `ns`; trajectories go to `traj`
 // (planes of ns * K * (M + 1) * ng elements, see StoreSink).  Evaluation: lane = point,
-// grid.y = piece of `spt_e` samples; writes partials of piece (piece0 + blockIdx.y).
+// grid.y = piece of `spt_e` samples, staged through LDS `tile_rows` (sample, walker, step)
+// rows at a time; writes partials of piece (piece0 + blockIdx.y).
 struct TParams {
     void* traj;                    // R-typed planes
     size_t plane;                  // elements per plane
@@ -50,9 +51,22 @@ struct TParams {
     uint32_t ns;                   // samples in this chunk
     uint64_t chunk_first;          // first sample index of the chunk
     uint32_t spt;                  // generation: samples per thread
+    int lg;                        // generation: lanes per row (multiple of 64, divides the block)
     uint32_t spt_e;                // evaluation: samples per piece
+    int tile_rows;                 // evaluation: rows per LDS tile
     int piece0;                    // global index of the chunk's first piece
 };
+
+constexpr int EVAL_BLOCK = 256;            // points per evaluation workgroup
+constexpr int EVAL_LDS = 32 * 1024;        // LDS tile budget of the evaluation kernel
+// Groups one evaluation workgroup can touch, and the LDS its tile of `rows` rows takes.
+inline int eval_groups(int B, int64_t P) {
+    const int64_t g = (EVAL_BLOCK + B - 1) / B + 1, ng = (P + B - 1) / B;
+    return (int)(g < ng ? g : ng);
+}
+inline size_t eval_lds_bytes(int B, int64_t P, int dim, int rows, size_t elem) {
+    return (size_t)rows * eval_groups(B, P) * (size_t)((dim + 2 + 3) & ~3) * elem;
+}
 
 hipError_t launch_traj(const KParams& kp, const TParams& tp, int dim, bool vr, bool fp32, unsigned lds_bytes,
                        hipStream_t s);
