@@ -1041,6 +1041,8 @@ struct SharedPlan {
     uint32_t chunk, spt_g, spt_e;
     int n_chunks, pieces_per_chunk, n_pieces;
     size_t plane, traj_bytes, part_bytes;
+    // partial slots: piece y of every chunk goes to slot y
+    int n_slots() const { return n_chunks > 1 ? pieces_per_chunk : n_pieces; }
 };
 
 SharedPlan make_shared_plan(const woi_problem* p, int64_t P, const woi_query* q, uint64_t ns) {
@@ -1077,7 +1079,7 @@ SharedPlan make_shared_plan(const woi_problem* p, int64_t P, const woi_query* q,
     sp.tile_rows = (int)std::max<size_t>(1, (size_t)woi::EVAL_LDS / row_bytes);
     sp.plane = (size_t)chunk * K * (q->M + 1) * sp.ng;
     sp.traj_bytes = (sp.plane * (m + 1) * rs + 255) & ~size_t(255);
-    sp.part_bytes = (size_t)sp.n_pieces * (size_t)P * (2 + 2 * m) * sizeof(double);
+    sp.part_bytes = (size_t)sp.n_slots() * (size_t)P * (2 + 2 * m) * sizeof(double);
     return sp;
 }
 
@@ -1119,7 +1121,7 @@ woi_status estimate_shared(const woi_problem* p, const double* points, int64_t P
     for (int c = 0; c < sp.n_chunks; ++c) {
         tp.chunk_first = (uint64_t)c * sp.chunk;
         tp.ns = (uint32_t)std::min<uint64_t>(sp.chunk, ns - tp.chunk_first);
-        tp.piece0 = c * sp.pieces_per_chunk;
+        tp.accumulate = c > 0;
         hipError_t e = woi::launch_traj(kp, tp, p->H.m, vr, f32, lds, s);
         if (e != hipSuccess) return fail(WOI_E_DEVICE, "trajectory launch failed: %s", hipGetErrorString(e));
         e = woi::launch_eval(kp, tp, p->H.m, vr, f32, s);
@@ -1131,9 +1133,10 @@ woi_status estimate_shared(const woi_problem* p, const double* points, int64_t P
     rp.partials = kp.partials;
     rp.P = P;
     rp.dim = p->H.m;
-    rp.n_chunks = sp.n_pieces;
+    rp.n_chunks = sp.n_slots();
     rp.samples_per_thread = sp.spt_e;
-    rp.n_samples = ns;
+    rp.full = (uint64_t)(sp.n_chunks - 1) * sp.spt_e;
+    rp.tail = ns - (uint64_t)(sp.n_chunks - 1) * sp.chunk;
     rp.mean = mean;
     rp.se = se;
     rp.grad = grad;
@@ -1207,7 +1210,8 @@ woi_status woi_estimate(const woi_problem* p, const double* points, int64_t P, c
     rp.dim = p->H.m;
     rp.n_chunks = pl.chunks;
     rp.samples_per_thread = pl.spt;
-    rp.n_samples = ns;
+    rp.full = 0;
+    rp.tail = ns;
     rp.mean = mean;
     rp.se = se;
     rp.grad = grad;

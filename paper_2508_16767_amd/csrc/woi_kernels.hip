@@ -205,27 +205,42 @@ __global__ __launch_bounds__(256) void eval_kernel(KParams kp, TParams tp) {
             }
         }
     }
-    if (active) {
-        double* o = kp.partials + ((size_t)(tp.piece0 + blockIdx.y) * kp.P + p) * (2 + 2 * D);
-        o[0] = S1; o[1] = S2;
+    if (active) {   // slot blockIdx.y: the same piece of every chunk, summed in chunk order
+        double* o = kp.partials + ((size_t)blockIdx.y * kp.P + p) * (2 + 2 * D);
+        if (tp.accumulate) {
+            o[0] += S1; o[1] += S2;
 #pragma unroll
-        for (int i = 0; i < D; ++i) { o[2 + i] = G1[i]; o[2 + D + i] = G2[i]; }
+            for (int i = 0; i < D; ++i) { o[2 + i] += G1[i]; o[2 + D + i] += G2[i]; }
+        } else {
+            o[0] = S1; o[1] = S2;
+#pragma unroll
+            for (int i = 0; i < D; ++i) { o[2 + i] = G1[i]; o[2 + D + i] = G2[i]; }
+        }
     }
 }
 
-// Per-point merge of the chunk partials in chunk order: deterministic.
-__global__ void reduce_kernel(RParams rp) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Per-point merge of the slot partials: one wave per point; lane l merges slots l, l + 64, ...
+// in order, then the lanes' triples are combined in a fixed butterfly.  Deterministic.
+// Slot c holds full + min(spt, max(0, tail - c spt)) samples.
+__global__ __launch_bounds__(256) void reduce_kernel(RParams rp) {
+    const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (p >= rp.P) return;
     const int D = rp.dim, W = 2 + 2 * D;
     Moments f{0, 0, 0}, g[WOI_MAX_DIM];
     for (int i = 0; i < D; ++i) g[i] = Moments{0, 0, 0};
-    for (int c = 0; c < rp.n_chunks; ++c) {
+    for (int c = lane; c < rp.n_chunks; c += 64) {
         const uint64_t lo = (uint64_t)c * rp.samples_per_thread;
-        const uint64_t hi = min(lo + (uint64_t)rp.samples_per_thread, rp.n_samples);
-        merge_partial(f, g, D, (double)(hi - lo), rp.partials + ((size_t)c * rp.P + p) * W);
+        const uint64_t own = lo < rp.tail ? min((uint64_t)rp.samples_per_thread, rp.tail - lo) : 0;
+        const uint64_t nc = rp.full + own;
+        if (nc == 0) continue;
+        merge_partial(f, g, D, (double)nc, rp.partials + ((size_t)c * rp.P + p) * W);
     }
-    store_moments(f, g, D, p, rp.mean, rp.se, rp.grad, rp.grad_se);
+    for (int o = 1; o < 64; o <<= 1) {
+        f.combine(shfl_xor_moments(f, o));
+        for (int i = 0; i < D; ++i) g[i].combine(shfl_xor_moments(g[i], o));
+    }
+    if (lane == 0) store_moments(f, g, D, p, rp.mean, rp.se, rp.grad, rp.grad_se);
 }
 
 // ----------------------------------------------------------------------------- launchers
@@ -378,8 +393,7 @@ int lds_budget() {
 }
 
 hipError_t launch_reduce(const RParams& rp, hipStream_t s) {
-    const int bs = 256;
-    hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)((rp.P + bs - 1) / bs)), dim3(bs), 0, s, rp);
+    hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)((rp.P + 3) / 4)), dim3(256), 0, s, rp);
     return hipGetLastError();
 }
 

@@ -29,13 +29,15 @@ struct KParams {
     uint64_t* counters;
 };
 
+// Reduction of n_chunks partial slots per point ([slot][P][2 + 2 dim] doubles); slot c holds
+// full + min(samples_per_thread, max(0, tail - c samples_per_thread)) samples.
 struct RParams {
     const double* partials;
     int64_t P;
     int dim;
     int n_chunks;
     uint32_t samples_per_thread;
-    uint64_t n_samples;
+    uint64_t full, tail;
     double *mean, *se, *grad, *grad_se;
 };
 
@@ -43,7 +45,8 @@ struct RParams {
 // `lg` lanes walk runs of `spt` samples of the chunk's `ns`; trajectories go to `traj`
 // (planes of ns * K * (M + 1) * ng elements, see StoreSink).  Evaluation: lane = point,
 // grid.y = piece of `spt_e` samples, staged through LDS `tile_rows` (sample, walker, step)
-// rows at a time; writes partials of piece (piece0 + blockIdx.y).
+// rows at a time; writes (accumulate = 0) or adds to (accumulate = 1) the partials of slot
+// blockIdx.y, so slot y collects piece y of every chunk.
 struct TParams {
     void* traj;                    // R-typed planes
     size_t plane;                  // elements per plane
@@ -54,7 +57,7 @@ struct TParams {
     int lg;                        // generation: lanes per row (multiple of 64, divides the block)
     uint32_t spt_e;                // evaluation: samples per piece
     int tile_rows;                 // evaluation: rows per LDS tile
-    int piece0;                    // global index of the chunk's first piece
+    int accumulate;                // evaluation: add to the slots (every chunk after the first)
 };
 
 constexpr int EVAL_BLOCK = 256;            // points per evaluation workgroup

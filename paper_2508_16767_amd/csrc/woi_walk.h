@@ -744,9 +744,22 @@ struct Moments {
         m2 += m2c + dl * dl * n * nc / nt;
         n = nt;
     }
+    // merge another running triple (the same update with the other side's mean and M2)
+    __device__ __forceinline__ void combine(const Moments& b) {
+        const double nt = n + b.n;
+        if (nt == 0) return;
+        const double dl = b.mu - mu;
+        mu += dl * b.n / nt;
+        m2 += b.m2 + dl * dl * n * b.n / nt;
+        n = nt;
+    }
     // standard error of the mean
     __device__ __forceinline__ double se() const { return n > 1 ? sqrt(fmax(m2, 0.0) / (n - 1) / n) : 0.0; }
 };
+
+__device__ __forceinline__ Moments shfl_xor_moments(const Moments& a, int o) {
+    return Moments{__shfl_xor(a.n, o, 64), __shfl_xor(a.mu, o, 64), __shfl_xor(a.m2, o, 64)};
+}
 
 // Merge one partial record (sum F, sum F^2, sum G[D], sum G^2[D]) of nc samples.
 __device__ __forceinline__ void merge_partial(Moments& f, Moments* g, int D, double nc, const double* __restrict__ o) {
