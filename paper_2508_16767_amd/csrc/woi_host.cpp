@@ -1052,27 +1052,27 @@ SharedPlan make_shared_plan(const woi_problem* p, int64_t P, const woi_query* q,
     sp.ng = (int)((P + q->batch_share - 1) / q->batch_share);
     const DevProblem* hdr = reinterpret_cast<const DevProblem*>(p->blob.data());
     sp.lds = hdr->lds_bytes > 0 && m == 2 && hdr->lds_bytes <= woi::lds_budget() ? (unsigned)hdr->lds_bytes : 0u;
-    // evaluation pieces: enough (point, piece) lanes to fill the device, >= 16 samples each
-    const uint64_t lanes_target = 1ull << 22;
-    uint64_t pieces = std::max<uint64_t>(1, lanes_target / (uint64_t)P);
-    uint64_t spt_e = std::max<uint64_t>(16, (ns + pieces - 1) / pieces);
-    spt_e = std::min<uint64_t>(spt_e, ns);
-    // trajectory chunk: a multiple of spt_e whose planes stay within 256 MiB
+    // trajectory chunk: the samples whose planes fit in 1 GiB; evaluation pieces: enough of
+    // them per chunk for ~4096 workgroups of EVAL_BLOCK points
     const size_t per_sample = (size_t)sp.ng * K * (q->M + 1) * (m + 1) * rs;
-    uint64_t chunk = std::max<uint64_t>(1, (256ull << 20) / per_sample);
-    chunk = std::max<uint64_t>(spt_e, chunk / spt_e * spt_e);
+    const uint64_t chunk0 = std::min<uint64_t>(ns, std::max<uint64_t>(1, (1ull << 30) / per_sample));
+    const uint64_t tiles = (uint64_t)((P + woi::EVAL_BLOCK - 1) / woi::EVAL_BLOCK);
+    const uint64_t want_pieces = std::max<uint64_t>(1, (4096 + tiles - 1) / tiles);
+    const uint64_t spt_e = std::max<uint64_t>(1, (chunk0 + want_pieces - 1) / want_pieces);
+    uint64_t chunk = std::max<uint64_t>(spt_e, chunk0 / spt_e * spt_e);
     chunk = std::min<uint64_t>(chunk, (ns + spt_e - 1) / spt_e * spt_e);
     sp.chunk = (uint32_t)chunk;
     sp.spt_e = (uint32_t)spt_e;
     sp.pieces_per_chunk = (int)(chunk / spt_e);
     sp.n_chunks = (int)((ns + chunk - 1) / chunk);
     sp.n_pieces = (int)((ns + spt_e - 1) / spt_e);
-    // generation: lanes = groups in rows of lg lanes; split the chunk so that >= 2^19
-    // walkers run at once
+    // generation: lanes = groups in rows of lg lanes; split the chunk into runs so that about
+    // 2^21 walkers are launched (several workgroups per CU: short tails)
     const int bs = sp.lds ? 512 : 256;
     sp.lg = 64;
     while (sp.lg < sp.ng && sp.lg < bs) sp.lg *= 2;
-    const uint64_t want = std::max<uint64_t>(1, (1ull << 19) / (uint64_t)sp.ng);
+    const uint64_t want = std::min<uint64_t>(std::max<uint64_t>(1, (1ull << 21) / (uint64_t)sp.ng),
+                                             65535ull * (uint64_t)(bs / sp.lg));   // grid.y limit
     sp.spt_g = (uint32_t)std::max<uint64_t>(1, (chunk + want - 1) / want);
     // evaluation tiles: as many (sample, walker, step) rows as the LDS budget holds
     const size_t row_bytes = woi::eval_lds_bytes(q->batch_share, P, m, 1, rs);

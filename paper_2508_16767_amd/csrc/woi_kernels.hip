@@ -155,8 +155,10 @@ __global__ __launch_bounds__(256) void eval_kernel(KParams kp, TParams tp) {
     for (int r0 = 0; r0 < rows; r0 += tp.tile_rows) {
         const int rn = min(tp.tile_rows, rows - r0);
         __syncthreads();                                // the previous tile is consumed
+        // record e = r nb + gg; (r, gg) advance by (step_r, step_g) per stride of blockDim.x
+        int r = (int)threadIdx.x / nb, gg = (int)threadIdx.x - r * nb;
+        const int step_r = (int)blockDim.x / nb, step_g = (int)blockDim.x - step_r * nb;
         for (int e = threadIdx.x; e < rn * nb; e += blockDim.x) {
-            const int r = e / nb, gg = e - r * nb;
             const size_t src = (row0 + r0 + r) * tp.ng + g_lo + gg;
             const R c = planes[src];
             R* o = rec + (size_t)e * S;
@@ -164,6 +166,9 @@ __global__ __launch_bounds__(256) void eval_kernel(KParams kp, TParams tp) {
             o[1] = c * cg;
 #pragma unroll
             for (int d = 0; d < D; ++d) o[2 + d] = planes[(d + 1) * tp.plane + src];
+            r += step_r;
+            gg += step_g;
+            if (gg >= nb) { gg -= nb; ++r; }
         }
         __syncthreads();
         const R* q = rec + (size_t)gl * S;
