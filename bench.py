@@ -1,16 +1,20 @@
 #!/usr/bin/env python3
 """Walk-on-Interfaces benchmark on one MI355X.
 
-Workload (the 2D tree configuration): unit disk containing 3 nested star interfaces
-r0 (1 + 0.2 cos k t) with (r0, k) = (0.7, 3), (0.4, 5), (0.2, 7) as 2048-vertex polylines
-and 5 circular inclusions (N = 9 regions, depth 3), sigma = 10^U(-1, 2), 5-mode random
-Fourier flux data with zero mean; 4096 evaluation points (25 % within 1e-3 of an
+Headline workload (the 2D tree configuration): unit disk containing 3 nested star
+interfaces r0 (1 + 0.2 cos k t) with (r0, k) = (0.7, 3), (0.4, 5), (0.2, 7) as 2048-vertex
+polylines and 5 circular inclusions (N = 9 regions, depth 3), sigma = 10^U(-1, 2), 5-mode
+random Fourier flux data with zero mean; 4096 evaluation points (25 % within 1e-3 of an
 interface); W = 1e5 walkers per point, M = 4; values and gradients.
 
-One step = one full estimate of all points: the walk kernel plus the per-point reduction,
-inputs resident in HBM.  The headline path is FP32 walks with FP64 per-point sums and the
-wave-uniform shared schedule; the FP64 plain path (same kernel in FP64) is measured for the
-equal-standard-error comparison.  Prints one JSON line.
+One step = one full estimate of all points (walk kernel plus per-point reduction), inputs
+resident in HBM.  The headline path is FP32 walks with FP64 per-point sums and the
+wave-uniform shared schedule; the FP64 plain path (same kernel in FP64) gives the
+equal-standard-error comparison.  Beside it the line reports, at their full sizes: config 2
+with shared trajectories (B = 16 <= 0.5 % of the points, Sec. 4.6), the 512-instance batch
+(one persistent graph launch), 3D spheres + ellipsoids with the variance-reduced estimator,
+and the 6D nested spheres; each with its FP64 plain comparison at equal SE and the paired
+FP32 - FP64 difference on identical random streams.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -26,20 +30,28 @@ sys.path.insert(0, ROOT)
 
 METRIC = "walk-steps/s and eval-points/s at fixed std. error, FP32-batched vs FP64 plain"
 
-# Algorithmic FP work per event of the walk kernel (2D, counted from the kernel source; a
+# Algorithmic FP work per event of the 2D walk kernel (counted from the kernel source; a
 # transcendental counts as one flop, an FMA as two, compares and integer work count zero).
 FLOPS_PER_WALKER_STEP = 29      # Phi + grad Phi + accumulation (19) and the Q/T/sign update (10)
 FLOPS_PER_OTHER = 18            # uniform re-sample + |K*| |dOmega| factor
-FLOPS_PER_NODE_TEST = 7         # signed distance of a block end vertex to the line (5) +- bound (2)
-FLOPS_PER_SEGMENT_TEST = 5      # signed distance of the segment end vertex (crossings add ~10, rare)
+FLOPS_PER_NODE_TEST = 4         # distance of a block end vertex from the line (two FMAs)
+FLOPS_PER_SEGMENT_TEST = 4      # distance of the segment end vertex (crossings add ~10, rare)
 FLOPS_PER_WALKER = 57           # step-0 datum b(y_0) (5-mode Fourier) and Q_0
 PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 (packed) peak
-PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the timed FP32 walk kernel at W = 1e5, from the FETCH_SIZE and
 # WRITE_SIZE passes in profiles/walk_kernel_config2_hbm_counters.md, scaled by what the same
 # counters read for a 1 GiB device copy.  None whenever the kernel has changed since those
 # passes were taken.
 TRAFFIC_BYTES = None
+
+
+def eval_flops_per_pair(m):
+    """Algorithmic flops of one (point, trajectory step) pair of the evaluation kernel:
+    x - y with the low part of x (2m), r^2 (2m - 1), the kernel powers, c_F phi accumulated
+    (2), c_G r^-m (2) and the gradient FMAs (2m); a transcendental counts as one."""
+    if m == 2:
+        return 2 * m + (2 * m - 1) + 2 + 2 + 1 + 2 * m          # log2 and rcp
+    return 2 * m + (2 * m - 1) + 1 + 1 + (m - 2) // 2 + m % 2 + 2 + 2 + 2 * m
 
 
 class HipEvents:
@@ -49,7 +61,6 @@ class HipEvents:
         self.hip = ctypes.CDLL("libamdhip64.so")
         self.hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
         self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
-        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
 
     def create(self):
         e = ctypes.c_void_p()
@@ -69,60 +80,97 @@ def flops_of(counts):
             FLOPS_PER_SEGMENT_TEST * segs + FLOPS_PER_WALKER * walkers)
 
 
-def run_path(woi, torch, prob, pts, walks, M, precision, steps, warmup, ev, seed0):
-    """Untimed counting launch (same workload, its own seed) for the work counts, warm-up
-    launches, then `steps` timed launches of the non-counting kernel."""
-    P = pts.shape[0]
-    out = (torch.empty(P, dtype=torch.float64, device="cuda"), torch.empty(P, dtype=torch.float64, device="cuda"),
-           torch.empty(P, 2, dtype=torch.float64, device="cuda"), torch.empty(P, 2, dtype=torch.float64, device="cuda"))
-    q = woi.make_query(walks, M, precision=precision, schedule_mode=woi.SCHED_SHARED)
-    ws = torch.empty(woi.workspace_size(prob, P, q), dtype=torch.uint8, device="cuda")
-    cnt = woi.new_counters()
-    woi.estimate(prob, pts, walks, M, seed=seed0 + 999, precision=precision, schedule_mode=woi.SCHED_SHARED,
-                 out=out, workspace=ws, counters=cnt)
-    for w in range(warmup):
-        woi.estimate(prob, pts, walks, M, seed=seed0 + 1000 + w, precision=precision, schedule_mode=woi.SCHED_SHARED,
-                     out=out, workspace=ws)
-    evs = [(ev.create(), ev.create()) for _ in range(steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(steps):
-        woi.estimate(prob, pts, walks, M, seed=seed0 + k, precision=precision, schedule_mode=woi.SCHED_SHARED,
-                     out=out, workspace=ws, events=evs[k])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kern_ms = [ev.ms(a, b) for a, b in evs]
-    se = out[1].cpu().numpy()
-    return wall, kern_ms, cnt.cpu().numpy().astype(float) * steps, se, out[0].cpu().numpy()
-
-
 def timed(torch, ev, fn, steps, warmup):
-    """Warm-up calls, then `steps` timed calls of fn(events); returns wall seconds and the
-    per-call HIP-event milliseconds (events recorded by the library on the launch stream)."""
-    for _ in range(warmup):
-        fn(None)
+    """Warm-up calls, then `steps` timed calls fn(k, events); returns wall seconds per call
+    and the per-call HIP-event milliseconds (events recorded by the library on the launch
+    stream around its kernels)."""
+    for w in range(warmup):
+        fn(1000 + w, None)
     evs = [(ev.create(), ev.create()) for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
-        fn(evs[k])
+        fn(k, evs[k])
     torch.cuda.synchronize()
-    return time.perf_counter() - t0, [ev.ms(a, b) for a, b in evs]
+    return (time.perf_counter() - t0) / steps, [ev.ms(a, b) for a, b in evs]
 
 
-def run_shared(woi, torch, prob, pts, walks, M, B, steps, warmup, ev):
-    """Config 2 with shared trajectories (Sec. 4.6): points p with equal p // B share one
-    trajectory set.  Walk-steps here are (point, walk, step) contributions, as for the
-    per-point path."""
-    P = pts.shape[0]
-    out = (torch.empty(P, dtype=torch.float64, device="cuda"), torch.empty(P, dtype=torch.float64, device="cuda"),
-           torch.empty(P, 2, dtype=torch.float64, device="cuda"), torch.empty(P, 2, dtype=torch.float64, device="cuda"))
-    q = woi.make_query(walks, M, precision=woi.FP32, schedule_mode=woi.SCHED_SHARED, batch_share=B)
-    ws = torch.empty(woi.workspace_size(prob, P, q), dtype=torch.uint8, device="cuda")
-    fn = lambda e: woi.estimate(prob, pts, walks, M, seed=77, precision=woi.FP32, schedule_mode=woi.SCHED_SHARED,
-                                batch_share=B, out=out, workspace=ws, events=e)
-    wall, ms = timed(torch, ev, fn, steps, warmup)
-    return wall / steps, ms, out[1].cpu().numpy()
+class Path:
+    """One estimator configuration on resident points: per-point (B = 1) or shared
+    trajectories (B > 1).  Step k uses seed seed0 + k, so two precisions with the same
+    seed0 run on identical random streams."""
+
+    def __init__(self, woi, torch, prob, pts, walks, M, precision, estimator=0, B=1, seed0=1):
+        self.woi, self.torch, self.prob, self.pts = woi, torch, prob, pts
+        self.walks, self.M, self.precision, self.estimator, self.B, self.seed0 = walks, M, precision, estimator, B, seed0
+        P, m = pts.shape
+        self.out = tuple(torch.empty(*s, dtype=torch.float64, device="cuda") for s in ((P,), (P,), (P, m), (P, m)))
+        q = woi.make_query(walks, M, precision=precision, estimator=estimator, schedule_mode=woi.SCHED_SHARED,
+                           batch_share=B)
+        self.ws = torch.empty(woi.workspace_size(prob, P, q), dtype=torch.uint8, device="cuda")
+        self.first = None
+
+    def __call__(self, k, events=None, counters=None):
+        self.woi.estimate(self.prob, self.pts, self.walks, self.M, seed=self.seed0 + k, precision=self.precision,
+                          estimator=self.estimator, schedule_mode=self.woi.SCHED_SHARED, batch_share=self.B,
+                          out=self.out, workspace=self.ws, events=events, counters=counters)
+        if k == 0 and events is not None:
+            self.first = (self.out[0].clone(), self.out[1].clone())
+
+    def run(self, ev, steps, warmup):
+        wall, ms = timed(self.torch, ev, self, steps, warmup)
+        mean, se = (t.cpu().numpy() for t in self.first)
+        return {"wall": wall, "ms": ms, "mean": mean, "se": se}
+
+    def counts(self):
+        cnt = self.woi.new_counters()
+        self(999, counters=cnt)
+        return cnt.cpu().numpy().astype(float)
+
+
+def fixed_se(r, eps):
+    """Time per step rescaled to standard error eps (SE ~ 1/sqrt(W))."""
+    import numpy as np
+    return r["wall"] * float(np.mean(r["se"] ** 2)) / eps ** 2
+
+
+def paired(r32, r64):
+    """FP32 - FP64 means on identical streams, in units of the FP64 standard error."""
+    import numpy as np
+    z = (r32["mean"] - r64["mean"]) / r64["se"]
+    return {"mean_z": float(np.mean(z)), "mean_abs_z": float(np.mean(np.abs(z))), "max_abs_z": float(np.max(np.abs(z)))}
+
+
+def config_block(woi, torch, ev, name, prob_desc, pts_np, walks, M, estimator, B, steps):
+    """Per-point FP32 and FP64 and shared-trajectory FP32 for one configuration."""
+    import numpy as np
+    prob = woi.Problem(prob_desc)
+    woi._lib.woi_problem_upload(prob.handle)
+    pts = torch.tensor(pts_np, dtype=torch.float64, device="cuda")
+    P, m = pts.shape
+    K = 2 if estimator else 1
+    point_steps = P * walks * (M + 1)                           # (point, walker, step) contributions
+    r32 = Path(woi, torch, prob, pts, walks, M, woi.FP32, estimator).run(ev, steps, 1)
+    r64 = Path(woi, torch, prob, pts, walks, M, woi.FP64, estimator).run(ev, 1, 0)
+    rsh = Path(woi, torch, prob, pts, walks, M, woi.FP32, estimator, B).run(ev, steps, 1)
+    eps = float(np.median(r64["se"]))
+    t64 = fixed_se(r64, eps)
+    pairs = P * (walks // K) * K * (M + 1)
+    ev_fl = pairs * eval_flops_per_pair(m) / (float(np.mean(rsh["ms"])) * 1e-3) / 1e12
+    return {
+        "workload": name, "points": P, "walkers": walks, "M": M, "estimator": "VR" if estimator else "plain",
+        "fixed_se": eps,
+        "fp32_per_point": {"walk_steps_per_s": point_steps / r32["wall"], "ms_per_step": r32["wall"] * 1e3,
+                           "speedup_vs_fp64_plain_fixed_se": t64 / fixed_se(r32, eps)},
+        "fp64_plain": {"walk_steps_per_s": point_steps / r64["wall"], "ms_per_step": r64["wall"] * 1e3,
+                       "eval_points_per_s_fixed_se": P / t64},
+        "fp32_shared_trajectories": {"batch_share": B, "walk_steps_per_s": point_steps / rsh["wall"],
+                                     "ms_per_step": rsh["wall"] * 1e3,
+                                     "eval_points_per_s_fixed_se": P / fixed_se(rsh, eps),
+                                     "speedup_vs_fp64_plain_fixed_se": t64 / fixed_se(rsh, eps),
+                                     "pair_eval_tflops_over_traj_plus_eval": ev_fl},
+        "fp32_vs_fp64_paired_z": paired(r32, r64),
+    }
 
 
 def run_batch(woi, torch, W, precision, steps, warmup, ev):
@@ -136,11 +184,37 @@ def run_batch(woi, torch, W, precision, steps, warmup, ev):
     cnt = woi.new_counters()
     woi.Batch(entries, counters=cnt).run()
     b = woi.Batch(entries)
-    wall, ms = timed(torch, ev, lambda e: b.run(events=e), steps, warmup)
+    wall, ms = timed(torch, ev, lambda k, e: b.run(events=e), steps, warmup)
     counts = cnt.cpu().numpy().astype(float)
     se = [o[1].cpu().numpy() for o in b.outputs]
-    return {"wall": wall / steps, "ms": ms, "counts": counts, "se": se,
+    mean = [o[0].cpu().numpy() for o in b.outputs]
+    return {"wall": wall, "ms": ms, "counts": counts, "se": se, "mean": mean,
             "points": sum(x.shape[0] for _, x, _ in inst), "walkers": sum(x.shape[0] * w for _, x, w in inst)}
+
+
+def batch_block(woi, torch, W, ev, steps):
+    import numpy as np
+    b32 = run_batch(woi, torch, W, woi.FP32, steps, 1, ev)
+    b64 = run_batch(woi, torch, W, woi.FP64, 1, 0, ev)
+    # fixed SE per instance: median SE of the FP64 batch, time rescaled by the mean SE^2 ratio
+    bt32 = b32["wall"] * np.mean([np.mean(a ** 2) / np.median(c) ** 2 for a, c in zip(b32["se"], b64["se"])])
+    bt64 = b64["wall"] * np.mean([np.mean(c ** 2) / np.median(c) ** 2 for c in b64["se"]])
+    z = np.concatenate([(a - c) / s for a, c, s in zip(b32["mean"], b64["mean"], b64["se"])])
+    kms = float(np.mean(b32["ms"]))
+    bfl = flops_of(b32["counts"])
+    return {
+        "workload": "512 independent 2D instances: 1-16 circle/512-vertex star interfaces in random nesting trees, "
+                    "sigma 10^U(-1,3), P = 2^U(4,10), W = 10^U(3,6), M = 4; one persistent graph launch",
+        "points": b32["points"], "walkers": b32["walkers"],
+        "walk_steps_per_s": b32["counts"][0] / b32["wall"], "ms_per_step": b32["wall"] * 1e3, "graph_ms": kms,
+        "fp64_walk_steps_per_s": b64["counts"][0] / b64["wall"], "fp64_ms_per_step": b64["wall"] * 1e3,
+        "speedup_fp32_vs_fp64_fixed_se": bt64 / bt32,
+        "fp32_vs_fp64_paired_z": {"mean_z": float(np.mean(z)), "mean_abs_z": float(np.mean(np.abs(z))),
+                                  "max_abs_z": float(np.max(np.abs(z)))},
+        "roofline": {"bound": "alu", "achieved": bfl / (kms * 1e-3) / 1e12, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": bfl / (kms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "batch_kernel<float, 2, false, false, WV, true> + fill + reduce (graph)",
+                     "counts_per_launch": {n: float(v) for n, v in zip(woi.COUNTER_NAMES, b32["counts"])}}}
 
 
 def cpu_baseline(prob, pts, walks, M, budget_s):
@@ -172,8 +246,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-extra", action="store_true",
-                    help="measure only the headline path (skip config 3 batched and shared trajectories)")
-    ap.add_argument("--batch-steps", type=int, default=2)
+                    help="measure only the headline path (skip shared trajectories and configs 3-5)")
+    ap.add_argument("--extra-steps", type=int, default=2, help="timed steps of the other configurations")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after the run, copy this many bytes device-to-device three times (a plain copy "
@@ -191,38 +265,35 @@ def main():
     from paper_2508_16767_amd import woi
 
     torch.cuda.set_device(0)
+    ev = HipEvents()
     prob_desc, pts_np = W.config2()
     M = 4
     prob = woi.Problem(prob_desc)
     woi._lib.woi_problem_upload(prob.handle)
     pts = torch.tensor(pts_np, dtype=torch.float64, device="cuda")
     P = pts.shape[0]
-    ev = HipEvents()
 
-    wall32, k32, c32, se32, _ = run_path(woi, torch, prob, pts, args.walks, M, woi.FP32, args.steps, args.warmup, ev, 1)
-    wall64, k64, c64, se64, _ = run_path(woi, torch, prob, pts, args.walks, M, woi.FP64, args.fp64_steps,
-                                         min(args.warmup, 1), ev, 101)
+    p32 = Path(woi, torch, prob, pts, args.walks, M, woi.FP32)
+    c32 = p32.counts()                                 # untimed counting launch of the same workload
+    r32 = p32.run(ev, args.steps, args.warmup)
+    p64 = Path(woi, torch, prob, pts, args.walks, M, woi.FP64)
+    c64 = p64.counts()
+    r64 = p64.run(ev, args.fp64_steps, min(args.warmup, 1))
 
-    steps32 = c32[0] / args.steps                     # walker-steps per step
-    value = c32[0] / wall32
-    value64 = c64[0] / wall64
-    t32, t64 = wall32 / args.steps, wall64 / args.fp64_steps
-    eps = float(np.median(se64))                      # fixed SE: median per-point SE of FP64 plain
-    t32_eps = t32 * float(np.mean(se32 ** 2)) / eps ** 2
-    t64_eps = t64 * float(np.mean(se64 ** 2)) / eps ** 2
-    kern_ms = float(np.mean(k32))
-    flops = flops_of(c32 / args.steps)
+    eps = float(np.median(r64["se"]))                  # fixed SE: median per-point SE of FP64 plain
+    t32_eps, t64_eps = fixed_se(r32, eps), fixed_se(r64, eps)
+    kern_ms = float(np.mean(r32["ms"]))
+    flops = flops_of(c32)
     achieved = flops / (kern_ms * 1e-3) / 1e12
-    kern64_ms = float(np.mean(k64))
-    flops64 = flops_of(c64 / args.fp64_steps)
+    kern64_ms = float(np.mean(r64["ms"]))
     rec = {
         "metric": METRIC,
-        "value": value,
+        "value": c32[0] / r32["wall"],
         "unit": "walk-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": t32 * 1e3,
+        "ms_per_step": r32["wall"] * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -235,45 +306,40 @@ def main():
                    "precision": "FP32 walks, FP64 per-point sums"},
         "eval_points_per_s_fixed_se": P / t32_eps,
         "fixed_se": eps,
-        "fp64_plain": {"walk_steps_per_s": value64, "ms_per_step": t64 * 1e3,
+        "fp64_plain": {"walk_steps_per_s": c64[0] / r64["wall"], "ms_per_step": r64["wall"] * 1e3,
                        "eval_points_per_s_fixed_se": P / t64_eps, "walk_kernel_ms": kern64_ms,
-                       "fp64_tflops": flops64 / (kern64_ms * 1e-3) / 1e12},
+                       "fp64_tflops": flops_of(c64) / (kern64_ms * 1e-3) / 1e12},
         "speedup_fp32_vs_fp64_fixed_se": t64_eps / t32_eps,
+        "fp32_vs_fp64_paired_z": paired(r32, r64),
         "walk_kernel_ms": kern_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": TRAFFIC_BYTES if args.walks == 100000 else None,
                      "kernel": "walk_kernel<float, 2, false, false, true> (FP32, 2D, plain, LDS-staged polylines)",
                      "flops_per_launch": flops,
-                     "counts_per_launch": {n: float(v / args.steps) for n, v in zip(woi.COUNTER_NAMES, c32)}},
+                     "counts_per_launch": {n: float(v) for n, v in zip(woi.COUNTER_NAMES, c32)}},
     }
     if not args.no_extra:
-        B = 16                                            # <= 0.5 % of the 4096 points
-        t_sh, ms_sh, se_sh = run_shared(woi, torch, prob, pts, args.walks, M, B, args.steps, args.warmup, ev)
-        t_sh_eps = t_sh * float(np.mean(se_sh ** 2)) / eps ** 2
+        B = 16                                          # <= 0.5 % of the 4096 points
+        rsh = Path(woi, torch, prob, pts, args.walks, M, woi.FP32, 0, B).run(ev, args.steps, args.warmup)
+        pairs = P * args.walks * (M + 1)
         rec["shared_trajectories"] = {
-            "batch_share": B, "walk_steps_per_s": P * args.walks * (M + 1) / t_sh, "ms_per_step": t_sh * 1e3,
-            "traj_plus_eval_ms": float(np.mean(ms_sh)), "eval_points_per_s_fixed_se": P / t_sh_eps,
-            "speedup_vs_fp64_plain_fixed_se": t64_eps / t_sh_eps}
-        b32 = run_batch(woi, torch, W, woi.FP32, args.batch_steps, 1, ev)
-        b64 = run_batch(woi, torch, W, woi.FP64, 1, 0, ev)
-        # fixed SE per instance: median SE of the FP64 batch; points/s at that SE summed over instances
-        bt32 = b32["wall"] * np.mean([np.mean(a ** 2) / np.median(c) ** 2 for a, c in zip(b32["se"], b64["se"])])
-        bt64 = b64["wall"] * np.mean([np.mean(c ** 2) / np.median(c) ** 2 for c in b64["se"]])
-        kms = float(np.mean(b32["ms"]))
-        bfl = flops_of(b32["counts"])
-        rec["batched_config3"] = {
-            "workload": "512 independent 2D instances: 1-16 circle/512-vertex star interfaces in random nesting "
-                        "trees, sigma 10^U(-1,3), P = 2^U(4,10), W = 10^U(3,6), M = 4; one persistent graph launch",
-            "points": b32["points"], "walkers": b32["walkers"],
-            "walk_steps_per_s": b32["counts"][0] / b32["wall"], "ms_per_step": b32["wall"] * 1e3,
-            "graph_ms": kms, "fp64_walk_steps_per_s": b64["counts"][0] / b64["wall"],
-            "fp64_ms_per_step": b64["wall"] * 1e3,
-            "speedup_fp32_vs_fp64_fixed_se": bt64 / bt32,
-            "roofline": {"bound": "alu", "achieved": bfl / (kms * 1e-3) / 1e12, "peak": PEAK_FP32_TFLOPS,
-                         "unit": "TFLOP/s", "frac": bfl / (kms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, "traffic": None,
-                         "kernel": "batch_kernel<float, 2, false, false, WV, true> + fill + reduce (graph)",
-                         "counts_per_launch": {n: float(v) for n, v in zip(woi.COUNTER_NAMES, b32["counts"])}}}
+            "batch_share": B, "walk_steps_per_s": pairs / rsh["wall"], "ms_per_step": rsh["wall"] * 1e3,
+            "traj_plus_eval_ms": float(np.mean(rsh["ms"])),
+            "eval_points_per_s_fixed_se": P / fixed_se(rsh, eps),
+            "speedup_vs_fp64_plain_fixed_se": t64_eps / fixed_se(rsh, eps),
+            "pair_eval_tflops_over_traj_plus_eval":
+                pairs * eval_flops_per_pair(2) / (float(np.mean(rsh["ms"])) * 1e-3) / 1e12}
+        rec["batched_config3"] = batch_block(woi, torch, W, ev, args.extra_steps)
+        p4, x4 = W.config4()
+        rec["config4_3d_vr"] = config_block(
+            woi, torch, ev, "unit ball, spheres 0.6 > 0.3, 10 ellipsoids (semi-axes 0.03-0.08), sigma 10^U(log .5, "
+            "log 50), real SH l <= 4 data; 16384 points; VR, W = 1e5 walkers, M = 6", p4, x4, 100000, 6, 1, 64,
+            args.extra_steps)
+        p5, x5 = W.config5()
+        rec["config5_6d"] = config_block(
+            woi, torch, ev, "unit 6-ball, spheres 0.7 > 0.35, sigma (1, 5, 0.2), c + lambda x1/|x| data; 1024 points; "
+            "W = 1e6, M = 8", p5, x5, 1000000, 8, 0, 4, args.extra_steps)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(prob_desc, pts_np, args.walks, M, args.cpu_seconds)
     print(json.dumps(rec), flush=True)
