@@ -13,6 +13,10 @@ namespace woi {
 
 enum : int { REL_SAME = 1, REL_DESC = 2, REL_OTHER = 3 };
 
+// Device-only data kind: DIRPOLY data in dimension 2 or 3 stored as a dense triangular
+// coefficient table in nested-Horner order (nt = total degree n), followed by the center.
+constexpr int DK_DIRPOLY_HORNER = 16;
+
 // Geometry payload of one region (offsets g64 / g32, same layout in both types):
 //   SPHERE     : c[m], R
 //   ELLIPSOID  : c[m], A[m*m], L[m*m] (= A^{-1/2}), 1/lambda_max(A)

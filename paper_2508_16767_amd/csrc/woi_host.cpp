@@ -661,6 +661,35 @@ double seg_dist(const double* p, const double* a, const double* b) {
 // [b 2^l, min((b+1) 2^l, n)] lies within bnd of the block's chord segment, so its signed
 // distance to any line lies within [min(h_first, h_last) - bnd, max(...) + bnd].
 // Inflated to stay conservative under FP32 rounding.
+// DIRPOLY data in dimension 2 or 3 as a dense triangular coefficient table c[i][j](k) over
+// total degree <= n, in the order a nested Horner evaluation reads it (i, j, k descending):
+// b = sum_i e0^i sum_j e1^j sum_k e2^k c_ijk.  Declined (false) when the table would be
+// much larger than the term list.
+bool dirpoly_dense(const HostRegion& g, int m, std::vector<double>& dense, int& n) {
+    n = 0;
+    for (int t = 0; t < g.nt; ++t) {
+        int s = 0;
+        for (int d = 0; d < m; ++d) s += g.exps[(size_t)t * m + d];
+        n = std::max(n, s);
+    }
+    const size_t size = m == 2 ? (size_t)(n + 1) * (n + 2) / 2 : (size_t)(n + 1) * (n + 2) * (n + 3) / 6;
+    if (size > std::max<size_t>(64, 4 * (size_t)g.nt)) return false;
+    auto pos = [&](int i, int j, int k) -> size_t {   // index of (i, j, k) in Horner order
+        size_t p = 0;
+        for (int a = n; a > i; --a)
+            p += m == 2 ? (size_t)(n - a + 1) : (size_t)(n - a + 1) * (n - a + 2) / 2;
+        for (int b = n - i; b > j; --b) p += m == 2 ? 1 : (size_t)(n - i - b + 1);
+        if (m == 3) p += (size_t)(n - i - j - k);
+        return p;
+    };
+    dense.assign(size, 0.0);
+    for (int t = 0; t < g.nt; ++t) {
+        const uint8_t* e = &g.exps[(size_t)t * m];
+        dense[pos(e[0], e[1], m == 3 ? e[2] : 0)] += g.coef[t];
+    }
+    return true;
+}
+
 void block_bounds(const HostRegion& g, std::vector<float>& bnd, int& n2, int& top) {
     const int n = g.nv();
     n2 = 1;
@@ -859,7 +888,16 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
                 pi.push_back(std::max(0, std::min(j, n - 1)));
             }
         }
-        if (!g.coef.empty()) {
+        std::vector<double> dense;
+        int degree = 0;
+        if (g.dkind == WOI_DATA_DIRPOLY && m <= 3 && dirpoly_dense(g, m, dense, degree)) {
+            // device form: dense triangular coefficients in nested-Horner order, then the center
+            for (int k = 0; k < m; ++k) dense.push_back(g.coef[g.nt + k]);
+            r.dkind = woi::DK_DIRPOLY_HORNER;
+            r.nt = degree;
+            r.d64 = put64(dense.data(), dense.size());
+            r.d32 = put32(dense.data(), dense.size());
+        } else if (!g.coef.empty()) {
             r.d64 = put64(g.coef.data(), g.coef.size());
             r.d32 = put32(g.coef.data(), g.coef.size());
         }

@@ -222,7 +222,12 @@ __device__ __forceinline__ R data_b(const DevProblem* dp, const DevRegion& g, co
         return cf[0] * dn / rm;
     }
     // direction-based data: e = (y - c)/|y - c|, c stored after the coefficients
-    const R* c = cf + (g.dkind == WOI_DATA_FOURIER2D ? 2 * g.nt + 1 : g.nt);
+    int ncoef = g.dkind == WOI_DATA_FOURIER2D ? 2 * g.nt + 1 : g.nt;
+    if (D <= 3 && g.dkind == DK_DIRPOLY_HORNER) {
+        const int n = g.nt;
+        ncoef = D == 2 ? (n + 1) * (n + 2) / 2 : (n + 1) * (n + 2) * (n + 3) / 6;
+    }
+    const R* c = cf + ncoef;
     R e[D], r2 = 0;
 #pragma unroll
     for (int i = 0; i < D; ++i) { e[i] = y[i] - c[i]; r2 += e[i] * e[i]; }
@@ -238,6 +243,27 @@ __device__ __forceinline__ R data_b(const DevProblem* dp, const DevRegion& g, co
             b += cf[2 * k - 1] * zr + cf[2 * k] * zi;
         }
         return b;
+    }
+    if constexpr (D <= 3) {
+        if (g.dkind == DK_DIRPOLY_HORNER) {   // nested Horner over the dense triangular table
+            const int n = g.nt;
+            const R* q = cf;
+            R b0 = 0;
+            for (int i = n; i >= 0; --i) {
+                R b1 = 0;
+                for (int j = n - i; j >= 0; --j) {
+                    if constexpr (D == 3) {
+                        R b2 = 0;
+                        for (int k = n - i - j; k >= 0; --k) b2 = b2 * e[2] + *q++;
+                        b1 = b1 * e[1] + b2;
+                    } else {
+                        b1 = b1 * e[1] + *q++;
+                    }
+                }
+                b0 = b0 * e[0] + b1;
+            }
+            return b0;
+        }
     }
     const unsigned char* ex = reinterpret_cast<const unsigned char*>(dp) + dp->offb + g.dexp;
     R b = 0;

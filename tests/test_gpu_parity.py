@@ -277,3 +277,27 @@ def test_shared_trajectory_exact_expectation():
     ref = [CF.concentric_uM([1, .5], [10, 1], [1, 1], 1, 2, 4, x, H, gH) for x in xs]
     z = (mean - np.array([r[0] for r in ref])) / se
     assert np.max(np.abs(z)) < 4.5
+
+
+def test_shared_trajectories_across_chunks():
+    """Trajectory planes larger than one chunk (1 GiB): the evaluation slots accumulate piece y of
+    every chunk.  6D nested spheres, 4096 points in pairs (B = 2), M = 32: about 1.9 MB of
+    trajectories per sample, so W = 2000 spans four chunks; sampled points against the oracle
+    on the same streams, FP32 paired with FP64."""
+    p, _ = W.config5()
+    xs = W.ball_points(np.random.default_rng(17), 4096, 6, 0.95)
+    gp = woi.Problem(p)
+    B, M, walks = 2, 32, 2000
+    m64, s64, g64, _ = [_np(t) for t in woi.estimate(gp, xs, walks, M, seed=8, schedule_mode=1, batch_share=B)]
+    m32, _, _, _ = [_np(t) for t in woi.estimate(gp, xs, walks, M, seed=8, precision=woi.FP32, schedule_mode=1,
+                                                  batch_share=B)]
+    idx = np.array([0, 1, 2047, 2048, 4094, 4095])
+    mo, so, go, _, _ = O.estimate(O.OracleProblem(p), xs[idx], walks, M, seed=8, schedule_mode=1, batch_share=B,
+                                  groups=idx // B)
+    assert np.allclose(m64[idx], mo, rtol=1e-9, atol=1e-9 * so.max())
+    assert np.allclose(s64[idx], so, rtol=1e-7)
+    assert np.allclose(g64[idx], go, rtol=1e-9, atol=1e-9 * np.abs(go).max())
+    # FP32 paired with FP64: at M = 32 a rare FP32 decision flip carries weights up to
+    # ||alpha||_1^32, so single points may move by a few SE; the bulk must not move
+    z = np.abs(m32 - m64) / s64
+    assert np.all(np.isfinite(z)) and np.median(z) < 0.01 and np.quantile(z, 0.99) < 0.1 and z.max() < 5.0
