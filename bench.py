@@ -42,7 +42,7 @@ PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 (packed) peak
 # WRITE_SIZE passes in profiles/walk_kernel_config2_hbm_counters.md, scaled by what the same
 # counters read for a 1 GiB device copy.  None whenever the kernel has changed since those
 # passes were taken.
-TRAFFIC_BYTES = 3428 * 1024 * 2.0 + 63997 * 1024 * 1.0
+TRAFFIC_BYTES = None
 
 
 def eval_flops_per_pair(m):

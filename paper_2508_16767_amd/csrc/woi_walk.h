@@ -137,6 +137,17 @@ struct Counts {
     uint32_t steps, redraws, rejections, caps, zero, nodes, segs, other;
 };
 
+// Polyline tables staged by the workgroup (FP32 vertices, FP16 block bounds).
+extern __shared__ __align__(16) char woi_smem[];
+
+// Vertices of a polyline in precision R: the LDS copy when the kernel staged the polylines
+// (FP32 only: the staged copy is the FP32 array itself), else the payload in global memory.
+template <typename R, bool LDS>
+__device__ __forceinline__ const R* poly_xy(const DevRegion& g, const R* __restrict__ pay) {
+    if constexpr (LDS && std::is_same<R, float>::value) return reinterpret_cast<const R*>(woi_smem + g.lds_v);
+    else return pay + Pay<R>::g(g);
+}
+
 constexpr int dir_words(int D) { return D == 2 ? 1 : (D == 3 ? 2 : 2 * ((D + 1) / 2)); }
 
 // ----------------------------------------------------------------------------- directions
@@ -174,7 +185,7 @@ template <typename R, int D>
 __device__ __forceinline__ void normal_at(const DevRegion& g, const R* __restrict__ pay, const R y[D], int seg, R n[D]) {
     const R* q = pay + Pay<R>::g(g);
     if (g.kind == WOI_SHAPE_SPHERE) {
-        const R iR = R(1) / q[D];
+        const R iR = RO<R>::rcp(q[D]);   // FP64: exact division
 #pragma unroll
         for (int i = 0; i < D; ++i) n[i] = (y[i] - q[i]) * iR;
     } else if (g.kind == WOI_SHAPE_ELLIPSOID) {
@@ -186,7 +197,7 @@ __device__ __forceinline__ void normal_at(const DevRegion& g, const R* __restric
             for (int j = 0; j < D; ++j) t += q[D + i * D + j] * (y[j] - q[j]);
             n[i] = t; s += t * t;
         }
-        const R inv = R(1) / RO<R>::sq(s);
+        const R inv = RO<R>::rsq(s);     // FP64: 1 / sqrt
 #pragma unroll
         for (int i = 0; i < D; ++i) n[i] *= inv;
     } else {
@@ -287,7 +298,7 @@ __device__ __forceinline__ const int* int_payload(const DevProblem* dp) {
 // into the trajectory-generation kernel at -O2/-O3 (ROCm 7.2 clang) it produced points off
 // the polyline in "other" transitions, while -O1, an out-of-line call, and the per-point
 // kernel were exact; the shared-trajectory parity tests check this path.
-template <typename R, int D>
+template <typename R, int D, bool LDS>
 __device__ __noinline__ bool polyline_at(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay, R s,
                                             R y[D], int& seg) {
     if constexpr (D == 2) {
@@ -298,7 +309,7 @@ __device__ __noinline__ bool polyline_at(const DevProblem* dp, const DevRegion& 
         int j = int_payload(dp)[g.guide + k];
         while (j < n - 1 && cum[j + 1] <= s) ++j;
         while (j > 0 && cum[j] > s) --j;
-        const R* v = pay + Pay<R>::g(g) + 2 * j;
+        const R* v = poly_xy<R, LDS>(g, pay) + 2 * j;
         const R f = (s - cum[j]) / pay[Pay<R>::len(g) + j];
         y[0] = v[0] + f * (v[2] - v[0]); y[1] = v[1] + f * (v[3] - v[1]);
         seg = j;
@@ -311,13 +322,13 @@ __device__ __forceinline__ int surf_words(const DevRegion& g) {
     return g.kind == WOI_SHAPE_POLYLINE2D ? 1 : dir_words(D) + (g.kind == WOI_SHAPE_ELLIPSOID ? 1 : 0);
 }
 
-template <typename R, int D>
+template <typename R, int D, bool LDS>
 __device__ __forceinline__ bool surf_attempt(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
                                              const Stream& st, uint32_t step, int att, R y[D], int& seg) {
     seg = 0;
     if (g.kind == WOI_SHAPE_POLYLINE2D) {
         Words<1> W; W.fill(st, step, (uint32_t)att);
-        return polyline_at<R, D>(dp, g, pay, RO<R>::u(W.w[0]) * Pay<R>::total(g), y, seg);
+        return polyline_at<R, D, LDS>(dp, g, pay, RO<R>::u(W.w[0]) * Pay<R>::total(g), y, seg);
     }
     const R* q = pay + Pay<R>::g(g);
     if (g.kind == WOI_SHAPE_SPHERE) {
@@ -348,11 +359,11 @@ __device__ __forceinline__ bool surf_attempt(const DevProblem* dp, const DevRegi
 }
 
 // point at arclength s on a closed 2D curve (circle or polyline)
-template <typename R, int D>
+template <typename R, int D, bool LDS>
 __device__ __forceinline__ void curve_at(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay, R s,
                                          R y[D], int& seg) {
     if constexpr (D == 2) {
-        if (g.kind == WOI_SHAPE_POLYLINE2D) { polyline_at<R, D>(dp, g, pay, s, y, seg); return; }
+        if (g.kind == WOI_SHAPE_POLYLINE2D) { polyline_at<R, D, LDS>(dp, g, pay, s, y, seg); return; }
         const R* q = pay + Pay<R>::g(g);
         R sn, cs;
         RO<R>::sc2pi(s / (R(2) * R(3.14159265358979323846) * q[2]), sn, cs);
@@ -361,7 +372,7 @@ __device__ __forceinline__ void curve_at(const DevProblem* dp, const DevRegion& 
 }
 
 // one attempt of a uniform sample on the VR half `cls` of region h
-template <typename R, int D>
+template <typename R, int D, bool LDS>
 __device__ __forceinline__ bool vr_attempt(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
                                            int cls, const Stream& st, int att, R y[D], int& seg) {
     if constexpr (D == 2) {
@@ -375,17 +386,17 @@ __device__ __forceinline__ bool vr_attempt(const DevProblem* dp, const DevRegion
             if (c == cls) {
                 const R l = end - start;
                 if (t < acc + l || p == g.nbrk) {
-                    curve_at<R, D>(dp, g, pay, fmin(start + (t - acc), end), y, seg);
+                    curve_at<R, D, LDS>(dp, g, pay, fmin(start + (t - acc), end), y, seg);
                     return true;
                 }
                 acc += l;
             }
             start = end; c ^= 1;
         }
-        curve_at<R, D>(dp, g, pay, start, y, seg);
+        curve_at<R, D, LDS>(dp, g, pay, start, y, seg);
         return true;
     } else {
-        if (!surf_attempt<R, D>(dp, g, pay, st, 0, att, y, seg)) return false;
+        if (!surf_attempt<R, D, LDS>(dp, g, pay, st, 0, att, y, seg)) return false;
         return (Pay<R>::s(g) * data_b<R, D>(dp, g, pay, y, seg) >= R(0)) == (cls == 0);
     }
 }
@@ -434,8 +445,6 @@ __device__ __forceinline__ int quadric_hit(const DevRegion& g, const R* __restri
 // FIND = false: count all hits (q) remembering the first two; FIND: stop at hit `want`.
 struct PolyHits { int q, j0, j1; };
 
-// Polyline tables staged by the workgroup (FP32 vertices, FP16 block bounds).
-extern __shared__ __align__(16) char woi_smem[];
 
 constexpr bool COUNT_POLY = true;   // dead code unless the counting kernel reads the counters
 
@@ -443,7 +452,7 @@ template <typename R, bool LDS, bool FIND>
 __device__ __forceinline__ PolyHits poly_hits(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
                                               const R y[2], const R d[2], bool ray, int yseg, int want, Counts& cnt) {
     constexpr bool F32 = std::is_same<R, float>::value;
-    const R* __restrict__ v = pay + Pay<R>::g(g);            // exact tests, precision R
+    const R* __restrict__ v = poly_xy<R, LDS>(g, pay);       // exact tests, precision R
     const int n = g.nv, n2 = g.n2, top = g.top;
     // block tests run in FP32 on the staged (or global) FP32 copy; bounds absorb the rounding
     const float* __restrict__ vf;
@@ -625,8 +634,8 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
     int seg = 0, att;
     for (att = 0; att < WOI_ATTEMPT_CAP; ++att) {
         bool ok;
-        if constexpr (VR) ok = vr_attempt<R, D>(dp, *g, pay, k, st, att, y, seg);
-        else ok = surf_attempt<R, D>(dp, *g, pay, st, 0, att, y, seg);
+        if constexpr (VR) ok = vr_attempt<R, D, LDS>(dp, *g, pay, k, st, att, y, seg);
+        else ok = surf_attempt<R, D, LDS>(dp, *g, pay, st, 0, att, y, seg);
         if (ok) break;
         cnt.rejections++;
     }
@@ -656,7 +665,7 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
             // y_i uniform on dOmega_{h_i}: Q *= |K*(y_i, y_{i-1})| |dOmega_{h_i}|
             cnt.other++;
             for (att = 0; att < WOI_ATTEMPT_CAP; ++att) {
-                if (surf_attempt<R, D>(dp, *g, pay, st, (uint32_t)i, att, yn, segn)) break;
+                if (surf_attempt<R, D, LDS>(dp, *g, pay, st, (uint32_t)i, att, yn, segn)) break;
                 cnt.rejections++;
             }
             if (att == WOI_ATTEMPT_CAP) cnt.caps++;
@@ -687,7 +696,7 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
                         pick = min((int)(up * (R)qn), qn - 1);
                         int j = pick == 0 ? ph.j0 : ph.j1;
                         if (pick >= 2) j = poly_hits<R, LDS, true>(dp, *g, pay, y, d, ray, seg, pick, cnt).j0;
-                        const R* v = pay + Pay<R>::g(*g) + 2 * j;
+                        const R* v = poly_xy<R, LDS>(*g, pay) + 2 * j;
                         const R ex = v[2] - v[0], ey = v[3] - v[1];
                         const R den = d[0] * ey - d[1] * ex;
                         const R s = ((v[0] - y[0]) * d[1] - (v[1] - y[1]) * d[0]) / den;
