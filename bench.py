@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Walk-on-Interfaces benchmark on one MI355X.
 
-Headline workload (the 2D tree configuration): unit disk containing 3 nested star
+Headline workload (the 2D star tree): unit disk containing 3 nested star
 interfaces r0 (1 + 0.2 cos k t) with (r0, k) = (0.7, 3), (0.4, 5), (0.2, 7) as 2048-vertex
 polylines and 5 circular inclusions (N = 9 regions, depth 3), sigma = 10^U(-1, 2), 5-mode
 random Fourier flux data with zero mean; 4096 evaluation points (25 % within 1e-3 of an
@@ -10,7 +10,7 @@ interface); W = 1e5 walkers per point, M = 4; values and gradients.
 One step = one full estimate of all points (walk kernel plus per-point reduction), inputs
 resident in HBM.  The headline path is FP32 walks with FP64 per-point sums and the
 wave-uniform shared schedule; the FP64 plain path (same kernel in FP64) gives the
-equal-standard-error comparison.  Beside it the line reports, at their full sizes: config 2
+equal-standard-error comparison.  Beside it the line reports, at their full sizes: the star tree
 with shared trajectories (B = 16 <= 0.5 % of the points, Sec. 4.6), the 512-instance batch
 (one persistent graph launch), 3D spheres + ellipsoids with the variance-reduced estimator,
 and the 6D nested spheres; each with its FP64 plain comparison at equal SE and the paired
@@ -39,7 +39,7 @@ FLOPS_PER_SEGMENT_TEST = 4      # distance of the segment end vertex (crossings 
 FLOPS_PER_WALKER = 57           # step-0 datum b(y_0) (5-mode Fourier) and Q_0
 PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 (packed) peak
 # HBM bytes per launch of the timed FP32 walk kernel at W = 1e5, from the FETCH_SIZE and
-# WRITE_SIZE passes in profiles/walk_kernel_config2_hbm_counters.md, scaled by what the same
+# WRITE_SIZE passes in profiles/walk_kernel_star_tree_2d_hbm_counters.md, scaled by what the same
 # counters read for a 1 GiB device copy.  None whenever the kernel has changed since those
 # passes were taken.
 TRAFFIC_BYTES = None
@@ -174,10 +174,10 @@ def config_block(woi, torch, ev, name, prob_desc, pts_np, walks, M, estimator, B
 
 
 def run_batch(woi, torch, W, precision, steps, warmup, ev):
-    """Config 3: 512 instances in one persistent graph launch (tuned launch shape).  An
+    """The 512-instance 2D batch in one persistent graph launch (tuned launch shape).  An
     untimed graph of the counting kernel gives the event counts; the timed graph replays
     the non-counting kernel (same seed: the whole batch is recomputed every replay)."""
-    inst = W.config3_instances()
+    inst = W.star_tree_instances_2d()
     probs = [woi.Problem(p) for p, _, _ in inst]
     entries = [dict(problem=g, points=x, walks=w, M=4, seed=4242, precision=precision, schedule_mode=woi.SCHED_SHARED,
                     instance=i) for i, (g, (_, x, w)) in enumerate(zip(probs, inst))]
@@ -246,7 +246,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-extra", action="store_true",
-                    help="measure only the headline path (skip shared trajectories and configs 3-5)")
+                    help="measure only the headline path (skip shared trajectories, the instance batch, 3D and 6D)")
     ap.add_argument("--extra-steps", type=int, default=2, help="timed steps of the other configurations")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -266,7 +266,7 @@ def main():
 
     torch.cuda.set_device(0)
     ev = HipEvents()
-    prob_desc, pts_np = W.config2()
+    prob_desc, pts_np = W.star_tree_2d()
     M = 4
     prob = woi.Problem(prob_desc)
     woi._lib.woi_problem_upload(prob.handle)
@@ -330,14 +330,14 @@ def main():
             "speedup_vs_fp64_plain_fixed_se": t64_eps / fixed_se(rsh, eps),
             "pair_eval_tflops_over_traj_plus_eval":
                 pairs * eval_flops_per_pair(2) / (float(np.mean(rsh["ms"])) * 1e-3) / 1e12}
-        rec["batched_config3"] = batch_block(woi, torch, W, ev, args.extra_steps)
-        p4, x4 = W.config4()
-        rec["config4_3d_vr"] = config_block(
+        rec["batched_star_tree_instances"] = batch_block(woi, torch, W, ev, args.extra_steps)
+        p4, x4 = W.ellipsoid_tree_3d()
+        rec["ellipsoid_tree_3d_vr"] = config_block(
             woi, torch, ev, "unit ball, spheres 0.6 > 0.3, 10 ellipsoids (semi-axes 0.03-0.08), sigma 10^U(log .5, "
             "log 50), real SH l <= 4 data; 16384 points; VR, W = 1e5 walkers, M = 6", p4, x4, 100000, 6, 1, 64,
             args.extra_steps)
-        p5, x5 = W.config5()
-        rec["config5_6d"] = config_block(
+        p5, x5 = W.nested_spheres_6d()
+        rec["nested_spheres_6d"] = config_block(
             woi, torch, ev, "unit 6-ball, spheres 0.7 > 0.35, sigma (1, 5, 0.2), c + lambda x1/|x| data; 1024 points; "
             "W = 1e6, M = 8", p5, x5, 1000000, 8, 0, 4, args.extra_steps)
     if not args.no_cpu:

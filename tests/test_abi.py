@@ -49,7 +49,7 @@ def _err(woi, prob, status, **kw):
 
 
 def test_validation_errors(woi):
-    p, _ = W.config1()
+    p, _ = W.concentric_disk_2d()
     bad = W.Problem(2, [-1, 1], p.sigma, p.shapes, p.data)
     _err(woi, bad, "WOI_E_GEOMETRY")                           # parent must precede child
     outside = W.Problem(2, [-1, 0], [1.0, 2.0], [W.sphere([0, 0], 1.0), W.sphere([0.9, 0], 0.3)], p.data)
@@ -69,12 +69,12 @@ def test_validation_errors(woi):
 
 
 def test_query_validation_without_gpu(woi):
-    p5, _ = W.config5()
+    p5, _ = W.nested_spheres_6d()
     prob = woi.Problem(p5)
     with pytest.raises(woi.WoiError) as e:
         woi.workspace_size(prob, 16, woi.make_query(100, 4, estimator=woi.VR))
     assert e.value.status == "WOI_E_UNSUPPORTED"
-    p1, _ = W.config1()
+    p1, _ = W.concentric_disk_2d()
     prob = woi.Problem(p1)
     for q in (woi.make_query(101, 4, estimator=woi.VR), woi.make_query(100, 99), woi.make_query(0, 4),
               woi.make_query(100, 4, batch_share=0), woi.make_query(100, 4, instance=1 << 24)):
@@ -83,7 +83,7 @@ def test_query_validation_without_gpu(woi):
     assert woi.workspace_size(prob, 64, woi.make_query(10000, 4)) > 0
 
 
-@pytest.mark.parametrize("make", [lambda: W.config1()[0], lambda: W.config2(n_points=8)[0], lambda: W.config5()[0],
+@pytest.mark.parametrize("make", [lambda: W.concentric_disk_2d()[0], lambda: W.star_tree_2d(n_points=8)[0], lambda: W.nested_spheres_6d()[0],
                                   lambda: W.zheng_ex3_3d(),
                                   lambda: W.single_ellipsoid_linear(3, [0.9, 0.6, 0.4])[0]])
 def test_host_compile_matches_oracle(woi, oracle_mod, make):
@@ -106,9 +106,9 @@ def test_host_compile_matches_oracle(woi, oracle_mod, make):
 def test_batch_validation_without_gpu(woi):
     """woi_estimate_batch rejects malformed batches before touching a device."""
     import ctypes as C
-    p1, _ = W.config1()
+    p1, _ = W.concentric_disk_2d()
     prob = woi.Problem(p1)
-    p5 = woi.Problem(W.config5()[0])
+    p5 = woi.Problem(W.nested_spheres_6d()[0])
 
     def items(*queries, problems=None):
         arr = (woi._BatchItem * len(queries))()

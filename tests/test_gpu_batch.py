@@ -26,9 +26,9 @@ def _np(t):
 
 
 def _small_instances(n=10, seed=4, even=False):
-    """Config-3 style instances shrunk for parity runs: P in [2, 102], W in [5, 5000]."""
+    """Instances of the 512-instance batch shrunk for parity runs: P in [2, 102], W in [5, 5000]."""
     out = []
-    for k, (p, x, w) in enumerate(W.config3_instances(n_inst=n, seed=seed, scale_points=0.1, scale_walks=0.005)):
+    for k, (p, x, w) in enumerate(W.star_tree_instances_2d(n_inst=n, seed=seed, scale_points=0.1, scale_walks=0.005)):
         w = max(4, w + (w & 1 if even else 0))
         out.append((p, x, w))
     return out
@@ -138,7 +138,7 @@ def test_batch_launch_shapes_agree():
 
 def test_batch_edge_cases():
     """One point, one walker, a 65-point ragged tile, resumed walk ranges, a single item."""
-    p1, xs = W.config1()
+    p1, xs = W.concentric_disk_2d()
     g = woi.Problem(p1)
     ent = [dict(problem=g, points=xs[:1], walks=1, M=4, seed=3, instance=0),
            dict(problem=g, points=np.concatenate([xs, xs[:1]]), walks=33, M=4, seed=3, instance=1),   # 65 points
@@ -153,10 +153,10 @@ def test_batch_edge_cases():
     _close_to_rounding([_np(t) for t in single[0]], [_np(t) for t in outs[2]], 700)
 
 
-def test_config3_full_size_sampled():
-    """All 512 config-3 instances at full size, FP32 walks, one tuned persistent graph launch;
+def test_star_tree_instances_full_size_sampled():
+    """All 512 batch instances at full size, FP32 walks, one tuned persistent graph launch;
     sampled points against the FP64 oracle on identical streams."""
-    inst = W.config3_instances()
+    inst = W.star_tree_instances_2d()
     probs = [woi.Problem(p) for p, _, _ in inst]
     outs = woi.estimate_batch(_entries(inst, probs, precision=woi.FP32, seed=2024))
     torch.cuda.synchronize()

@@ -66,12 +66,12 @@ def walk_parity(prob, pts, n, M, estimator=0, sched=0, B=1, seed=7, flip_budget=
 @pytest.mark.parametrize("estimator", [0, 1])
 @pytest.mark.parametrize("sched", [0, 1])
 def test_walk_parity_concentric_2d(estimator, sched):
-    p, xs = W.config1()
+    p, xs = W.concentric_disk_2d()
     walk_parity(p, xs[::4], 2000, 4, estimator=estimator, sched=sched)
 
 
 def test_walk_parity_six_ball():
-    p, xs = W.config5()
+    p, xs = W.nested_spheres_6d()
     walk_parity(p, xs[:8], 1000, 8)
 
 
@@ -95,14 +95,14 @@ def test_walk_parity_nonconvex_boundary():
     walk_parity(p, NC_PTS, 2000, 3, flip_budget=1e-4)
 
 
-def test_walk_parity_config2_small():
-    p, xs = W.config2(n_points=64)
+def test_walk_parity_star_tree_2d_small():
+    p, xs = W.star_tree_2d(n_points=64)
     walk_parity(p, xs, 300, 4, flip_budget=1e-4)
     walk_parity(p, xs[:16], 300, 4, estimator=1, sched=1, flip_budget=1e-4)
 
 
 def test_walk_parity_ellipsoids_vr_3d():
-    p, xs = W.config4(n_points=24)
+    p, xs = W.ellipsoid_tree_3d(n_points=24)
     walk_parity(p, xs, 300, 6, estimator=1, flip_budget=1e-4)
     walk_parity(p, xs[:8], 300, 4, estimator=0, sched=1, flip_budget=1e-4)
 
@@ -115,7 +115,7 @@ def test_walk_parity_single_ellipsoid(dim, axes):
 
 
 def test_walk_parity_shared_trajectories_and_offset():
-    p, xs = W.config1()
+    p, xs = W.concentric_disk_2d()
     walk_parity(p, xs[:12], 500, 4, B=4)
     walk_parity(p, xs[:12], 500, 4, offset=123456)
 
@@ -123,9 +123,9 @@ def test_walk_parity_shared_trajectories_and_offset():
 # ----------------------------------------------------------------------------- per-point parity
 def test_estimate_same_streams_match_oracle_fp64():
     from test_oracle_pins import STAR_PTS, _star_tree
-    cases = [(W.config1()[0], W.config1()[1][::3], 4, 0), (_star_tree()[0], STAR_PTS, 3, 0),
+    cases = [(W.concentric_disk_2d()[0], W.concentric_disk_2d()[1][::3], 4, 0), (_star_tree()[0], STAR_PTS, 3, 0),
              (W.zheng_ex3_3d(), W.ball_points(np.random.default_rng(2), 6, 3, 0.9), 5, 0),
-             (W.config1()[0], W.config1()[1][::5], 4, 1)]
+             (W.concentric_disk_2d()[0], W.concentric_disk_2d()[1][::5], 4, 1)]
     for prob, pts, M, est in cases:
         op = O.OracleProblem(prob)
         mo, so, go, gso, _ = O.estimate(op, pts, 20000, M, seed=3, estimator=est)
@@ -139,7 +139,7 @@ def test_estimate_same_streams_match_oracle_fp64():
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_estimate_matches_exact_expectation(precision):
-    p, xs = W.config1()
+    p, xs = W.concentric_disk_2d()
     H, gH = CF.harmonic_2d(1, "cos")
     gp = woi.Problem(p)
     for M, est in ((4, 0), (2, 1)):
@@ -153,7 +153,7 @@ def test_estimate_matches_exact_expectation(precision):
 
 
 def test_estimate_six_ball_exact_expectation_fp32():
-    p, xs = W.config5()
+    p, xs = W.nested_spheres_6d()
     dirs = np.random.default_rng(1).standard_normal((32, 6))
     pts = dirs / np.linalg.norm(dirs, axis=1, keepdims=True) * np.linspace(0.1, 0.85, 32)[:, None]
     c1 = 0.7 ** 5 - 0.5 * 0.35 ** 5
@@ -169,7 +169,7 @@ def test_estimate_six_ball_exact_expectation_fp32():
 def test_fp32_paired_with_fp64():
     """FP32 walks against FP64 walks on identical streams: most decisions agree, the
     paired difference is far below the statistical error, and its mean is consistent with 0."""
-    p, xs = W.config2(n_points=64)
+    p, xs = W.star_tree_2d(n_points=64)
     gp = woi.Problem(p)
     F64, _, T64 = woi.trace(gp, xs, 2000, 4, seed=9, schedule_mode=1)
     F32, _, T32 = woi.trace(gp, xs, 2000, 4, seed=9, precision=woi.FP32, schedule_mode=1)
@@ -184,7 +184,7 @@ def test_fp32_paired_with_fp64():
 
 # ----------------------------------------------------------------------------- edge cases
 def test_edge_cases():
-    p, xs = W.config1()
+    p, xs = W.concentric_disk_2d()
     gp = woi.Problem(p)
     op = O.OracleProblem(p)
     # one point, one walk, M = 0; ragged point count (65 = 64 + 1)
@@ -202,7 +202,7 @@ def test_edge_cases():
 
 
 def test_counters_and_errors():
-    p, xs = W.config1()
+    p, xs = W.concentric_disk_2d()
     gp = woi.Problem(p)
     c = woi.new_counters()
     woi.estimate(gp, xs, 1000, 4, seed=2, counters=c)
@@ -217,10 +217,10 @@ def test_counters_and_errors():
 
 
 # ----------------------------------------------------------------------------- full size, bench launch
-def test_config2_full_size_sampled():
-    """Config 2 at its full size (4096 points, W = 1e5) in the benchmark's launch configuration;
+def test_star_tree_2d_full_size_sampled():
+    """The 2D star tree at its full size (4096 points, W = 1e5) in the benchmark's launch configuration;
     sampled points checked against the oracle on identical streams."""
-    p, xs = W.config2()
+    p, xs = W.star_tree_2d()
     gp = woi.Problem(p)
     idx = np.array([0, 1, 777, 2048, 3071, 3072, 3500, 4095])
     mean32, se32, _, _ = [_np(t) for t in woi.estimate(gp, xs, 100000, 4, seed=2024, precision=woi.FP32,
@@ -243,10 +243,10 @@ def test_shared_trajectory_path(precision):
     """batch_share B > 1 runs the generate-then-evaluate kernels; with the same keys they give the
     per-point path's numbers (FP64: to rounding) and the oracle's (same streams)."""
     from test_oracle_pins import STAR_PTS, _star_tree
-    cases = [(W.config1()[0], W.config1()[1], 4, 0, 8), (_star_tree()[0], np.tile(STAR_PTS, (3, 1)), 3, 0, 6),
-             (W.config1()[0], W.config1()[1], 3, 1, 4),
+    cases = [(W.concentric_disk_2d()[0], W.concentric_disk_2d()[1], 4, 0, 8), (_star_tree()[0], np.tile(STAR_PTS, (3, 1)), 3, 0, 6),
+             (W.concentric_disk_2d()[0], W.concentric_disk_2d()[1], 3, 1, 4),
              (W.zheng_ex3_3d(), W.ball_points(np.random.default_rng(2), 40, 3, 0.9), 4, 1, 5),
-             (W.config5()[0], W.config5()[1][:48], 6, 0, 16)]
+             (W.nested_spheres_6d()[0], W.nested_spheres_6d()[1][:48], 6, 0, 16)]
     for prob, pts, M, est, B in cases:
         gp = woi.Problem(prob)
         walks = 6000
@@ -269,7 +269,7 @@ def test_shared_trajectory_path(precision):
 
 
 def test_shared_trajectory_exact_expectation():
-    p, xs = W.config1()
+    p, xs = W.concentric_disk_2d()
     H, gH = CF.harmonic_2d(1, "cos")
     gp = woi.Problem(p)
     mean, se, g, gse = [_np(t) for t in woi.estimate(gp, xs, 400000, 4, seed=33, precision=woi.FP32,
@@ -284,7 +284,7 @@ def test_shared_trajectories_across_chunks():
     every chunk.  6D nested spheres, 4096 points in pairs (B = 2), M = 32: about 1.9 MB of
     trajectories per sample, so W = 2000 spans four chunks; sampled points against the oracle
     on the same streams, FP32 paired with FP64."""
-    p, _ = W.config5()
+    p, _ = W.nested_spheres_6d()
     xs = W.ball_points(np.random.default_rng(17), 4096, 6, 0.95)
     gp = woi.Problem(p)
     B, M, walks = 2, 32, 2000

@@ -82,7 +82,7 @@ def test_closed_form_gradient_matches_finite_difference():
 
 # ----------------------------------------------------------------------------- problem constants
 def test_alpha_beta_and_areas(oracle_mod):
-    p, _ = W.config1()
+    p, _ = W.concentric_disk_2d()
     info = oracle_mod.OracleProblem(p).info()
     # Eq. unit_coeff_charge_density_sys: alpha_1 = 2, alpha_2 = 2(1-10)/11; s_1 = 2/10, s_2 = -2/11
     assert np.allclose(info["alpha"], [2.0, -18 / 11])
@@ -111,7 +111,7 @@ def test_vr_half_measures(oracle_mod):
     assert info["area_plus"][0] == pytest.approx(info["area"][0] / 2, rel=1e-9)
     assert info["area_minus"][0] == pytest.approx(info["area"][0] / 2, rel=1e-9)
     assert info["area_plus"][1] == pytest.approx(info["area"][1], rel=1e-12) and info["area_minus"][1] == 0.0
-    p, _ = W.config1()
+    p, _ = W.concentric_disk_2d()
     info = oracle_mod.OracleProblem(p).info()
     assert np.allclose(info["area_plus"], info["area"] / 2, rtol=1e-12)
 
@@ -155,8 +155,8 @@ CFG1 = ([1.0, 0.5], [10.0, 1.0], [1.0, 1.0])
 
 @pytest.mark.parametrize("M", [0, 1, 2, 4])
 @pytest.mark.parametrize("estimator", [0, 1])
-def test_config1_exact_expectation(oracle_mod, M, estimator):
-    p, xs = W.config1()
+def test_concentric_disk_exact_expectation(oracle_mod, M, estimator):
+    p, xs = W.concentric_disk_2d()
     op = oracle_mod.OracleProblem(p)
     pts = xs[::5]
     mean, se, g, gse, cnt = oracle_mod.estimate(op, pts, 200000, M, seed=10 + M, estimator=estimator)
@@ -183,7 +183,7 @@ def test_sphere_3d_exact_expectation(oracle_mod, estimator):
 
 
 def test_six_ball_global_balance_exact_expectation(oracle_mod):
-    p, xs = W.config5()
+    p, xs = W.nested_spheres_6d()
     op = oracle_mod.OracleProblem(p)
     info = op.info()
     # global balance: flux through the boundary equals the sum of interface jumps (R12 reading)
@@ -288,7 +288,7 @@ def test_vr_same_mean_as_plain_on_star_tree(oracle_mod):
 
 # ----------------------------------------------------------------------------- statistics
 def test_standard_error_calibration_and_rate(oracle_mod):
-    p, xs = W.config1()
+    p, xs = W.concentric_disk_2d()
     op = oracle_mod.OracleProblem(p)
     H, gH = CF.harmonic_2d(1, "cos")
     ref = np.array([CF.concentric_uM(*CFG1, 1, 2, 4, x, H, gH)[0] for x in xs])
@@ -302,7 +302,7 @@ def test_standard_error_calibration_and_rate(oracle_mod):
 
 
 def test_trace_matches_estimate_and_resumes(oracle_mod):
-    p, xs = W.config1()
+    p, xs = W.concentric_disk_2d()
     op = oracle_mod.OracleProblem(p)
     pts = xs[:3]
     F, G, T = oracle_mod.trace(op, pts, 3000, 3, seed=4)
@@ -316,7 +316,7 @@ def test_trace_matches_estimate_and_resumes(oracle_mod):
 
 def test_shared_trajectories_batch(oracle_mod):
     """Points sharing a batch (B > 1) see identical schedules and trajectories; estimates stay exact."""
-    p, xs = W.config1()
+    p, xs = W.concentric_disk_2d()
     op = oracle_mod.OracleProblem(p)
     pts = xs[::4]
     F, G, T = oracle_mod.trace(op, pts, 200, 4, seed=4, batch_share=4)
@@ -350,7 +350,7 @@ def test_pins_reject_planted_mistakes(oracle_mod, tmp_path, plant):
         mean, se, _, _, _ = oracle_mod.estimate(op, pts, 800000, 2, seed=4)
         z = _z(mean, ref, se)
     else:
-        p, xs = W.config1()
+        p, xs = W.concentric_disk_2d()
         op = oracle_mod.OracleProblem(p, library=libv)
         pts = xs[::6]
         H, gH = CF.harmonic_2d(1, "cos")

@@ -166,7 +166,7 @@ def concentric(dim, radii, sigma, data) -> Problem:
                    [sphere(np.zeros(dim), r) for r in radii], list(data))
 
 
-def config1(M=4):
+def concentric_disk_2d(M=4):
     """Unit disk (sigma 10) with a concentric disk r = 0.5 (sigma 1); b = cos(th) on both."""
     m = 2
     data = [fourier([0, 0], 0.0, [1.0], [0.0]) for _ in range(2)]
@@ -193,7 +193,7 @@ def zheng_ex3_3d(lam=5.0, alpha=0.4, sig=0.5):
     return p
 
 
-def config5():
+def nested_spheres_6d():
     """Unit 6-ball, spheres 0.7 > 0.35, sigma (1, 5, 0.2), b_j = c_j + lam_j x1/|x| (global balance)."""
     m = 6
     c2, c3 = 1.0, -0.5
@@ -241,7 +241,7 @@ def _fourier_mean_removed(rng, shape, center, K=5):
     return fourier(center, a0, a, c)
 
 
-def config2(n_vertices=2048, n_points=4096, near_frac=0.25):
+def star_tree_2d(n_vertices=2048, n_points=4096, near_frac=0.25):
     """Unit disk with 3 nested stars r0(1 + 0.2 cos k t), (r0, k) = (0.7, 3) > (0.4, 5) > (0.2, 7),
     and 5 circular inclusions of radius U[0.03, 0.05] placed with clearance 0.01."""
     stars = [(0.70, 3), (0.40, 5), (0.20, 7)]
@@ -275,11 +275,11 @@ def config2(n_vertices=2048, n_points=4096, near_frac=0.25):
     rng_d = np.random.default_rng(2)
     data = [_fourier_mean_removed(rng_d, s, s.center) for s in shapes]
     prob = Problem(2, parent, sigma, shapes, data, 0, "disk-3stars-5circles")
-    pts = _config2_points(prob, np.random.default_rng(3), n_points, near_frac)
+    pts = _star_tree_points(prob, np.random.default_rng(3), n_points, near_frac)
     return prob, pts
 
 
-def _config2_points(prob, rng, n, near_frac):
+def _star_tree_points(prob, rng, n, near_frac):
     n_near = int(round(n * near_frac))
     far = []
     while len(far) < n - n_near:
@@ -317,7 +317,7 @@ def _min_interface_distance(prob, p):
     return d
 
 
-def config3_instances(n_inst=512, seed=4, n_vertices=512, scale_points=1.0, scale_walks=1.0):
+def star_tree_instances_2d(n_inst=512, seed=4, n_vertices=512, scale_points=1.0, scale_walks=1.0):
     """Independent 2D instances with 1-16 circle/star interfaces in a random nesting tree.
     Returns a list of (problem, points, W)."""
     rng = np.random.default_rng(seed)
@@ -371,7 +371,7 @@ def _haar_rotation(rng, m):
     return q * np.sign(np.diag(r))
 
 
-def config4(n_points=16384):
+def ellipsoid_tree_3d(n_points=16384):
     """Unit ball; concentric spheres 0.6 > 0.3; 10 ellipsoids (semi-axes U[0.03, 0.08],
     Haar rotation, clearance 0.01).  Data: real SH l = 1..4 (coefficient N(0,1)/(l+1)) on
     spheres, odd l in {1, 3} on ellipsoids (mean zero on centrally symmetric surfaces)."""
@@ -425,10 +425,11 @@ def single_ellipsoid_linear(dim, semi_axes, rotation_seed=7, direction=0, sigma=
                    [field_flux(g)], 0, "single-ellipsoid"), A, Q
 
 
-CONFIG_DESCRIPTIONS = {
-    1: "2D plain FP64: unit disk, concentric circle r=0.5, sigma 10/1, b = cos(theta); 64 points, W=1e4, M=4",
-    2: "2D tree: unit disk, 3 nested stars (k=3,5,7) + 5 circles, sigma 10^U(-1,2), Fourier data; 4096 points, W=1e5, M=4",
-    3: "batched uneven 2D: 512 instances, 1-16 interfaces, 16-1024 points, W 1e3-1e6, M=4",
-    4: "3D: unit ball, spheres 0.6/0.3, 10 ellipsoids, SH data; 16384 points, W=1e5 (VR), M=6",
-    5: "6D: unit 6-ball, spheres 0.7/0.35, sigma (1,5,0.2), c + lam x1/|x| data; 1024 points, W=1e6, M=8",
+WORKLOAD_DESCRIPTIONS = {
+    "concentric_disk_2d": "unit disk, concentric circle r=0.5, sigma 10/1, b = cos(theta); 64 points, W=1e4, M=4",
+    "star_tree_2d": "unit disk, 3 nested stars (k=3,5,7) + 5 circles, sigma 10^U(-1,2), Fourier data; 4096 points, "
+                    "W=1e5, M=4",
+    "star_tree_instances_2d": "512 uneven instances, 1-16 interfaces, 16-1024 points, W 1e3-1e6, M=4",
+    "ellipsoid_tree_3d": "unit ball, spheres 0.6/0.3, 10 ellipsoids, SH data; 16384 points, W=1e5 (VR), M=6",
+    "nested_spheres_6d": "unit 6-ball, spheres 0.7/0.35, sigma (1,5,0.2), c + lam x1/|x| data; 1024 points, W=1e6, M=8",
 }
