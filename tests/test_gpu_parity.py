@@ -301,3 +301,44 @@ def test_shared_trajectories_across_chunks():
     # ||alpha||_1^32, so single points may move by a few SE; the bulk must not move
     z = np.abs(m32 - m64) / s64
     assert np.all(np.isfinite(z)) and np.median(z) < 0.01 and np.quantile(z, 0.99) < 0.1 and z.max() < 5.0
+
+
+def test_ellipsoid_tree_3d_full_size_sampled():
+    """The 3D ellipsoid tree at its full size (16384 points, VR, W = 1e5, M = 6) in the
+    benchmark's launch configuration; sampled points against the oracle on identical streams.
+    Each side integrates |dOmega^+-| by its own quadrature (agreeing to 1e-6), so FP64 means
+    agree to 1e-5 relative; FP32 paired with FP64 on the same streams."""
+    p, xs = W.ellipsoid_tree_3d()
+    gp = woi.Problem(p)
+    m64, s64, _, _ = [_np(t) for t in woi.estimate(gp, xs, 100000, 6, seed=31, estimator=woi.VR, schedule_mode=1)]
+    m32, _, _, _ = [_np(t) for t in woi.estimate(gp, xs, 100000, 6, seed=31, estimator=woi.VR, precision=woi.FP32,
+                                                  schedule_mode=1)]
+    idx = np.array([0, 5000, 16383])
+    mo, so, _, _, _ = O.estimate(O.OracleProblem(p), xs[idx], 100000, 6, seed=31, estimator=1, schedule_mode=1,
+                                 groups=idx)
+    assert np.allclose(m64[idx], mo, rtol=1e-5, atol=1e-5 * so.max())
+    assert np.allclose(s64[idx], so, rtol=1e-4)
+    z = np.abs(m32 - m64) / s64
+    assert np.all(np.isfinite(z)) and np.median(z) < 0.05 and np.quantile(z, 0.99) < 0.5
+
+
+def test_nested_spheres_6d_full_size_sampled():
+    """The 6D nested spheres at their full size (1024 points, W = 1e6, M = 8): sampled points
+    against the oracle on identical streams (FP64, 1e-9), and the FP32 bias against the exact
+    u_M of the truncated series at every point: per-point z within 5, mean z within 5 / sqrt(P)."""
+    p, xs = W.nested_spheres_6d()
+    gp = woi.Problem(p)
+    M = 8
+    m64, s64, _, _ = [_np(t) for t in woi.estimate(gp, xs, 1000000, M, seed=77, schedule_mode=1)]
+    m32, s32, _, _ = [_np(t) for t in woi.estimate(gp, xs, 1000000, M, seed=77, precision=woi.FP32, schedule_mode=1)]
+    idx = np.array([0, 1023])
+    mo, so, _, _, _ = O.estimate(O.OracleProblem(p), xs[idx], 1000000, M, seed=77, schedule_mode=1, groups=idx)
+    assert np.allclose(m64[idx], mo, rtol=1e-9, atol=1e-9 * so.max())
+    c1 = 0.7 ** 5 - 0.5 * 0.35 ** 5
+    H0, g0 = CF.harmonic_const(6); H1, g1 = CF.harmonic_x1(6)
+    ref = np.array([CF.concentric_uM([1, .7, .35], [1, 5, .2], [c1, 1, -.5], 0, 6, M, x, H0, g0)[0] +
+                    CF.concentric_uM([1, .7, .35], [1, 5, .2], [1, .5, -.3], 1, 6, M, x, H1, g1)[0] for x in xs])
+    z32 = (m32 - ref) / s32
+    z64 = (m64 - ref) / s64
+    assert np.max(np.abs(z32)) < 5.0 and np.max(np.abs(z64)) < 5.0
+    assert abs(np.mean(z32)) < 5.0 / np.sqrt(len(xs)) and abs(np.mean(z64)) < 5.0 / np.sqrt(len(xs))
