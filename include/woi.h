@@ -212,10 +212,12 @@ woi_status woi_batch_workspace_size(const woi_batch_item *items, int n, size_t *
  * The first call with a given (items, workspace, counters, device) builds the plan in
  * library-owned device memory and captures the graph; with block_size 0 it also times the
  * candidate launch shapes on a scaled-down copy of the batch, which synchronizes `stream`
- * and the device.  Later calls with identical arguments only launch the cached graph (up
- * to 8 cached batches per process, least recently used evicted).  A cached graph reads
- * the current contents of the points and problems; a problem must stay alive while a
- * batch that uses it can run.  Calls that share a workspace must be ordered on one stream.
+ * and the device.  Later calls with the same arguments only launch the cached graph (up
+ * to 8 cached batches per process, least recently used evicted); the seeds are not part
+ * of that key: changed seeds are copied into the library's seed table on `stream` before
+ * the launch.  A cached graph reads the current contents of the points and problems; a
+ * problem must stay alive while a batch that uses it can run.  Calls that share a
+ * workspace or an item list must be ordered on one stream.
  * counters: NULL or device uint64[WOI_COUNTERS], added to as in woi_estimate.
  * Errors: INVALID_ARG, UNSUPPORTED, OOM (workspace too small or plan allocation), DEVICE. */
 woi_status woi_estimate_batch(const woi_batch_item *items, int n, void *workspace, size_t workspace_bytes,

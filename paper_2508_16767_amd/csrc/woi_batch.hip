@@ -37,8 +37,9 @@ __global__ __launch_bounds__(64 * WV) void batch_kernel(BParams bp) {
         }
         KParams kp{};
         kp.dp = dp;
-        kp.k0 = in.k0;
-        kp.k1 = in.k1;
+        const uint64_t key = bp.seeds[item.inst];
+        kp.k0 = (uint32_t)key;
+        kp.k1 = (uint32_t)(key >> 32);
         kp.M = in.M;
         kp.batch_share = 1;
         kp.shared_sched = in.shared_sched;

@@ -64,8 +64,9 @@ struct Plan {
     uint64_t n_slots = 0;
     int64_t n_points = 0;
     size_t partial_bytes(int dim) const { return (size_t)n_slots * 64 * (2 + 2 * dim) * sizeof(double); }
-    size_t table_bytes() const {
-        return inst.size() * sizeof(woi::BInst) + items.size() * sizeof(woi::BItem) + ctab.size() * sizeof(uint32_t);
+    size_t table_bytes() const {   // [BInst][BItem][ctab][pad to 8][seeds]
+        const size_t a = inst.size() * sizeof(woi::BInst) + items.size() * sizeof(woi::BItem) + ctab.size() * sizeof(uint32_t);
+        return ((a + 7) & ~size_t(7)) + inst.size() * sizeof(uint64_t);
     }
 };
 
@@ -171,8 +172,6 @@ Plan make_plan(const woi_batch_item* items, const Spec& sp, Tune t, unsigned gri
         b.se = it.se;
         b.grad = it.grad;
         b.grad_se = it.grad_se;
-        b.k0 = (uint32_t)it.query.seed;
-        b.k1 = (uint32_t)(it.query.seed >> 32);
         b.M = it.query.M;
         b.shared_sched = it.query.schedule_mode == WOI_SCHED_SHARED;
         b.instance = it.query.instance;
@@ -224,25 +223,35 @@ unsigned grid_for(const Spec& sp, const Device& d, int waves) {
     return (unsigned)std::max(1, per_cu) * (unsigned)d.cus;
 }
 
-// Tables of a plan in one device buffer: [BInst][BItem][ctab].
+// Tables of a plan in one device buffer: [BInst][BItem][ctab][seeds].
 struct DevTables {
     void* buf = nullptr;
     woi::BInst* inst = nullptr;
     woi::BItem* items = nullptr;
     uint32_t* ctab = nullptr;
+    uint64_t* seeds = nullptr;
 };
 
-woi_status upload(const Plan& pl, void* buf, DevTables& t) {
+woi_status upload(const Plan& pl, const std::vector<uint64_t>& seeds, void* buf, DevTables& t) {
     char* b = static_cast<char*>(buf);
     t.buf = buf;
     t.inst = reinterpret_cast<woi::BInst*>(b);
     t.items = reinterpret_cast<woi::BItem*>(b + pl.inst.size() * sizeof(woi::BInst));
     t.ctab = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(t.items) + pl.items.size() * sizeof(woi::BItem));
+    const size_t a = reinterpret_cast<char*>(t.ctab + pl.ctab.size()) - b;
+    t.seeds = reinterpret_cast<uint64_t*>(b + ((a + 7) & ~size_t(7)));
     if (hipMemcpy(t.inst, pl.inst.data(), pl.inst.size() * sizeof(woi::BInst), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(t.items, pl.items.data(), pl.items.size() * sizeof(woi::BItem), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(t.ctab, pl.ctab.data(), pl.ctab.size() * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess)
+        hipMemcpy(t.ctab, pl.ctab.data(), pl.ctab.size() * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(t.seeds, seeds.data(), seeds.size() * sizeof(uint64_t), hipMemcpyHostToDevice) != hipSuccess)
         return set_error(WOI_E_DEVICE, "plan upload failed");
     return WOI_OK;
+}
+
+std::vector<uint64_t> seeds_of(const woi_batch_item* items, int n) {
+    std::vector<uint64_t> s((size_t)n);
+    for (int i = 0; i < n; ++i) s[i] = items[i].query.seed;
+    return s;
 }
 
 woi::BParams batch_params(const Plan& pl, const DevTables& t, void* ws, uint64_t* counters) {
@@ -250,6 +259,7 @@ woi::BParams batch_params(const Plan& pl, const DevTables& t, void* ws, uint64_t
     bp.inst = t.inst;
     bp.items = t.items;
     bp.ctab = t.ctab;
+    bp.seeds = t.seeds;
     bp.n_items = (uint32_t)pl.items.size();
     bp.head = static_cast<uint32_t*>(ws);
     bp.partials = reinterpret_cast<double*>(static_cast<char*>(ws) + kHead);
@@ -284,7 +294,7 @@ woi_status autotune(const woi_batch_item* items, const Spec& sp, const Device& d
     float best_ms = 0;
     for (size_t c = 0; c < plans.size() && st == WOI_OK; ++c) {
         DevTables t;
-        st = upload(plans[c], tbuf, t);
+        st = upload(plans[c], seeds_of(items, sp.n), tbuf, t);
         if (st != WOI_OK) break;
         const woi::BParams bp = batch_params(plans[c], t, ws, nullptr);
         float ms = 0;
@@ -315,7 +325,18 @@ struct Entry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     size_t need = 0;
+    // Seeds are not part of the graph: the device seed table is refreshed on the caller's
+    // stream before a launch whose seeds differ, from one of two pinned staging buffers
+    // (each reused only after the copy that last read it has completed).
+    std::vector<uint64_t> seeds;          // what the device table holds once queued copies land
+    uint64_t* pinned[2] = {nullptr, nullptr};
+    hipEvent_t copied[2] = {nullptr, nullptr};
+    int next = 0;
     ~Entry() {
+        for (int b = 0; b < 2; ++b) {
+            if (copied[b]) (void)hipEventDestroy(copied[b]);
+            if (pinned[b]) (void)hipHostFree(pinned[b]);
+        }
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (tab.buf) {
@@ -344,7 +365,7 @@ std::vector<uint64_t> make_key(const woi_batch_item* items, int n, const Spec& s
         const woi_batch_item& it = items[i];
         const woi_query& q = it.query;
         const uint64_t f[] = {sp.ref.empty() ? 0 : sp.ref[i].serial, (uint64_t)(uintptr_t)it.problem,
-                              (uint64_t)(uintptr_t)it.points, (uint64_t)it.P, q.seed, q.walks, q.walk_offset,
+                              (uint64_t)(uintptr_t)it.points, (uint64_t)it.P, q.walks, q.walk_offset,
                               (uint64_t)q.M, (uint64_t)q.estimator, (uint64_t)q.precision, (uint64_t)q.schedule_mode,
                               (uint64_t)q.batch_share, (uint64_t)q.instance, (uint64_t)q.block_size,
                               (uint64_t)(uintptr_t)it.mean, (uint64_t)(uintptr_t)it.se, (uint64_t)(uintptr_t)it.grad,
@@ -377,8 +398,15 @@ woi_status build_entry(const woi_batch_item* items, const Spec& sp, Device& d, v
         return set_error(WOI_E_OOM, "workspace of %zu bytes is smaller than the %zu bytes needed", ws_bytes, e.need);
     if (hipMalloc(&e.tab.buf, e.plan.table_bytes()) != hipSuccess)
         return set_error(WOI_E_OOM, "hipMalloc(%zu) for the work items failed", e.plan.table_bytes());
-    st = upload(e.plan, e.tab.buf, e.tab);
+    e.seeds = seeds_of(items, sp.n);
+    st = upload(e.plan, e.seeds, e.tab.buf, e.tab);
     if (st != WOI_OK) return st;
+    for (int b = 0; b < 2; ++b) {
+        if (hipHostMalloc(reinterpret_cast<void**>(&e.pinned[b]), e.seeds.size() * sizeof(uint64_t)) != hipSuccess)
+            return set_error(WOI_E_OOM, "hipHostMalloc for the seed table failed");
+        if (hipEventCreateWithFlags(&e.copied[b], hipEventDisableTiming) != hipSuccess)
+            return set_error(WOI_E_DEVICE, "hipEventCreate failed");
+    }
     const woi::BParams bp = batch_params(e.plan, e.tab, ws, counters);
     woi::BRParams rp{};
     rp.inst = e.tab.inst;
@@ -466,6 +494,18 @@ woi_status woi_estimate_batch(const woi_batch_item* items, int n, void* workspac
     if (workspace_bytes < e->need)
         return set_error(WOI_E_OOM, "workspace of %zu bytes is smaller than the %zu bytes needed", workspace_bytes, e->need);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<uint64_t> seeds = seeds_of(items, n);
+    if (seeds != e->seeds) {   // new seeds: refresh the device table on the caller's stream
+        const int b = e->next;
+        if (hipEventSynchronize(e->copied[b]) != hipSuccess) return set_error(WOI_E_DEVICE, "hipEventSynchronize failed");
+        std::memcpy(e->pinned[b], seeds.data(), seeds.size() * sizeof(uint64_t));
+        if (hipMemcpyAsync(e->tab.seeds, e->pinned[b], seeds.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            hipEventRecord(e->copied[b], s) != hipSuccess)
+            return set_error(WOI_E_DEVICE, "seed table update failed");
+        e->next ^= 1;
+        e->seeds.swap(seeds);
+    }
     const woi_query& q0 = items[0].query;
     if (q0.event_begin && hipEventRecord(static_cast<hipEvent_t>(q0.event_begin), s) != hipSuccess)
         return set_error(WOI_E_DEVICE, "hipEventRecord(begin) failed");

@@ -21,7 +21,8 @@ constexpr int DK_DIRPOLY_HORNER = 16;
 //   SPHERE     : c[m], R
 //   ELLIPSOID  : c[m], A[m*m], L[m*m] (= A^{-1/2}), 1/lambda_max(A)
 //   POLYLINE2D : vertices v[2*(nv+1)] (v[nv] = v[0]), segment lengths len[nv],
-//                cumulative arclength cum[nv+1], outward unit normals nrm[2*nv].
+//                cumulative arclength cum[nv+1] (FP64; the FP32 table holds the pairs
+//                (cum[j], 1/len[j]), j <= nv), outward unit normals nrm[2*nv].
 // Polyline search tables (float payload, shared by both precisions):
 //   for every level l >= 1 and aligned block b (vertices [b 2^l, min((b+1) 2^l, nv)]),
 //   bnd[(N2 >> l) + b] bounds the distance of the block's vertices from its chord (heap
@@ -41,7 +42,8 @@ struct DevRegion {
     int b64, b32, nbrk, class0;// VR (2D): sign breakpoints of beta along arclength
     int lds_v, lds_b;          // byte offsets of the LDS copies (FP32 vertices, FP16 bounds), -1 if none
     double alpha, sgn, s, area, meas[2], total;
-    float alpha_f, sgn_f, s_f, area_f, meas_f[2], total_f, pad1;
+    double gscale;             // polyline: nv / total length (guide-table index scale)
+    float alpha_f, sgn_f, s_f, area_f, meas_f[2], total_f, gscale_f;
 };
 
 // Largest LDS staging area per workgroup: two 512-thread workgroups per CU share its

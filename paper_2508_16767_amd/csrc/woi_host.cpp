@@ -867,7 +867,15 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
             r.len64 = put64(g.len.data(), g.len.size());
             r.len32 = put32(g.len.data(), g.len.size());
             r.cum64 = put64(g.cum.data(), g.cum.size());
-            r.cum32 = put32(g.cum.data(), g.cum.size());
+            // FP32 sampling table: (cum[j], 1 / len[j]) pairs, one load per probe
+            std::vector<double> cl(2 * (n + 1));
+            for (int j = 0; j <= n; ++j) {
+                cl[2 * j] = g.cum[j];
+                cl[2 * j + 1] = j < n ? 1.0 / g.len[j] : 0.0;
+            }
+            r.cum32 = put32(cl.data(), cl.size());
+            r.gscale = (double)n / g.cum[n];
+            r.gscale_f = (float)r.gscale;
             std::vector<double> nrm(2 * n);
             for (int j = 0; j < n; ++j) {   // outward normal of a counter-clockwise segment
                 const double ex = g.v[2 * j + 2] - g.v[2 * j], ey = g.v[2 * j + 3] - g.v[2 * j + 1];

@@ -96,7 +96,6 @@ struct BInst {
     uint64_t slot0;
     int64_t out0;              // index of the instance's first point in the flattened point list
     double *mean, *se, *grad, *grad_se;
-    uint32_t k0, k1;
     int M, shared_sched;
     uint32_t instance;
     uint32_t lds;              // bytes of polyline tables staged in LDS (0: read from global memory)
@@ -111,6 +110,7 @@ struct BParams {
     const BInst* inst;
     const BItem* items;
     const uint32_t* ctab;
+    const uint64_t* seeds;     // Philox key of every instance (refreshed before each launch)
     uint32_t n_items;
     uint32_t* head;            // queue head, zeroed before the launch
     double* partials;

@@ -107,6 +107,7 @@ template <> struct Pay<double> {
     static __device__ __forceinline__ double area(const DevRegion& r) { return r.area; }
     static __device__ __forceinline__ double meas(const DevRegion& r, int k) { return r.meas[k]; }
     static __device__ __forceinline__ double total(const DevRegion& r) { return r.total; }
+    static __device__ __forceinline__ double gscale(const DevRegion& r) { return r.gscale; }
     static __device__ __forceinline__ double s(const DevRegion& r) { return r.s; }
     static __device__ __forceinline__ double sgn(const DevRegion& r) { return r.sgn; }
     static __device__ __forceinline__ double l1(const DevProblem* dp) { return dp->alpha_l1; }
@@ -126,6 +127,7 @@ template <> struct Pay<float> {
     static __device__ __forceinline__ float area(const DevRegion& r) { return r.area_f; }
     static __device__ __forceinline__ float meas(const DevRegion& r, int k) { return r.meas_f[k]; }
     static __device__ __forceinline__ float total(const DevRegion& r) { return r.total_f; }
+    static __device__ __forceinline__ float gscale(const DevRegion& r) { return r.gscale_f; }
     static __device__ __forceinline__ float s(const DevRegion& r) { return r.s_f; }
     static __device__ __forceinline__ float sgn(const DevRegion& r) { return r.sgn_f; }
     static __device__ __forceinline__ float l1(const DevProblem* dp) { return dp->alpha_l1_f; }
@@ -181,7 +183,7 @@ __device__ __forceinline__ void unit_dir(const Words<NW>& W, R d[D]) {
 }
 
 // ----------------------------------------------------------------------------- geometry
-template <typename R, int D>
+template <typename R, int D, bool LDS = false>
 __device__ __forceinline__ void normal_at(const DevRegion& g, const R* __restrict__ pay, const R y[D], int seg, R n[D]) {
     const R* q = pay + Pay<R>::g(g);
     if (g.kind == WOI_SHAPE_SPHERE) {
@@ -202,8 +204,15 @@ __device__ __forceinline__ void normal_at(const DevRegion& g, const R* __restric
         for (int i = 0; i < D; ++i) n[i] *= inv;
     } else {
         if constexpr (D == 2) {
-            const R* nr = pay + Pay<R>::nrm(g) + 2 * seg;
-            n[0] = nr[0]; n[1] = nr[1];
+            if constexpr (LDS && std::is_same<R, float>::value) {
+                // FP32 with staged vertices: the segment's normal from its LDS endpoints
+                const float* v = poly_xy<R, LDS>(g, pay) + 2 * seg;
+                const float ex = v[2] - v[0], ey = v[3] - v[1], il = RO<float>::rsq(ex * ex + ey * ey);
+                n[0] = ey * il; n[1] = -ex * il;
+            } else {
+                const R* nr = pay + Pay<R>::nrm(g) + 2 * seg;
+                n[0] = nr[0]; n[1] = nr[1];
+            }
         }
     }
 }
@@ -302,15 +311,20 @@ template <typename R, int D, bool LDS>
 __device__ __noinline__ bool polyline_at(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay, R s,
                                             R y[D], int& seg) {
     if constexpr (D == 2) {
+        // FP32: cum and 1/len interleaved (stride 2); FP64: cum, and len in its own table
+        constexpr bool F32 = std::is_same<R, float>::value;
+        constexpr int CS = F32 ? 2 : 1;
         const R* cum = pay + Pay<R>::cum(g);
         const int n = g.nv;
-        int k = (int)(s * ((R)n / Pay<R>::total(g)));
+        int k = (int)(s * Pay<R>::gscale(g));   // guide hint; the probes below find the exact j
         k = min(max(k, 0), n - 1);
         int j = int_payload(dp)[g.guide + k];
-        while (j < n - 1 && cum[j + 1] <= s) ++j;
-        while (j > 0 && cum[j] > s) --j;
+        while (j < n - 1 && cum[CS * (j + 1)] <= s) ++j;
+        while (j > 0 && cum[CS * j] > s) --j;
         const R* v = poly_xy<R, LDS>(g, pay) + 2 * j;
-        const R f = (s - cum[j]) / pay[Pay<R>::len(g) + j];
+        R f;
+        if constexpr (F32) f = (s - cum[2 * j]) * cum[2 * j + 1];
+        else f = (s - cum[j]) / pay[Pay<R>::len(g) + j];
         y[0] = v[0] + f * (v[2] - v[0]); y[1] = v[1] + f * (v[3] - v[1]);
         seg = j;
     }
@@ -669,7 +683,7 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
                 cnt.rejections++;
             }
             if (att == WOI_ATTEMPT_CAP) cnt.caps++;
-            normal_at<R, D>(*g, pay, yn, segn, nn);
+            normal_at<R, D, LDS>(*g, pay, yn, segn, nn);
             R dn = 0, r2 = 0;
 #pragma unroll
             for (int j = 0; j < D; ++j) { const R e = yn[j] - y[j]; dn += e * nn[j]; r2 += e * e; }
@@ -719,7 +733,7 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
                 break;
             }
             if (!ray) Q *= R(0.5);
-            normal_at<R, D>(*g, pay, yn, segn, nn);
+            normal_at<R, D, LDS>(*g, pay, yn, segn, nn);
         }
         R dn = 0;
 #pragma unroll

@@ -275,8 +275,12 @@ class Batch:
         _check(_lib.woi_batch_workspace_size(self.items, n, C.byref(nbytes)))
         self.workspace = torch.empty(max(nbytes.value, 8), dtype=torch.uint8, device="cuda")
 
-    def run(self, events=None):
-        """Enqueue the batch on the current stream; returns the list of (mean, se, grad, grad_se)."""
+    def run(self, events=None, seed=None):
+        """Enqueue the batch on the current stream; returns the list of (mean, se, grad, grad_se).
+        seed: if given, every item's seed for this and later runs (the cached graph is reused)."""
+        if seed is not None:
+            for it in self.items:
+                it.query.seed = int(seed)
         q0 = self.items[0].query
         q0.event_begin, q0.event_end = events if events is not None else (None, None)
         cnt = C.c_void_p(self.counters.data_ptr()) if self.counters is not None else None
