@@ -456,9 +456,19 @@ __device__ __forceinline__ int quadric_hit(const DevRegion& g, const R* __restri
 // keeps all its vertices strictly on one side of the line is skipped, otherwise it is
 // halved; at stride 1 the segment is tested exactly.  Every iteration costs the same
 // (one vertex, one bound), so lanes of a wave stay in step.
-// FIND = false: count all hits (q) remembering the first two; FIND: stop at hit `want`.
-struct PolyHits { int q, j0, j1; };
-
+// FIND = false: count all hits (q) remembering the first POLY_KEEP (in registers: every
+// index below is a compile-time constant after unrolling); FIND: stop at hit `want`.
+constexpr int POLY_KEEP = 8;
+struct PolyHits {
+    int q, j[POLY_KEEP];
+    // segment of hit k < POLY_KEEP (a select chain, no dynamic register indexing)
+    __device__ __forceinline__ int at(int k) const {
+        int r = j[0];
+#pragma unroll
+        for (int i = 1; i < POLY_KEEP; ++i) r = k == i ? j[i] : r;
+        return r;
+    }
+};
 
 constexpr bool COUNT_POLY = true;   // dead code unless the counting kernel reads the counters
 
@@ -480,7 +490,10 @@ __device__ __forceinline__ PolyHits poly_hits(const DevProblem* dp, const DevReg
         if constexpr (LDS) return __half2float(reinterpret_cast<const __half*>(woi_smem + g.lds_b)[idx]);
         else return Pay<float>::base(dp)[g.bnd + idx];
     };
-    PolyHits r{0, -1, -1};
+    PolyHits r;
+    r.q = 0;
+#pragma unroll
+    for (int i = 0; i < POLY_KEEP; ++i) r.j[i] = -1;
     int j = 0, lvl = top;
     float hj = hf(0);
     const unsigned topbit = 1u << top;
@@ -517,10 +530,10 @@ __device__ __forceinline__ PolyHits poly_hits(const DevProblem* dp, const DevReg
             const R t = ((a[0] - y[0]) * ey - (a[1] - y[1]) * ex) / den;
             if ((den != R(0)) & (ray ? (t > R(0)) : (fabs(t) > RO<R>::line_eps))) {
                 if constexpr (FIND) {
-                    if (r.q == want) { r.j0 = j; r.q++; return r; }
+                    if (r.q == want) { r.j[0] = j; r.q++; return r; }
                 } else {
-                    r.j0 = r.q == 0 ? j : r.j0;
-                    r.j1 = r.q == 1 ? j : r.j1;
+#pragma unroll
+                    for (int i = 0; i < POLY_KEEP; ++i) r.j[i] = r.q == i ? j : r.j[i];
                 }
                 r.q++;
             }
@@ -708,8 +721,8 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
                         qn = ph.q;
                         if (qn == 0) { cnt.redraws++; continue; }
                         pick = min((int)(up * (R)qn), qn - 1);
-                        int j = pick == 0 ? ph.j0 : ph.j1;
-                        if (pick >= 2) j = poly_hits<R, LDS, true>(dp, *g, pay, y, d, ray, seg, pick, cnt).j0;
+                        int j = ph.at(pick);
+                        if (pick >= POLY_KEEP) j = poly_hits<R, LDS, true>(dp, *g, pay, y, d, ray, seg, pick, cnt).j[0];
                         const R* v = poly_xy<R, LDS>(*g, pay) + 2 * j;
                         const R ex = v[2] - v[0], ey = v[3] - v[1];
                         const R den = d[0] * ey - d[1] * ex;
