@@ -456,17 +456,22 @@ __device__ __forceinline__ int quadric_hit(const DevRegion& g, const R* __restri
 // keeps all its vertices strictly on one side of the line is skipped, otherwise it is
 // halved; at stride 1 the segment is tested exactly.  Every iteration costs the same
 // (one vertex, one bound), so lanes of a wave stay in step.
-// FIND = false: count all hits (q) remembering the first POLY_KEEP (in registers: every
-// index below is a compile-time constant after unrolling); FIND: stop at hit `want`.
+// FIND = false: count all hits (q) remembering the first POLY_KEEP = 8 in named registers;
+// FIND: stop at hit `want`.
 constexpr int POLY_KEEP = 8;
 struct PolyHits {
-    int q, j[POLY_KEEP];
-    // segment of hit k < POLY_KEEP (a select chain, no dynamic register indexing)
+    int q, j0, j1, j2, j3, j4, j5, j6, j7;
+    __device__ __forceinline__ void keep(int j) {
+        j0 = q == 0 ? j : j0; j1 = q == 1 ? j : j1; j2 = q == 2 ? j : j2; j3 = q == 3 ? j : j3;
+        j4 = q == 4 ? j : j4; j5 = q == 5 ? j : j5; j6 = q == 6 ? j : j6; j7 = q == 7 ? j : j7;
+    }
+    // segment of hit k < 8: a select tree on the bits of k (no indexed access, so the hits
+    // stay in registers)
     __device__ __forceinline__ int at(int k) const {
-        int r = j[0];
-#pragma unroll
-        for (int i = 1; i < POLY_KEEP; ++i) r = k == i ? j[i] : r;
-        return r;
+        const bool b0 = k & 1, b1 = k & 2, b2 = k & 4;
+        const int a = b0 ? j1 : j0, b = b0 ? j3 : j2, c = b0 ? j5 : j4, d = b0 ? j7 : j6;
+        const int e = b1 ? b : a, f = b1 ? d : c;
+        return b2 ? f : e;
     }
 };
 
@@ -490,10 +495,7 @@ __device__ __forceinline__ PolyHits poly_hits(const DevProblem* dp, const DevReg
         if constexpr (LDS) return __half2float(reinterpret_cast<const __half*>(woi_smem + g.lds_b)[idx]);
         else return Pay<float>::base(dp)[g.bnd + idx];
     };
-    PolyHits r;
-    r.q = 0;
-#pragma unroll
-    for (int i = 0; i < POLY_KEEP; ++i) r.j[i] = -1;
+    PolyHits r{0, -1, -1, -1, -1, -1, -1, -1, -1};
     int j = 0, lvl = top;
     float hj = hf(0);
     const unsigned topbit = 1u << top;
@@ -530,10 +532,9 @@ __device__ __forceinline__ PolyHits poly_hits(const DevProblem* dp, const DevReg
             const R t = ((a[0] - y[0]) * ey - (a[1] - y[1]) * ex) / den;
             if ((den != R(0)) & (ray ? (t > R(0)) : (fabs(t) > RO<R>::line_eps))) {
                 if constexpr (FIND) {
-                    if (r.q == want) { r.j[0] = j; r.q++; return r; }
+                    if (r.q == want) { r.j0 = j; r.q++; return r; }
                 } else {
-#pragma unroll
-                    for (int i = 0; i < POLY_KEEP; ++i) r.j[i] = r.q == i ? j : r.j[i];
+                    r.keep(j);
                 }
                 r.q++;
             }
@@ -722,7 +723,7 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
                         if (qn == 0) { cnt.redraws++; continue; }
                         pick = min((int)(up * (R)qn), qn - 1);
                         int j = ph.at(pick);
-                        if (pick >= POLY_KEEP) j = poly_hits<R, LDS, true>(dp, *g, pay, y, d, ray, seg, pick, cnt).j[0];
+                        if (pick >= POLY_KEEP) j = poly_hits<R, LDS, true>(dp, *g, pay, y, d, ray, seg, pick, cnt).j0;
                         const R* v = poly_xy<R, LDS>(*g, pay) + 2 * j;
                         const R ex = v[2] - v[0], ey = v[3] - v[1];
                         const R den = d[0] * ey - d[1] * ex;
