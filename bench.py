@@ -40,12 +40,12 @@ FLOPS_PER_SEGMENT_TEST = 4      # distance of the segment end vertex (crossings 
 FLOPS_PER_WALKER = 57           # step-0 datum b(y_0) (5-mode Fourier) and Q_0
 PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 (packed) peak
 # HBM bytes per launch of the timed FP32 walk kernel at W = 1e5, from the FETCH_SIZE and
-# WRITE_SIZE passes in profiles/walk_kernel_star_tree_2d_hbm_counters.md, scaled by what the same
+# WRITE_SIZE passes in profiles/headline_kernels_star_tree_2d_counters.md, scaled by what the same
 # counters read for a 1 GiB device copy.  None whenever the kernel has changed since those
 # passes were taken.
-TRAFFIC_BYTES = None
+TRAFFIC_BYTES = 2616 * 1024 * 2.0 + 63744 * 1024 * 1.0
 # The same for the persistent batch kernel of the headline graph.
-BATCH_TRAFFIC_BYTES = None
+BATCH_TRAFFIC_BYTES = 3293 * 1024 * 2.0 + 295154 * 1024 * 1.0
 
 
 def eval_flops_per_pair(m):
