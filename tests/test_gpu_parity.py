@@ -342,3 +342,20 @@ def test_nested_spheres_6d_full_size_sampled():
     z64 = (m64 - ref) / s64
     assert np.max(np.abs(z32)) < 5.0 and np.max(np.abs(z64)) < 5.0
     assert abs(np.mean(z32)) < 5.0 / np.sqrt(len(xs)) and abs(np.mean(z64)) < 5.0 / np.sqrt(len(xs))
+
+
+def test_large_point_count():
+    """2^20 points with few walkers: the grid spans many workgroups in x and the partial buffer
+    is a single chunk; sampled points against the oracle on identical streams (FP64) and the
+    FP32 path paired with it."""
+    p, _ = W.concentric_disk_2d()
+    xs = W.ball_points(np.random.default_rng(5), 1 << 20, 2, 0.98)
+    gp = woi.Problem(p)
+    m64, s64, g64, _ = [_np(t) for t in woi.estimate(gp, xs, 16, 4, seed=12)]
+    m32 = _np(woi.estimate(gp, xs, 16, 4, seed=12, precision=woi.FP32)[0])
+    idx = np.array([0, 12345, (1 << 19) + 7, (1 << 20) - 1])
+    mo, so, go, _, _ = O.estimate(O.OracleProblem(p), xs[idx], 16, 4, seed=12, groups=idx)
+    assert np.allclose(m64[idx], mo, rtol=1e-9, atol=1e-9 * so.max())
+    assert np.allclose(g64[idx], go, rtol=1e-9, atol=1e-9 * np.abs(go).max())
+    z = np.abs(m32 - m64) / np.maximum(s64, 1e-300)
+    assert np.all(np.isfinite(m32)) and np.median(z) < 0.01
