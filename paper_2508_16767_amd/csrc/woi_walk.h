@@ -75,6 +75,7 @@ template <> struct RO<double> {
     static __device__ __forceinline__ double lg(double x) { return log(x); }
     static __device__ __forceinline__ double sq(double x) { return sqrt(x); }
     static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double div(double a, double b) { return a / b; }
     static __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
     static constexpr double line_eps = 1e-12;   // |t| below which a polyline hit is y itself
     static constexpr double ray_eps = 0.0;
@@ -88,6 +89,8 @@ template <> struct RO<float> {
     static __device__ __forceinline__ float lg(float x) { return __logf(x); }
     static __device__ __forceinline__ float sq(float x) { return __builtin_sqrtf(x); }
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    // a / b to about 2 ulp (hardware reciprocal), for the FP32 walks
+    static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
     static __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
     static constexpr float line_eps = 1e-5f;
     static constexpr float ray_eps = 0.0f;
@@ -440,12 +443,12 @@ __device__ __forceinline__ int quadric_hit(const DevRegion& g, const R* __restri
         }
     }
     if (!ray) {   // y on the quadric: other root of t (a t + 2 b) = 0
-        t = R(-2) * b / a;
+        t = RO<R>::div(R(-2) * b, a);
         return t != R(0) ? 1 : 0;
     }
     const R disc = b * b - a * cc;
     if (disc < R(0)) return 0;
-    t = (-b + RO<R>::sq(disc)) / a;
+    t = RO<R>::div(-b + RO<R>::sq(disc), a);
     return t > R(0) ? 1 : 0;
 }
 
@@ -529,7 +532,7 @@ __device__ __forceinline__ PolyHits poly_hits(const DevProblem* dp, const DevReg
             const R* a = v + 2 * j;
             const R ex = a[2] - a[0], ey = a[3] - a[1];
             const R den = d[0] * ey - d[1] * ex;
-            const R t = ((a[0] - y[0]) * ey - (a[1] - y[1]) * ex) / den;
+            const R t = RO<R>::div((a[0] - y[0]) * ey - (a[1] - y[1]) * ex, den);
             if ((den != R(0)) & (ray ? (t > R(0)) : (fabs(t) > RO<R>::line_eps))) {
                 if constexpr (FIND) {
                     if (r.q == want) { r.j0 = j; r.q++; return r; }
@@ -571,7 +574,7 @@ __device__ __forceinline__ void add_term(const DevProblem* dp, const R xh[D], co
         irm = p * ir2;
     }
     F += c * phi;
-    const R gs = -c * irm / Pay<R>::ua(dp);
+    const R gs = RO<R>::div(-c * irm, Pay<R>::ua(dp));
 #pragma unroll
     for (int i = 0; i < D; ++i) G[i] += gs * d[i];
 }
@@ -705,7 +708,7 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
 #pragma unroll
             for (int j = 0; j < D / 2; ++j) rm *= r2;
             if constexpr (D % 2) rm *= RO<R>::sq(r2);
-            Q *= fabs(dn / (Pay<R>::ua(dp) * rm)) * Pay<R>::area(*g);
+            Q *= fabs(RO<R>::div(dn, Pay<R>::ua(dp) * rm)) * Pay<R>::area(*g);
         } else {
             // isotropic line (same interface) or ray (descendant to ancestor); uniform pick among q hits
             const bool ray = rel == REL_DESC;
@@ -727,7 +730,7 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
                         const R* v = poly_xy<R, LDS>(*g, pay) + 2 * j;
                         const R ex = v[2] - v[0], ey = v[3] - v[1];
                         const R den = d[0] * ey - d[1] * ex;
-                        const R s = ((v[0] - y[0]) * d[1] - (v[1] - y[1]) * d[0]) / den;
+                        const R s = RO<R>::div((v[0] - y[0]) * d[1] - (v[1] - y[1]) * d[0], den);
                         yn[0] = v[0] + s * ex; yn[1] = v[1] + s * ey; segn = j;
                     }
                 } else {
