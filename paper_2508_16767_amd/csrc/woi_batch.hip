@@ -63,9 +63,11 @@ __global__ __launch_bounds__(64 * WV) void batch_kernel(BParams bp) {
             double F = 0, Gs[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) Gs[i] = 0;
+            Start<R, D> st2[2];
+            if constexpr (VR) vr_starts<R, D, LDS>(dp, pay, kp, w, (uint32_t)pc, first_region(dp, kp, w, (uint32_t)pc), st2, cnt);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                walker<R, D, VR, LDS>(dp, pay, kp, w, (uint32_t)pc, k, sink, nullptr, cnt);
+                walker<R, D, VR, LDS>(dp, pay, kp, w, (uint32_t)pc, k, sink, nullptr, cnt, VR ? &st2[k] : nullptr);
                 F += (double)(sink.F * (R)dp->N);
 #pragma unroll
                 for (int i = 0; i < D; ++i) Gs[i] += (double)(sink.G[i] * (R)dp->N);

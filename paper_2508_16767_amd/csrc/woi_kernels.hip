@@ -30,12 +30,14 @@ __global__ __launch_bounds__(LDS ? 512 : 256) void walk_kernel(KParams kp) {
         double F = 0, Gs[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) Gs[i] = 0;
+        Start<R, D> st2[2];
+        if constexpr (VR) vr_starts<R, D, LDS>(dp, pay, kp, w, group, first_region(dp, kp, w, group), st2, cnt);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             uint32_t* tr = nullptr;
             const size_t idx = ((size_t)pc * kp.n_samples + s) * K + k;
             if (kp.trace && active) tr = kp.trace + idx * (kp.M + 1);
-            walker<R, D, VR, LDS>(dp, pay, kp, w, group, k, sink, tr, cnt);
+            walker<R, D, VR, LDS>(dp, pay, kp, w, group, k, sink, tr, cnt, VR ? &st2[k] : nullptr);
             const R Fk = sink.F * (R)dp->N;
             R Gk[D];
 #pragma unroll
@@ -93,6 +95,8 @@ __global__ __launch_bounds__(LDS ? 512 : 256) void traj_kernel(KParams kp, TPara
     Counts cnt{0, 0, 0, 0, 0, 0, 0, 0};
     for (uint32_t s = s0; s < s1; ++s) {
         const uint32_t w = (uint32_t)(kp.first_sample + tp.chunk_first + s);
+        Start<R, D> st2[2];
+        if constexpr (VR) vr_starts<R, D, LDS>(dp, pay, kp, w, (uint32_t)gc, first_region(dp, kp, w, (uint32_t)gc), st2, cnt);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             StoreSink<R, D> sink;
@@ -101,7 +105,7 @@ __global__ __launch_bounds__(LDS ? 512 : 256) void traj_kernel(KParams kp, TPara
             sink.ng = tp.ng;
             sink.M = kp.M;
             sink.on = active;
-            walker<R, D, VR, LDS>(dp, pay, kp, w, (uint32_t)gc, k, sink, nullptr, cnt);
+            walker<R, D, VR, LDS>(dp, pay, kp, w, (uint32_t)gc, k, sink, nullptr, cnt, VR ? &st2[k] : nullptr);
         }
     }
 }

@@ -629,12 +629,71 @@ struct StoreSink {
     }
 };
 
+// First point of a VR walker, drawn before its walk (see vr_starts).
+template <typename R, int D>
+struct Start {
+    R y[D];
+    int seg, att;
+};
+
+// Region H_0 of sample w (Theorem 2: uniform over the regions); wave-uniform with the shared
+// schedule.  The walker draws it from the same counter.
+__device__ __forceinline__ int first_region(const DevProblem* __restrict__ dp, const KParams& kp, uint32_t w,
+                                            uint32_t group) {
+    const uint32_t inst = (kp.instance & 0xFFFFFFu) << 8;
+    const uint4 sb = kp.shared_sched ? philox(make_uint4(w, 0xFFFFFFFFu, inst, 0u), kp.k0, kp.k1)
+                                     : philox(make_uint4(w, group, inst, 0u), kp.k0, kp.k1);
+    const int t = (int)floor(RO<double>::u(sb.x) * dp->N);
+    int h = t < dp->N ? t : dp->N - 1;
+    if (kp.shared_sched) h = __builtin_amdgcn_readfirstlane(h);
+    return h;
+}
+
+// First points of both walkers of a VR sample (Alg. 3: walker 0 on {beta >= 0}, walker 1 on
+// {beta < 0} of dOmega_{H_0}) drawn by one rejection loop: each lane draws for whichever of
+// its walkers still lacks a point, so a wave waits for its slowest lane once rather than once
+// per walker.  Walker k keeps its own stream and attempt count, so the points, attempt counts
+// and cap rule (after WOI_ATTEMPT_CAP attempts the last proposal is kept) are exactly those
+// of drawing the walkers one after the other.  A walker whose half is empty draws nothing.
+template <typename R, int D, bool LDS>
+__device__ __forceinline__ void vr_starts(const DevProblem* __restrict__ dp, const R* __restrict__ pay,
+                                          const KParams& kp, uint32_t w, uint32_t group, int h, Start<R, D> s[2],
+                                          Counts& cnt) {
+    const DevRegion& g = dp->reg[h];
+    const uint32_t inst = (kp.instance & 0xFFFFFFu) << 8;
+    const Stream st0{kp.k0, kp.k1, w, group, inst | 1u};
+    const Stream st1{kp.k0, kp.k1, w, group, inst | (1u << 4) | 1u};
+    bool need0 = Pay<R>::meas(g, 0) != R(0), need1 = Pay<R>::meas(g, 1) != R(0);
+    s[0].att = s[1].att = 0;
+    s[0].seg = s[1].seg = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) { s[0].y[i] = R(0); s[1].y[i] = R(0); }
+    while (need0 || need1) {
+        const int k = need0 ? 0 : 1;
+        const int att = k ? s[1].att : s[0].att;
+        R y[D];
+        int seg = 0;
+        const bool ok = vr_attempt<R, D, LDS>(dp, g, pay, k, k ? st1 : st0, att, y, seg);
+        if (!ok) cnt.rejections++;
+        const bool done = ok || att + 1 == WOI_ATTEMPT_CAP;
+        if (!ok && done) cnt.caps++;
+        Start<R, D>& t = k ? s[1] : s[0];
+#pragma unroll
+        for (int i = 0; i < D; ++i) t.y[i] = y[i];
+        t.seg = seg;
+        t.att = ok ? att : att + 1;
+        if (k) need1 = !done;
+        else need0 = !done;
+    }
+}
+
 // Walker k of sample `w`: emits c_i and y_i, i = 0..M, to the sink (the accumulating sink
 // forms sum_i c_i Phi(x, y_i) and sum_i c_i grad_x Phi; the caller multiplies by N).
+// pre: the walker's first point drawn beforehand (VR, see vr_starts), or null.
 template <typename R, int D, bool VR, bool LDS, class Sink>
 __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const R* __restrict__ pay,
                                        const KParams& kp, uint32_t w, uint32_t group, int k, Sink& sink,
-                                       uint32_t* __restrict__ tr, Counts& cnt) {
+                                       uint32_t* __restrict__ tr, Counts& cnt, const Start<R, D>* pre = nullptr) {
     const int N = dp->N, M = kp.M;
     const uint32_t inst = (kp.instance & 0xFFFFFFu) << 8;
     // Schedule words: counter (w, group or all-ones, instance, draw).  With the shared schedule
@@ -663,14 +722,21 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
     }
     R y[D];
     int seg = 0, att;
-    for (att = 0; att < WOI_ATTEMPT_CAP; ++att) {
-        bool ok;
-        if constexpr (VR) ok = vr_attempt<R, D, LDS>(dp, *g, pay, k, st, att, y, seg);
-        else ok = surf_attempt<R, D, LDS>(dp, *g, pay, st, 0, att, y, seg);
-        if (ok) break;
-        cnt.rejections++;
+    if (pre) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) y[i] = pre->y[i];
+        seg = pre->seg;
+        att = pre->att;
+    } else {
+        for (att = 0; att < WOI_ATTEMPT_CAP; ++att) {
+            bool ok;
+            if constexpr (VR) ok = vr_attempt<R, D, LDS>(dp, *g, pay, k, st, att, y, seg);
+            else ok = surf_attempt<R, D, LDS>(dp, *g, pay, st, 0, att, y, seg);
+            if (ok) break;
+            cnt.rejections++;
+        }
+        if (att == WOI_ATTEMPT_CAP) cnt.caps++;
     }
-    if (att == WOI_ATTEMPT_CAP) cnt.caps++;
     R Q = Pay<R>::s(*g) * data_b<R, D>(dp, *g, pay, y, seg) * meas, T = 1;
     sink.add(0, (M == 0 ? R(0.5) : R(1)) * Q * T, y, cnt);
     cnt.steps++;
