@@ -43,9 +43,9 @@ PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 (packed) peak
 # WRITE_SIZE passes in profiles/headline_kernels_star_tree_2d_counters.md, scaled by what the same
 # counters read for a 1 GiB device copy.  None whenever the kernel has changed since those
 # passes were taken.
-TRAFFIC_BYTES = None
+TRAFFIC_BYTES = 2624 * 1024 * 2.0 + 60773 * 1024 * 1.0
 # The same for the persistent batch kernel of the headline graph.
-BATCH_TRAFFIC_BYTES = None
+BATCH_TRAFFIC_BYTES = 3297 * 1024 * 2.0 + 295254 * 1024 * 1.0
 
 
 def eval_flops_per_pair(m):
@@ -273,7 +273,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="measure only the headline path (skip shared trajectories, the instance batch, 3D and 6D)")
     ap.add_argument("--extra-steps", type=int, default=2, help="timed steps of the other configurations")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=25.0)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after the run, copy this many bytes device-to-device three times (a plain copy "
                          "kernel of known size, to scale the FETCH_SIZE / WRITE_SIZE counters)")
