@@ -26,8 +26,9 @@ constexpr int DK_DIRPOLY_HORNER = 16;
 // Polyline search tables (float payload, shared by both precisions):
 //   for every level l >= 1 and aligned block b (vertices [b 2^l, min((b+1) 2^l, nv)]),
 //   bnd[(N2 >> l) + b] bounds the distance of the block's vertices from its chord (heap
-//   layout, N2 = nv rounded up to a power of two, entry 0 unused); the walk starts at
-//   level top.  Guide table (int payload): gd[k] = largest j with
+//   layout, N2 = nv rounded up to a power of two, entry 0 unused); the segments (level 0)
+//   follow as bnd[N2 + j] = 0, so block (j, l) sits at (N2 + j) >> l at every level; the
+//   walk starts at level top.  Guide table (int payload): gd[k] = largest j with
 //   cum[j] <= k L / nv.
 struct DevRegion {
     int kind, dkind, nt, nv;
@@ -35,7 +36,7 @@ struct DevRegion {
     int len64, len32;          // polyline segment lengths
     int cum64, cum32;          // polyline cumulative lengths
     int nrm64, nrm32;          // polyline segment normals
-    int bnd;                   // float offset of the block bounds
+    int bnd;                   // float offset of the block bounds (N2 + nv entries)
     int n2, top;               // nv rounded up to a power of two, first walk level
     int guide;                 // int offset of the guide table (nv entries)
     int d64, d32, dexp;        // data coefficients, DIRPOLY exponents (byte offset)

@@ -660,7 +660,8 @@ double seg_dist(const double* p, const double* a, const double* b) {
 // Block bounds of the polyline search: every vertex of the aligned block
 // [b 2^l, min((b+1) 2^l, n)] lies within bnd of the block's chord segment, so its signed
 // distance to any line lies within [min(h_first, h_last) - bnd, max(...) + bnd].
-// Inflated to stay conservative under FP32 rounding.
+// Inflated to stay conservative under FP32 rounding.  The segments themselves (level 0, a
+// block whose chord is the segment) follow at N2 + j with bound 0.
 // DIRPOLY data in dimension 2 or 3 as a dense triangular coefficient table c[i][j](k) over
 // total degree <= n, in the order a nested Horner evaluation reads it (i, j, k descending):
 // b = sum_i e0^i sum_j e1^j sum_k e2^k c_ijk.  Declined (false) when the table would be
@@ -699,7 +700,7 @@ void block_bounds(const HostRegion& g, std::vector<float>& bnd, int& n2, int& to
     double scale = 0;
     for (double x : g.v) scale = std::max(scale, std::fabs(x));
     const double pad = 4e-6 * (1.0 + scale);
-    bnd.assign(n2, 0.0f);
+    bnd.assign((size_t)n2 + n, 0.0f);
     for (int l = 1; l <= L; ++l) {
         const int base = n2 >> l;   // heap layout: level l occupies [n2 >> l, 2 (n2 >> l))
         for (int j0 = 0, blk = 0; j0 < n; j0 += 1 << l, ++blk) {
@@ -934,8 +935,8 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
         r.meas_f[1] = (float)r.meas[1];
         r.total_f = (float)r.total;
     }
-    // LDS staging layout: FP32 vertices (8 B each, n + 1) and FP16 bounds (2 B each, n2) of
-    // every polyline
+    // LDS staging layout: FP32 vertices (8 B each, n + 1) and FP16 bounds (2 B each, n2 + n)
+    // of every polyline
     {
         int off = 0;
         for (int i = 0; i < N; ++i) {
@@ -945,7 +946,7 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
             r.lds_v = off;
             off += 8 * (r.nv + 1);
             r.lds_b = off;
-            off += 2 * r.n2;
+            off += 2 * (r.n2 + r.nv);
             off = (off + 15) & ~15;
         }
         hdr.lds_bytes = off;   // staged only if the device's workgroup limit allows (decided at launch)

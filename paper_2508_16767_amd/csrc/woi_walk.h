@@ -487,48 +487,59 @@ __device__ __forceinline__ PolyHits poly_hits(const DevProblem* dp, const DevReg
     const R* __restrict__ v = poly_xy<R, LDS>(g, pay);       // exact tests, precision R
     const int n = g.nv, n2 = g.n2, top = g.top;
     // block tests run in FP32 on the staged (or global) FP32 copy; bounds absorb the rounding
-    const float* __restrict__ vf;
-    if constexpr (LDS) vf = reinterpret_cast<const float*>(woi_smem + g.lds_v);
-    else vf = Pay<float>::base(dp) + g.g32;
     const float yf0 = (float)y[0], yf1 = (float)y[1], df0 = (float)d[0], df1 = (float)d[1];
     // h(v) = d x (v - y) = d0 v1 - d1 v0 - (d0 y1 - d1 y0): two FMAs per vertex
     const float hc = df0 * yf1 - df1 * yf0;
-    auto hf = [&](int j) -> float { return fmaf(df0, vf[2 * j + 1], fmaf(-df1, vf[2 * j], -hc)); };
     auto bound = [&](int idx) -> float {
         if constexpr (LDS) return __half2float(reinterpret_cast<const __half*>(woi_smem + g.lds_b)[idx]);
         else return Pay<float>::base(dp)[g.bnd + idx];
     };
     PolyHits r{0, -1, -1, -1, -1, -1, -1, -1, -1};
-    int j = 0, lvl = top;
-    float hj = hf(0);
+    // The walk position is kept as jn = n2 + j: block (j, lvl) then sits at heap index
+    // jn >> lvl, segments included (their bound is 0), and ctz(jn | 2^top) is the highest
+    // level a block starting at j may take.
+    const int jend = n2 + n, ysn = ray ? -1 : n2 + yseg;   // a line excludes the segment of y
+    // h of vertex jn - n2; the LDS byte offset of vertex 0 less 8 n2, in wrapping 32-bit
+    // arithmetic, makes the address one shift-add of jn
+    const uint32_t vbase = (uint32_t)g.lds_v - 8u * (uint32_t)n2;
+    const float2* __restrict__ vg = reinterpret_cast<const float2*>(Pay<float>::base(dp) + g.g32);
+    auto hn = [&](int jn) -> float {
+        float2 p;
+        if constexpr (LDS) p = *reinterpret_cast<const float2*>(woi_smem + (vbase + 8u * (uint32_t)jn));
+        else p = vg[jn - n2];
+        return fmaf(df0, p.y, fmaf(-df1, p.x, -hc));
+    };
+    int jn = n2, lvl = top;
+    float hj = hn(jn);
     const unsigned topbit = 1u << top;
-    const int hmask = n2 - 1;
-    // Straight-line body: the block test, the segment crossing and the next (j, level) are
+    // Straight-line body: the block test, the segment crossing and the next (jn, level) are
     // computed with bitwise logic and selects by every lane; only a lane that crosses a
     // segment enters the (rare) hit branch.
-    while (j < n) {
-        const int je = min(j + (1 << lvl), n);
-        const float he = hf(je);
+    while (jn < jend) {
+        const int je = min(jn + (1 << lvl), jend);
+        const float he = hn(je);
         const bool seg = lvl == 0;
-        // block (j, lvl) sits at (n2 >> lvl) + (j >> lvl); at stride 1 the mask keeps the
-        // (unused) read inside the table
-        const float b = bound(((n2 >> lvl) + (j >> lvl)) & hmask);
-        const bool skip = ((hj > b) & (he > b)) | ((hj < -b) & (he < -b));
-        R ha, hb;
+        const float b = bound(jn >> lvl);
+        // Every vertex of the block strictly on one side of the line.  A block bound exceeds
+        // the true deviation from the chord (it is inflated), so an end value equal to b still
+        // leaves every vertex off the line.  For a segment (b = 0) the test reads "no crossing":
+        // a zero start value belongs to this segment and a zero end value to the next (a
+        // segment with both values zero lies along the line and is left to the hit test).
+        const bool skip = ((hj > b) & (he >= b)) | ((hj < -b) & (he <= -b));
+        bool cross;
         if constexpr (F32) {
-            ha = hj;
-            hb = he;
+            cross = !skip;
         } else {                                              // FP64 exact values at stride 1 only
-            ha = R(0);
-            hb = R(0);
+            R ha = R(0), hb = R(0);
             if (seg) {
-                const R* a = v + 2 * j;
+                const R* a = v + 2 * (jn - n2);
                 ha = d[0] * (a[1] - y[1]) - d[1] * (a[0] - y[0]);
                 hb = d[0] * (a[3] - y[1]) - d[1] * (a[2] - y[0]);
             }
+            cross = (hb != R(0)) & ((ha == R(0)) | ((ha > R(0)) != (hb > R(0))));
         }
-        const bool cross = (hb != R(0)) & ((ha == R(0)) | ((ha > R(0)) != (hb > R(0))));
-        if (seg & cross & (ray | (j != yseg))) {
+        if (seg & cross & (jn != ysn)) {
+            const int j = jn - n2;
             const R* a = v + 2 * j;
             const R ex = a[2] - a[0], ey = a[3] - a[1];
             const R den = d[0] * ey - d[1] * ex;
@@ -545,7 +556,7 @@ __device__ __forceinline__ PolyHits poly_hits(const DevProblem* dp, const DevReg
         if (COUNT_POLY) { cnt.nodes += seg ? 0 : 1; cnt.segs += seg ? 1 : 0; }
         const bool adv = seg | skip;
         const int lz = (int)__builtin_ctz((unsigned)je | topbit);   // <= top
-        j = adv ? je : j;
+        jn = adv ? je : jn;
         hj = adv ? he : hj;
         lvl = adv ? lz : lvl - 1;
     }
@@ -861,7 +872,7 @@ __device__ __forceinline__ void stage_polylines(const DevProblem* __restrict__ d
         const float2* sv = reinterpret_cast<const float2*>(f32 + g.g32);
         for (int t = threadIdx.x; t <= g.nv; t += blockDim.x) dv[t] = sv[t];
         __half* db = reinterpret_cast<__half*>(woi_smem + g.lds_b);
-        for (int t = threadIdx.x; t < g.n2; t += blockDim.x) db[t] = __float2half_ru(f32[g.bnd + t]);
+        for (int t = threadIdx.x; t < g.n2 + g.nv; t += blockDim.x) db[t] = __float2half_ru(f32[g.bnd + t]);
     }
     __syncthreads();
 }
