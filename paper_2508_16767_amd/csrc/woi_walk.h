@@ -454,37 +454,49 @@ __device__ __forceinline__ int quadric_hit(const DevRegion& g, const R* __restri
 
 // Polyline: hits of the line / ray y + t d in segment order.  The signed distance of
 // vertex j from the line is h_j = d x (v_j - y); segment j is hit iff h_j = 0 != h_{j+1}
-// or the signs differ (the half-open segment [v_j, v_{j+1})).  One flat loop per lane
+// or the signs differ (the half-open segment [v_j, v_{j+1})), the line excludes the segment
+// of y, and the crossing parameter passes the line / ray test.  One flat loop per lane
 // walks the vertex index with an adaptive aligned stride 2^l: a block whose chord bound
 // keeps all its vertices strictly on one side of the line is skipped, otherwise it is
-// halved; at stride 1 the segment is tested exactly.  Every iteration costs the same
-// (one vertex, one bound), so lanes of a wave stay in step.
-// FIND = false: count all hits (q) remembering the first POLY_KEEP = 8 in named registers;
-// FIND: stop at hit `want`.
-constexpr int POLY_KEEP = 8;
-struct PolyHits {
-    int q, j0, j1, j2, j3, j4, j5, j6, j7;
-    __device__ __forceinline__ void keep(int j) {
-        j0 = q == 0 ? j : j0; j1 = q == 1 ? j : j1; j2 = q == 2 ? j : j2; j3 = q == 3 ? j : j3;
-        j4 = q == 4 ? j : j4; j5 = q == 5 ? j : j5; j6 = q == 6 ? j : j6; j7 = q == 7 ? j : j7;
+// halved; at stride 1 the sign test picks out candidate segments.  Every iteration costs the
+// same (one vertex, one bound), so lanes of a wave stay in step.  The walk only queues the
+// candidates; their crossing parameters are tested after it, so that the wave does not run
+// the test in every iteration in which some lane reaches a candidate.
+
+// Up to eight segment indices of 16 bits, slot k in half (k & 1) of word k >> 1.  push()
+// moves every slot up by one (slot 7 drops out) and writes slot 0; pop() takes slot 0 and
+// moves every slot down.
+struct Queue16 {
+    uint32_t w0, w1, w2, w3;
+    __device__ __forceinline__ void push(uint32_t j) {
+        w3 = __builtin_amdgcn_alignbit(w3, w2, 16);
+        w2 = __builtin_amdgcn_alignbit(w2, w1, 16);
+        w1 = __builtin_amdgcn_alignbit(w1, w0, 16);
+        w0 = (w0 << 16) | j;
     }
-    // segment of hit k < 8: a select tree on the bits of k (no indexed access, so the hits
-    // stay in registers)
-    __device__ __forceinline__ int at(int k) const {
-        const bool b0 = k & 1, b1 = k & 2, b2 = k & 4;
-        const int a = b0 ? j1 : j0, b = b0 ? j3 : j2, c = b0 ? j5 : j4, d = b0 ? j7 : j6;
-        const int e = b1 ? b : a, f = b1 ? d : c;
-        return b2 ? f : e;
+    __device__ __forceinline__ uint32_t pop() {
+        const uint32_t j = w0 & 0xFFFFu;
+        w0 = __builtin_amdgcn_alignbit(w1, w0, 16);
+        w1 = __builtin_amdgcn_alignbit(w2, w1, 16);
+        w2 = __builtin_amdgcn_alignbit(w3, w2, 16);
+        w3 >>= 16;
+        return j;
+    }
+    __device__ __forceinline__ uint32_t at(int k) const {   // select on the bits of k (registers only)
+        const uint32_t lo = (k & 2) ? w1 : w0, hi = (k & 2) ? w3 : w2;
+        return (((k & 4) ? hi : lo) >> ((k & 1) << 4)) & 0xFFFFu;
     }
 };
+constexpr int POLY_QUEUE = 8;
 
 constexpr bool COUNT_POLY = true;   // dead code unless the counting kernel reads the counters
 
-template <typename R, bool LDS, bool FIND>
-__device__ __forceinline__ PolyHits poly_hits(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
-                                              const R y[2], const R d[2], bool ray, int yseg, int want, Counts& cnt) {
+// The walk: calls cand(j) for every candidate segment j in increasing order, and stops
+// early when cand returns true.
+template <typename R, bool LDS, class Cand>
+__device__ __forceinline__ void poly_walk(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
+                                          const R y[2], const R d[2], bool ray, int yseg, Counts& cnt, Cand cand) {
     constexpr bool F32 = std::is_same<R, float>::value;
-    const R* __restrict__ v = poly_xy<R, LDS>(g, pay);       // exact tests, precision R
     const int n = g.nv, n2 = g.n2, top = g.top;
     // block tests run in FP32 on the staged (or global) FP32 copy; bounds absorb the rounding
     const float yf0 = (float)y[0], yf1 = (float)y[1], df0 = (float)d[0], df1 = (float)d[1];
@@ -494,7 +506,6 @@ __device__ __forceinline__ PolyHits poly_hits(const DevProblem* dp, const DevReg
         if constexpr (LDS) return __half2float(reinterpret_cast<const __half*>(woi_smem + g.lds_b)[idx]);
         else return Pay<float>::base(dp)[g.bnd + idx];
     };
-    PolyHits r{0, -1, -1, -1, -1, -1, -1, -1, -1};
     // The walk position is kept as jn = n2 + j: block (j, lvl) then sits at heap index
     // jn >> lvl, segments included (their bound is 0), and ctz(jn | 2^top) is the highest
     // level a block starting at j may take.
@@ -509,12 +520,10 @@ __device__ __forceinline__ PolyHits poly_hits(const DevProblem* dp, const DevReg
         else p = vg[jn - n2];
         return fmaf(df0, p.y, fmaf(-df1, p.x, -hc));
     };
+    const R* __restrict__ v = poly_xy<R, LDS>(g, pay);       // exact values (FP64)
     int jn = n2, lvl = top;
     float hj = hn(jn);
     const unsigned topbit = 1u << top;
-    // Straight-line body: the block test, the segment crossing and the next (jn, level) are
-    // computed with bitwise logic and selects by every lane; only a lane that crosses a
-    // segment enters the (rare) hit branch.
     while (jn < jend) {
         const int je = min(jn + (1 << lvl), jend);
         const float he = hn(je);
@@ -539,19 +548,7 @@ __device__ __forceinline__ PolyHits poly_hits(const DevProblem* dp, const DevReg
             cross = (hb != R(0)) & ((ha == R(0)) | ((ha > R(0)) != (hb > R(0))));
         }
         if (seg & cross & (jn != ysn)) {
-            const int j = jn - n2;
-            const R* a = v + 2 * j;
-            const R ex = a[2] - a[0], ey = a[3] - a[1];
-            const R den = d[0] * ey - d[1] * ex;
-            const R t = RO<R>::div((a[0] - y[0]) * ey - (a[1] - y[1]) * ex, den);
-            if ((den != R(0)) & (ray ? (t > R(0)) : (fabs(t) > RO<R>::line_eps))) {
-                if constexpr (FIND) {
-                    if (r.q == want) { r.j0 = j; r.q++; return r; }
-                } else {
-                    r.keep(j);
-                }
-                r.q++;
-            }
+            if (cand(jn - n2)) return;
         }
         if (COUNT_POLY) { cnt.nodes += seg ? 0 : 1; cnt.segs += seg ? 1 : 0; }
         const bool adv = seg | skip;
@@ -560,7 +557,56 @@ __device__ __forceinline__ PolyHits poly_hits(const DevProblem* dp, const DevReg
         hj = adv ? he : hj;
         lvl = adv ? lz : lvl - 1;
     }
-    return r;
+}
+
+// Number of hits q and, when q > 0, the segment jp of hit `pick` = min(floor(up q), q - 1)
+// (uniform among the hits).  With more than POLY_QUEUE candidates (or segment indices past
+// 16 bits) the hits are counted by a second walk and found by a third.
+template <typename R, bool LDS>
+__device__ __forceinline__ int poly_pick(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
+                                         const R y[2], const R d[2], bool ray, int yseg, R up, int& pick, int& jp,
+                                         Counts& cnt) {
+    const R* __restrict__ v = poly_xy<R, LDS>(g, pay);
+    // crossing parameter test of candidate segment j (precision R)
+    auto hit = [&](int j) -> bool {
+        const R* a = v + 2 * j;
+        const R ex = a[2] - a[0], ey = a[3] - a[1];
+        const R den = d[0] * ey - d[1] * ex;
+        const R t = RO<R>::div((a[0] - y[0]) * ey - (a[1] - y[1]) * ex, den);
+        return (den != R(0)) & (ray ? (t > R(0)) : (fabs(t) > RO<R>::line_eps));
+    };
+    Queue16 cq{0u, 0u, 0u, 0u};
+    int c = 0;
+    poly_walk<R, LDS>(dp, g, pay, y, d, ray, yseg, cnt, [&](int j) -> bool {
+        cq.push((uint32_t)j);
+        ++c;
+        return false;
+    });
+    int q = 0;
+    if (c <= POLY_QUEUE && g.nv <= 0xFFFF) {
+        // newest candidate first, so the hit queue ends with the first hit in slot 0
+        Queue16 hq{0u, 0u, 0u, 0u};
+        for (int k = 0; k < c; ++k) {
+            const uint32_t j = cq.pop();
+            if (hit((int)j)) { hq.push(j); ++q; }
+        }
+        if (q > 0) {
+            pick = min((int)(up * (R)q), q - 1);
+            jp = (int)hq.at(pick);
+        }
+        return q;
+    }
+    poly_walk<R, LDS>(dp, g, pay, y, d, ray, yseg, cnt, [&](int j) -> bool { q += hit(j) ? 1 : 0; return false; });
+    if (q > 0) {
+        pick = min((int)(up * (R)q), q - 1);
+        int k = 0;
+        poly_walk<R, LDS>(dp, g, pay, y, d, ray, yseg, cnt, [&](int j) -> bool {
+            if (!hit(j)) return false;
+            jp = j;
+            return k++ == pick;
+        });
+    }
+    return q;
 }
 
 // ----------------------------------------------------------------------------- accumulation
@@ -798,12 +844,9 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
                 const R up = RO<R>::u(W.w[NW - 1]);
                 if (g->kind == WOI_SHAPE_POLYLINE2D) {
                     if constexpr (D == 2) {
-                        const PolyHits ph = poly_hits<R, LDS, false>(dp, *g, pay, y, d, ray, seg, -1, cnt);
-                        qn = ph.q;
+                        int j = 0;
+                        qn = poly_pick<R, LDS>(dp, *g, pay, y, d, ray, seg, up, pick, j, cnt);
                         if (qn == 0) { cnt.redraws++; continue; }
-                        pick = min((int)(up * (R)qn), qn - 1);
-                        int j = ph.at(pick);
-                        if (pick >= POLY_KEEP) j = poly_hits<R, LDS, true>(dp, *g, pay, y, d, ray, seg, pick, cnt).j0;
                         const R* v = poly_xy<R, LDS>(*g, pay) + 2 * j;
                         const R ex = v[2] - v[0], ey = v[3] - v[1];
                         const R den = d[0] * ey - d[1] * ex;

@@ -95,6 +95,31 @@ def test_walk_parity_nonconvex_boundary():
     walk_parity(p, NC_PTS, 2000, 3, flip_budget=1e-4)
 
 
+def _gear():
+    """A 12-armed gear (r = 0.7 (1 + 0.6 cos 12 theta), 4096 segments) around a circle: lines
+    and rays cross the gear up to 24 times."""
+    return W.Problem(2, [-1, 0], [1.0, 5.0],
+                     [W.star_polyline([0.0, 0.0], 0.7, 0.6, 12, 4096), W.sphere([0.0, 0.0], 0.15)],
+                     [W.fourier([0, 0], 0.0, [0.0, 0.5], [0.3, 0.0]), W.fourier([0, 0], 0.0, [1.0], [0.0])], 2, "gear")
+
+
+def test_walk_parity_many_crossings():
+    """Steps with more hits than the polyline search queues (eight candidates) take the
+    counting and finding walks: identical decisions and values to the oracle, and FP32 on
+    the same streams agrees with FP64."""
+    p = _gear()
+    pts = np.array([[0.0, 0.05], [0.2, 0.1], [-0.1, -0.3], [0.4, 0.0]])
+    walk_parity(p, pts, 1000, 4, flip_budget=1e-4)
+    gp = woi.Problem(p)
+    _, _, T = woi.trace(gp, pts, 1000, 4, seed=7, precision=woi.FP64)
+    t = _np(T).astype(np.uint32)[..., 1:]
+    q = (t >> 8) & 0xFF
+    assert ((q > 8) & ((t & 0x3F) == 0)).sum() > 1000          # many steps past the queue
+    m64, s64, g64, _ = [_np(a) for a in woi.estimate(gp, pts, 20000, 4, seed=3, precision=woi.FP64)]
+    m32, _, g32, _ = [_np(a) for a in woi.estimate(gp, pts, 20000, 4, seed=3, precision=woi.FP32)]
+    assert np.all(np.abs(m32 - m64) < 0.1 * s64), (m32 - m64) / s64
+
+
 def test_walk_parity_star_tree_2d_small():
     p, xs = W.star_tree_2d(n_points=64)
     walk_parity(p, xs, 300, 4, flip_budget=1e-4)
