@@ -28,7 +28,8 @@ constexpr int DK_DIRPOLY_HORNER = 16;
 //   bnd[(N2 >> l) + b] bounds the distance of the block's vertices from its chord (heap
 //   layout, N2 = nv rounded up to a power of two, entry 0 unused); the segments (level 0)
 //   follow as bnd[N2 + j] = 0, so block (j, l) sits at (N2 + j) >> l at every level; the
-//   walk starts at level top.  Guide table (int payload): gd[k] = largest j with
+//   walk starts at level top.  The FP32 vertex copy is padded with v[nv] up to N2 + 1
+//   entries (a block [j, j + 2^l] past nv then ends on v[nv], the end of its chord).  Guide table (int payload): gd[k] = largest j with
 //   cum[j] <= k L / nv.
 struct DevRegion {
     int kind, dkind, nt, nv;

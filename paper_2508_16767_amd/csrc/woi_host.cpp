@@ -696,7 +696,7 @@ void block_bounds(const HostRegion& g, std::vector<float>& bnd, int& n2, int& to
     n2 = 1;
     int L = 0;
     while (n2 < n) { n2 *= 2; ++L; }
-    top = std::max(1, L - 4);
+    top = std::max(1, L - 3);   // first block: 1/8 of the polyline
     double scale = 0;
     for (double x : g.v) scale = std::max(scale, std::fabs(x));
     const double pad = 4e-6 * (1.0 + scale);
@@ -862,7 +862,17 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
             r.nv = g.nv();
         }
         r.g64 = put64(geo.data(), geo.size());
-        r.g32 = put32(geo.data(), geo.size());
+        if (g.kind == WOI_SHAPE_POLYLINE2D) {
+            // FP32 vertices padded with v[nv] up to N2 + 1 entries: every aligned block of
+            // the search then ends on a stored vertex
+            int n2 = 1;
+            while (n2 < g.nv()) n2 *= 2;
+            std::vector<double> pad(geo);
+            for (int j = g.nv() + 1; j <= n2; ++j) { pad.push_back(geo[2 * g.nv()]); pad.push_back(geo[2 * g.nv() + 1]); }
+            r.g32 = put32(pad.data(), pad.size());
+        } else {
+            r.g32 = put32(geo.data(), geo.size());
+        }
         if (g.kind == WOI_SHAPE_POLYLINE2D) {
             const int n = g.nv();
             r.len64 = put64(g.len.data(), g.len.size());
@@ -935,8 +945,8 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
         r.meas_f[1] = (float)r.meas[1];
         r.total_f = (float)r.total;
     }
-    // LDS staging layout: FP32 vertices (8 B each, n + 1) and FP16 bounds (2 B each, n2 + n)
-    // of every polyline
+    // LDS staging layout: FP32 vertices (8 B each, n2 + 1, padded) and FP16 bounds (2 B
+    // each, n2 + n) of every polyline
     {
         int off = 0;
         for (int i = 0; i < N; ++i) {
@@ -944,7 +954,7 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
             r.lds_v = r.lds_b = -1;
             if (r.kind != WOI_SHAPE_POLYLINE2D) continue;
             r.lds_v = off;
-            off += 8 * (r.nv + 1);
+            off += 8 * (r.n2 + 1);
             r.lds_b = off;
             off += 2 * (r.n2 + r.nv);
             off = (off + 15) & ~15;

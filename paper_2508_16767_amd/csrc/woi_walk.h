@@ -507,8 +507,9 @@ __device__ __forceinline__ void poly_walk(const DevProblem* dp, const DevRegion&
         else return Pay<float>::base(dp)[g.bnd + idx];
     };
     // The walk position is kept as jn = n2 + j: block (j, lvl) then sits at heap index
-    // jn >> lvl, segments included (their bound is 0), and ctz(jn | 2^top) is the highest
-    // level a block starting at j may take.
+    // jn >> lvl, segments included (their bound is 0), and ctz(jn) is the highest level a
+    // block starting at j may take.  The walk starts with the block [0, 2^top] and after
+    // each skipped block takes the largest aligned block that follows.
     const int jend = n2 + n, ysn = ray ? -1 : n2 + yseg;   // a line excludes the segment of y
     // h of vertex jn - n2; the LDS byte offset of vertex 0 less 8 n2, in wrapping 32-bit
     // arithmetic, makes the address one shift-add of jn
@@ -523,9 +524,8 @@ __device__ __forceinline__ void poly_walk(const DevProblem* dp, const DevRegion&
     const R* __restrict__ v = poly_xy<R, LDS>(g, pay);       // exact values (FP64)
     int jn = n2, lvl = top;
     float hj = hn(jn);
-    const unsigned topbit = 1u << top;
     while (jn < jend) {
-        const int je = min(jn + (1 << lvl), jend);
+        const int je = jn + (1 << lvl);   // <= 2 n2: the FP32 vertices are padded to n2 + 1
         const float he = hn(je);
         const bool seg = lvl == 0;
         const float b = bound(jn >> lvl);
@@ -552,7 +552,7 @@ __device__ __forceinline__ void poly_walk(const DevProblem* dp, const DevRegion&
         }
         if (COUNT_POLY) { cnt.nodes += seg ? 0 : 1; cnt.segs += seg ? 1 : 0; }
         const bool adv = seg | skip;
-        const int lz = (int)__builtin_ctz((unsigned)je | topbit);   // <= top
+        const int lz = (int)__builtin_ctz((unsigned)je);
         jn = adv ? je : jn;
         hj = adv ? he : hj;
         lvl = adv ? lz : lvl - 1;
@@ -913,7 +913,7 @@ __device__ __forceinline__ void stage_polylines(const DevProblem* __restrict__ d
         if (g.lds_v < 0) continue;
         float2* dv = reinterpret_cast<float2*>(woi_smem + g.lds_v);
         const float2* sv = reinterpret_cast<const float2*>(f32 + g.g32);
-        for (int t = threadIdx.x; t <= g.nv; t += blockDim.x) dv[t] = sv[t];
+        for (int t = threadIdx.x; t <= g.n2; t += blockDim.x) dv[t] = sv[t];   // padded copy
         __half* db = reinterpret_cast<__half*>(woi_smem + g.lds_b);
         for (int t = threadIdx.x; t < g.n2 + g.nv; t += blockDim.x) db[t] = __float2half_ru(f32[g.bnd + t]);
     }
