@@ -58,6 +58,9 @@ struct DevProblem {
     float alpha_l1_f, unit_area_f, phi_c_f, pad1;
     double cdf[WOI_MAX_REGIONS];              // schedule CDF over |alpha| / ||alpha||_1
     unsigned char rel[WOI_MAX_REGIONS][WOI_MAX_REGIONS];
+    // start of the inverse-CDF search for u in [k/64, (k+1)/64): the search's result at
+    // u = k/64, so no region below it can be the result for a larger u
+    unsigned char sguide[64];
     DevRegion reg[WOI_MAX_REGIONS];
     uint64_t off64, off32, offb, offi;        // byte offsets of the payload arrays
     uint64_t bytes;

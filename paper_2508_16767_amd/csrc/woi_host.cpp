@@ -833,6 +833,12 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
         acc += std::fabs(H.r[i].alpha);
         hdr.cdf[i] = acc / H.alpha_l1;
     }
+    for (int k = 0; k < 64; ++k) {
+        const double u = k / 64.0;
+        int h = 0;
+        while (h < N - 1 && !(u < hdr.cdf[h])) ++h;
+        hdr.sguide[k] = (unsigned char)h;
+    }
     for (int a = 0; a < N; ++a)
         for (int b = 0; b < N; ++b) {
             int rel = woi::REL_OTHER;

@@ -805,7 +805,8 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
         if ((i & 3) == 0) sb = sched_block((uint32_t)(i >> 2));
         const uint32_t wv = (i & 3) == 0 ? sb.x : (i & 3) == 1 ? sb.y : (i & 3) == 2 ? sb.z : sb.w;
         const double uu = RO<double>::u(wv);
-        int hn = 0;
+        // inverse CDF: the first region with uu < cdf, searched from the guide entry of uu
+        int hn = dp->sguide[min((int)(uu * 64.0), 63)];
         while (hn < N - 1 && !(uu < dp->cdf[hn])) ++hn;
         if (kp.shared_sched) hn = __builtin_amdgcn_readfirstlane(hn);
         const int rel = dp->rel[h][hn];
