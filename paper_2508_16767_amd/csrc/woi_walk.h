@@ -529,15 +529,15 @@ __device__ __forceinline__ void poly_walk(const DevProblem* dp, const DevRegion&
         const float he = hn(je);
         const bool seg = lvl == 0;
         const float b = bound(jn >> lvl);
-        // Every vertex of the block strictly on one side of the line.  A block bound exceeds
-        // the true deviation from the chord (it is inflated), so an end value equal to b still
-        // leaves every vertex off the line.  For a segment (b = 0) the test reads "no crossing":
-        // a zero start value belongs to this segment and a zero end value to the next (a
-        // segment with both values zero lies along the line and is left to the hit test).
-        const bool skip = ((hj > b) & (he >= b)) | ((hj < -b) & (he <= -b));
+        // Every vertex of the block strictly on one side of the line: the end value nearer
+        // zero, med3(h_j, h_e, 0) (zero when the signs differ), exceeds the bound in magnitude.
+        // For a segment (b = 0) this reads "both values nonzero, one sign".  A segment crosses
+        // when it is not skipped and its end value is nonzero: a zero start value belongs to
+        // this segment and a zero end value to the next.
+        const bool skip = fabsf(__builtin_amdgcn_fmed3f(hj, he, 0.0f)) > b;
         bool cross;
         if constexpr (F32) {
-            cross = !skip;
+            cross = !(skip | (he == 0.0f));
         } else {                                              // FP64 exact values at stride 1 only
             R ha = R(0), hb = R(0);
             if (seg) {
