@@ -120,6 +120,25 @@ def test_walk_parity_many_crossings():
     assert np.all(np.abs(m32 - m64) < 0.1 * s64), (m32 - m64) / s64
 
 
+@pytest.mark.parametrize("nv", [1500, 70001])
+def test_walk_parity_ragged_polylines(nv):
+    """Segment counts off a power of two: 1500 (staged in LDS, the FP32 copy padded to 2048
+    vertices) and 70001 (global memory, past the 16-bit candidate queue, so every search takes
+    the counting and finding walks).  Identical decisions and values to the oracle; FP32 on the
+    same streams agrees with FP64."""
+    p = W.Problem(2, [-1, 0], [1.0, 4.0],
+                  [W.sphere([0.0, 0.0], 1.0), W.star_polyline([0.02, -0.01], 0.55, 0.25, 6, nv, phase=0.1)],
+                  [W.fourier([0, 0], 0.0, [0.5, -0.2], [0.1, 0.3]),
+                   W.fourier([0.02, -0.01], 0.0, [0.3, 0.0, 0.2], [0.0, -0.4, 0.1])], 2, "ragged")
+    pts = np.array([[0.1, 0.05], [-0.3, 0.2], [0.7, -0.5], [0.0, -0.45]])
+    walk_parity(p, pts, 1000 if nv < 65536 else 200, 4, flip_budget=1e-4)
+    walk_parity(p, pts, 500 if nv < 65536 else 100, 3, sched=1, flip_budget=1e-4)
+    gp = woi.Problem(p)
+    m64, s64, _, _ = [_np(a) for a in woi.estimate(gp, pts, 20000, 4, seed=3, precision=woi.FP64, schedule_mode=1)]
+    m32, _, _, _ = [_np(a) for a in woi.estimate(gp, pts, 20000, 4, seed=3, precision=woi.FP32, schedule_mode=1)]
+    assert np.all(np.abs(m32 - m64) < 0.1 * s64), (m32 - m64) / s64
+
+
 def test_walk_parity_star_tree_2d_small():
     p, xs = W.star_tree_2d(n_points=64)
     walk_parity(p, xs, 300, 4, flip_budget=1e-4)
