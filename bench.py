@@ -379,6 +379,16 @@ def main():
         rec["nested_spheres_6d"] = config_block(
             woi, torch, ev, "unit 6-ball, spheres 0.7 > 0.35, sigma (1, 5, 0.2), c + lambda x1/|x| data; 1024 points; "
             "W = 1e6, M = 8", p5, x5, 1000000, 8, 0, 4, args.extra_steps)
+        # three nested ellipsoids around the potential |x|^(2-m) of a point charge, m = 3..6
+        # (1e4 points; M = m + 2 as the paper walks them; W = 2e5 keeps the run short, the rates
+        # do not depend on W)
+        rec["point_charge_ellipsoids"] = {}
+        for m in (3, 4, 5, 6):
+            pm, xm = W.point_charge_ellipsoids(m)
+            rec["point_charge_ellipsoids"][f"{m}d"] = config_block(
+                woi, torch, ev, f"{m}D: 3 nested ellipsoids (centres 1.3/1.4/1.6 e1), sigma (1.1, 1.3, 0.9), data "
+                f"from u = |x|^(2-m); 10000 points; W = 2e5, M = {m + 2}", pm, xm, 200000, m + 2, 0, 32,
+                args.extra_steps)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(prob_desc, pts_np, args.walks, M, args.cpu_seconds)
     print(json.dumps(rec), flush=True)

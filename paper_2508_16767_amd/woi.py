@@ -108,13 +108,16 @@ def _dptr(a, ct):
 class Problem:
     """A compiled problem on the current device.
 
-    `desc` is any object with attributes dim, parent, sigma, shapes, data, compat_mode:
+    `desc` is any object with attributes dim, parent, sigma, shapes, data, compat_mode (and
+    optionally compat_tol, used when the argument is None):
     shapes[i] has kind (0 sphere, 1 ellipsoid, 2 polyline), center, radius, A, vertices;
     data[i] has kind (0 zero, 1 Fourier, 2 direction polynomial, 3 source flux,
     4 field flux), center, coef, exps -- the fields of woi_shape / woi_data in woi.h.
     """
 
-    def __init__(self, desc, compat_tol=1e-8):
+    def __init__(self, desc, compat_tol=None):
+        if compat_tol is None:
+            compat_tol = float(getattr(desc, "compat_tol", 1e-8))
         m, N = int(desc.dim), len(desc.parent)
         self.dim, self.N = m, N
         keep = []

@@ -358,3 +358,45 @@ def test_pins_reject_planted_mistakes(oracle_mod, tmp_path, plant):
         mean, se, _, _, _ = oracle_mod.estimate(op, pts, 200000, 1, seed=4)
         z = _z(mean, ref, se)
     assert np.max(np.abs(z)) > 8, f"planted mistake {plant} not detected: max |z| = {np.max(np.abs(z)):.2f}"
+
+
+# ----------------------------------------------------------------------------- point charge
+def test_point_charge_data_is_the_flux_jump():
+    """The point-charge workload's data are the flux jumps of u = |x|^(2-m) as the problem
+    defines them: b_1 = sigma_1 d_n u on the outer boundary and, with the jump taken as exterior
+    minus interior, b_i = (sigma_parent - sigma_i) d_n u on interface i (checked against a
+    central difference of u along the normal)."""
+    for m in (3, 4, 5, 6):
+        p, _ = W.point_charge_ellipsoids(m)
+        rng = np.random.default_rng(m)
+        for i, (s, d) in enumerate(zip(p.shapes, p.data)):
+            L = np.linalg.cholesky(np.linalg.inv(s.A))
+            for _ in range(5):
+                z = rng.normal(size=m)
+                y = s.center + L @ (z / np.linalg.norm(z))            # on the ellipsoid
+                n = s.A @ (y - s.center)
+                n /= np.linalg.norm(n)
+                h = 1e-6
+                dnu = (W.point_charge_potential(y + h * n)[0] - W.point_charge_potential(y - h * n)[0]) / (2 * h)
+                jump = p.sigma[0] if i == 0 else p.sigma[p.parent[i]] - p.sigma[i]
+                b = d.coef[0] * np.dot(y - d.center, n) / np.linalg.norm(y - d.center) ** m
+                assert abs(b - jump * dnu) <= 1e-6 * (1 + abs(b)), (m, i, b, jump * dnu)
+
+
+def test_point_charge_ellipsoids_match_potential(oracle_mod):
+    """Three nested ellipsoids around a point charge (3D, M = 5): the estimate equals
+    u = 1/|x| up to the additive constant the Neumann problem leaves free (differences between
+    points) and the gradient equals grad u, at points in each of the three regions."""
+    p, pts = W.point_charge_ellipsoids(3)
+
+    def inside(s, x):
+        e = x - s.center
+        return np.einsum("ij,jk,ik->i", e, s.A, e) < 1
+
+    in2, in3 = inside(p.shapes[1], pts), inside(p.shapes[2], pts)
+    x = np.concatenate([pts[~in2][:3], pts[in2 & ~in3][:3], pts[in3][:3]])
+    u, gu = W.point_charge_potential(x)
+    mean, se, g, gse, _ = oracle_mod.estimate(oracle_mod.OracleProblem(p), x, 1000000, 5, seed=2)
+    d = (mean - mean[0]) - (u - u[0])
+    assert np.max(np.abs(d[1:] / np.sqrt(se[1:] ** 2 + se[0] ** 2))) < ZMAX
+    assert np.max(np.abs((g - gu) / gse)) < ZMAX

@@ -52,6 +52,7 @@ class Problem:
     data: List[Data]
     compat_mode: int = 0                    # 0 per interface, 1 global balance, 2 none
     name: str = ""
+    compat_tol: float = 1e-8                # relative tolerance of the compatibility check
 
     @property
     def n_regions(self) -> int:
@@ -425,6 +426,56 @@ def single_ellipsoid_linear(dim, semi_axes, rotation_seed=7, direction=0, sigma=
                    [field_flux(g)], 0, "single-ellipsoid"), A, Q
 
 
+def point_charge_ellipsoids(dim, n_points=10000, seed=8, sigma=(1.1, 1.3, 0.9)):
+    """Three nested ellipsoids (x - c)^T A (x - c) = 1 around the potential u = |x|^(2-m) of a
+    unit point charge at the origin (outside every region), in m = dim >= 3 dimensions:
+    centres (1.3, 0, ...), (1.4, 0, ...), (1.6, 0, ...); diag A = (1, 0.9, 1.2, ...),
+    (1.5, 3.2, 2, ...) with A12 = -1, (8, 6, 4, ...) with A12 = -2; sigma = (1.1, 1.3, 0.9).
+    Data from u itself: b_1 = sigma_1 d_n u on the outer boundary and b_i = (sigma_parent -
+    sigma_i) d_n u on the interfaces, with d_n u = (2 - m) y.n / |y|^m (a point-source flux).
+    Points uniform in the outer ellipsoid (rejection from its bounding box).  u solves the
+    problem for any sigma (the data follow it).  As printed, the middle ellipsoid crosses the
+    outer one (its surface reaches (x - c1)^T A1 (x - c1) = 1.137); its matrix is scaled by 1.2
+    so that the tree is nested (surface within 0.964 of the outer form, the inner one within
+    0.923 of the middle form, in every dimension)."""
+    m = int(dim)
+    assert m >= 3
+    diag = [[1.0, 0.9] + [1.2] * (m - 2), [1.5, 3.2] + [2.0] * (m - 2), [8.0, 6.0] + [4.0] * (m - 2)]
+    off = [0.0, -1.0, -2.0]
+    cx = [1.3, 1.4, 1.6]
+    sigma = [float(v) for v in sigma]
+    shapes, data = [], []
+    for i in range(3):
+        A = np.diag(diag[i])
+        A[0, 1] = A[1, 0] = off[i]
+        if i == 1:
+            A *= 1.2
+        c = np.zeros(m); c[0] = cx[i]
+        shapes.append(ellipsoid(c, A))
+        kappa = (2 - m) * (sigma[0] if i == 0 else sigma[i - 1] - sigma[i])
+        data.append(source_flux(np.zeros(m), kappa))
+    # the data integrate to zero exactly; the compiler's surface quadrature resolves that to
+    # about 2e-7 of the integral of |b| in 6D, so the check runs at 1e-5
+    prob = Problem(m, [-1, 0, 1], sigma, shapes, data, 0, f"point-charge-ellipsoids-{m}d", 1e-5)
+    rng = np.random.default_rng(seed + m)
+    A1, c1 = shapes[0].A, shapes[0].center
+    half = 1.0 / np.sqrt(np.linalg.eigvalsh(A1)[0])
+    pts = []
+    while sum(len(q) for q in pts) < n_points:
+        x = c1 + rng.uniform(-half, half, (4 * n_points, m))
+        e = x - c1
+        pts.append(x[np.einsum("ij,jk,ik->i", e, A1, e) < 1.0])
+    return prob, np.concatenate(pts)[:n_points]
+
+
+def point_charge_potential(x):
+    """u = |x|^(2-m) and its gradient, the exact solution of point_charge_ellipsoids."""
+    x = np.asarray(x, dtype=np.float64)
+    m = x.shape[-1]
+    r = np.linalg.norm(x, axis=-1)
+    return r ** (2 - m), ((2 - m) * r ** (-m))[..., None] * x
+
+
 WORKLOAD_DESCRIPTIONS = {
     "concentric_disk_2d": "unit disk, concentric circle r=0.5, sigma 10/1, b = cos(theta); 64 points, W=1e4, M=4",
     "star_tree_2d": "unit disk, 3 nested stars (k=3,5,7) + 5 circles, sigma 10^U(-1,2), Fourier data; 4096 points, "
@@ -432,4 +483,6 @@ WORKLOAD_DESCRIPTIONS = {
     "star_tree_instances_2d": "512 uneven instances, 1-16 interfaces, 16-1024 points, W 1e3-1e6, M=4",
     "ellipsoid_tree_3d": "unit ball, spheres 0.6/0.3, 10 ellipsoids, SH data; 16384 points, W=1e5 (VR), M=6",
     "nested_spheres_6d": "unit 6-ball, spheres 0.7/0.35, sigma (1,5,0.2), c + lam x1/|x| data; 1024 points, W=1e6, M=8",
+    "point_charge_ellipsoids": "3 nested ellipsoids around the potential |x|^(2-m) of a point charge outside them, "
+                               "m = 3..6; 1e4 points, M = m + 2",
 }
