@@ -35,7 +35,10 @@ class _In(C.Structure):
                 ("vertices", C.POINTER(C.c_double)), ("data_kind", C.POINTER(C.c_int)),
                 ("data_center", C.POINTER(C.c_double)), ("n_terms", C.POINTER(C.c_int)),
                 ("coef_offset", C.POINTER(C.c_int64)), ("coef", C.POINTER(C.c_double)),
-                ("exps", C.POINTER(C.c_ubyte))]
+                ("exps", C.POINTER(C.c_ubyte)),
+                ("n_triangles", C.POINTER(C.c_int)), ("mesh_vertex_offset", C.POINTER(C.c_int64)),
+                ("mesh_vertices", C.POINTER(C.c_double)), ("triangle_offset", C.POINTER(C.c_int64)),
+                ("triangles", C.POINTER(C.c_int))]
 
 
 class _Query(C.Structure):
@@ -116,11 +119,22 @@ class OracleProblem:
         keep["radius"] = np.array([s.radius for s in prob.shapes], dtype=np.float64)
         keep["A"] = np.array([s.A if s.A is not None else np.zeros((m, m)) for s in prob.shapes],
                              dtype=np.float64).reshape(-1)
+        # polylines (kind 2) and meshes (kind 3) keep their vertices in separate arrays
         nv = [len(s.vertices) if s.vertices is not None else 0 for s in prob.shapes]
         keep["nv"] = np.asarray(nv, dtype=np.int32)
-        keep["voff"] = np.concatenate([[0], np.cumsum(nv)[:-1]]).astype(np.int64)
-        verts = [s.vertices for s in prob.shapes if s.vertices is not None]
+        pl = [n if s.kind == 2 else 0 for n, s in zip(nv, prob.shapes)]
+        ms = [n if s.kind == 3 else 0 for n, s in zip(nv, prob.shapes)]
+        keep["voff"] = np.concatenate([[0], np.cumsum(pl)[:-1]]).astype(np.int64)
+        verts = [s.vertices for s in prob.shapes if s.vertices is not None and s.kind == 2]
         keep["verts"] = np.ascontiguousarray(np.concatenate(verts, 0) if verts else np.zeros((1, 2)), dtype=np.float64).reshape(-1)
+        keep["mvoff"] = np.concatenate([[0], np.cumsum(ms)[:-1]]).astype(np.int64)
+        mverts = [s.vertices for s in prob.shapes if s.vertices is not None and s.kind == 3]
+        keep["mverts"] = np.ascontiguousarray(np.concatenate(mverts, 0) if mverts else np.zeros((1, 3)), dtype=np.float64).reshape(-1)
+        nt = [len(s.triangles) if getattr(s, "triangles", None) is not None else 0 for s in prob.shapes]
+        keep["nt"] = np.asarray(nt, dtype=np.int32)
+        keep["toff"] = np.concatenate([[0], np.cumsum(nt)[:-1]]).astype(np.int64)
+        tris = [s.triangles for s in prob.shapes if getattr(s, "triangles", None) is not None]
+        keep["tris"] = np.ascontiguousarray(np.concatenate(tris, 0) if tris else np.zeros((1, 3)), dtype=np.int32).reshape(-1)
         keep["dkind"] = np.array([d.kind for d in prob.data], dtype=np.int32)
         keep["dcenter"] = np.array([np.asarray(d.center, dtype=np.float64).reshape(m) for d in prob.data]).reshape(-1)
         keep["nterms"] = np.array([d.n_terms for d in prob.data], dtype=np.int32)
@@ -138,7 +152,9 @@ class OracleProblem:
                 _p(keep["center"], C.c_double), _p(keep["radius"], C.c_double), _p(keep["A"], C.c_double),
                 _p(keep["nv"], C.c_int), _p(keep["voff"], C.c_int64), _p(keep["verts"], C.c_double),
                 _p(keep["dkind"], C.c_int), _p(keep["dcenter"], C.c_double), _p(keep["nterms"], C.c_int),
-                _p(keep["coff"], C.c_int64), _p(keep["coef"], C.c_double), _p(keep["exps"], C.c_ubyte))
+                _p(keep["coff"], C.c_int64), _p(keep["coef"], C.c_double), _p(keep["exps"], C.c_ubyte),
+                _p(keep["nt"], C.c_int), _p(keep["mvoff"], C.c_int64), _p(keep["mverts"], C.c_double),
+                _p(keep["toff"], C.c_int64), _p(keep["tris"], C.c_int))
         h = C.c_void_p()
         rc = self.lib.or_problem_create(C.byref(s), C.byref(h))
         if rc != 0:

@@ -88,7 +88,9 @@ typedef struct {
     double c[OR_MAX_DIM], R;
     double A[OR_MAX_DIM * OR_MAX_DIM], L[OR_MAX_DIM * OR_MAX_DIM], lam_max, detL;
     int nv;
-    double *v, *len, *cum, total;
+    double *v, *len, *cum, total;   /* polyline; mesh: v = vertices (3 each), cum = cumulative triangle areas */
+    int ntri, *tri;                 /* mesh triangles (3 vertex indices each) */
+    double *tn;                     /* mesh: unit outward normal per triangle */
     double area;
     int dkind, nt;
     double dc[OR_MAX_DIM];
@@ -177,6 +179,8 @@ static void normal_at(const region_t *g, int m, const double *y, int seg, double
             n[i] = t; s += t * t;
         }
         s = sqrt(s); for (int i = 0; i < m; ++i) n[i] /= s;
+    } else if (g->kind == OR_MESH) {
+        for (int i = 0; i < 3; ++i) n[i] = g->tn[3 * seg + i];
     } else {
         const double *a = g->v + 2 * seg, *b = g->v + 2 * ((seg + 1) % g->nv);
         double ex = b[0] - a[0], ey = b[1] - a[1], l = sqrt(ex * ex + ey * ey);
@@ -261,6 +265,7 @@ static void polyline_at(const region_t *g, double s, double *y, int *seg)
 static int surf_words(const region_t *g, int m)
 {
     if (g->kind == OR_POLYLINE) return 1;
+    if (g->kind == OR_MESH) return 3;
     return dir_words(m) + (g->kind == OR_ELLIPSOID ? 1 : 0);
 }
 
@@ -269,6 +274,19 @@ static int surf_attempt(const region_t *g, int m, words_t *w, double *y, int *se
 {
     *seg = 0;
     if (g->kind == OR_POLYLINE) { polyline_at(g, unif(words_next(w)) * g->total, y, seg); return 1; }
+    if (g->kind == OR_MESH) {
+        /* triangle with probability area / total (largest j with cum[j] <= s), then a uniform
+           point in it: y = (1 - r) a + r (1 - u) b + r u c with r = sqrt(u1) */
+        double s = unif(words_next(w)) * g->total;
+        int lo = 0, hi = g->ntri - 1;
+        while (lo < hi) { int mid = (lo + hi + 1) / 2; if (g->cum[mid] <= s) lo = mid; else hi = mid - 1; }
+        double r = sqrt(unif(words_next(w))), u2 = unif(words_next(w));
+        const int *t = g->tri + 3 * lo;
+        const double *a = g->v + 3 * t[0], *b = g->v + 3 * t[1], *c = g->v + 3 * t[2];
+        for (int i = 0; i < 3; ++i) y[i] = (1 - r) * a[i] + r * (1 - u2) * b[i] + r * u2 * c[i];
+        *seg = lo;
+        return 1;
+    }
     double u[OR_MAX_DIM];
     unit_dir(m, w, u);
     if (g->kind == OR_SPHERE) { for (int i = 0; i < m; ++i) y[i] = g->c[i] + g->R * u[i]; return 1; }
@@ -345,6 +363,29 @@ static int hits_of(const region_t *g, int m, const double *y, int yseg, const do
         out[0].t = t; out[0].seg = 0; return 1;
     }
     int q = 0;
+    if (g->kind == OR_MESH) {
+        /* Moller-Trumbore per triangle, in triangle order; a line skips the triangle of y */
+        for (int j = 0; j < g->ntri; ++j) {
+            if (!ray && j == yseg) continue;
+            const int *tt = g->tri + 3 * j;
+            const double *a = g->v + 3 * tt[0], *b = g->v + 3 * tt[1], *c = g->v + 3 * tt[2];
+            double e1[3], e2[3], sv[3], pv[3], qv[3];
+            for (int i = 0; i < 3; ++i) { e1[i] = b[i] - a[i]; e2[i] = c[i] - a[i]; sv[i] = y[i] - a[i]; }
+            pv[0] = d[1] * e2[2] - d[2] * e2[1]; pv[1] = d[2] * e2[0] - d[0] * e2[2]; pv[2] = d[0] * e2[1] - d[1] * e2[0];
+            double det = e1[0] * pv[0] + e1[1] * pv[1] + e1[2] * pv[2];
+            if (det == 0) continue;
+            double u = (sv[0] * pv[0] + sv[1] * pv[1] + sv[2] * pv[2]) / det;
+            if (u < 0 || u > 1) continue;
+            qv[0] = sv[1] * e1[2] - sv[2] * e1[1]; qv[1] = sv[2] * e1[0] - sv[0] * e1[2]; qv[2] = sv[0] * e1[1] - sv[1] * e1[0];
+            double v = (d[0] * qv[0] + d[1] * qv[1] + d[2] * qv[2]) / det;
+            if (v < 0 || u + v > 1) continue;
+            double t = (e2[0] * qv[0] + e2[1] * qv[1] + e2[2] * qv[2]) / det;
+            if (ray ? !(t > 0) : fabs(t) <= 1e-12) continue;
+            if (q < cap) { out[q].t = t; out[q].seg = j; }
+            q++;
+        }
+        return q < cap ? q : cap;
+    }
     for (int j = 0; j < g->nv; ++j) {
         if (!ray && j == yseg) continue;
         const double *a = g->v + 2 * j, *b = g->v + 2 * ((j + 1) % g->nv);
@@ -485,8 +526,9 @@ static void one_sample(const or_problem *pr, const double *x, const or_query *q,
                         double den = d[0] * ey - d[1] * ex;
                         double s = ((a[0] - y[0]) * d[1] - (a[1] - y[1]) * d[0]) / den;
                         yn[0] = a[0] + s * ex; yn[1] = a[1] + s * ey; segn = j;
-                    } else {
+                    } else {   /* quadric (seg 0) or mesh (the triangle hit) */
                         for (int j = 0; j < m; ++j) yn[j] = y[j] + hits[pick].t * d[j];
+                        segn = hits[pick].seg;
                     }
                     found = 1;
                     break;
@@ -745,6 +787,31 @@ int or_problem_create(const or_problem_in *in, or_problem **out)
             }
             g->total = g->cum[nv];
             g->area = g->total;
+        } else if (g->kind == OR_MESH) {
+            if (m != 3 || !in->n_triangles || in->n_vertices[i] < 4 || in->n_triangles[i] < 4) { or_problem_destroy(pr); return OR_EINVAL; }
+            int nv = g->nv = in->n_vertices[i], nt = g->ntri = in->n_triangles[i];
+            g->v = malloc(sizeof(double) * 3 * nv); g->tri = malloc(sizeof(int) * 3 * nt);
+            g->tn = malloc(sizeof(double) * 3 * nt); g->cum = malloc(sizeof(double) * (nt + 1));
+            if (!g->v || !g->tri || !g->tn || !g->cum) { or_problem_destroy(pr); return OR_ENOMEM; }
+            memcpy(g->v, in->mesh_vertices + 3 * in->mesh_vertex_offset[i], sizeof(double) * 3 * nv);
+            memcpy(g->tri, in->triangles + 3 * in->triangle_offset[i], sizeof(int) * 3 * nt);
+            double vol = 0;
+            g->cum[0] = 0;
+            for (int j = 0; j < nt; ++j) {
+                const int *t = g->tri + 3 * j;
+                for (int k = 0; k < 3; ++k) if (t[k] < 0 || t[k] >= nv) { or_problem_destroy(pr); return OR_EINVAL; }
+                const double *a = g->v + 3 * t[0], *b = g->v + 3 * t[1], *c = g->v + 3 * t[2];
+                double e1[3], e2[3], cr[3];
+                for (int k = 0; k < 3; ++k) { e1[k] = b[k] - a[k]; e2[k] = c[k] - a[k]; }
+                cr[0] = e1[1] * e2[2] - e1[2] * e2[1]; cr[1] = e1[2] * e2[0] - e1[0] * e2[2]; cr[2] = e1[0] * e2[1] - e1[1] * e2[0];
+                double l = sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+                if (!(l > 0)) { or_problem_destroy(pr); return OR_EGEOM; }
+                for (int k = 0; k < 3; ++k) g->tn[3 * j + k] = cr[k] / l;
+                g->cum[j + 1] = g->cum[j] + 0.5 * l;
+                vol += a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0]) + a[2] * (b[0] * c[1] - b[1] * c[0]);
+            }
+            if (!(vol > 0)) { or_problem_destroy(pr); return OR_EGEOM; }   /* normals must point outward */
+            g->total = g->area = g->cum[nt];
         } else { or_problem_destroy(pr); return OR_EINVAL; }
         if (g->kind == OR_SPHERE && m == 2) g->total = 2 * OR_PI * g->R;
         /* data */
@@ -798,6 +865,20 @@ int or_problem_create(const or_problem_in *in, or_problem **out)
                 s += 0.5 * gw[k] * g->len[j] * data_b(g, m, y, j);
             }
             g->flux = s;
+        } else if (g->kind == OR_MESH) {
+            /* edge-midpoint rule per triangle (exact for quadratics) */
+            double s = 0;
+            for (int j = 0; j < g->ntri; ++j) {
+                const int *t = g->tri + 3 * j;
+                const double *a = g->v + 3 * t[0], *b = g->v + 3 * t[1], *c = g->v + 3 * t[2];
+                double ar = g->cum[j + 1] - g->cum[j];
+                for (int k = 0; k < 3; ++k) {
+                    const double *p0 = k == 0 ? a : k == 1 ? b : c, *p1 = k == 0 ? b : k == 1 ? c : a;
+                    double y[3] = {0.5 * (p0[0] + p1[0]), 0.5 * (p0[1] + p1[1]), 0.5 * (p0[2] + p1[2])};
+                    s += ar / 3 * data_b(g, m, y, j);
+                }
+            }
+            g->flux = s;
         } else {
             qctx_t c = {pr, i, 1};
             g->flux = sphere_integral(m, surf_integrand, &c, quad_nodes(m));
@@ -805,9 +886,12 @@ int or_problem_create(const or_problem_in *in, or_problem **out)
     }
     /* VR halves */
     pr->vr_ok = m <= 3;
+    for (int i = 0; i < N; ++i) if (pr->r[i].kind == OR_MESH) pr->vr_ok = 0;   /* no VR halves on meshes */
     for (int i = 0; i < N; ++i) {
         region_t *g = &pr->r[i];
-        if (m == 2) {
+        if (!pr->vr_ok) {
+            g->meas[0] = g->meas[1] = NAN;
+        } else if (m == 2) {
             int rc = vr_prepare_2d(pr, i);
             if (rc) { or_problem_destroy(pr); return rc; }
         } else if (m == 3) {
@@ -827,7 +911,7 @@ void or_problem_destroy(or_problem *pr)
     if (!pr) return;
     for (int i = 0; i < OR_MAX_REGIONS; ++i) {
         region_t *g = &pr->r[i];
-        free(g->v); free(g->len); free(g->cum); free(g->coef); free(g->exps); free(g->brk);
+        free(g->v); free(g->len); free(g->cum); free(g->coef); free(g->exps); free(g->brk); free(g->tri); free(g->tn);
     }
     free(pr);
 }

@@ -28,7 +28,7 @@
 #define OR_MAX_REGIONS 64
 #define OR_MAX_M 64
 
-enum { OR_SPHERE = 0, OR_ELLIPSOID = 1, OR_POLYLINE = 2 };
+enum { OR_SPHERE = 0, OR_ELLIPSOID = 1, OR_POLYLINE = 2, OR_MESH = 3 };
 enum { OR_DATA_ZERO = 0, OR_DATA_FOURIER2D = 1, OR_DATA_DIRPOLY = 2, OR_DATA_SOURCE_FLUX = 3, OR_DATA_FIELD_FLUX = 4 };
 enum { OR_OK = 0, OR_EINVAL = -1, OR_EGEOM = -2, OR_EINCOMPAT = -3, OR_EUNSUP = -4, OR_ENOMEM = -6 };
 
@@ -49,6 +49,14 @@ typedef struct {
     const int64_t *coef_offset;   /* [N]                                             */
     const double *coef;           /* FOURIER2D: a0,a1,c1,..,aK,cK; DIRPOLY: one per term; SOURCE_FLUX: kappa; FIELD_FLUX: g[dim] */
     const unsigned char *exps;    /* DIRPOLY exponents, [sum n_terms * dim] (offset coef_offset*dim) */
+    /* MESH (dim 3): closed triangle mesh, n_vertices[i] vertices and n_triangles[i] triangles,
+       each triangle's vertices counter-clockwise seen from outside (outward normal
+       (b - a) x (c - a)); indices are local to the mesh */
+    const int *n_triangles;       /* [N] (0 otherwise)                               */
+    const int64_t *mesh_vertex_offset; /* [N] offset (in vertices) into mesh_vertices[] */
+    const double *mesh_vertices;  /* [sum * 3]                                       */
+    const int64_t *triangle_offset;    /* [N] offset (in triangles) into triangles[]   */
+    const int *triangles;         /* [sum * 3]                                       */
 } or_problem_in;
 
 typedef struct {

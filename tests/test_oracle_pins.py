@@ -400,3 +400,60 @@ def test_point_charge_ellipsoids_match_potential(oracle_mod):
     d = (mean - mean[0]) - (u - u[0])
     assert np.max(np.abs(d[1:] / np.sqrt(se[1:] ** 2 + se[0] ** 2))) < ZMAX
     assert np.max(np.abs((g - gu) / gse)) < ZMAX
+
+
+# ----------------------------------------------------------------------------- triangle meshes
+def test_mesh_surface_samples(oracle_mod):
+    """Uniform sampling on a triangle mesh: samples lie on their triangles' planes, and the
+    fraction of samples per triangle matches its share of the area (chi-square)."""
+    sh = W.icosphere([0.1, -0.2, 0.05], 0.8, 2, jitter=0.05, seed=3)
+    p = W.Problem(3, [-1], [1.0], [sh], [W.zero_data(3)], 2, "mesh")
+    op = oracle_mod.OracleProblem(p)
+    n = 200000
+    y = op.sample_surface(0, 5, n)
+    V, T = sh.vertices, sh.triangles
+    a, b, c = V[T[:, 0]], V[T[:, 1]], V[T[:, 2]]
+    nrm = np.cross(b - a, c - a)
+    area = 0.5 * np.linalg.norm(nrm, axis=1)
+    nrm /= (2 * area)[:, None]
+    # the triangle of each sample: on its plane and inside its edges (barycentric test)
+    d = np.abs(np.einsum("tk,ntk->nt", nrm, y[:, None, :] - a[None]))
+    tri = np.argmin(d, axis=1)
+    assert np.max(d[np.arange(n), tri]) < 1e-12
+    counts = np.bincount(tri, minlength=len(T))
+    expect = n * area / area.sum()
+    chi2 = np.sum((counts - expect) ** 2 / expect)
+    dof = len(T) - 1
+    assert abs(chi2 - dof) < 5 * np.sqrt(2 * dof)
+
+
+def test_mesh_sphere_matches_depolarization(oracle_mod):
+    """A 1280-triangle icosphere with linear Neumann data: the gradient matches the exact u_M
+    of the sphere (depolarization factor 1/3) up to the O(h^2) mesh error (0.5 % of the area)."""
+    sh = W.icosphere([0, 0, 0], 1.0, 3)
+    p = W.Problem(3, [-1], [1.0], [sh], [W.field_flux([1.0, 0.0, 0.0])], 0, "icosphere")
+    op = oracle_mod.OracleProblem(p)
+    pts = np.random.default_rng(0).standard_normal((3, 3)) * 0.1
+    for M in (1, 3):
+        _, _, g, gse, _ = oracle_mod.estimate(op, pts, 200000, M, seed=9)
+        gref = CF.ellipsoid_grad_uM([1.0, 1.0, 1.0], np.eye(3), 0, M)
+        assert np.max(np.abs(_z(g, gref[None, :], gse))) < ZMAX
+
+
+def test_nested_meshes_match_concentric_spheres(oracle_mod):
+    """Two nested icospheres (R = 1 and 0.5, 1280 triangles each) with l = 1 data: means and
+    gradients match the exact u_M of concentric spheres (rays, lines and uniform transitions
+    on meshes), with the O(h^2) mesh error far below the Monte Carlo error."""
+    shapes = [W.icosphere([0, 0, 0], 1.0, 3), W.icosphere([0, 0, 0], 0.5, 3)]
+    lam, sig = [1.0, -0.5], [1.0, 4.0]
+    data = [W.dirpoly([0, 0, 0], {(1, 0, 0): lam[0]}), W.dirpoly([0, 0, 0], {(1, 0, 0): lam[1]})]
+    p = W.Problem(3, [-1, 0], sig, shapes, data, 0, "nested-icospheres")
+    op = oracle_mod.OracleProblem(p)
+    x = np.array([[0.2, 0.1, -0.1], [0.7, -0.2, 0.1], [-0.3, 0.3, 0.35]])
+    H, gH = CF.harmonic_x1(3)
+    M = 3
+    mean, se, g, gse, _ = oracle_mod.estimate(op, x, 200000, M, seed=4)
+    for k, xk in enumerate(x):
+        u, gu = CF.concentric_uM([1.0, 0.5], sig, lam, 1, 3, M, xk, H, gH)
+        assert abs(mean[k] - u) < ZMAX * se[k]
+        assert np.max(np.abs((g[k] - gu) / gse[k])) < ZMAX

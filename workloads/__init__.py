@@ -14,7 +14,8 @@ from typing import List, Optional
 
 import numpy as np
 
-SPHERE, ELLIPSOID, POLYLINE = 0, 1, 2
+SPHERE, ELLIPSOID, POLYLINE, MESH3D = 0, 1, 2, 3
+SHAPE_MESH3D = MESH3D
 DATA_ZERO, DATA_FOURIER2D, DATA_DIRPOLY, DATA_SOURCE_FLUX, DATA_FIELD_FLUX = 0, 1, 2, 3, 4
 
 
@@ -24,7 +25,8 @@ class Shape:
     center: np.ndarray
     radius: float = 0.0
     A: Optional[np.ndarray] = None          # ellipsoid: (y-c)^T A (y-c) = 1
-    vertices: Optional[np.ndarray] = None   # polyline: (n, 2), counter-clockwise
+    vertices: Optional[np.ndarray] = None   # polyline: (n, 2), counter-clockwise; mesh: (n, 3)
+    triangles: Optional[np.ndarray] = None  # mesh: (t, 3) vertex indices, counter-clockwise from outside
 
 
 @dataclass
@@ -78,6 +80,40 @@ def star_polyline(center, r0, amp, k, n, phase=0.0) -> Shape:
 
 
 # ----------------------------------------------------------------------------- data
+def mesh(vertices, triangles) -> Shape:
+    """Closed 3D triangle mesh, outward normal (b - a) x (c - a) for triangle (a, b, c)."""
+    v = np.asarray(vertices, dtype=np.float64)
+    return Shape(SHAPE_MESH3D, v.mean(0), vertices=v, triangles=np.asarray(triangles, dtype=np.int32))
+
+
+def icosphere(center, radius, subdiv, jitter=0.0, seed=0) -> Shape:
+    """Icosahedron subdivided `subdiv` times (20 * 4^subdiv triangles), vertices on the sphere,
+    optionally moved radially by up to `jitter` (relative) to break the symmetry."""
+    t = (1 + 5 ** 0.5) / 2
+    v = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+         (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    v = [np.array(p, dtype=np.float64) / np.linalg.norm(p) for p in v]
+    f = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2), (10, 7, 6),
+         (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5), (2, 4, 11), (6, 2, 10),
+         (8, 6, 7), (9, 8, 1)]
+    for _ in range(subdiv):
+        mid = {}
+
+        def m(a, b):
+            k = (min(a, b), max(a, b))
+            if k not in mid:
+                p = v[a] + v[b]
+                v.append(p / np.linalg.norm(p))
+                mid[k] = len(v) - 1
+            return mid[k]
+        f = [g for a, b, c in f for g in ((a, m(a, b), m(c, a)), (b, m(b, c), m(a, b)), (c, m(c, a), m(b, c)),
+                                          (m(a, b), m(b, c), m(c, a)))]
+    V = np.array(v)
+    if jitter:
+        V *= (1 + jitter * np.random.default_rng(seed).uniform(-1, 1, (len(V), 1)))
+    return mesh(np.asarray(center, dtype=np.float64) + radius * V, np.array(f, dtype=np.int32))
+
+
 def zero_data(m) -> Data:
     return Data(DATA_ZERO, np.zeros(m))
 
