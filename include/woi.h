@@ -49,16 +49,22 @@ typedef enum {
 typedef enum {
     WOI_SHAPE_SPHERE = 0,     /* |y - center| = radius, any dimension                   */
     WOI_SHAPE_ELLIPSOID = 1,  /* (y - c)^T A (y - c) = 1, A symmetric positive definite  */
-    WOI_SHAPE_POLYLINE2D = 2  /* closed counter-clockwise polygon, dimension 2 only      */
+    WOI_SHAPE_POLYLINE2D = 2, /* closed counter-clockwise polygon, dimension 2 only      */
+    WOI_SHAPE_MESH3D = 3      /* closed triangle mesh, dimension 3 only: every edge shared by
+                                 two triangles in opposite directions, outward normals
+                                 (b - a) x (c - a); no variance-reduced estimator         */
 } woi_shape_kind;
 
 typedef struct {
     int kind;                 /* woi_shape_kind                                        */
-    int n_vertices;           /* POLYLINE2D: vertex count (>= 3)                       */
+    int n_vertices;           /* POLYLINE2D: vertex count (>= 3); MESH3D (>= 4)        */
     double center[WOI_MAX_DIM];
     double radius;            /* SPHERE                                                */
     const double *A;          /* ELLIPSOID: dim*dim row-major, host memory             */
-    const double *vertices;   /* POLYLINE2D: n_vertices*2 (x, y), host memory, CCW     */
+    const double *vertices;   /* POLYLINE2D: n_vertices*2 (x, y), host memory, CCW;
+                                 MESH3D: n_vertices*3 (x, y, z)                          */
+    int n_triangles;          /* MESH3D: triangle count (>= 4)                           */
+    const int *triangles;     /* MESH3D: n_triangles*3 vertex indices, host memory       */
 } woi_shape;
 
 /* Flux-jump / Neumann data b_i on an interface (Eq. interface_problem). */

@@ -125,7 +125,11 @@ struct HostRegion {
     double meas[2] = {0, 0};
     std::vector<double> brk;
     int class0 = 0;
+    std::vector<double> mv;     // mesh vertices (3 each)
+    std::vector<int> tri;       // mesh triangles (3 vertex indices each); cum holds cumulative areas
+    std::vector<double> tn;     // mesh unit outward normals (3 per triangle)
     int nv() const { return (int)len.size(); }
+    int ntri() const { return (int)tri.size() / 3; }
 };
 
 struct Host {
@@ -150,12 +154,29 @@ void outward_normal(const Host& H, const HostRegion& g, const double* y, int seg
         }
         nn = std::sqrt(nn);
         for (int i = 0; i < m; ++i) n[i] /= nn;
+    } else if (g.kind == WOI_SHAPE_MESH3D) {
+        for (int i = 0; i < 3; ++i) n[i] = g.tn[3 * seg + i];
     } else {
         const double ex = g.v[2 * seg + 2] - g.v[2 * seg], ey = g.v[2 * seg + 3] - g.v[2 * seg + 1];
         const double l = std::sqrt(ex * ex + ey * ey);
         n[0] = ey / l;
         n[1] = -ex / l;
     }
+}
+
+// Ray y + t d (t > 0) against triangle (a, b, c): true on a hit (barycentric test).
+bool ray_hits_triangle(const double* y, const double* d, const double* a, const double* b, const double* c) {
+    double e1[3], e2[3], w[3];
+    for (int k = 0; k < 3; ++k) { e1[k] = b[k] - a[k]; e2[k] = c[k] - a[k]; w[k] = y[k] - a[k]; }
+    const double p[3] = {d[1] * e2[2] - d[2] * e2[1], d[2] * e2[0] - d[0] * e2[2], d[0] * e2[1] - d[1] * e2[0]};
+    const double det = e1[0] * p[0] + e1[1] * p[1] + e1[2] * p[2];
+    if (det == 0) return false;
+    const double u = (w[0] * p[0] + w[1] * p[1] + w[2] * p[2]) / det;
+    if (u < 0 || u > 1) return false;
+    const double q[3] = {w[1] * e1[2] - w[2] * e1[1], w[2] * e1[0] - w[0] * e1[2], w[0] * e1[1] - w[1] * e1[0]};
+    const double v = (d[0] * q[0] + d[1] * q[1] + d[2] * q[2]) / det;
+    if (v < 0 || u + v > 1) return false;
+    return (e2[0] * q[0] + e2[1] * q[1] + e2[2] * q[2]) / det > 0;
 }
 
 // b_i(y): data payload layout matches the device (coefficients, then centre / source)
@@ -282,6 +303,15 @@ bool point_inside(const Host& H, const HostRegion& g, const double* y) {
             for (int j = 0; j < m; ++j) q += (y[i] - g.c[i]) * g.A[i * m + j] * (y[j] - g.c[j]);
         return q < 1.0;
     }
+    if (g.kind == WOI_SHAPE_MESH3D) {   // parity of the crossings of a ray in a fixed skew direction
+        static const double d[3] = {0.5376448, 0.6427876, 0.5457595};
+        bool in = false;
+        for (int j = 0; j < g.ntri(); ++j) {
+            const int* t = &g.tri[3 * j];
+            if (ray_hits_triangle(y, d, &g.mv[3 * t[0]], &g.mv[3 * t[1]], &g.mv[3 * t[2]])) in = !in;
+        }
+        return in;
+    }
     bool in = false;   // crossing number
     for (int j = 0; j < g.nv(); ++j) {
         const double* a = &g.v[2 * j];
@@ -298,6 +328,13 @@ bool point_inside(const Host& H, const HostRegion& g, const double* y) {
 void probe_points(const Host& H, const HostRegion& g, std::vector<double>& pts) {
     const int m = H.m;
     pts.clear();
+    if (g.kind == WOI_SHAPE_MESH3D) {   // vertices and triangle centroids
+        pts = g.mv;
+        for (int j = 0; j < g.ntri(); ++j)
+            for (int k = 0; k < 3; ++k)
+                pts.push_back((g.mv[3 * g.tri[3 * j] + k] + g.mv[3 * g.tri[3 * j + 1] + k] + g.mv[3 * g.tri[3 * j + 2] + k]) / 3.0);
+        return;
+    }
     if (g.kind == WOI_SHAPE_POLYLINE2D) {
         for (int j = 0; j < g.nv(); ++j)
             for (int s = 0; s < 2; ++s) {
@@ -543,6 +580,44 @@ woi_status compile_shapes(const woi_problem_desc* d, Host& H) {
             }
             if (!(area2 > 0)) return fail(WOI_E_GEOMETRY, "region %d: polyline must be counter-clockwise", i);
             g.total = g.area = g.cum[n];
+        } else if (s.kind == WOI_SHAPE_MESH3D) {
+            if (m != 3) return fail(WOI_E_INVALID_ARG, "region %d: triangle meshes need dim 3", i);
+            if (s.n_vertices < 4 || !s.vertices || s.n_triangles < 4 || !s.triangles)
+                return fail(WOI_E_INVALID_ARG, "region %d: a mesh needs >= 4 vertices and >= 4 triangles", i);
+            const int nv = s.n_vertices, nt = s.n_triangles;
+            g.mv.assign(s.vertices, s.vertices + 3 * (size_t)nv);
+            g.tri.assign(s.triangles, s.triangles + 3 * (size_t)nt);
+            for (int t : g.tri)
+                if (t < 0 || t >= nv) return fail(WOI_E_INVALID_ARG, "region %d: triangle index %d out of range", i, t);
+            // closed and consistently oriented: every directed edge once, and its reverse once
+            std::vector<uint64_t> e;
+            e.reserve(3 * (size_t)nt);
+            for (int j = 0; j < nt; ++j)
+                for (int k = 0; k < 3; ++k)
+                    e.push_back((uint64_t)(uint32_t)g.tri[3 * j + k] << 32 | (uint32_t)g.tri[3 * j + (k + 1) % 3]);
+            std::sort(e.begin(), e.end());
+            for (size_t k = 0; k < e.size(); ++k) {
+                if (k + 1 < e.size() && e[k + 1] == e[k])
+                    return fail(WOI_E_GEOMETRY, "region %d: mesh edge used twice in one direction", i);
+                const uint64_t r = (e[k] << 32) | (e[k] >> 32);
+                if (!std::binary_search(e.begin(), e.end(), r))
+                    return fail(WOI_E_GEOMETRY, "region %d: mesh is not closed (edge without its reverse)", i);
+            }
+            g.tn.resize(3 * (size_t)nt);
+            g.cum.assign(nt + 1, 0.0);
+            double vol = 0;
+            for (int j = 0; j < nt; ++j) {
+                const double *a = &g.mv[3 * g.tri[3 * j]], *b = &g.mv[3 * g.tri[3 * j + 1]], *c = &g.mv[3 * g.tri[3 * j + 2]];
+                const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+                const double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+                const double l = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+                if (!(l > 0)) return fail(WOI_E_GEOMETRY, "region %d: degenerate triangle %d", i, j);
+                for (int k = 0; k < 3; ++k) g.tn[3 * j + k] = cr[k] / l;
+                g.cum[j + 1] = g.cum[j] + 0.5 * l;
+                vol += a[0] * cr[0] + a[1] * cr[1] + a[2] * cr[2];
+            }
+            if (!(vol > 0)) return fail(WOI_E_GEOMETRY, "region %d: mesh normals must point outward", i);
+            g.total = g.area = g.cum[nt];
         } else {
             return fail(WOI_E_INVALID_ARG, "region %d: unknown shape kind %d", i, s.kind);
         }
@@ -626,6 +701,22 @@ void flux_integrals(Host& H) {
                     s += 0.5 * gw[k] * g.len[j] * b;
                     sa += 0.5 * gw[k] * g.len[j] * std::fabs(b);
                 }
+            g.flux = s;
+            g.absflux = sa;
+        } else if (g.kind == WOI_SHAPE_MESH3D) {
+            // per triangle, the interior rule with nodes (2/3, 1/6, 1/6) (degree 2)
+            double s = 0, sa = 0;
+            for (int j = 0; j < g.ntri(); ++j) {
+                const double* P[3] = {&g.mv[3 * g.tri[3 * j]], &g.mv[3 * g.tri[3 * j + 1]], &g.mv[3 * g.tri[3 * j + 2]]};
+                const double ar = g.cum[j + 1] - g.cum[j];
+                for (int k = 0; k < 3; ++k) {
+                    double y[3];
+                    for (int c = 0; c < 3; ++c) y[c] = (4 * P[k][c] + P[(k + 1) % 3][c] + P[(k + 2) % 3][c]) / 6.0;
+                    const double b = b_value(H, g, y, j);
+                    s += ar / 3 * b;
+                    sa += ar / 3 * std::fabs(b);
+                }
+            }
             g.flux = s;
             g.absflux = sa;
         } else {
@@ -795,10 +886,13 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
         return fail(WOI_E_INVALID_ARG, "unknown compat_mode %d", d->compat_mode);
     }
     // VR halves
-    const bool vr_ok = m <= 3;
+    bool vr_ok = m <= 3;
+    for (int i = 0; i < N; ++i)
+        if (H.r[i].kind == WOI_SHAPE_MESH3D) vr_ok = false;   // no VR halves on meshes
     for (int i = 0; i < N; ++i) {
         HostRegion& g = H.r[i];
-        if (m == 2) vr_halves_2d(H, g);
+        if (!vr_ok) g.meas[0] = g.meas[1] = std::nan("");
+        else if (m == 2) vr_halves_2d(H, g);
         else if (m == 3) vr_halves_3d(H, g);
         else g.meas[0] = g.meas[1] = std::nan("");
         if (m == 3)
@@ -863,6 +957,15 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
             geo.insert(geo.end(), g.A, g.A + m * m);
             geo.insert(geo.end(), g.L, g.L + m * m);
             geo.push_back(1.0 / g.lam_max);
+        } else if (g.kind == WOI_SHAPE_MESH3D) {
+            // per triangle (a, b - a, c - a): the Moller-Trumbore operands
+            for (int j = 0; j < g.ntri(); ++j) {
+                const double *a = &g.mv[3 * g.tri[3 * j]], *b = &g.mv[3 * g.tri[3 * j + 1]], *c = &g.mv[3 * g.tri[3 * j + 2]];
+                for (int k = 0; k < 3; ++k) geo.push_back(a[k]);
+                for (int k = 0; k < 3; ++k) geo.push_back(b[k] - a[k]);
+                for (int k = 0; k < 3; ++k) geo.push_back(c[k] - a[k]);
+            }
+            r.nv = g.ntri();
         } else {
             geo = g.v;
             r.nv = g.nv();
@@ -906,6 +1009,22 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
             block_bounds(g, bnd, r.n2, r.top);
             r.bnd = (int)p32.size();
             p32.insert(p32.end(), bnd.begin(), bnd.end());
+            r.guide = (int)pi.size();
+            for (int k = 0; k < n; ++k) {
+                const double s0 = g.cum[n] * k / n;
+                int j = (int)(std::upper_bound(g.cum.begin(), g.cum.begin() + n, s0) - g.cum.begin()) - 1;
+                pi.push_back(std::max(0, std::min(j, n - 1)));
+            }
+        } else if (g.kind == WOI_SHAPE_MESH3D) {
+            const int n = g.ntri();
+            r.nrm64 = put64(g.tn.data(), g.tn.size());
+            r.nrm32 = put32(g.tn.data(), g.tn.size());
+            r.cum64 = put64(g.cum.data(), g.cum.size());
+            std::vector<double> cl(2 * (n + 1), 0.0);   // FP32 table of (cum[j], 0) pairs, the polyline layout
+            for (int j = 0; j <= n; ++j) cl[2 * j] = g.cum[j];
+            r.cum32 = put32(cl.data(), cl.size());
+            r.gscale = (double)n / g.cum[n];
+            r.gscale_f = (float)r.gscale;
             r.guide = (int)pi.size();
             for (int k = 0; k < n; ++k) {
                 const double s0 = g.cum[n] * k / n;
@@ -1059,6 +1178,9 @@ woi_status check_query_impl(const woi_problem* p, int64_t P, const woi_query* q)
     if (q->precision != WOI_PREC_FP64 && q->precision != WOI_PREC_FP32) return fail(WOI_E_INVALID_ARG, "bad precision");
     if (q->estimator == WOI_EST_VR) {
         if (p->H.m > 3) return fail(WOI_E_UNSUPPORTED, "variance reduction needs dim <= 3");
+        for (int i = 0; i < p->H.N; ++i)
+            if (p->H.r[i].kind == WOI_SHAPE_MESH3D)
+                return fail(WOI_E_UNSUPPORTED, "variance reduction is not available with triangle meshes (region %d)", i);
         if ((q->walks & 1) || (q->walk_offset & 1)) return fail(WOI_E_INVALID_ARG, "VR needs even walks and walk_offset");
     }
     if (q->batch_share < 1) return fail(WOI_E_INVALID_ARG, "batch_share must be >= 1");

@@ -205,6 +205,10 @@ __device__ __forceinline__ void normal_at(const DevRegion& g, const R* __restric
         const R inv = RO<R>::rsq(s);     // FP64: 1 / sqrt
 #pragma unroll
         for (int i = 0; i < D; ++i) n[i] *= inv;
+    } else if (g.kind == WOI_SHAPE_MESH3D) {
+        const R* nr = pay + Pay<R>::nrm(g) + 3 * seg;
+#pragma unroll
+        for (int i = 0; i < D && i < 3; ++i) n[i] = nr[i];
     } else {
         if constexpr (D == 2) {
             if constexpr (LDS && std::is_same<R, float>::value) {
@@ -336,13 +340,43 @@ __device__ __noinline__ bool polyline_at(const DevProblem* dp, const DevRegion& 
 
 template <typename R, int D>
 __device__ __forceinline__ int surf_words(const DevRegion& g) {
-    return g.kind == WOI_SHAPE_POLYLINE2D ? 1 : dir_words(D) + (g.kind == WOI_SHAPE_ELLIPSOID ? 1 : 0);
+    return g.kind == WOI_SHAPE_POLYLINE2D ? 1 : g.kind == WOI_SHAPE_MESH3D ? 3
+         : dir_words(D) + (g.kind == WOI_SHAPE_ELLIPSOID ? 1 : 0);
+}
+
+// Triangle mesh (3D): the triangle j with cum[j] <= s < cum[j + 1] (cumulative areas; guide
+// table and probes as for polylines), then the uniform point a + r (1 - u) e1 + r u e2 with
+// r = sqrt(u1), from the per-triangle record (a, e1 = b - a, e2 = c - a).
+template <typename R>
+__device__ __forceinline__ int mesh_triangle(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay, R s) {
+    constexpr int CS = std::is_same<R, float>::value ? 2 : 1;
+    const R* cum = pay + Pay<R>::cum(g);
+    const int n = g.nv;
+    int k = (int)(s * Pay<R>::gscale(g));
+    k = min(max(k, 0), n - 1);
+    int j = int_payload(dp)[g.guide + k];
+    while (j < n - 1 && cum[CS * (j + 1)] <= s) ++j;
+    while (j > 0 && cum[CS * j] > s) --j;
+    return j;
 }
 
 template <typename R, int D, bool LDS>
 __device__ __forceinline__ bool surf_attempt(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
                                              const Stream& st, uint32_t step, int att, R y[D], int& seg) {
     seg = 0;
+    if (g.kind == WOI_SHAPE_MESH3D) {
+        if constexpr (D == 3) {
+            Words<3> W; W.fill(st, step, (uint32_t)att);
+            const int j = mesh_triangle<R>(dp, g, pay, RO<R>::u(W.w[0]) * Pay<R>::total(g));
+            const R r = RO<R>::sq(RO<R>::u(W.w[1])), u2 = RO<R>::u(W.w[2]);
+            const R* T = pay + Pay<R>::g(g) + 9 * j;
+            const R f1 = r * (R(1) - u2), f2 = r * u2;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) y[i] = T[i] + f1 * T[3 + i] + f2 * T[6 + i];
+            seg = j;
+        }
+        return true;
+    }
     if (g.kind == WOI_SHAPE_POLYLINE2D) {
         Words<1> W; W.fill(st, step, (uint32_t)att);
         return polyline_at<R, D, LDS>(dp, g, pay, RO<R>::u(W.w[0]) * Pay<R>::total(g), y, seg);
@@ -609,6 +643,56 @@ __device__ __forceinline__ int poly_pick(const DevProblem* dp, const DevRegion& 
     return q;
 }
 
+// Triangle mesh: hits of the line / ray y + t d in triangle order (Moller-Trumbore with the
+// closed barycentric bounds; a line skips the triangle of y and |t| <= eps, a ray keeps t > 0).
+// Returns q and, when q > 0, the parameter t and triangle of hit `pick` = min(floor(up q), q - 1).
+// The first walk counts the hits and keeps the first two; a second walk finds a later pick.
+template <typename R>
+__device__ __forceinline__ int mesh_pick(const DevRegion& g, const R* __restrict__ pay, const R y[3], const R d[3],
+                                         bool ray, int yseg, R up, int& pick, R& tp, int& jp, Counts& cnt) {
+    const R* __restrict__ T = pay + Pay<R>::g(g);
+    const int n = g.nv;
+    auto hit = [&](int j, R& t) -> bool {
+        const R* a = T + 9 * j;
+        const R *e1 = a + 3, *e2 = a + 6;
+        const R sv[3] = {y[0] - a[0], y[1] - a[1], y[2] - a[2]};
+        const R pv[3] = {d[1] * e2[2] - d[2] * e2[1], d[2] * e2[0] - d[0] * e2[2], d[0] * e2[1] - d[1] * e2[0]};
+        const R det = e1[0] * pv[0] + e1[1] * pv[1] + e1[2] * pv[2];
+        const R u = RO<R>::div(sv[0] * pv[0] + sv[1] * pv[1] + sv[2] * pv[2], det);
+        const R qv[3] = {sv[1] * e1[2] - sv[2] * e1[1], sv[2] * e1[0] - sv[0] * e1[2], sv[0] * e1[1] - sv[1] * e1[0]};
+        const R v = RO<R>::div(d[0] * qv[0] + d[1] * qv[1] + d[2] * qv[2], det);
+        t = RO<R>::div(e2[0] * qv[0] + e2[1] * qv[1] + e2[2] * qv[2], det);
+        return (ray | (j != yseg)) & (det != R(0)) & (u >= R(0)) & (u <= R(1)) & (v >= R(0)) & (u + v <= R(1)) &
+               (ray ? (t > R(0)) : (fabs(t) > RO<R>::line_eps));
+    };
+    int q = 0, j0 = 0, j1 = 0;
+    R t0 = 0, t1 = 0;
+    for (int j = 0; j < n; ++j) {
+        R t;
+        const bool h = hit(j, t);
+        t0 = (h & (q == 0)) ? t : t0; j0 = (h & (q == 0)) ? j : j0;
+        t1 = (h & (q == 1)) ? t : t1; j1 = (h & (q == 1)) ? j : j1;
+        q += h ? 1 : 0;
+        if (COUNT_POLY) cnt.segs++;
+    }
+    if (q > 0) {
+        pick = min((int)(up * (R)q), q - 1);
+        tp = pick == 0 ? t0 : t1;
+        jp = pick == 0 ? j0 : j1;
+        if (pick >= 2) {
+            int k = 0;
+            for (int j = 0; j < n; ++j) {
+                R t;
+                if (hit(j, t)) {
+                    if (k == pick) { tp = t; jp = j; break; }
+                    ++k;
+                }
+            }
+        }
+    }
+    return q;
+}
+
 // ----------------------------------------------------------------------------- accumulation
 template <typename R, int D>
 __device__ __forceinline__ void add_term(const DevProblem* dp, const R xh[D], const R xl[D], const R y[D], R c,
@@ -853,6 +937,16 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
                         const R den = d[0] * ey - d[1] * ex;
                         const R s = RO<R>::div((v[0] - y[0]) * d[1] - (v[1] - y[1]) * d[0], den);
                         yn[0] = v[0] + s * ex; yn[1] = v[1] + s * ey; segn = j;
+                    }
+                } else if (g->kind == WOI_SHAPE_MESH3D) {
+                    if constexpr (D == 3) {
+                        R t = 0;
+                        int j = 0;
+                        qn = mesh_pick<R>(*g, pay, y, d, ray, seg, up, pick, t, j, cnt);
+                        if (qn == 0) { cnt.redraws++; continue; }
+#pragma unroll
+                        for (int k = 0; k < D; ++k) yn[k] = y[k] + t * d[k];
+                        segn = j;
                     }
                 } else {
                     R t;

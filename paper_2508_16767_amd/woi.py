@@ -32,7 +32,8 @@ class WoiError(RuntimeError):
 
 class _Shape(C.Structure):
     _fields_ = [("kind", C.c_int), ("n_vertices", C.c_int), ("center", C.c_double * MAX_DIM),
-                ("radius", C.c_double), ("A", C.POINTER(C.c_double)), ("vertices", C.POINTER(C.c_double))]
+                ("radius", C.c_double), ("A", C.POINTER(C.c_double)), ("vertices", C.POINTER(C.c_double)),
+                ("n_triangles", C.c_int), ("triangles", C.POINTER(C.c_int))]
 
 
 class _Data(C.Structure):
@@ -139,7 +140,12 @@ class Problem:
             if v is not None:
                 v = np.ascontiguousarray(v, dtype=np.float64).reshape(-1); keep.append(v)
                 shapes[i].vertices = _dptr(v, C.c_double)
-                shapes[i].n_vertices = len(v) // 2
+                shapes[i].n_vertices = len(v) // (3 if int(s.kind) == 3 else 2)
+            t = getattr(s, "triangles", None)
+            if t is not None:
+                t = np.ascontiguousarray(t, dtype=np.int32).reshape(-1); keep.append(t)
+                shapes[i].triangles = _dptr(t, C.c_int)
+                shapes[i].n_triangles = len(t) // 3
             datas[i].kind = int(d.kind)
             dc = np.zeros(MAX_DIM); dc[:m] = np.asarray(d.center, dtype=np.float64).reshape(-1)[:m]
             datas[i].center[:] = list(dc)

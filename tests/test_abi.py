@@ -68,6 +68,23 @@ def test_validation_errors(woi):
     _err(woi, neg, "WOI_E_INVALID_ARG")
 
 
+def test_mesh_validation(woi):
+    """Triangle meshes: closed, outward, nested, 3D only; no variance reduction."""
+    sh = W.icosphere([0, 0, 0], 1.0, 2)
+    ff = W.field_flux([1.0, 0.0, 0.0])
+    prob = woi.Problem(W.Problem(3, [-1], [1.0], [sh], [ff]))  # accepted (compatible linear data)
+    flipped = W.mesh(sh.vertices, sh.triangles[:, ::-1])
+    _err(woi, W.Problem(3, [-1], [1.0], [flipped], [ff]), "WOI_E_GEOMETRY")          # inward normals
+    _err(woi, W.Problem(3, [-1], [1.0], [W.mesh(sh.vertices, sh.triangles[:-1])], [ff]), "WOI_E_GEOMETRY")  # open
+    _err(woi, W.Problem(3, [-1, 0], [1.0, 2.0], [sh, W.icosphere([0.7, 0, 0], 0.5, 1)], [ff, ff]),
+         "WOI_E_GEOMETRY")                                                            # leaves its parent
+    bad = W.mesh(sh.vertices, np.where(sh.triangles == 0, len(sh.vertices), sh.triangles))
+    _err(woi, W.Problem(3, [-1], [1.0], [bad], [ff]), "WOI_E_INVALID_ARG")          # index out of range
+    with pytest.raises(woi.WoiError) as e:
+        woi.workspace_size(prob, 16, woi.make_query(100, 4, estimator=woi.VR))
+    assert e.value.status == "WOI_E_UNSUPPORTED"
+
+
 def test_query_validation_without_gpu(woi):
     p5, _ = W.nested_spheres_6d()
     prob = woi.Problem(p5)

@@ -419,6 +419,40 @@ def test_point_charge_ellipsoids(m):
         assert np.all(np.isfinite(zg)) and abs(np.mean(zg)) < 0.2 and np.median(np.abs(zg)) < 0.8
 
 
+def _mesh_tree(subdiv=2):
+    """Jittered icosphere (R = 1) around a jittered icosphere (R = 0.45) and a sphere sibling,
+    quadratic direction-polynomial data (no compatibility check)."""
+    shapes = [W.icosphere([0.0, 0.0, 0.0], 1.0, subdiv, jitter=0.03, seed=1),
+              W.icosphere([0.1, -0.05, 0.02], 0.45, subdiv, jitter=0.05, seed=2),
+              W.sphere([-0.55, 0.3, 0.1], 0.15)]
+    rng = np.random.default_rng(5)
+    data = [W.dirpoly(sh.center, {(1, 0, 0): rng.normal(), (0, 1, 1): rng.normal(), (2, 0, 0): rng.normal(),
+                                  (0, 0, 1): rng.normal()}) for sh in shapes]
+    return W.Problem(3, [-1, 0, 0], [1.0, 4.0, 0.5], shapes, data, 2, "mesh-tree")
+
+
+MESH_PTS = np.array([[0.0, 0.1, 0.0], [0.3, -0.2, 0.25], [-0.55, 0.3, 0.12], [0.6, 0.4, -0.3], [0.1, 0.0, -0.1]])
+
+
+def test_walk_parity_meshes():
+    """Triangle-mesh interfaces (3D): per-walker parity with the oracle under both schedules,
+    the shared-trajectory path against the per-point samples, FP32 paired with FP64."""
+    p = _mesh_tree()
+    walk_parity(p, MESH_PTS, 1000, 4, flip_budget=1e-4)
+    walk_parity(p, MESH_PTS, 600, 4, sched=1, flip_budget=1e-4)
+    gp = woi.Problem(p)
+    pts = np.tile(MESH_PTS, (4, 1))
+    sh = [_np(t) for t in woi.estimate(gp, pts, 4000, 4, seed=4, schedule_mode=1, batch_share=4)]
+    F, _, _ = woi.trace(gp, pts, 4000, 4, seed=4, schedule_mode=1, batch_share=4)
+    Fs = _np(F).sum(-1)
+    assert np.allclose(sh[0], Fs.mean(1), rtol=1e-9, atol=1e-9 * (Fs.std(1) / np.sqrt(Fs.shape[1])).max())
+    m64, s64, _, _ = [_np(a) for a in woi.estimate(gp, MESH_PTS, 20000, 4, seed=3, schedule_mode=1)]
+    m32, _, _, _ = [_np(a) for a in woi.estimate(gp, MESH_PTS, 20000, 4, seed=3, precision=woi.FP32, schedule_mode=1)]
+    assert np.all(np.abs(m32 - m64) < 0.1 * s64), (m32 - m64) / s64
+    with pytest.raises(woi.WoiError):                        # no VR halves on meshes
+        woi.estimate(gp, MESH_PTS, 100, 2, seed=1, estimator=woi.VR)
+
+
 def test_large_point_count():
     """2^20 points with few walkers: the grid spans many workgroups in x and the partial buffer
     is a single chunk; sampled points against the oracle on identical streams (FP64) and the
