@@ -389,6 +389,12 @@ def main():
                 woi, torch, ev, f"{m}D: 3 nested ellipsoids (centres 1.3/1.4/1.6 e1), sigma (1.1, 1.3, 0.9), data "
                 f"from u = |x|^(2-m); 10000 points; W = 2e5, M = {m + 2}", pm, xm, 200000, m + 2, 0, 32,
                 args.extra_steps)
+        # triangle-mesh interfaces (brute-force hit scan over 1280 triangles per mesh)
+        p6, x6 = W.mesh_tree_3d()
+        rec["mesh_tree_3d"] = config_block(
+            woi, torch, ev, "3D: jittered icosphere (R 1, 1280 triangles) around a jittered icosphere (R 0.45, 1280 "
+            "triangles) and a sphere; sigma (1, 4, 0.5); quadratic direction-polynomial data; 4096 points; W = 2e4, "
+            "M = 4", p6, x6, 20000, 4, 0, 16, args.extra_steps)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(prob_desc, pts_np, args.walks, M, args.cpu_seconds)
     print(json.dumps(rec), flush=True)

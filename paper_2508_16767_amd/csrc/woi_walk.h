@@ -205,7 +205,7 @@ __device__ __forceinline__ void normal_at(const DevRegion& g, const R* __restric
         const R inv = RO<R>::rsq(s);     // FP64: 1 / sqrt
 #pragma unroll
         for (int i = 0; i < D; ++i) n[i] *= inv;
-    } else if (g.kind == WOI_SHAPE_MESH3D) {
+    } else if (D == 3 && g.kind == WOI_SHAPE_MESH3D) {
         const R* nr = pay + Pay<R>::nrm(g) + 3 * seg;
 #pragma unroll
         for (int i = 0; i < D && i < 3; ++i) n[i] = nr[i];
@@ -364,7 +364,7 @@ template <typename R, int D, bool LDS>
 __device__ __forceinline__ bool surf_attempt(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
                                              const Stream& st, uint32_t step, int att, R y[D], int& seg) {
     seg = 0;
-    if (g.kind == WOI_SHAPE_MESH3D) {
+    if (D == 3 && g.kind == WOI_SHAPE_MESH3D) {
         if constexpr (D == 3) {
             Words<3> W; W.fill(st, step, (uint32_t)att);
             const int j = mesh_triangle<R>(dp, g, pay, RO<R>::u(W.w[0]) * Pay<R>::total(g));
@@ -938,7 +938,7 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
                         const R s = RO<R>::div((v[0] - y[0]) * d[1] - (v[1] - y[1]) * d[0], den);
                         yn[0] = v[0] + s * ex; yn[1] = v[1] + s * ey; segn = j;
                     }
-                } else if (g->kind == WOI_SHAPE_MESH3D) {
+                } else if (D == 3 && g->kind == WOI_SHAPE_MESH3D) {
                     if constexpr (D == 3) {
                         R t = 0;
                         int j = 0;

@@ -512,6 +512,21 @@ def point_charge_potential(x):
     return r ** (2 - m), ((2 - m) * r ** (-m))[..., None] * x
 
 
+def mesh_tree_3d(n_points=4096, subdiv=3, seed=12):
+    """Triangle-mesh interfaces: a jittered icosphere (R = 1, 20 4^subdiv triangles) around a
+    jittered icosphere (R = 0.45, centre (0.1, -0.05, 0.02)) and a sphere sibling (R = 0.15 at
+    (-0.55, 0.3, 0.1)); sigma (1, 4, 0.5); quadratic direction-polynomial data with N(0, 1)
+    coefficients (no compatibility requirement); points uniform in the ball of radius 0.85."""
+    shapes = [icosphere([0.0, 0.0, 0.0], 1.0, subdiv, jitter=0.03, seed=1),
+              icosphere([0.1, -0.05, 0.02], 0.45, subdiv, jitter=0.05, seed=2),
+              sphere([-0.55, 0.3, 0.1], 0.15)]
+    rng = np.random.default_rng(seed)
+    data = [dirpoly(sh.center, {(1, 0, 0): rng.normal(), (0, 1, 1): rng.normal(), (2, 0, 0): rng.normal(),
+                                (0, 0, 1): rng.normal()}) for sh in shapes]
+    prob = Problem(3, [-1, 0, 0], [1.0, 4.0, 0.5], shapes, data, 2, "mesh-tree-3d")
+    return prob, ball_points(np.random.default_rng(seed + 1), n_points, 3, 0.85)
+
+
 WORKLOAD_DESCRIPTIONS = {
     "concentric_disk_2d": "unit disk, concentric circle r=0.5, sigma 10/1, b = cos(theta); 64 points, W=1e4, M=4",
     "star_tree_2d": "unit disk, 3 nested stars (k=3,5,7) + 5 circles, sigma 10^U(-1,2), Fourier data; 4096 points, "
@@ -521,4 +536,6 @@ WORKLOAD_DESCRIPTIONS = {
     "nested_spheres_6d": "unit 6-ball, spheres 0.7/0.35, sigma (1,5,0.2), c + lam x1/|x| data; 1024 points, W=1e6, M=8",
     "point_charge_ellipsoids": "3 nested ellipsoids around the potential |x|^(2-m) of a point charge outside them, "
                                "m = 3..6; 1e4 points, M = m + 2",
+    "mesh_tree_3d": "jittered icospheres (1280 triangles each) around a sphere sibling, direction-polynomial data; "
+                    "4096 points, M = 4",
 }
