@@ -23,6 +23,11 @@ constexpr int DK_DIRPOLY_HORNER = 16;
 //   POLYLINE2D : vertices v[2*(nv+1)] (v[nv] = v[0]), segment lengths len[nv],
 //                cumulative arclength cum[nv+1] (FP64; the FP32 table holds the pairs
 //                (cum[j], 1/len[j]), j <= nv), outward unit normals nrm[2*nv].
+// Mesh BVH (float payload, shared by both precisions): nodes in depth-first order, 8 floats
+//   each: box min (3), box max (3) -- widened outward to stay conservative under FP32
+//   rounding --, the index of the node that follows the subtree, and for a leaf
+//   8 * (first entry in the leaf triangle list) + (triangle count <= 4), -1 for an inner node
+//   (floats holding exact integers); the list holds original triangle indices.
 // Polyline search tables (float payload, shared by both precisions):
 //   for every level l >= 1 and aligned block b (vertices [b 2^l, min((b+1) 2^l, nv)]),
 //   bnd[(N2 >> l) + b] bounds the distance of the block's vertices from its chord (heap
@@ -43,6 +48,7 @@ struct DevRegion {
     int d64, d32, dexp;        // data coefficients, DIRPOLY exponents (byte offset)
     int b64, b32, nbrk, class0;// VR (2D): sign breakpoints of beta along arclength
     int lds_v, lds_b;          // byte offsets of the LDS copies (FP32 vertices, FP16 bounds), -1 if none
+    int bvh, nbvh, bvhidx;     // mesh: float offset of the BVH nodes, node count, int offset of the leaf triangle lists
     double alpha, sgn, s, area, meas[2], total;
     double gscale;             // polyline: nv / total length (guide-table index scale)
     float alpha_f, sgn_f, s_f, area_f, meas_f[2], total_f, gscale_f;

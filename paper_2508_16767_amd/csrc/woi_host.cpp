@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <numeric>
+#include <functional>
 #include <atomic>
 #include <mutex>
 #include <cmath>
@@ -739,6 +741,70 @@ void flux_integrals(Host& H) {
     }
 }
 
+// Bounding-volume hierarchy over a mesh's triangles: median split of the centroids along the
+// longest axis of their box, leaves of at most 4 triangles, nodes in depth-first order with the
+// index of the node after each subtree.  Node: box min, box max (widened outward by a relative
+// 1e-5 of the mesh size plus FP32 rounding), skip index, 8 * leaf list start + triangle count
+// (-1 for inner nodes).
+void mesh_bvh(const HostRegion& g, std::vector<float>& nodes, std::vector<int32_t>& list) {
+    const int nt = g.ntri();
+    std::vector<int> ids(nt);
+    std::iota(ids.begin(), ids.end(), 0);
+    std::vector<double> cen(3 * (size_t)nt);
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int j = 0; j < nt; ++j)
+        for (int k = 0; k < 3; ++k) {
+            double c = 0;
+            for (int v = 0; v < 3; ++v) {
+                const double x = g.mv[3 * g.tri[3 * j + v] + k];
+                c += x / 3;
+                lo[k] = std::min(lo[k], x);
+                hi[k] = std::max(hi[k], x);
+            }
+            cen[3 * j + k] = c;
+        }
+    const double pad = 1e-5 * std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], std::fabs(lo[0]), std::fabs(hi[0]),
+                                        std::fabs(lo[1]), std::fabs(hi[1]), std::fabs(lo[2]), std::fabs(hi[2])});
+    nodes.clear();
+    list.clear();
+    std::function<void(int, int)> build = [&](int a, int b) {   // triangles ids[a, b)
+        const size_t me = nodes.size();
+        nodes.resize(me + 8);
+        double bl[3] = {1e300, 1e300, 1e300}, bh[3] = {-1e300, -1e300, -1e300};
+        double cl[3] = {1e300, 1e300, 1e300}, ch[3] = {-1e300, -1e300, -1e300};
+        for (int i = a; i < b; ++i)
+            for (int k = 0; k < 3; ++k) {
+                for (int v = 0; v < 3; ++v) {
+                    const double x = g.mv[3 * g.tri[3 * ids[i] + v] + k];
+                    bl[k] = std::min(bl[k], x);
+                    bh[k] = std::max(bh[k], x);
+                }
+                cl[k] = std::min(cl[k], cen[3 * ids[i] + k]);
+                ch[k] = std::max(ch[k], cen[3 * ids[i] + k]);
+            }
+        for (int k = 0; k < 3; ++k) {
+            nodes[me + k] = std::nextafter((float)(bl[k] - pad), -INFINITY);
+            nodes[me + 3 + k] = std::nextafter((float)(bh[k] + pad), INFINITY);
+        }
+        if (b - a <= 4) {
+            nodes[me + 7] = (float)(8 * list.size() + (size_t)(b - a));   // start * 8 + count, exact in FP32
+            for (int i = a; i < b; ++i) list.push_back(ids[i]);
+        } else {
+            nodes[me + 7] = -1.0f;
+            int ax = 0;
+            for (int k = 1; k < 3; ++k)
+                if (ch[k] - cl[k] > ch[ax] - cl[ax]) ax = k;
+            const int mid = (a + b) / 2;
+            std::nth_element(ids.begin() + a, ids.begin() + mid, ids.begin() + b,
+                             [&](int x, int y) { return cen[3 * x + ax] < cen[3 * y + ax]; });
+            build(a, mid);
+            build(mid, b);
+        }
+        nodes[me + 6] = (float)(nodes.size() / 8);   // the node after this subtree
+    };
+    build(0, nt);
+}
+
 // Distance from point p to the segment [a, b].
 double seg_dist(const double* p, const double* a, const double* b) {
     const double ex = b[0] - a[0], ey = b[1] - a[1], wx = p[0] - a[0], wy = p[1] - a[1];
@@ -1019,6 +1085,14 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
             const int n = g.ntri();
             r.nrm64 = put64(g.tn.data(), g.tn.size());
             r.nrm32 = put32(g.tn.data(), g.tn.size());
+            std::vector<float> nodes;
+            std::vector<int32_t> list;
+            mesh_bvh(g, nodes, list);
+            r.bvh = (int)p32.size();
+            r.nbvh = (int)(nodes.size() / 8);
+            p32.insert(p32.end(), nodes.begin(), nodes.end());
+            r.bvhidx = (int)pi.size();
+            pi.insert(pi.end(), list.begin(), list.end());
             r.cum64 = put64(g.cum.data(), g.cum.size());
             std::vector<double> cl(2 * (n + 1), 0.0);   // FP32 table of (cum[j], 0) pairs, the polyline layout
             for (int j = 0; j <= n; ++j) cl[2 * j] = g.cum[j];

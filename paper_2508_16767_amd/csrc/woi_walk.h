@@ -646,13 +646,13 @@ __device__ __forceinline__ int poly_pick(const DevProblem* dp, const DevRegion& 
 // Triangle mesh: hits of the line / ray y + t d in triangle order (Moller-Trumbore with the
 // closed barycentric bounds; a line skips the triangle of y and |t| <= eps, a ray keeps t > 0).
 // Returns q and, when q > 0, the parameter t and triangle of hit `pick` = min(floor(up q), q - 1).
-// The first walk counts the hits and keeps the first two; a second walk finds a later pick.
 template <typename R>
-__device__ __forceinline__ int mesh_pick(const DevRegion& g, const R* __restrict__ pay, const R y[3], const R d[3],
-                                         bool ray, int yseg, R up, int& pick, R& tp, int& jp, Counts& cnt) {
-    const R* __restrict__ T = pay + Pay<R>::g(g);
-    const int n = g.nv;
-    auto hit = [&](int j, R& t) -> bool {
+struct MeshHit {
+    const R* __restrict__ T;   // per triangle (a, b - a, c - a)
+    const R *y, *d;
+    bool ray;
+    int yseg;
+    __device__ __forceinline__ bool operator()(int j, R& t) const {
         const R* a = T + 9 * j;
         const R *e1 = a + 3, *e2 = a + 6;
         const R sv[3] = {y[0] - a[0], y[1] - a[1], y[2] - a[2]};
@@ -664,7 +664,13 @@ __device__ __forceinline__ int mesh_pick(const DevRegion& g, const R* __restrict
         t = RO<R>::div(e2[0] * qv[0] + e2[1] * qv[1] + e2[2] * qv[2], det);
         return (ray | (j != yseg)) & (det != R(0)) & (u >= R(0)) & (u <= R(1)) & (v >= R(0)) & (u + v <= R(1)) &
                (ray ? (t > R(0)) : (fabs(t) > RO<R>::line_eps));
-    };
+    }
+};
+
+// Every triangle in order (wave-uniform: all lanes test the same triangle).  The first scan
+// counts the hits and keeps the first two; a second scan finds a later pick.
+template <typename R>
+__device__ __forceinline__ int mesh_scan(const MeshHit<R>& hit, int n, R up, int& pick, R& tp, int& jp, Counts& cnt) {
     int q = 0, j0 = 0, j1 = 0;
     R t0 = 0, t1 = 0;
     for (int j = 0; j < n; ++j) {
@@ -690,6 +696,67 @@ __device__ __forceinline__ int mesh_pick(const DevRegion& g, const R* __restrict
             }
         }
     }
+    return q;
+}
+
+// Through the mesh's BVH: a stackless walk over the depth-first node list (enter a node whose
+// widened box meets the line -- an FP32 slab test -- else jump to the node after its subtree),
+// exact tests of the triangles of the leaves reached, hits queued by triangle index.  The hit
+// of rank `pick` among the queued indices is the pick-th in triangle order.  More than
+// POLY_QUEUE hits (or indices past 16 bits) fall back to the scan.
+template <typename R>
+__device__ __forceinline__ int mesh_pick(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
+                                         const R y[3], const R d[3], bool ray, int yseg, R up, int& pick, R& tp,
+                                         int& jp, Counts& cnt) {
+    const MeshHit<R> hit{pay + Pay<R>::g(g), y, d, ray, yseg};
+    const int n = g.nv;
+    const float* __restrict__ nodes = Pay<float>::base(dp) + g.bvh;
+    const int* __restrict__ list = int_payload(dp) + g.bvhidx;
+    const float yf[3] = {(float)y[0], (float)y[1], (float)y[2]};
+    const float inv[3] = {1.0f / (float)d[0], 1.0f / (float)d[1], 1.0f / (float)d[2]};
+    const float tlo = ray ? 0.0f : -INFINITY;
+    Queue16 hq{0u, 0u, 0u, 0u};
+    int q = 0;
+    for (int i = 0; i < g.nbvh;) {
+        const float* nd = nodes + 8 * i;
+        float t0 = tlo, t1 = INFINITY;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float a = (nd[k] - yf[k]) * inv[k], b = (nd[3 + k] - yf[k]) * inv[k];
+            t0 = fmaxf(t0, fminf(a, b));
+            t1 = fminf(t1, fmaxf(a, b));
+        }
+        const bool in = t0 <= t1;
+        const float lf = nd[7];
+        if (in & (lf >= 0.0f)) {
+            const int code = (int)lf, first = code >> 3, count = code & 7;
+            for (int c = 0; c < count; ++c) {
+                const int j = list[first + c];
+                R t;
+                if (hit(j, t)) {
+                    if (q < POLY_QUEUE) hq.push((uint32_t)j);
+                    ++q;
+                }
+                if (COUNT_POLY) cnt.segs++;
+            }
+        }
+        if (COUNT_POLY) cnt.nodes++;
+        i = (in & (lf < 0.0f)) ? i + 1 : (int)nd[6];
+    }
+    if (q == 0) return 0;
+    if (q > POLY_QUEUE || n > 0xFFFF) return mesh_scan<R>(hit, n, up, pick, tp, jp, cnt);
+    pick = min((int)(up * (R)q), q - 1);
+    int jb = 0;
+    for (int a = 0; a < q; ++a) {
+        const int ja = (int)hq.at(a);
+        int rank = 0;
+        for (int b = 0; b < q; ++b) rank += (int)hq.at(b) < ja ? 1 : 0;
+        jb = rank == pick ? ja : jb;
+    }
+    R t = 0;
+    hit(jb, t);
+    tp = t;
+    jp = jb;
     return q;
 }
 
@@ -942,7 +1009,7 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
                     if constexpr (D == 3) {
                         R t = 0;
                         int j = 0;
-                        qn = mesh_pick<R>(*g, pay, y, d, ray, seg, up, pick, t, j, cnt);
+                        qn = mesh_pick<R>(dp, *g, pay, y, d, ray, seg, up, pick, t, j, cnt);
                         if (qn == 0) { cnt.redraws++; continue; }
 #pragma unroll
                         for (int k = 0; k < D; ++k) yn[k] = y[k] + t * d[k];

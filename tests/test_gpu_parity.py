@@ -453,6 +453,27 @@ def test_walk_parity_meshes():
         woi.estimate(gp, MESH_PTS, 100, 2, seed=1, estimator=woi.VR)
 
 
+def test_walk_parity_mesh_gear():
+    """A 5120-triangle sphere mesh modulated radially, r = 0.7 (1 + 0.45 cos 8 phi): the BVH
+    walk on a deeper tree, and lines crossing the mesh more than eight times (the scan
+    fallback).  Identical decisions and values to the oracle; FP32 paired with FP64."""
+    sh = W.icosphere([0.0, 0.0, 0.0], 1.0, 4)
+    v = sh.vertices
+    ph = np.arctan2(v[:, 1], v[:, 0])
+    gear = W.mesh(0.7 * v * (1 + 0.45 * np.cos(8 * ph))[:, None], sh.triangles)
+    data = [W.dirpoly([0.0, 0.0, 0.0], {(1, 0, 0): 0.7, (0, 1, 1): -0.4, (0, 0, 1): 0.3})]
+    p = W.Problem(3, [-1], [1.0], [gear], data, 2, "mesh-gear")
+    pts = np.array([[0.0, 0.05, 0.1], [0.3, -0.1, 0.2], [-0.2, 0.2, -0.3]])
+    walk_parity(p, pts, 600, 4, flip_budget=1e-4)
+    gp = woi.Problem(p)
+    _, _, T = woi.trace(gp, pts, 600, 4, seed=7, precision=woi.FP64)
+    q = (_np(T).astype(np.uint32)[..., 1:] >> 8) & 0xFF
+    assert (q > 8).sum() > 0
+    m64, s64, _, _ = [_np(a) for a in woi.estimate(gp, pts, 20000, 4, seed=3, schedule_mode=1)]
+    m32, _, _, _ = [_np(a) for a in woi.estimate(gp, pts, 20000, 4, seed=3, precision=woi.FP32, schedule_mode=1)]
+    assert np.all(np.abs(m32 - m64) < 0.1 * s64), (m32 - m64) / s64
+
+
 def test_large_point_count():
     """2^20 points with few walkers: the grid spans many workgroups in x and the partial buffer
     is a single chunk; sampled points against the oracle on identical streams (FP64) and the
