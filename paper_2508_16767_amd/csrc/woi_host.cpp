@@ -506,6 +506,12 @@ void vr_halves_3d(const Host& H, HostRegion& g) {
 
 }  // namespace
 
+static bool has_mesh(const Host& H) {
+    for (int i = 0; i < H.N; ++i)
+        if (H.r[i].kind == WOI_SHAPE_MESH3D) return true;
+    return false;
+}
+
 // ---------------------------------------------------------------------------- problem object
 struct woi_problem {
     Host H;
@@ -1364,6 +1370,7 @@ woi_status estimate_shared(const woi_problem* p, const double* points, int64_t P
     kp.M = q->M;
     kp.batch_share = q->batch_share;
     kp.shared_sched = q->schedule_mode == WOI_SCHED_SHARED;
+    kp.mesh = has_mesh(p->H) ? 1 : 0;
     kp.instance = q->instance;
     kp.partials = reinterpret_cast<double*>(static_cast<char*>(workspace) + sp.traj_bytes);
     kp.counters = counters;
@@ -1452,6 +1459,7 @@ woi_status woi_estimate(const woi_problem* p, const double* points, int64_t P, c
     kp.M = q->M;
     kp.batch_share = q->batch_share;
     kp.shared_sched = q->schedule_mode == WOI_SCHED_SHARED;
+    kp.mesh = has_mesh(p->H) ? 1 : 0;
     kp.instance = q->instance;
     kp.partials = static_cast<double*>(workspace);
     kp.counters = counters;
@@ -1502,6 +1510,7 @@ woi_status woi_trace(const woi_problem* p, const double* points, int64_t P, cons
     kp.M = q->M;
     kp.batch_share = q->batch_share;
     kp.shared_sched = q->schedule_mode == WOI_SCHED_SHARED;
+    kp.mesh = has_mesh(p->H) ? 1 : 0;
     kp.instance = q->instance;
     kp.traceF = F;
     kp.traceG = G;
@@ -1528,6 +1537,7 @@ woi_status set_error(woi_status s, const char* fmt, ...) {
 }
 
 woi_status check_query(const woi_problem* p, int64_t P, const woi_query* q) { return check_query_impl(p, P, q); }
+bool problem_has_mesh(const woi_problem* p) { return p && has_mesh(p->H); }
 
 woi_status problem_ref(woi_problem* p, ProblemRef* out) {
     const woi_status st = woi_problem_upload(p);

@@ -12,6 +12,8 @@ namespace woi {
 woi_status set_error(woi_status s, const char* fmt, ...);
 // Validation of one query for P points (the checks woi_estimate makes).
 woi_status check_query(const woi_problem* p, int64_t P, const woi_query* q);
+// Whether any interface of the problem is a triangle mesh (host state only).
+bool problem_has_mesh(const woi_problem* p);
 
 // A problem as the launch code sees it (uploading it to the current device if needed).
 struct ProblemRef {

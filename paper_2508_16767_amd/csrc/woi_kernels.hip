@@ -6,11 +6,14 @@
 
 namespace woi {
 
+// LDS: in 2D, the polylines are staged in LDS (512-thread workgroups); in 3D, the kernel
+// handles triangle-mesh interfaces (their tables stay in global memory), which the other 3D
+// kernels leave out so that quadric-only problems keep their register budget.
 template <typename R, int D, bool VR, bool COUNT, bool LDS>
 __global__ __launch_bounds__(LDS ? 512 : 256) void walk_kernel(KParams kp) {
     const DevProblem* __restrict__ dp = kp.dp;
     const R* __restrict__ pay = Pay<R>::base(dp);
-    if constexpr (LDS) stage_polylines(dp);
+    if constexpr (LDS && D == 2) stage_polylines(dp);
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = p < kp.P;
     const int64_t pc = active ? p : kp.P - 1;
@@ -82,7 +85,7 @@ template <typename R, int D, bool VR, bool LDS>
 __global__ __launch_bounds__(LDS ? 512 : 256) void traj_kernel(KParams kp, TParams tp) {
     const DevProblem* __restrict__ dp = kp.dp;
     const R* __restrict__ pay = Pay<R>::base(dp);
-    if constexpr (LDS) stage_polylines(dp);
+    if constexpr (LDS && D == 2) stage_polylines(dp);
     const int lg = tp.lg;
     const int row = __builtin_amdgcn_readfirstlane((int)threadIdx.x / lg);
     const int g = blockIdx.x * lg + (int)threadIdx.x % lg;
@@ -255,8 +258,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(RParams rp) {
 // ----------------------------------------------------------------------------- launchers
 template <typename R, int D, bool VR, bool COUNT, bool LDS>
 static hipError_t launch_walk_t(const KParams& kp, dim3 grid, dim3 block, unsigned smem, hipStream_t s) {
-    if constexpr (LDS) {
-        if (D != 2) return hipErrorInvalidValue;
+    if constexpr (LDS && D == 2) {
         static bool attr = false;
         if (!attr) {
             hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&walk_kernel<R, D, VR, COUNT, LDS>),
@@ -272,6 +274,8 @@ static hipError_t launch_walk_t(const KParams& kp, dim3 grid, dim3 block, unsign
 template <typename R, bool COUNT>
 static hipError_t launch_walk_c(const KParams& kp, int dim, bool vr, bool lds, dim3 grid, dim3 block, unsigned smem,
                                 hipStream_t s) {
+    if (dim == 3 && kp.mesh)   // the mesh-capable 3D kernel (no VR on meshes)
+        return vr ? hipErrorInvalidValue : launch_walk_t<R, 3, false, COUNT, true>(kp, grid, block, 0, s);
     if (lds) {
         if (dim != 2) return hipErrorInvalidValue;
         return vr ? launch_walk_t<R, 2, true, COUNT, true>(kp, grid, block, smem, s)
@@ -299,7 +303,7 @@ static hipError_t launch_walk_c(const KParams& kp, int dim, bool vr, bool lds, d
 template <typename R, int D, bool VR, bool LDS>
 static hipError_t launch_traj_t(const KParams& kp, const TParams& tp, unsigned smem, hipStream_t s) {
     const int bs = LDS ? 512 : 256;
-    if constexpr (LDS) {
+    if constexpr (LDS && D == 2) {
         static bool attr = false;
         if (!attr) {
             hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&traj_kernel<R, D, VR, LDS>),
@@ -317,6 +321,7 @@ static hipError_t launch_traj_t(const KParams& kp, const TParams& tp, unsigned s
 
 template <typename R>
 static hipError_t launch_traj_r(const KParams& kp, const TParams& tp, int dim, bool vr, unsigned lds, hipStream_t s) {
+    if (dim == 3 && kp.mesh) return vr ? hipErrorInvalidValue : launch_traj_t<R, 3, false, true>(kp, tp, 0, s);
     if (lds && dim == 2) return vr ? launch_traj_t<R, 2, true, true>(kp, tp, lds, s) : launch_traj_t<R, 2, false, true>(kp, tp, lds, s);
     if (vr) {
         switch (dim) {

@@ -21,6 +21,7 @@ struct KParams {
     int M;
     int batch_share;
     int shared_sched;
+    int mesh;                      // 3D problem with triangle-mesh interfaces: the mesh-capable kernels
     uint32_t instance;
     double* partials;              // [chunks][P][2 + 2 dim] or null
     double* traceF;                // per-walker values (trace mode) or null

@@ -205,7 +205,7 @@ __device__ __forceinline__ void normal_at(const DevRegion& g, const R* __restric
         const R inv = RO<R>::rsq(s);     // FP64: 1 / sqrt
 #pragma unroll
         for (int i = 0; i < D; ++i) n[i] *= inv;
-    } else if (D == 3 && g.kind == WOI_SHAPE_MESH3D) {
+    } else if (D == 3 && LDS && g.kind == WOI_SHAPE_MESH3D) {
         const R* nr = pay + Pay<R>::nrm(g) + 3 * seg;
 #pragma unroll
         for (int i = 0; i < D && i < 3; ++i) n[i] = nr[i];
@@ -225,14 +225,14 @@ __device__ __forceinline__ void normal_at(const DevRegion& g, const R* __restric
 }
 
 // b_i(y) (Eq. interface_problem data).
-template <typename R, int D>
+template <typename R, int D, bool LDS = false>
 __device__ __forceinline__ R data_b(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
                                     const R y[D], int seg) {
     const R* cf = pay + Pay<R>::dat(g);
     if (g.dkind == WOI_DATA_ZERO) return R(0);
     if (g.dkind == WOI_DATA_FIELD_FLUX || g.dkind == WOI_DATA_SOURCE_FLUX) {
         R n[D];
-        normal_at<R, D>(g, pay, y, seg, n);
+        normal_at<R, D, LDS>(g, pay, y, seg, n);
         if (g.dkind == WOI_DATA_FIELD_FLUX) {
             R b = 0;
 #pragma unroll
@@ -364,7 +364,7 @@ template <typename R, int D, bool LDS>
 __device__ __forceinline__ bool surf_attempt(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
                                              const Stream& st, uint32_t step, int att, R y[D], int& seg) {
     seg = 0;
-    if (D == 3 && g.kind == WOI_SHAPE_MESH3D) {
+    if (D == 3 && LDS && g.kind == WOI_SHAPE_MESH3D) {
         if constexpr (D == 3) {
             Words<3> W; W.fill(st, step, (uint32_t)att);
             const int j = mesh_triangle<R>(dp, g, pay, RO<R>::u(W.w[0]) * Pay<R>::total(g));
@@ -448,7 +448,7 @@ __device__ __forceinline__ bool vr_attempt(const DevProblem* dp, const DevRegion
         return true;
     } else {
         if (!surf_attempt<R, D, LDS>(dp, g, pay, st, 0, att, y, seg)) return false;
-        return (Pay<R>::s(g) * data_b<R, D>(dp, g, pay, y, seg) >= R(0)) == (cls == 0);
+        return (Pay<R>::s(g) * data_b<R, D, LDS>(dp, g, pay, y, seg) >= R(0)) == (cls == 0);
     }
 }
 
@@ -945,7 +945,7 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
         }
         if (att == WOI_ATTEMPT_CAP) cnt.caps++;
     }
-    R Q = Pay<R>::s(*g) * data_b<R, D>(dp, *g, pay, y, seg) * meas, T = 1;
+    R Q = Pay<R>::s(*g) * data_b<R, D, LDS>(dp, *g, pay, y, seg) * meas, T = 1;
     sink.add(0, (M == 0 ? R(0.5) : R(1)) * Q * T, y, cnt);
     cnt.steps++;
     if (tr) tr[0] = trace_word(h, 0, 1, 0, 0, att);
@@ -1005,7 +1005,7 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
                         const R s = RO<R>::div((v[0] - y[0]) * d[1] - (v[1] - y[1]) * d[0], den);
                         yn[0] = v[0] + s * ex; yn[1] = v[1] + s * ey; segn = j;
                     }
-                } else if (D == 3 && g->kind == WOI_SHAPE_MESH3D) {
+                } else if (D == 3 && LDS && g->kind == WOI_SHAPE_MESH3D) {
                     if constexpr (D == 3) {
                         R t = 0;
                         int j = 0;

@@ -153,3 +153,5 @@ def test_batch_validation_without_gpu(woi):
     bad[0].mean = None
     assert status(bad) == "WOI_E_INVALID_ARG"
     assert status(items(woi.make_query(100, 4, estimator=woi.VR), problems=[p5])) == "WOI_E_UNSUPPORTED"
+    pm = woi.Problem(W.mesh_tree_3d(n_points=8, subdiv=1)[0])
+    assert status(items(woi.make_query(100, 4), problems=[pm])) == "WOI_E_UNSUPPORTED"    # triangle meshes
