@@ -182,6 +182,9 @@ class OracleProblem:
         return y
 
 
+PLAIN, VR, NAIVE = 0, 1, 2   # estimators: Alg. 2, Alg. 3, the naive Markov-tree estimator (Sec. 4.2)
+
+
 def _query(walks, M, seed=0, estimator=0, schedule_mode=0, batch_share=1, walk_offset=0, instance=0):
     return _Query(int(seed), int(walks), int(walk_offset), int(M), int(estimator), int(schedule_mode),
                   int(batch_share), int(instance))
@@ -209,12 +212,13 @@ def estimate(op: OracleProblem, x, walks, M, seed=0, estimator=0, schedule_mode=
 def trace(op: OracleProblem, x, n_samples, M, seed=0, estimator=0, schedule_mode=0, batch_share=1,
           walk_offset=0, instance=0, threads=None):
     """Per-walk values: F[p, j, k] (walker k of sample j at point p, times N), G[p, j, k, :],
-    decision words T[p, j, k, i]."""
+    decision words T[p, j, k, i].  For the naive estimator, F[p, j, 0] is tree j's value
+    (Eq. naive_woi_estimator) and T stays zero."""
     x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, op.dim)
-    P = len(x); K = 2 if estimator else 1
+    P = len(x); K = 2 if estimator == VR else 1
     F = np.zeros((P, n_samples, K)); G = np.zeros((P, n_samples, K, op.dim))
     T = np.zeros((P, n_samples, K, M + 1), dtype=np.uint32)
-    walks = 2 * n_samples if estimator else n_samples
+    walks = 2 * n_samples if estimator == VR else n_samples
     q = _query(walks, M, seed, estimator, schedule_mode, batch_share, walk_offset, instance)
     rc = op.lib.or_trace(op.h, _p(x, C.c_double), P, C.byref(q), n_samples, threads or os.cpu_count() or 1,
                         _p(F, C.c_double), _p(G, C.c_double), _p(T, C.c_uint32))

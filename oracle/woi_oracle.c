@@ -32,7 +32,7 @@
 /* OR_PLANT selects a deliberately wrong variant, built only by the tests that show
    the pins reject it: 1 sign product from m = 0, 2 sign applied twice in the "other"
    transition, 3 no 1/2 weight on the last term, 4 K* with the normal at y_{i-1},
-   5 T without the intersection count q. */
+   5 T without the intersection count q, 6 naive trees weighted by |alpha| instead of alpha. */
 #ifndef OR_PLANT
 #define OR_PLANT 0
 #endif
@@ -433,6 +433,74 @@ static uint32_t trace_word(int h, int cs, int q, int pick, int neg, int att)
            ((uint32_t)(neg ? 1 : 0) << 24) | ((uint32_t)att << 25);
 }
 
+/* One transition y_{i-1} -> y_i onto interface h (the three cases of Eq. naive_woi_p):
+   uniform on dOmega_h with Q *= |K*(y_i, y_{i-1})| |dOmega_h| ("other"), or the isotropic
+   line (same interface, Q *= 1/2) / ray (descendant -> ancestor) with a uniform pick among
+   its q hits.  Returns the factor q sign((y_i - y_{i-1}) . n(y_i)) of T, or 0 when no line
+   or ray hit turned up within OR_MAX_ATTEMPTS draws (the walk stops there). */
+static double transition(const or_problem *pr, int hprev, int h, words_t *w, const double *y, int seg,
+                         double *yn, int *segn, double *nn, double *Q, int *qn_out, int *pick_out, int *att_out,
+                         or_counters *cnt)
+{
+    const int m = pr->m;
+    const region_t *g = &pr->r[h];
+    const int rel = pr->rel[hprev][h];
+    int qn = 1, pick = 0, att;
+    *segn = 0;
+    if (rel == REL_OTHER) {
+        /* y_i uniform on dOmega_{h_i}; Q *= |K*(y_i, y_{i-1})| |dOmega_{h_i}| */
+        int nbo = (surf_words(g, m) + 3) / 4;
+        for (att = 0; att < OR_MAX_ATTEMPTS; ++att) {
+            words_seek(w, (uint32_t)(att * nbo));
+            if (surf_attempt(g, m, w, yn, segn)) break;
+            cnt->rejections++;
+        }
+        if (att == OR_MAX_ATTEMPTS) cnt->cap_hits++;
+        normal_at(g, m, yn, *segn, nn);
+        double dd[OR_MAX_DIM], r2 = 0, nk[OR_MAX_DIM];
+        for (int j = 0; j < m; ++j) { dd[j] = yn[j] - y[j]; r2 += dd[j] * dd[j]; }
+        if (OR_PLANT == 4) normal_at(&pr->r[hprev], m, y, seg, nk); else memcpy(nk, nn, sizeof nk);
+        double kstar = dot(dd, nk, m) / (pr->unit_area * pow(r2, 0.5 * m));
+        *Q *= (OR_PLANT == 2 ? kstar : fabs(kstar)) * g->area;
+    } else {
+        /* isotropic line (same interface) or ray (descendant -> ancestor), uniform pick */
+        hit_t hits[512];
+        int nbl = (dir_words(m) + 1 + 3) / 4, found = 0;
+        for (att = 0; att < OR_MAX_ATTEMPTS; ++att) {
+            double d[OR_MAX_DIM];
+            words_seek(w, (uint32_t)(att * nbl));
+            unit_dir(m, w, d);
+            double up = unif(words_next(w));
+            qn = hits_of(g, m, y, seg, d, rel == REL_DESC, hits, 512);
+            if (qn == 0) { cnt->redraws++; continue; }
+            pick = (int)floor(up * qn);
+            if (pick >= qn) pick = qn - 1;
+            if (g->kind == OR_POLYLINE) {
+                int j = hits[pick].seg;
+                const double *a = g->v + 2 * j, *b = g->v + 2 * ((j + 1) % g->nv);
+                double ex = b[0] - a[0], ey = b[1] - a[1];
+                double den = d[0] * ey - d[1] * ex;
+                double s = ((a[0] - y[0]) * d[1] - (a[1] - y[1]) * d[0]) / den;
+                yn[0] = a[0] + s * ex; yn[1] = a[1] + s * ey; *segn = j;
+            } else {   /* quadric (seg 0) or mesh (the triangle hit) */
+                for (int j = 0; j < m; ++j) yn[j] = y[j] + hits[pick].t * d[j];
+                *segn = hits[pick].seg;
+            }
+            found = 1;
+            break;
+        }
+        *att_out = att; *qn_out = 0; *pick_out = 0;
+        if (!found) { cnt->cap_hits++; return 0.0; }
+        if (rel == REL_SAME) *Q *= 0.5;
+        normal_at(g, m, yn, *segn, nn);
+    }
+    double dd[OR_MAX_DIM];
+    for (int j = 0; j < m; ++j) dd[j] = yn[j] - y[j];
+    double sg = dot(dd, nn, m) < 0 ? -1.0 : 1.0;
+    *att_out = att; *qn_out = qn; *pick_out = pick;
+    return (OR_PLANT == 5 ? 1 : qn) * sg;
+}
+
 static void one_sample(const or_problem *pr, const double *x, const or_query *q, uint64_t wi, uint32_t group,
                        double *Fk, double *Gk, uint32_t *trk, or_counters *cnt)
 {
@@ -484,70 +552,77 @@ static void one_sample(const or_problem *pr, const double *x, const or_query *q,
         cnt->zero_dist += add_term(pr, x, y, cS[0] * Q * T, &F, G);
         cnt->walk_steps++;
         if (tr) tr[0] = trace_word(h[0], 0, 1, 0, 0, att);
-        int stopped = 0;
-        for (int i = 1; i <= M && !stopped; ++i) {
-            const region_t *g = &pr->r[h[i]];
-            int rel = pr->rel[h[i - 1]][h[i]], qn = 1, pick = 0;
+        for (int i = 1; i <= M; ++i) {
+            int rel = pr->rel[h[i - 1]][h[i]], qn, pick, segn;
             double yn[OR_MAX_DIM], nn[OR_MAX_DIM];
-            int segn = 0;
             words_init(&w, q->seed, w32, group, c2, (uint32_t)i);
-            if (rel == REL_OTHER) {
-                /* y_i uniform on dOmega_{h_i}; Q *= |K*(y_i, y_{i-1})| |dOmega_{h_i}| */
-                int nbo = (surf_words(g, m) + 3) / 4;
-                for (att = 0; att < OR_MAX_ATTEMPTS; ++att) {
-                    words_seek(&w, (uint32_t)(att * nbo));
-                    if (surf_attempt(g, m, &w, yn, &segn)) break;
-                    cnt->rejections++;
-                }
-                if (att == OR_MAX_ATTEMPTS) cnt->cap_hits++;
-                normal_at(g, m, yn, segn, nn);
-                double dd[OR_MAX_DIM], r2 = 0, nk[OR_MAX_DIM];
-                for (int j = 0; j < m; ++j) { dd[j] = yn[j] - y[j]; r2 += dd[j] * dd[j]; }
-                if (OR_PLANT == 4) normal_at(&pr->r[h[i - 1]], m, y, seg, nk); else memcpy(nk, nn, sizeof nk);
-                double kstar = dot(dd, nk, m) / (pr->unit_area * pow(r2, 0.5 * m));
-                Q *= (OR_PLANT == 2 ? kstar : fabs(kstar)) * g->area;
-            } else {
-                /* isotropic line (same interface) or ray (descendant -> ancestor), uniform pick */
-                hit_t hits[512];
-                int nbl = (dir_words(m) + 1 + 3) / 4, found = 0;
-                for (att = 0; att < OR_MAX_ATTEMPTS; ++att) {
-                    double d[OR_MAX_DIM];
-                    words_seek(&w, (uint32_t)(att * nbl));
-                    unit_dir(m, &w, d);
-                    double up = unif(words_next(&w));
-                    qn = hits_of(g, m, y, seg, d, rel == REL_DESC, hits, 512);
-                    if (qn == 0) { cnt->redraws++; continue; }
-                    pick = (int)floor(up * qn);
-                    if (pick >= qn) pick = qn - 1;
-                    if (g->kind == OR_POLYLINE) {
-                        int j = hits[pick].seg;
-                        const double *a = g->v + 2 * j, *b = g->v + 2 * ((j + 1) % g->nv);
-                        double ex = b[0] - a[0], ey = b[1] - a[1];
-                        double den = d[0] * ey - d[1] * ex;
-                        double s = ((a[0] - y[0]) * d[1] - (a[1] - y[1]) * d[0]) / den;
-                        yn[0] = a[0] + s * ex; yn[1] = a[1] + s * ey; segn = j;
-                    } else {   /* quadric (seg 0) or mesh (the triangle hit) */
-                        for (int j = 0; j < m; ++j) yn[j] = y[j] + hits[pick].t * d[j];
-                        segn = hits[pick].seg;
-                    }
-                    found = 1;
-                    break;
-                }
-                if (!found) { cnt->cap_hits++; stopped = 1; if (tr) for (int j = i; j <= M; ++j) tr[j] = trace_word(h[j], rel, 0, 0, 0, att); break; }
-                if (rel == REL_SAME) Q *= 0.5;
-                normal_at(g, m, yn, segn, nn);
-            }
-            double dd[OR_MAX_DIM];
-            for (int j = 0; j < m; ++j) dd[j] = yn[j] - y[j];
-            double sg = dot(dd, nn, m) < 0 ? -1.0 : 1.0;
-            T *= (OR_PLANT == 5 ? 1 : qn) * sg;
+            double tf = transition(pr, h[i - 1], h[i], &w, y, seg, yn, &segn, nn, &Q, &qn, &pick, &att, cnt);
+            if (tf == 0) { if (tr) for (int j = i; j <= M; ++j) tr[j] = trace_word(h[j], rel, 0, 0, 0, att); break; }
+            T *= tf;
             memcpy(y, yn, sizeof(double) * m); seg = segn;
             cnt->zero_dist += add_term(pr, x, y, cS[i] * Q * T, &F, G);
             cnt->walk_steps++;
-            if (tr) tr[i] = trace_word(h[i], rel, qn, pick, sg < 0, att);
+            if (tr) tr[i] = trace_word(h[i], rel, qn, pick, tf < 0, att);
         }
         Fk[k] = N * F;
         for (int j = 0; j < m; ++j) Gk[k * m + j] = N * G[j];
+    }
+}
+
+/* ---------------------------------------------------------------- naive WoI */
+/* The naive estimator (Sec. 4.2, Eq. naive_woi_estimator): one observation is a Markov tree.
+   Its roots are y_(h0), uniform on dOmega_{h0} for every h0 (p_0 of Eq. naive_woi_p0); every
+   node (h0, ..., hi), i < M, has a child for every next interface h_{i+1}, drawn from the node
+   by the transition of Eq. naive_woi_p (the branch is a Markov chain, reused by all its
+   extensions, Sec. 4.2 "Reuse of Markov Chains").  The observation is
+     sum over nodes of w_i (prod_{m=1}^{i} alpha_{h_m}) Q T Phi(x, y_(h0..hi)),
+   Q and T of Eqs. naive_woi_Q and naive_woi_T, w_i = 1 - delta_{iM}/2.
+   Random numbers: node (h0, ..., hi) draws from the counter (tree, point group,
+   OR_NAIVE_TAG | id, step i), id = the base-(N+1) number with digits h0+1, ..., hi+1. */
+#define OR_NAIVE_TAG 0x80000000u
+
+static void naive_node(const or_problem *pr, const double *x, const or_query *q, uint32_t tree, uint32_t group,
+                       int i, int h, uint32_t id, const double *y, int seg, double Q, double T, double A,
+                       double *F, double *G, or_counters *cnt)
+{
+    const int M = q->M, N = pr->N;
+    cnt->zero_dist += add_term(pr, x, y, (i == M && OR_PLANT != 3 ? 0.5 : 1.0) * A * Q * T, F, G);
+    cnt->walk_steps++;
+    if (i == M) return;
+    for (int hn = 0; hn < N; ++hn) {
+        const uint32_t idn = id * (uint32_t)(N + 1) + (uint32_t)(hn + 1);
+        words_t w;
+        words_init(&w, q->seed, tree, group, OR_NAIVE_TAG | idn, (uint32_t)(i + 1));
+        double yn[OR_MAX_DIM], nn[OR_MAX_DIM], Qn = Q;
+        int segn, qn, pick, att;
+        double tf = transition(pr, h, hn, &w, y, seg, yn, &segn, nn, &Qn, &qn, &pick, &att, cnt);
+        if (tf == 0) continue;   /* no hit within the attempt cap: this subtree contributes nothing */
+        const double an = OR_PLANT == 6 ? fabs(pr->r[hn].alpha) : pr->r[hn].alpha;
+        naive_node(pr, x, q, tree, group, i + 1, hn, idn, yn, segn, Qn, T * tf, A * an, F, G, cnt);
+    }
+}
+
+static void naive_tree(const or_problem *pr, const double *x, const or_query *q, uint64_t ti, uint32_t group,
+                       double *F, double *G, or_counters *cnt)
+{
+    const int m = pr->m;
+    *F = 0;
+    for (int d = 0; d < m; ++d) G[d] = 0;
+    for (int h0 = 0; h0 < pr->N; ++h0) {
+        const region_t *g0 = &pr->r[h0];
+        const uint32_t id = (uint32_t)(h0 + 1);
+        words_t w;
+        words_init(&w, q->seed, (uint32_t)ti, group, OR_NAIVE_TAG | id, 0);
+        double y[OR_MAX_DIM];
+        int seg = 0, att, nb = (surf_words(g0, m) + 3) / 4;
+        for (att = 0; att < OR_MAX_ATTEMPTS; ++att) {
+            words_seek(&w, (uint32_t)(att * nb));
+            if (surf_attempt(g0, m, &w, y, &seg)) break;
+            cnt->rejections++;
+        }
+        if (att == OR_MAX_ATTEMPTS) cnt->cap_hits++;
+        naive_node(pr, x, q, (uint32_t)ti, group, 0, h0, id, y, seg, beta_at(pr, h0, y, seg) * g0->area, 1.0, 1.0,
+                   F, G, cnt);
     }
 }
 
@@ -960,21 +1035,29 @@ typedef struct {
 
 static uint32_t group_of(const job_t *j, int64_t p, int B) { return j->groups ? j->groups[p] : (uint32_t)(p / B); }
 
-static uint64_t n_samples_of(const or_query *q) { return q->estimator ? q->walks / 2 : q->walks; }
-static uint64_t first_sample(const or_query *q) { return q->estimator ? q->walk_offset / 2 : q->walk_offset; }
+static uint64_t n_samples_of(const or_query *q) { return q->estimator == 1 ? q->walks / 2 : q->walks; }
+static uint64_t first_sample(const or_query *q) { return q->estimator == 1 ? q->walk_offset / 2 : q->walk_offset; }
+
+/* one observation: walker values (K = 2 for VR) or, for the naive estimator, one tree's value */
+static void observation(const or_problem *pr, const double *x, const or_query *q, uint64_t s, uint32_t group,
+                        double *Fk, double *Gk, uint32_t *trk, or_counters *cnt)
+{
+    if (q->estimator == 2) naive_tree(pr, x, q, s, group, Fk, Gk, cnt);
+    else one_sample(pr, x, q, s, group, Fk, Gk, trk, cnt);
+}
 
 static void *trace_job(void *arg)
 {
     job_t *j = arg;
     const or_problem *pr = j->pr;
-    int m = pr->m, K = j->q->estimator ? 2 : 1, M = j->q->M;
+    int m = pr->m, K = j->q->estimator == 1 ? 2 : 1, M = j->q->M;
     int B = j->q->batch_share > 0 ? j->q->batch_share : 1;
     for (int64_t p = j->p0; p < j->p1; ++p)
         for (uint64_t s = 0; s < j->n; ++s) {
             size_t idx = (size_t)p * j->n + s;
             double Fk[2], Gk[2 * OR_MAX_DIM];
-            one_sample(pr, j->x + p * m, j->q, first_sample(j->q) + s, group_of(j, p, B), Fk, Gk,
-                       j->trace ? j->trace + idx * K * (M + 1) : NULL, &j->cnt);
+            observation(pr, j->x + p * m, j->q, first_sample(j->q) + s, group_of(j, p, B), Fk, Gk,
+                        j->trace ? j->trace + idx * K * (M + 1) : NULL, &j->cnt);
             for (int k = 0; k < K; ++k) {
                 j->F[idx * K + k] = Fk[k];
                 if (j->G) for (int d = 0; d < m; ++d) j->G[(idx * K + k) * m + d] = Gk[k * m + d];
@@ -987,14 +1070,14 @@ static void *estimate_job(void *arg)
 {
     job_t *j = arg;
     const or_problem *pr = j->pr;
-    int m = pr->m, K = j->q->estimator ? 2 : 1;
+    int m = pr->m, K = j->q->estimator == 1 ? 2 : 1;
     int B = j->q->batch_share > 0 ? j->q->batch_share : 1;
     uint64_t n = n_samples_of(j->q);
     for (int64_t p = j->p0; p < j->p1; ++p) {
         double mu = 0, m2 = 0, gmu[OR_MAX_DIM] = {0}, gm2[OR_MAX_DIM] = {0};
         for (uint64_t s = 0; s < n; ++s) {
             double Fk[2], Gk[2 * OR_MAX_DIM];
-            one_sample(pr, j->x + p * m, j->q, first_sample(j->q) + s, group_of(j, p, B), Fk, Gk, NULL, &j->cnt);
+            observation(pr, j->x + p * m, j->q, first_sample(j->q) + s, group_of(j, p, B), Fk, Gk, NULL, &j->cnt);
             double f = 0, g[OR_MAX_DIM] = {0};
             for (int k = 0; k < K; ++k) { f += Fk[k]; for (int d = 0; d < m; ++d) g[d] += Gk[k * m + d]; }
             /* Welford, as in Alg. 1 */
@@ -1014,8 +1097,12 @@ static void *estimate_job(void *arg)
 
 static int check_query(const or_problem *pr, const or_query *q)
 {
-    if (!q || q->M < 0 || q->M > OR_MAX_M || q->walks == 0 || q->estimator < 0 || q->estimator > 1) return OR_EINVAL;
-    if (q->estimator && (!pr->vr_ok || (q->walks & 1) || (q->walk_offset & 1))) return pr->vr_ok ? OR_EINVAL : OR_EUNSUP;
+    if (!q || q->M < 0 || q->M > OR_MAX_M || q->walks == 0 || q->estimator < 0 || q->estimator > 2) return OR_EINVAL;
+    if (q->estimator == 1 && (!pr->vr_ok || (q->walks & 1) || (q->walk_offset & 1))) return pr->vr_ok ? OR_EINVAL : OR_EUNSUP;
+    if (q->estimator == 2) {   /* node ids (N+1)^(M+1) below 2^31; no instance; one tree stream per point */
+        double ids = pow(pr->N + 1.0, q->M + 1.0);
+        if (ids > 2147483648.0 || q->instance != 0 || q->batch_share > 1) return OR_EINVAL;
+    }
     return OR_OK;
 }
 

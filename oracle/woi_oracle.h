@@ -11,6 +11,7 @@
  *   alpha_i, beta_i    Sec. 3, Eq. (unit_coeff_charge_density_sys)
  *   transition pdfs    Sec. 4.2.1, Eqs. (naive_woi_p0), (naive_woi_p)
  *   Q / T factors      Sec. 4.2.2, Eqs. (naive_woi_Q), (naive_woi_T)
+ *   naive estimator    Sec. 4.2.2-4.2.4, Eq. (naive_woi_estimator): Markov trees
  *   schedules          Sec. 4.3.1, Theorem 2, Eq. (scheduled_interface_pdf)
  *   estimator          Eq. (woi_estimator), Algorithms 1 and 2
  *   variance reduction Sec. 4.4, Eq. (variance_reduced_woi_estimator), Alg. 3
@@ -64,7 +65,9 @@ typedef struct {
     uint64_t walks;        /* walkers per point; VR uses walks/2 two-walker samples  */
     uint64_t walk_offset;  /* first walker index (even for VR)                         */
     int M;                 /* truncation: steps 0..M                                  */
-    int estimator;         /* 0 plain (Alg. 2), 1 variance reduced (Alg. 3)           */
+    int estimator;         /* 0 plain (Alg. 2), 1 variance reduced (Alg. 3), 2 naive
+                              Markov trees (Sec. 4.2; walks = trees, instance 0,
+                              batch_share 1, (N+1)^(M+1) <= 2^31)                     */
     int schedule_mode;     /* 0: schedule keyed by (walk, point group), 1: by walk    */
     int batch_share;       /* B >= 1: points p with equal p/B share trajectories      */
     uint32_t instance;     /* instance id (< 2^24) mixed into every counter           */

@@ -286,6 +286,72 @@ def test_vr_same_mean_as_plain_on_star_tree(oracle_mod):
     assert np.max(np.abs(_z(mean, u, se))) < ZMAX
 
 
+# ----------------------------------------------------------------------------- naive Markov trees
+# The naive estimator (Sec. 4.2, Eq. naive_woi_estimator) sums every interface tuple over an
+# N-ary Markov tree instead of scheduling one (Theorem 2): same expectation as WoI, so the same
+# exact u_M; its cost per tree is the tree size sum_{i=0}^{M} N^{i+1} interface points (the
+# paper counts the root x as well).
+def _tree_nodes(N, M):
+    return sum(N ** (i + 1) for i in range(M + 1))
+
+
+@pytest.mark.parametrize("M", [0, 1, 3])
+def test_naive_concentric_disk_exact_expectation(oracle_mod, M):
+    p, xs = W.concentric_disk_2d()
+    op = oracle_mod.OracleProblem(p)
+    pts = xs[::5]
+    T = 40000
+    mean, se, g, gse, cnt = oracle_mod.estimate(op, pts, T, M, seed=20 + M, estimator=oracle_mod.NAIVE)
+    H, gH = CF.harmonic_2d(1, "cos")
+    ref = [CF.concentric_uM(*CFG1, 1, 2, M, x, H, gH) for x in pts]
+    z = _z(mean, [r[0] for r in ref], se)
+    zg = _z(g, np.array([r[1] for r in ref]), gse)
+    assert np.max(np.abs(z)) < ZMAX and np.max(np.abs(zg)) < ZMAX
+    assert 0.3 < np.mean(np.concatenate([z, zg.ravel()]) ** 2) < 2.0
+    assert cnt["cap_hits"] == 0
+    assert cnt["walk_steps"] == len(pts) * T * _tree_nodes(2, M)
+
+
+def test_naive_sphere_3d_exact_expectation(oracle_mod):
+    p = W.zheng_ex3_3d()
+    op = oracle_mod.OracleProblem(p)
+    pts = np.array([[0.2, 0.1, -0.1], [0.5, -0.3, 0.2], [-0.1, 0.7, 0.1], [0.05, -0.2, 0.33], [0, 0, 0.9]])
+    Hx, gx = CF.harmonic_x1(3)
+    mean, se, g, gse, _ = oracle_mod.estimate(op, pts, 40000, 2, seed=21, estimator=oracle_mod.NAIVE)
+    ref = [CF.concentric_uM([1, .4], [1, .5], [5, 0], 1, 3, 2, x, Hx, gx) for x in pts]
+    assert np.max(np.abs(_z(mean, [r[0] for r in ref], se))) < ZMAX
+    assert np.max(np.abs(_z(g, np.array([r[1] for r in ref]), gse))) < ZMAX
+
+
+def test_naive_star_tree_matches_nystrom(oracle_mod):
+    """Polyline lines/rays with q > 1 hits, sibling and nested regions (N = 4)."""
+    p, curves, bf = _star_tree()
+    op = oracle_mod.OracleProblem(p)
+    u, gu = CF.nystrom_uM(curves, p.parent, p.sigma, bf, 2, STAR_PTS)
+    mean, se, g, gse, cnt = oracle_mod.estimate(op, STAR_PTS, 20000, 2, seed=22, estimator=oracle_mod.NAIVE)
+    assert np.max(np.abs(_z(mean, u, se))) < ZMAX
+    assert np.max(np.abs(_z(g, gu, gse))) < ZMAX
+    assert cnt["walk_steps"] == len(STAR_PTS) * 20000 * _tree_nodes(4, 2)
+
+
+def test_naive_trace_matches_estimate_and_rejects_bad_queries(oracle_mod):
+    p, xs = W.concentric_disk_2d()
+    op = oracle_mod.OracleProblem(p)
+    pts = xs[:3]
+    F, G, T = oracle_mod.trace(op, pts, 2000, 2, seed=4, estimator=oracle_mod.NAIVE)
+    mean, se, g, _, _ = oracle_mod.estimate(op, pts, 2000, 2, seed=4, estimator=oracle_mod.NAIVE)
+    assert F.shape == (3, 2000, 1) and not T.any()
+    assert np.allclose(F[:, :, 0].mean(1), mean, rtol=1e-12, atol=1e-15)
+    assert np.allclose(G[:, :, 0].mean(1), g, rtol=1e-12, atol=1e-15)
+    F2, _, _ = oracle_mod.trace(op, pts, 500, 2, seed=4, estimator=oracle_mod.NAIVE, walk_offset=1500)
+    assert np.array_equal(F2, F[:, 1500:])
+    for kw in ({"instance": 1}, {"batch_share": 2}):
+        with pytest.raises(ValueError):
+            oracle_mod.estimate(op, pts, 10, 2, estimator=oracle_mod.NAIVE, **kw)
+    with pytest.raises(ValueError):   # node ids (N + 1)^(M + 1) = 3^20 exceed 2^31
+        oracle_mod.estimate(op, pts, 10, 19, estimator=oracle_mod.NAIVE)
+
+
 # ----------------------------------------------------------------------------- statistics
 def test_standard_error_calibration_and_rate(oracle_mod):
     p, xs = W.concentric_disk_2d()
@@ -330,7 +396,7 @@ def test_shared_trajectories_batch(oracle_mod):
 
 
 # ----------------------------------------------------------------------------- planted mistakes
-@pytest.mark.parametrize("plant", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("plant", [1, 2, 3, 4, 5, 6])
 def test_pins_reject_planted_mistakes(oracle_mod, tmp_path, plant):
     """Each plausible mistake, planted in a copy of the oracle, fails one of the pins above."""
     libv = oracle_mod.load(oracle_mod.build_variant(plant, str(tmp_path)))
@@ -340,6 +406,14 @@ def test_pins_reject_planted_mistakes(oracle_mod, tmp_path, plant):
         u, gu = CF.nystrom_uM(curves, p.parent, p.sigma, bf, 1, NC_PTS)
         mean, se, g, gse, _ = oracle_mod.estimate(op, NC_PTS, 100000, 1, seed=4)
         z = np.concatenate([_z(mean, u, se), _z(g, gu, gse).ravel()])
+    elif plant == 6:  # |alpha| in the naive tree weights (alpha_2 < 0 here)
+        p, xs = W.concentric_disk_2d()
+        op = oracle_mod.OracleProblem(p, library=libv)
+        pts = xs[::6]
+        H, gH = CF.harmonic_2d(1, "cos")
+        ref = [CF.concentric_uM(*CFG1, 1, 2, 1, x, H, gH)[0] for x in pts]
+        mean, se, _, _, _ = oracle_mod.estimate(op, pts, 100000, 1, seed=4, estimator=oracle_mod.NAIVE)
+        z = _z(mean, ref, se)
     elif plant == 4:  # normal at the wrong end of K* matters for the "other" transition
         p = W.concentric(2, [1.0, 0.5], [1.0, 3.0], [W.fourier([0, 0], 0, [0.5], [1.0]), W.fourier([0, 0], 0, [1.0], [0.0])])
         op = oracle_mod.OracleProblem(p, library=libv)
