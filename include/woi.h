@@ -136,7 +136,15 @@ typedef struct {
 } woi_problem_info;
 woi_status woi_problem_get_info(const woi_problem *p, woi_problem_info *out);
 
-typedef enum { WOI_EST_PLAIN = 0, WOI_EST_VR = 1 } woi_estimator;      /* Alg. 2 / Alg. 3 */
+/* PLAIN: Alg. 2; VR: Alg. 3; NAIVE: the naive estimator of Sec. 4.2 (Eq. naive_woi_estimator),
+ * one observation per Markov tree: every interface tuple (h_0..h_i), i <= M, of the tree is
+ * summed with weight w_i prod_{m=1}^{i} alpha_{h_m} instead of being scheduled (Theorem 2 gives
+ * both the same expectation).  A tree has sum_{i=0}^{M} N^{i+1} interface points, drawn with the
+ * transitions of Eq. naive_woi_p; node (h_0..h_i) draws from its own counter, so a branch is
+ * reused by all its extensions.  For NAIVE, walks = trees per point (walk_offset = first tree);
+ * it requires FP64, batch_share = 1 and instance = 0 (WOI_E_UNSUPPORTED otherwise) and
+ * (N + 1)^(M + 1) <= 2^31 (WOI_E_INVALID_ARG); schedule_mode and block_size are ignored. */
+typedef enum { WOI_EST_PLAIN = 0, WOI_EST_VR = 1, WOI_EST_NAIVE = 2 } woi_estimator;
 typedef enum { WOI_PREC_FP64 = 0, WOI_PREC_FP32 = 1 } woi_precision;
 typedef enum { WOI_SCHED_PER_GROUP = 0, WOI_SCHED_SHARED = 1 } woi_schedule_mode;
 
@@ -177,7 +185,8 @@ woi_status woi_estimate(const woi_problem *p, const double *points, int64_t P, c
                         void *workspace, size_t workspace_bytes, uint64_t *counters, void *stream);
 
 /* Per-sample values for parity checks: samples [walk_offset, walk_offset + n_samples) of
- * every point.  F[(p*n + j)*K + k] = N * (walker k's sum), K = 1 (plain) or 2 (VR);
+ * every point.  F[(p*n + j)*K + k] = N * (walker k's sum), K = 1 (plain) or 2 (VR); for NAIVE,
+ * F[p*n + j] = tree j's value and trace must be NULL (WOI_E_INVALID_ARG otherwise);
  * G[((p*n + j)*K + k)*dim + d]; trace[((p*n + j)*K + k)*(M+1) + i] = decision word
  * (bits 0-5 region, 6-7 case 0 first/1 same/2 descendant/3 other, 8-15 q,
  * 16-23 pick, 24 negative sign, 25-31 attempts).  All device pointers; G, trace may be NULL. */

@@ -84,6 +84,8 @@ woi_status validate(const woi_batch_item* items, int n, Spec& sp) {
         if (!it.points || !it.mean || !it.se) return set_error(WOI_E_INVALID_ARG, "item %d: NULL points/mean/se", i);
         if (it.query.batch_share != 1)
             return set_error(WOI_E_UNSUPPORTED, "item %d: batched estimation needs batch_share = 1", i);
+        if (it.query.estimator == WOI_EST_NAIVE)
+            return set_error(WOI_E_UNSUPPORTED, "item %d: batched estimation does not take the naive estimator", i);
         if (woi::problem_has_mesh(it.problem))
             return set_error(WOI_E_UNSUPPORTED, "item %d: batched estimation does not take triangle meshes", i);
         const bool vr = it.query.estimator == WOI_EST_VR, f32 = it.query.precision == WOI_PREC_FP32;

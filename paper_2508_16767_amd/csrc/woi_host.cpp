@@ -1254,7 +1254,8 @@ woi_status check_query_impl(const woi_problem* p, int64_t P, const woi_query* q)
     if (P < 1) return fail(WOI_E_INVALID_ARG, "P = %lld must be >= 1", (long long)P);
     if (q->M < 0 || q->M > WOI_MAX_M) return fail(WOI_E_INVALID_ARG, "M = %d outside [0, %d]", q->M, WOI_MAX_M);
     if (q->walks < 1) return fail(WOI_E_INVALID_ARG, "walks must be >= 1");
-    if (q->estimator != WOI_EST_PLAIN && q->estimator != WOI_EST_VR) return fail(WOI_E_INVALID_ARG, "bad estimator");
+    if (q->estimator != WOI_EST_PLAIN && q->estimator != WOI_EST_VR && q->estimator != WOI_EST_NAIVE)
+        return fail(WOI_E_INVALID_ARG, "bad estimator");
     if (q->precision != WOI_PREC_FP64 && q->precision != WOI_PREC_FP32) return fail(WOI_E_INVALID_ARG, "bad precision");
     if (q->estimator == WOI_EST_VR) {
         if (p->H.m > 3) return fail(WOI_E_UNSUPPORTED, "variance reduction needs dim <= 3");
@@ -1264,6 +1265,14 @@ woi_status check_query_impl(const woi_problem* p, int64_t P, const woi_query* q)
         if ((q->walks & 1) || (q->walk_offset & 1)) return fail(WOI_E_INVALID_ARG, "VR needs even walks and walk_offset");
     }
     if (q->batch_share < 1) return fail(WOI_E_INVALID_ARG, "batch_share must be >= 1");
+    if (q->estimator == WOI_EST_NAIVE) {
+        if (q->precision != WOI_PREC_FP64) return fail(WOI_E_UNSUPPORTED, "the naive estimator runs in FP64 only");
+        if (q->batch_share != 1) return fail(WOI_E_UNSUPPORTED, "the naive estimator needs batch_share = 1");
+        if (q->instance != 0) return fail(WOI_E_UNSUPPORTED, "the naive estimator needs instance = 0");
+        if (std::pow(p->H.N + 1.0, q->M + 1.0) > 2147483648.0)
+            return fail(WOI_E_INVALID_ARG, "naive estimator: (N + 1)^(M + 1) = %.3g exceeds 2^31 tree-node ids",
+                        std::pow(p->H.N + 1.0, q->M + 1.0));
+    }
     if (q->instance >= (1u << 24)) return fail(WOI_E_INVALID_ARG, "instance must be < 2^24");
     const uint64_t ns = q->estimator == WOI_EST_VR ? q->walks / 2 : q->walks;
     const uint64_t first = q->estimator == WOI_EST_VR ? q->walk_offset / 2 : q->walk_offset;
@@ -1348,6 +1357,85 @@ SharedPlan make_shared_plan(const woi_problem* p, int64_t P, const woi_query* q,
     return sp;
 }
 
+// Naive estimator: one wave per (point, chunk of trees); about 2^14 waves in flight.
+struct NaivePlan {
+    unsigned gx;
+    uint32_t spt;
+    int chunks;
+    woi::NParams np;
+};
+
+NaivePlan make_naive_plan(const woi_problem* p, int64_t P, const woi_query* q, uint64_t n_trees) {
+    NaivePlan pl;
+    pl.gx = (unsigned)((P + 3) / 4);
+    uint64_t span = 1;
+    for (int i = 0; i < q->M; ++i) span *= (uint64_t)p->H.N;
+    pl.np.span0 = (uint32_t)span;
+    pl.np.leaves = (uint32_t)(span * (uint64_t)p->H.N);
+    uint64_t spt;
+    if (q->samples_per_thread > 0) spt = (uint64_t)q->samples_per_thread;
+    else {
+        const uint64_t chunks = std::max<uint64_t>(1, ((1u << 14) + (uint64_t)P - 1) / (uint64_t)P);
+        spt = (n_trees + chunks - 1) / chunks;
+    }
+    spt = std::max<uint64_t>(1, std::min<uint64_t>(spt, n_trees));
+    uint64_t chunks = (n_trees + spt - 1) / spt;
+    while (chunks > 65535) { spt *= 2; chunks = (n_trees + spt - 1) / spt; }
+    pl.spt = (uint32_t)spt;
+    pl.chunks = (int)chunks;
+    return pl;
+}
+
+woi::KParams naive_params(const woi_problem* p, const double* points, int64_t P, const woi_query* q,
+                          uint64_t n_trees, const NaivePlan& pl) {
+    woi::KParams kp{};
+    kp.dp = static_cast<const DevProblem*>(p->dev);
+    kp.points = points;
+    kp.P = P;
+    kp.n_samples = n_trees;
+    kp.first_sample = q->walk_offset;
+    kp.samples_per_thread = pl.spt;
+    kp.k0 = (uint32_t)q->seed;
+    kp.k1 = (uint32_t)(q->seed >> 32);
+    kp.M = q->M;
+    kp.batch_share = 1;
+    kp.mesh = has_mesh(p->H) ? 1 : 0;
+    return kp;
+}
+
+woi_status estimate_naive(const woi_problem* p, const double* points, int64_t P, const woi_query* q, double* mean,
+                          double* se, double* grad, double* grad_se, void* workspace, size_t workspace_bytes,
+                          uint64_t* counters, hipStream_t s) {
+    const NaivePlan pl = make_naive_plan(p, P, q, q->walks);
+    const size_t need = (size_t)pl.chunks * (size_t)P * (2 + 2 * p->H.m) * sizeof(double);
+    if (!workspace || workspace_bytes < need)
+        return fail(WOI_E_OOM, "workspace of %zu bytes is smaller than the %zu bytes needed", workspace_bytes, need);
+    woi::KParams kp = naive_params(p, points, P, q, q->walks, pl);
+    kp.partials = static_cast<double*>(workspace);
+    kp.counters = counters;
+    if (q->event_begin && hipEventRecord(static_cast<hipEvent_t>(q->event_begin), s) != hipSuccess)
+        return fail(WOI_E_DEVICE, "hipEventRecord(begin) failed");
+    hipError_t e = woi::launch_naive(kp, pl.np, p->H.m, dim3(pl.gx, pl.chunks), s);
+    if (e != hipSuccess) return fail(WOI_E_DEVICE, "naive launch failed: %s", hipGetErrorString(e));
+    if (q->event_end && hipEventRecord(static_cast<hipEvent_t>(q->event_end), s) != hipSuccess)
+        return fail(WOI_E_DEVICE, "hipEventRecord(end) failed");
+    woi::RParams rp{};
+    rp.partials = kp.partials;
+    rp.P = P;
+    rp.dim = p->H.m;
+    rp.n_chunks = pl.chunks;
+    rp.samples_per_thread = pl.spt;
+    rp.full = 0;
+    rp.tail = q->walks;
+    rp.mean = mean;
+    rp.se = se;
+    rp.grad = grad;
+    rp.grad_se = grad_se;
+    e = woi::launch_reduce(rp, s);
+    if (e != hipSuccess) return fail(WOI_E_DEVICE, "reduce launch failed: %s", hipGetErrorString(e));
+    return WOI_OK;
+}
+
 // Shared trajectories: per chunk, generate the trajectories of every point group, then
 // evaluate them at the group's points; finally the deterministic per-point reduction.
 woi_status estimate_shared(const woi_problem* p, const double* points, int64_t P, const woi_query* q, uint64_t ns,
@@ -1421,6 +1509,11 @@ woi_status woi_workspace_size(const woi_problem* p, int64_t P, const woi_query* 
     if (st != WOI_OK) return st;
     if (!bytes) return fail(WOI_E_INVALID_ARG, "NULL bytes");
     const uint64_t ns = q->estimator == WOI_EST_VR ? q->walks / 2 : q->walks;
+    if (q->estimator == WOI_EST_NAIVE) {
+        const NaivePlan pl = make_naive_plan(p, P, q, ns);
+        *bytes = (size_t)pl.chunks * (size_t)P * (2 + 2 * p->H.m) * sizeof(double);
+        return WOI_OK;
+    }
     if (q->batch_share > 1) {
         const SharedPlan sp = make_shared_plan(p, P, q, ns);
         *bytes = sp.traj_bytes + sp.part_bytes;
@@ -1440,6 +1533,9 @@ woi_status woi_estimate(const woi_problem* p, const double* points, int64_t P, c
     st = woi_problem_upload(const_cast<woi_problem*>(p));
     if (st != WOI_OK) return st;
     const uint64_t ns = q->estimator == WOI_EST_VR ? q->walks / 2 : q->walks;
+    if (q->estimator == WOI_EST_NAIVE)
+        return estimate_naive(p, points, P, q, mean, se, grad, grad_se, workspace, workspace_bytes, counters,
+                              static_cast<hipStream_t>(stream));
     if (q->batch_share > 1)
         return estimate_shared(p, points, P, q, ns, mean, se, grad, grad_se, workspace, workspace_bytes, counters,
                                static_cast<hipStream_t>(stream));
@@ -1497,6 +1593,16 @@ woi_status woi_trace(const woi_problem* p, const double* points, int64_t P, cons
     if (!points || !F) return fail(WOI_E_INVALID_ARG, "NULL points or F");
     st = woi_problem_upload(const_cast<woi_problem*>(p));
     if (st != WOI_OK) return st;
+    if (q->estimator == WOI_EST_NAIVE) {
+        if (trace) return fail(WOI_E_INVALID_ARG, "naive trees have no decision words: pass trace = NULL");
+        const NaivePlan pl = make_naive_plan(p, P, &qq, n_samples);
+        woi::KParams kp = naive_params(p, points, P, &qq, n_samples, pl);
+        kp.traceF = F;
+        kp.traceG = G;
+        hipError_t e = woi::launch_naive(kp, pl.np, p->H.m, dim3(pl.gx, pl.chunks), static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) return fail(WOI_E_DEVICE, "naive launch failed: %s", hipGetErrorString(e));
+        return WOI_OK;
+    }
     const Plan pl = make_plan(p, P, &qq, n_samples);
     woi::KParams kp{};
     kp.dp = static_cast<const DevProblem*>(p->dev);

@@ -793,6 +793,86 @@ __device__ __forceinline__ uint32_t trace_word(int h, int cs, int q, int pick, i
            ((uint32_t)(neg ? 1 : 0) << 24) | ((uint32_t)att << 25);
 }
 
+// One transition from y (on the previous interface; segment or triangle seg) onto interface
+// g (the three cases of Eq. naive_woi_p): uniform on dOmega_g with Q *= |K*(y_i, y_{i-1})|
+// |dOmega_g| ("other"), or the isotropic line (same interface, Q *= 1/2) or ray (descendant to
+// ancestor) with a uniform pick among its q hits.  Returns T's factor
+// q sign((y_i - y_{i-1}) . n(y_i)) (Eq. naive_woi_T), or 0 when no line or ray hit turned up
+// within WOI_ATTEMPT_CAP draws (the walk stops there).  Draws come from st at `step`.
+template <typename R, int D, bool LDS>
+__device__ __forceinline__ R transition(const DevProblem* __restrict__ dp, const R* __restrict__ pay,
+                                        const DevRegion* g, int rel, const Stream& st, uint32_t step,
+                                        const R y[D], int seg, R yn[D], int& segn, R& Q, int& qn, int& pick,
+                                        int& att, Counts& cnt) {
+    R nn[D];
+    segn = 0; qn = 1; pick = 0;
+    if (rel == REL_OTHER) {
+        cnt.other++;
+        for (att = 0; att < WOI_ATTEMPT_CAP; ++att) {
+            if (surf_attempt<R, D, LDS>(dp, *g, pay, st, step, att, yn, segn)) break;
+            cnt.rejections++;
+        }
+        if (att == WOI_ATTEMPT_CAP) cnt.caps++;
+        normal_at<R, D, LDS>(*g, pay, yn, segn, nn);
+        R dn = 0, r2 = 0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) { const R e = yn[j] - y[j]; dn += e * nn[j]; r2 += e * e; }
+        R rm = R(1);
+#pragma unroll
+        for (int j = 0; j < D / 2; ++j) rm *= r2;
+        if constexpr (D % 2) rm *= RO<R>::sq(r2);
+        Q *= fabs(RO<R>::div(dn, Pay<R>::ua(dp) * rm)) * Pay<R>::area(*g);
+    } else {
+        const bool ray = rel == REL_DESC;
+        constexpr int NW = dir_words(D) + 1, NB = (NW + 3) / 4;
+        bool found = false;
+        for (att = 0; att < WOI_ATTEMPT_CAP; ++att) {
+            Words<NW> W; W.fill(st, step, (uint32_t)(att * NB));
+            R d[D];
+            unit_dir<R, D>(W, d);
+            const R up = RO<R>::u(W.w[NW - 1]);
+            if (g->kind == WOI_SHAPE_POLYLINE2D) {
+                if constexpr (D == 2) {
+                    int j = 0;
+                    qn = poly_pick<R, LDS>(dp, *g, pay, y, d, ray, seg, up, pick, j, cnt);
+                    if (qn == 0) { cnt.redraws++; continue; }
+                    const R* v = poly_xy<R, LDS>(*g, pay) + 2 * j;
+                    const R ex = v[2] - v[0], ey = v[3] - v[1];
+                    const R den = d[0] * ey - d[1] * ex;
+                    const R s = RO<R>::div((v[0] - y[0]) * d[1] - (v[1] - y[1]) * d[0], den);
+                    yn[0] = v[0] + s * ex; yn[1] = v[1] + s * ey; segn = j;
+                }
+            } else if (D == 3 && LDS && g->kind == WOI_SHAPE_MESH3D) {
+                if constexpr (D == 3) {
+                    R t = 0;
+                    int j = 0;
+                    qn = mesh_pick<R>(dp, *g, pay, y, d, ray, seg, up, pick, t, j, cnt);
+                    if (qn == 0) { cnt.redraws++; continue; }
+#pragma unroll
+                    for (int k = 0; k < D; ++k) yn[k] = y[k] + t * d[k];
+                    segn = j;
+                }
+            } else {
+                R t;
+                qn = quadric_hit<R, D>(*g, pay, y, d, ray, t);
+                if (qn == 0) { cnt.redraws++; continue; }
+                pick = 0;
+#pragma unroll
+                for (int j = 0; j < D; ++j) yn[j] = y[j] + t * d[j];
+            }
+            found = true;
+            break;
+        }
+        if (!found) { cnt.caps++; return R(0); }
+        if (!ray) Q *= R(0.5);
+        normal_at<R, D, LDS>(*g, pay, yn, segn, nn);
+    }
+    R dn = 0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) dn += (yn[j] - y[j]) * nn[j];
+    return dn < R(0) ? -(R)qn : (R)qn;
+}
+
 // ----------------------------------------------------------------------------- one sample
 // Where a walker's terms c_i (y_i) go: accumulated at the lane's point, or stored as a
 // trajectory for evaluation at a batch of points (shared trajectories, Sec. 4.6).
@@ -965,87 +1045,21 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
         g = &dp->reg[h];
         S *= Pay<R>::sgn(*g);
         pw *= l1;
-        R yn[D], nn[D];
+        R yn[D];
         int segn = 0, qn = 1, pick = 0;
-        if (rel == REL_OTHER) {
-            // y_i uniform on dOmega_{h_i}: Q *= |K*(y_i, y_{i-1})| |dOmega_{h_i}|
-            cnt.other++;
-            for (att = 0; att < WOI_ATTEMPT_CAP; ++att) {
-                if (surf_attempt<R, D, LDS>(dp, *g, pay, st, (uint32_t)i, att, yn, segn)) break;
-                cnt.rejections++;
-            }
-            if (att == WOI_ATTEMPT_CAP) cnt.caps++;
-            normal_at<R, D, LDS>(*g, pay, yn, segn, nn);
-            R dn = 0, r2 = 0;
-#pragma unroll
-            for (int j = 0; j < D; ++j) { const R e = yn[j] - y[j]; dn += e * nn[j]; r2 += e * e; }
-            R rm = R(1);
-#pragma unroll
-            for (int j = 0; j < D / 2; ++j) rm *= r2;
-            if constexpr (D % 2) rm *= RO<R>::sq(r2);
-            Q *= fabs(RO<R>::div(dn, Pay<R>::ua(dp) * rm)) * Pay<R>::area(*g);
-        } else {
-            // isotropic line (same interface) or ray (descendant to ancestor); uniform pick among q hits
-            const bool ray = rel == REL_DESC;
-            constexpr int NW = dir_words(D) + 1, NB = (NW + 3) / 4;
-            bool found = false;
-            for (att = 0; att < WOI_ATTEMPT_CAP; ++att) {
-                Words<NW> W; W.fill(st, (uint32_t)i, (uint32_t)(att * NB));
-                R d[D];
-                unit_dir<R, D>(W, d);
-                const R up = RO<R>::u(W.w[NW - 1]);
-                if (g->kind == WOI_SHAPE_POLYLINE2D) {
-                    if constexpr (D == 2) {
-                        int j = 0;
-                        qn = poly_pick<R, LDS>(dp, *g, pay, y, d, ray, seg, up, pick, j, cnt);
-                        if (qn == 0) { cnt.redraws++; continue; }
-                        const R* v = poly_xy<R, LDS>(*g, pay) + 2 * j;
-                        const R ex = v[2] - v[0], ey = v[3] - v[1];
-                        const R den = d[0] * ey - d[1] * ex;
-                        const R s = RO<R>::div((v[0] - y[0]) * d[1] - (v[1] - y[1]) * d[0], den);
-                        yn[0] = v[0] + s * ex; yn[1] = v[1] + s * ey; segn = j;
-                    }
-                } else if (D == 3 && LDS && g->kind == WOI_SHAPE_MESH3D) {
-                    if constexpr (D == 3) {
-                        R t = 0;
-                        int j = 0;
-                        qn = mesh_pick<R>(dp, *g, pay, y, d, ray, seg, up, pick, t, j, cnt);
-                        if (qn == 0) { cnt.redraws++; continue; }
-#pragma unroll
-                        for (int k = 0; k < D; ++k) yn[k] = y[k] + t * d[k];
-                        segn = j;
-                    }
-                } else {
-                    R t;
-                    qn = quadric_hit<R, D>(*g, pay, y, d, ray, t);
-                    if (qn == 0) { cnt.redraws++; continue; }
-                    pick = 0;
-#pragma unroll
-                    for (int j = 0; j < D; ++j) yn[j] = y[j] + t * d[j];
-                }
-                found = true;
-                break;
-            }
-            if (!found) {   // no hit after the attempt cap: the walker stops here
-                cnt.caps++;
-                if (tr) for (int j = i; j <= M; ++j) tr[j] = trace_word(h, rel, 0, 0, 0, att);
-                break;
-            }
-            if (!ray) Q *= R(0.5);
-            normal_at<R, D, LDS>(*g, pay, yn, segn, nn);
+        const R tf = transition<R, D, LDS>(dp, pay, g, rel, st, (uint32_t)i, y, seg, yn, segn, Q, qn, pick, att, cnt);
+        if (tf == R(0)) {   // no hit after the attempt cap: the walker stops here
+            if (tr) for (int j = i; j <= M; ++j) tr[j] = trace_word(h, rel, 0, 0, 0, att);
+            break;
         }
-        R dn = 0;
-#pragma unroll
-        for (int j = 0; j < D; ++j) dn += (yn[j] - y[j]) * nn[j];
-        const R sg = dn < R(0) ? R(-1) : R(1);
-        T *= (R)qn * sg;
+        T *= tf;
 #pragma unroll
         for (int j = 0; j < D; ++j) y[j] = yn[j];
         seg = segn;
         sink.add(i, (i == M ? R(0.5) : R(1)) * pw * S * Q * T, y, cnt);
         cnt.steps++;
         done = i + 1;
-        if (tr) tr[i] = trace_word(h, rel, qn, pick, sg < R(0), att);
+        if (tr) tr[i] = trace_word(h, rel, qn, pick, tf < R(0), att);
     }
     sink.finish(done);
 }

@@ -17,7 +17,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libwoi.so")
 
 MAX_DIM, MAX_REGIONS, MAX_M, N_COUNTERS = 8, 32, 32, 8
-PLAIN, VR = 0, 1
+PLAIN, VR, NAIVE = 0, 1, 2   # estimators: Alg. 2, Alg. 3, naive Markov trees (Sec. 4.2)
 FP64, FP32 = 0, 1
 SCHED_PER_GROUP, SCHED_SHARED = 0, 1
 COUNTER_NAMES = ("walker_steps", "redraws", "rejections", "cap_hits", "zero_distance", "node_tests",
@@ -238,7 +238,8 @@ def estimate(problem, points, walks, M, seed=0, estimator=PLAIN, precision=FP64,
 
 def trace(problem, points, n_samples, M, seed=0, estimator=PLAIN, precision=FP64, schedule_mode=SCHED_PER_GROUP,
           batch_share=1, walk_offset=0, instance=0):
-    """Per-walker values F[P, n, K], gradients G[P, n, K, dim] and decision words T[P, n, K, M+1]."""
+    """Per-walker values F[P, n, K], gradients G[P, n, K, dim] and decision words T[P, n, K, M+1].
+    For the naive estimator: one value per tree (K = 1) and no decision words (T is None)."""
     x = _points(points, problem.dim)
     P = x.shape[0]
     K = 2 if estimator == VR else 1
@@ -247,8 +248,11 @@ def trace(problem, points, n_samples, M, seed=0, estimator=PLAIN, precision=FP64
     T = torch.zeros(P, n_samples, K, M + 1, dtype=torch.int32, device=x.device)
     q = make_query(2 * n_samples if estimator == VR else n_samples, M, seed, estimator, precision, schedule_mode,
                    batch_share, walk_offset, instance)
+    if estimator == NAIVE:
+        T = None
     _check(_lib.woi_trace(problem.handle, C.c_void_p(x.data_ptr()), P, C.byref(q), int(n_samples),
-                          C.c_void_p(F.data_ptr()), C.c_void_p(G.data_ptr()), C.c_void_p(T.data_ptr()), _stream()))
+                          C.c_void_p(F.data_ptr()), C.c_void_p(G.data_ptr()),
+                          C.c_void_p(None if T is None else T.data_ptr()), _stream()))
     return F, G, T
 
 
