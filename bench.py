@@ -43,9 +43,9 @@ PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 (packed) peak
 # WRITE_SIZE passes in profiles/headline_kernels_star_tree_2d_counters.md, scaled by what the same
 # counters read for a 1 GiB device copy.  None whenever the kernel has changed since those
 # passes were taken.
-TRAFFIC_BYTES = 2876 * 1024 * 2.0 + 63649 * 1024 * 1.0
+TRAFFIC_BYTES = 2893 * 1024 * 2.0 + 65374 * 1024 * 1.0
 # The same for the persistent batch kernel of the headline graph.
-BATCH_TRAFFIC_BYTES = 3474 * 1024 * 2.0 + 293600 * 1024 * 1.0
+BATCH_TRAFFIC_BYTES = 3460 * 1024 * 2.0 + 293479 * 1024 * 1.0
 
 
 def eval_flops_per_pair(m):
@@ -196,6 +196,33 @@ def config_block(woi, torch, ev, name, prob_desc, pts_np, walks, M, estimator, B
                                      "pair_eval_tflops_over_traj_plus_eval": ev_fl},
         "fp32_vs_fp64_paired_z": paired(r32, r64),
     }
+
+
+def naive_block(woi, torch, ev, prob, pts, steps):
+    """Naive Markov-tree estimator (FP64) against the scheduled FP64 estimator on the star tree
+    (N = 9), M = 1..3: per tree sum_{i=0}^{M} 9^{i+1} interface points, against M + 1 per
+    scheduled walker.  Cost at the same standard error, and the two means in combined SEs
+    (Theorem 2: same expectation)."""
+    import numpy as np
+    P = pts.shape[0]
+    N = prob.N
+    out = {"workload": "star tree 2D (N = 9: unit disk, 3 nested 2048-segment stars, 5 circles), 4096 points",
+           "M": {}}
+    for M, trees in ((1, 400), (2, 100), (3, 12)):
+        nodes = sum(N ** (i + 1) for i in range(M + 1))
+        rn = Path(woi, torch, prob, pts, trees, M, woi.FP64, woi.NAIVE).run(ev, steps, 1)
+        rs = Path(woi, torch, prob, pts, 100000, M, woi.FP64).run(ev, 1, 1)
+        eps = float(np.median(rs["se"]))
+        z = (rn["mean"] - rs["mean"]) / np.sqrt(rn["se"] ** 2 + rs["se"] ** 2)
+        out["M"][str(M)] = {
+            "trees_per_point": trees, "tree_points": nodes, "lane_node_draws_per_tree": (M + 1) * N ** (M + 1),
+            "ms_per_step": rn["wall"] * 1e3, "kernel_ms": float(np.mean(rn["ms"])),
+            "tree_points_per_s": P * trees * nodes / rn["wall"],
+            "eval_points_per_s_fixed_se": P / fixed_se(rn, eps),
+            "scheduled_fp64_eval_points_per_s_fixed_se": P / fixed_se(rs, eps),
+            "scheduled_speedup_fixed_se": fixed_se(rn, eps) / fixed_se(rs, eps),
+            "naive_vs_scheduled_z": {"mean_abs": float(np.mean(np.abs(z))), "max_abs": float(np.max(np.abs(z)))}}
+    return out
 
 
 def run_batch(woi, torch, W, precision, steps, warmup, ev):
@@ -389,12 +416,13 @@ def main():
                 woi, torch, ev, f"{m}D: 3 nested ellipsoids (centres 1.3/1.4/1.6 e1), sigma (1.1, 1.3, 0.9), data "
                 f"from u = |x|^(2-m); 10000 points; W = 2e5, M = {m + 2}", pm, xm, 200000, m + 2, 0, 32,
                 args.extra_steps)
-        # triangle-mesh interfaces (brute-force hit scan over 1280 triangles per mesh)
+        # triangle-mesh interfaces (BVH line/ray hits over 1280 triangles per mesh)
         p6, x6 = W.mesh_tree_3d()
         rec["mesh_tree_3d"] = config_block(
             woi, torch, ev, "3D: jittered icosphere (R 1, 1280 triangles) around a jittered icosphere (R 0.45, 1280 "
             "triangles) and a sphere; sigma (1, 4, 0.5); quadratic direction-polynomial data; 4096 points; W = 2e4, "
             "M = 4", p6, x6, 20000, 4, 0, 16, args.extra_steps)
+        rec["naive_markov_trees"] = naive_block(woi, torch, ev, prob, pts, args.extra_steps)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(prob_desc, pts_np, args.walks, M, args.cpu_seconds)
     print(json.dumps(rec), flush=True)
