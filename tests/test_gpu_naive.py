@@ -115,6 +115,24 @@ def test_naive_estimate_counters_and_exact_expectation():
     assert 0.5 < np.mean(z ** 2) < 1.6
 
 
+def test_naive_full_size_sampled():
+    """The benchmark's naive configuration in full (star tree, 4096 points, N = 9, M = 2, 100
+    trees per point, the launch it times); sampled points against the oracle on identical
+    streams (explicit point groups).  A tree whose discrete choices flip at rounding level moves
+    one point's mean by a fraction of its SE, so one such point is allowed."""
+    p, xs = W.star_tree_2d()
+    gp = woi.Problem(p)
+    mean, se, g, gse = [_np(t) for t in woi.estimate(gp, xs, 100, 2, seed=31, estimator=woi.NAIVE)]
+    assert np.all(np.isfinite(mean)) and np.all(np.isfinite(g)) and np.all(se > 0)
+    idx = np.random.default_rng(3).choice(len(xs), 8, replace=False)
+    mo, so, go, gso, cnt = O.estimate(O.OracleProblem(p), xs[idx], 100, 2, seed=31, estimator=O.NAIVE, groups=idx)
+    assert cnt["walk_steps"] == len(idx) * 100 * _tree_nodes(9, 2)
+    close = np.abs(mean[idx] - mo) <= 1e-9 * np.maximum(np.abs(mo), so)
+    gclose = np.all(np.abs(g[idx] - go) <= 1e-9 * np.maximum(np.abs(go), gso), axis=1)
+    assert (~(close & gclose)).sum() <= 1
+    assert np.max(np.abs(mean[idx] - mo) / so) < 0.5
+
+
 def test_naive_rejections():
     p, xs = W.concentric_disk_2d()
     gp = woi.Problem(p)
