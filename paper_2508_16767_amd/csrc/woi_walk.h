@@ -527,15 +527,28 @@ constexpr bool COUNT_POLY = true;   // dead code unless the counting kernel read
 
 // The walk: calls cand(j) for every candidate segment j in increasing order, and stops
 // early when cand returns true.
-template <typename R, bool LDS, class Cand>
+// Search modes: PS_RAY when every lane of the wave searches along a ray, else PS_ANY (each
+// lane's `ray` flag decides).  The ray mode also skips blocks behind the ray's origin: every
+// vertex v of a block has d.(v - y) <= max(g_j, g_e) + bound (the bound holds in every
+// direction), and a crossing point z with t = d.(z - y) <= 0 is no ray hit; segments are left
+// to the exact test.  Mixed waves gain nothing from it (a wave waits for its slowest lane), so
+// PS_ANY keeps the plain walk.
+enum : int { PS_ANY = 0, PS_RAY = 1 };
+
+template <typename R, bool LDS, int MODE, class Cand>
 __device__ __forceinline__ void poly_walk(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
-                                          const R y[2], const R d[2], bool ray, int yseg, Counts& cnt, Cand cand) {
+                                          const R y[2], const R d[2], bool ray_lane, int yseg, Counts& cnt,
+                                          Cand cand) {
+    constexpr bool RAY = MODE == PS_RAY;    // the walk keeps the ray parameters
+    const bool ray = RAY || ray_lane;
     constexpr bool F32 = std::is_same<R, float>::value;
     const int n = g.nv, n2 = g.n2, top = g.top;
     // block tests run in FP32 on the staged (or global) FP32 copy; bounds absorb the rounding
     const float yf0 = (float)y[0], yf1 = (float)y[1], df0 = (float)d[0], df1 = (float)d[1];
     // h(v) = d x (v - y) = d0 v1 - d1 v0 - (d0 y1 - d1 y0): two FMAs per vertex
     const float hc = df0 * yf1 - df1 * yf0;
+    // g(v) = d . (v - y), the ray parameter of v's projection (rays only)
+    const float gc = df0 * yf0 + df1 * yf1;
     auto bound = [&](int idx) -> float {
         if constexpr (LDS) return __half2float(reinterpret_cast<const __half*>(woi_smem + g.lds_b)[idx]);
         else return Pay<float>::base(dp)[g.bnd + idx];
@@ -555,12 +568,18 @@ __device__ __forceinline__ void poly_walk(const DevProblem* dp, const DevRegion&
         else p = vg[jn - n2];
         return fmaf(df0, p.y, fmaf(-df1, p.x, -hc));
     };
+    auto gn = [&](int jn) -> float {
+        float2 p;
+        if constexpr (LDS) p = *reinterpret_cast<const float2*>(woi_smem + (vbase + 8u * (uint32_t)jn));
+        else p = vg[jn - n2];
+        return fmaf(df0, p.x, fmaf(df1, p.y, -gc));
+    };
     const R* __restrict__ v = poly_xy<R, LDS>(g, pay);       // exact values (FP64)
     int jn = n2, lvl = top;
-    float hj = hn(jn);
+    float hj = hn(jn), gj = RAY ? gn(jn) : 0.0f;
     while (jn < jend) {
         const int je = jn + (1 << lvl);   // <= 2 n2: the FP32 vertices are padded to n2 + 1
-        const float he = hn(je);
+        const float he = hn(je), ge = RAY ? gn(je) : 0.0f;
         const bool seg = lvl == 0;
         const float b = bound(jn >> lvl);
         // Every vertex of the block strictly on one side of the line: the end value nearer
@@ -568,7 +587,8 @@ __device__ __forceinline__ void poly_walk(const DevProblem* dp, const DevRegion&
         // For a segment (b = 0) this reads "both values nonzero, one sign".  A segment crosses
         // when it is not skipped and its end value is nonzero: a zero start value belongs to
         // this segment and a zero end value to the next.
-        const bool skip = fabsf(__builtin_amdgcn_fmed3f(hj, he, 0.0f)) > b;
+        bool skip = fabsf(__builtin_amdgcn_fmed3f(hj, he, 0.0f)) > b;
+        if constexpr (RAY) skip |= !seg & (fmaxf(gj, ge) < -b);
         bool cross;
         if constexpr (F32) {
             cross = !(skip | (he == 0.0f));
@@ -589,6 +609,7 @@ __device__ __forceinline__ void poly_walk(const DevProblem* dp, const DevRegion&
         const int lz = (int)__builtin_ctz((unsigned)je);
         jn = adv ? je : jn;
         hj = adv ? he : hj;
+        if constexpr (RAY) gj = adv ? ge : gj;
         lvl = adv ? lz : lvl - 1;
     }
 }
@@ -596,10 +617,11 @@ __device__ __forceinline__ void poly_walk(const DevProblem* dp, const DevRegion&
 // Number of hits q and, when q > 0, the segment jp of hit `pick` = min(floor(up q), q - 1)
 // (uniform among the hits).  With more than POLY_QUEUE candidates (or segment indices past
 // 16 bits) the hits are counted by a second walk and found by a third.
-template <typename R, bool LDS>
-__device__ __forceinline__ int poly_pick(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
-                                         const R y[2], const R d[2], bool ray, int yseg, R up, int& pick, int& jp,
-                                         Counts& cnt) {
+template <typename R, bool LDS, int MODE>
+__device__ __forceinline__ int poly_pick_t(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
+                                           const R y[2], const R d[2], bool ray_lane, int yseg, R up, int& pick,
+                                           int& jp, Counts& cnt) {
+    const bool ray = MODE == PS_RAY || ray_lane;
     const R* __restrict__ v = poly_xy<R, LDS>(g, pay);
     // crossing parameter test of candidate segment j (precision R)
     auto hit = [&](int j) -> bool {
@@ -611,7 +633,7 @@ __device__ __forceinline__ int poly_pick(const DevProblem* dp, const DevRegion& 
     };
     Queue16 cq{0u, 0u, 0u, 0u};
     int c = 0;
-    poly_walk<R, LDS>(dp, g, pay, y, d, ray, yseg, cnt, [&](int j) -> bool {
+    poly_walk<R, LDS, MODE>(dp, g, pay, y, d, ray, yseg, cnt, [&](int j) -> bool {
         cq.push((uint32_t)j);
         ++c;
         return false;
@@ -630,17 +652,27 @@ __device__ __forceinline__ int poly_pick(const DevProblem* dp, const DevRegion& 
         }
         return q;
     }
-    poly_walk<R, LDS>(dp, g, pay, y, d, ray, yseg, cnt, [&](int j) -> bool { q += hit(j) ? 1 : 0; return false; });
+    poly_walk<R, LDS, MODE>(dp, g, pay, y, d, ray, yseg, cnt, [&](int j) -> bool { q += hit(j) ? 1 : 0; return false; });
     if (q > 0) {
         pick = min((int)(up * (R)q), q - 1);
         int k = 0;
-        poly_walk<R, LDS>(dp, g, pay, y, d, ray, yseg, cnt, [&](int j) -> bool {
+        poly_walk<R, LDS, MODE>(dp, g, pay, y, d, ray, yseg, cnt, [&](int j) -> bool {
             if (!hit(j)) return false;
             jp = j;
             return k++ == pick;
         });
     }
     return q;
+}
+
+template <typename R, bool LDS>
+__device__ __forceinline__ int poly_pick(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
+                                         const R y[2], const R d[2], bool ray, int yseg, R up, int& pick, int& jp,
+                                         Counts& cnt) {
+    // wave-uniform choice of the search mode (every wave is uniform when the schedule is shared)
+    if (__ballot(ray) == __builtin_amdgcn_read_exec())
+        return poly_pick_t<R, LDS, PS_RAY>(dp, g, pay, y, d, true, yseg, up, pick, jp, cnt);
+    return poly_pick_t<R, LDS, PS_ANY>(dp, g, pay, y, d, ray, yseg, up, pick, jp, cnt);
 }
 
 // Triangle mesh: hits of the line / ray y + t d in triangle order (Moller-Trumbore with the
