@@ -87,6 +87,7 @@ def test_walk_parity_star_tree(estimator):
     from test_oracle_pins import STAR_PTS, _star_tree
     p, _, _ = _star_tree()
     walk_parity(p, STAR_PTS, 2000, 4, estimator=estimator, flip_budget=1e-4)
+    walk_parity(p, STAR_PTS, 1000, 4, estimator=estimator, sched=1, flip_budget=1e-4)   # wave-uniform cases
 
 
 def test_walk_parity_nonconvex_boundary():
@@ -115,6 +116,14 @@ def test_walk_parity_many_crossings():
     t = _np(T).astype(np.uint32)[..., 1:]
     q = (t >> 8) & 0xFF
     assert ((q > 8) & ((t & 0x3F) == 0)).sum() > 1000          # many steps past the queue
+    # shared schedule: whole waves search along rays (the search that also skips blocks behind
+    # the ray's origin) or lines past the queue.  Rays from the inner circle cross the gear a
+    # few times only; the ragged-polyline test takes every ray search past the queue.
+    walk_parity(p, pts, 600, 4, sched=1, flip_budget=1e-4)
+    _, _, T = woi.trace(gp, pts, 600, 4, seed=7, precision=woi.FP64, schedule_mode=1)
+    t = _np(T).astype(np.uint32)[..., 1:]
+    case, q = (t >> 6) & 3, (t >> 8) & 0xFF
+    assert (case == 2).sum() > 1000 and ((case == 1) & (q > 8)).sum() > 100
     m64, s64, g64, _ = [_np(a) for a in woi.estimate(gp, pts, 20000, 4, seed=3, precision=woi.FP64)]
     m32, _, g32, _ = [_np(a) for a in woi.estimate(gp, pts, 20000, 4, seed=3, precision=woi.FP32)]
     assert np.all(np.abs(m32 - m64) < 0.1 * s64), (m32 - m64) / s64
