@@ -59,25 +59,31 @@ void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out
 
 static double unif(uint32_t v) { return ((double)v + 0.5) * (1.0 / 4294967296.0); }
 
-/* A word stream for one (walk, stream, instance|walker|purpose, step) counter prefix. */
+/* A word stream for one (walk, stream, instance|walker|purpose, step) counter prefix.
+   Paired streams (2D transitions): draw 0 (the first attempt, at most two words) comes from
+   the block shared by steps 2k+1 and 2k+2, counter word 3 = (0x8000 | k) << 16, words 0-1
+   for step 2k+1 and 2-3 for step 2k+2; later attempts draw from (step, draw) as usual. */
 typedef struct {
     uint32_t key[2], c0, c1, c2, step, draw;
     uint32_t buf[4];
-    int pos;
+    int pos, paired;
 } words_t;
 
 static void words_init(words_t *w, uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t step)
 {
     w->key[0] = (uint32_t)seed; w->key[1] = (uint32_t)(seed >> 32);
-    w->c0 = c0; w->c1 = c1; w->c2 = c2; w->step = step; w->draw = 0; w->pos = 4;
+    w->c0 = c0; w->c1 = c1; w->c2 = c2; w->step = step; w->draw = 0; w->pos = 4; w->paired = 0;
 }
 static void words_seek(words_t *w, uint32_t draw) { w->draw = draw; w->pos = 4; }
 static uint32_t words_next(words_t *w)
 {
     if (w->pos == 4) {
-        uint32_t ctr[4] = {w->c0, w->c1, w->c2, (w->step << 16) | (w->draw & 0xFFFFu)};
+        const int pair = w->paired && w->draw == 0;
+        uint32_t ctr[4] = {w->c0, w->c1, w->c2,
+                           pair ? (0x8000u | ((w->step - 1) >> 1)) << 16 : (w->step << 16) | (w->draw & 0xFFFFu)};
         or_philox4x32_10(ctr, w->key, w->buf);
-        w->draw++; w->pos = 0;
+        w->pos = pair ? 2 * (int)((w->step - 1) & 1) : 0;
+        w->draw++;
     }
     return w->buf[w->pos++];
 }
@@ -556,6 +562,7 @@ static void one_sample(const or_problem *pr, const double *x, const or_query *q,
             int rel = pr->rel[h[i - 1]][h[i]], qn, pick, segn;
             double yn[OR_MAX_DIM], nn[OR_MAX_DIM];
             words_init(&w, q->seed, w32, group, c2, (uint32_t)i);
+            w.paired = m == 2;
             double tf = transition(pr, h[i - 1], h[i], &w, y, seg, yn, &segn, nn, &Q, &qn, &pick, &att, cnt);
             if (tf == 0) { if (tr) for (int j = i; j <= M; ++j) tr[j] = trace_word(h[j], rel, 0, 0, 0, att); break; }
             T *= tf;

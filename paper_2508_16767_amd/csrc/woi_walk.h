@@ -65,6 +65,16 @@ struct Words {
             if (4 * b + 3 < NW) w[4 * b + 3] = v.w;
         }
     }
+    // Attempt words: the two words pre-drawn for the first attempt (2D transitions: one block
+    // serves steps 2k+1 and 2k+2, counter word 3 = (0x8000 | k) << 16), else draws from `first`.
+    __device__ __forceinline__ void take(const Stream& s, uint32_t step, uint32_t first, const uint32_t* pre) {
+        if (pre && first == 0 && NW <= 2) {
+#pragma unroll
+            for (int i = 0; i < NW && i < 2; ++i) w[i] = pre[i];
+        } else {
+            fill(s, step, first);
+        }
+    }
 };
 
 // ----------------------------------------------------------------------------- precision
@@ -377,7 +387,8 @@ __device__ __forceinline__ int mesh_triangle(const DevProblem* dp, const DevRegi
 
 template <typename R, int D, bool LDS, bool INL = true>
 __device__ __forceinline__ bool surf_attempt(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
-                                             const Stream& st, uint32_t step, int att, R y[D], int& seg) {
+                                             const Stream& st, uint32_t step, int att, R y[D], int& seg,
+                                             const uint32_t* pre = nullptr) {
     seg = 0;
     if (D == 3 && LDS && g.kind == WOI_SHAPE_MESH3D) {
         if constexpr (D == 3) {
@@ -393,13 +404,13 @@ __device__ __forceinline__ bool surf_attempt(const DevProblem* dp, const DevRegi
         return true;
     }
     if (g.kind == WOI_SHAPE_POLYLINE2D) {
-        Words<1> W; W.fill(st, step, (uint32_t)att);
+        Words<1> W; W.take(st, step, (uint32_t)att, pre);
         return polyline_at<R, D, LDS, INL>(dp, g, pay, RO<R>::u(W.w[0]) * Pay<R>::total(g), y, seg);
     }
     const R* q = pay + Pay<R>::g(g);
     if (g.kind == WOI_SHAPE_SPHERE) {
         constexpr int NW = dir_words(D), NB = (NW + 3) / 4;
-        Words<NW> W; W.fill(st, step, (uint32_t)(att * NB));
+        Words<NW> W; W.take(st, step, (uint32_t)(att * NB), pre);
         R u[D];
         unit_dir<R, D>(W, u);
 #pragma unroll
@@ -408,7 +419,7 @@ __device__ __forceinline__ bool surf_attempt(const DevProblem* dp, const DevRegi
     }
     // ellipsoid: y = c + A^{-1/2} u, accept with probability |A^{1/2} u| / sqrt(lambda_max)
     constexpr int NW = dir_words(D) + 1, NB = (NW + 3) / 4;
-    Words<NW> W; W.fill(st, step, (uint32_t)(att * NB));
+    Words<NW> W; W.take(st, step, (uint32_t)(att * NB), pre);
     R u[D];
     unit_dir<R, D>(W, u);
     const R acc = RO<R>::u(W.w[NW - 1]);
@@ -850,13 +861,13 @@ template <typename R, int D, bool LDS, bool INL = true>
 __device__ __forceinline__ R transition(const DevProblem* __restrict__ dp, const R* __restrict__ pay,
                                         const DevRegion* g, int rel, const Stream& st, uint32_t step,
                                         const R y[D], int seg, R yn[D], int& segn, R& Q, int& qn, int& pick,
-                                        int& att, Counts& cnt) {
+                                        int& att, Counts& cnt, const uint32_t* pre = nullptr) {
     R nn[D];
     segn = 0; qn = 1; pick = 0;
     if (rel == REL_OTHER) {
         cnt.other++;
         for (att = 0; att < WOI_ATTEMPT_CAP; ++att) {
-            if (surf_attempt<R, D, LDS, INL>(dp, *g, pay, st, step, att, yn, segn)) break;
+            if (surf_attempt<R, D, LDS, INL>(dp, *g, pay, st, step, att, yn, segn, pre)) break;
             cnt.rejections++;
         }
         if (att == WOI_ATTEMPT_CAP) cnt.caps++;
@@ -874,7 +885,7 @@ __device__ __forceinline__ R transition(const DevProblem* __restrict__ dp, const
         constexpr int NW = dir_words(D) + 1, NB = (NW + 3) / 4;
         bool found = false;
         for (att = 0; att < WOI_ATTEMPT_CAP; ++att) {
-            Words<NW> W; W.fill(st, step, (uint32_t)(att * NB));
+            Words<NW> W; W.take(st, step, (uint32_t)(att * NB), pre);
             R d[D];
             unit_dir<R, D>(W, d);
             const R up = RO<R>::u(W.w[NW - 1]);
@@ -1079,6 +1090,7 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
     int done = 1;
     R S = 1, pw = 1;
     const R l1 = Pay<R>::l1(dp);
+    uint4 pb = make_uint4(0u, 0u, 0u, 0u);
     for (int i = 1; i <= M; ++i) {
         if ((i & 3) == 0) sb = sched_block((uint32_t)(i >> 2));
         const uint32_t wv = (i & 3) == 0 ? sb.x : (i & 3) == 1 ? sb.y : (i & 3) == 2 ? sb.z : sb.w;
@@ -1094,7 +1106,15 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
         pw *= l1;
         R yn[D];
         int segn = 0, qn = 1, pick = 0;
-        const R tf = transition<R, D, LDS, INL>(dp, pay, g, rel, st, (uint32_t)i, y, seg, yn, segn, Q, qn, pick, att, cnt);
+        // 2D: the first attempts of steps 2k+1 and 2k+2 share one block (two words each)
+        uint32_t pre[2] = {0u, 0u};
+        if constexpr (D == 2) {
+            if (i & 1) pb = st.block(0x8000u | (uint32_t)((i - 1) >> 1), 0u);
+            pre[0] = (i & 1) ? pb.x : pb.z;
+            pre[1] = (i & 1) ? pb.y : pb.w;
+        }
+        const R tf = transition<R, D, LDS, INL>(dp, pay, g, rel, st, (uint32_t)i, y, seg, yn, segn, Q, qn, pick, att,
+                                                cnt, D == 2 ? pre : nullptr);
         if (tf == R(0)) {   // no hit after the attempt cap: the walker stops here
             if (tr) for (int j = i; j <= M; ++j) tr[j] = trace_word(h, rel, 0, 0, 0, att);
             break;
