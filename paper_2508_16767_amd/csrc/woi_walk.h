@@ -614,7 +614,7 @@ __device__ __forceinline__ void poly_walk(const DevProblem* dp, const DevRegion&
         // when it is not skipped and its end value is nonzero: a zero start value belongs to
         // this segment and a zero end value to the next.
         bool skip = fabsf(__builtin_amdgcn_fmed3f(hj, he, 0.0f)) > b;
-        if constexpr (RAY) skip |= !seg & (fmaxf(gj, ge) < -b);
+        if constexpr (RAY) skip |= !seg & (gj < -b) & (ge < -b);   // (fmaxf would add a NaN canonicalisation)
         bool cross;
         if constexpr (F32) {
             cross = !(skip | (he == 0.0f));
@@ -627,7 +627,7 @@ __device__ __forceinline__ void poly_walk(const DevProblem* dp, const DevRegion&
             }
             cross = (hb != R(0)) & ((ha == R(0)) | ((ha > R(0)) != (hb > R(0))));
         }
-        if (seg & cross & (jn != ysn)) {
+        if (seg & cross & (RAY || jn != ysn)) {   // a ray excludes no segment
             if (cand(jn - n2)) return;
         }
         if (COUNT_POLY) { cnt.nodes += seg ? 0 : 1; cnt.segs += seg ? 1 : 0; }
