@@ -177,7 +177,8 @@ woi_status woi_workspace_size(const woi_problem *p, int64_t P, const woi_query *
  *   workspace/workspace_bytes: device scratch of at least woi_workspace_size() bytes
  *   counters: NULL or device uint64[WOI_COUNTERS] that the call adds to: [0] walker-steps,
  *             [1] redraws (q = 0), [2] rejections, [3] attempt-cap hits, [4] zero distances,
- *             [5] polyline tree-node tests, [6] polyline segment tests, [7] uniform ("other")
+ *             [5] search node tests (polyline blocks, mesh BVH nodes), [6] segment or triangle
+ *             tests, [7] uniform ("other")
  *             transitions
  * Errors: INVALID_ARG (sizes, NULL, VR with odd walks or dim > 3), OOM (workspace), DEVICE. */
 woi_status woi_estimate(const woi_problem *p, const double *points, int64_t P, const woi_query *q,
