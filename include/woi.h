@@ -178,9 +178,10 @@ woi_status woi_workspace_size(const woi_problem *p, int64_t P, const woi_query *
  *   counters: NULL or device uint64[WOI_COUNTERS] that the call adds to: [0] walker-steps,
  *             [1] redraws (q = 0), [2] rejections, [3] attempt-cap hits, [4] zero distances,
  *             [5] search node tests (polyline blocks, mesh BVH nodes), [6] segment or triangle
- *             tests, [7] uniform ("other")
- *             transitions
- * Errors: INVALID_ARG (sizes, NULL, VR with odd walks or dim > 3), OOM (workspace), DEVICE. */
+ *             tests, [7] uniform ("other") transitions
+ * Errors: INVALID_ARG (sizes, NULL, VR with odd walks, naive with (N+1)^(M+1) > 2^31),
+ *         UNSUPPORTED (VR in dim > 3 or with meshes; naive with FP32, batch_share > 1 or
+ *         instance != 0), OOM (workspace), DEVICE. */
 woi_status woi_estimate(const woi_problem *p, const double *points, int64_t P, const woi_query *q,
                         double *mean, double *se, double *grad, double *grad_se,
                         void *workspace, size_t workspace_bytes, uint64_t *counters, void *stream);
