@@ -300,6 +300,10 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="measure only the headline path (skip shared trajectories, the instance batch, 3D and 6D)")
     ap.add_argument("--extra-steps", type=int, default=2, help="timed steps of the other configurations")
+    ap.add_argument("--blocks", default="all",
+                    help="comma-separated other configurations to run (shared_trajectories, batched_star_tree_instances, "
+                         "ellipsoid_tree_3d_vr, nested_spheres_6d, point_charge_ellipsoids, mesh_tree_3d, "
+                         "naive_markov_trees), default all")
     ap.add_argument("--cpu-seconds", type=float, default=25.0)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after the run, copy this many bytes device-to-device three times (a plain copy "
@@ -385,8 +389,13 @@ def main():
                      "flops_per_launch": flops,
                      "counts_per_launch": {n: float(v) for n, v in zip(woi.COUNTER_NAMES, c32)}},
     }
-    if not args.no_extra:
-        B = 16                                          # <= 0.5 % of the 4096 points
+    blocks = set(args.blocks.split(",")) if args.blocks != "all" else None
+
+    def want(name):
+        return not args.no_extra and (blocks is None or name in blocks)
+
+    B = 16                                              # <= 0.5 % of the 4096 points
+    if want("shared_trajectories"):
         rsh = Path(woi, torch, prob, pts, args.walks, M, woi.FP32, 0, B).run(ev, args.steps, args.warmup)
         pairs = P * args.walks * (M + 1)
         rec["shared_trajectories"] = {
@@ -396,16 +405,20 @@ def main():
             "speedup_vs_fp64_plain_fixed_se": t64_eps / fixed_se(rsh, eps),
             "pair_eval_tflops_over_traj_plus_eval":
                 pairs * eval_flops_per_pair(2) / (float(np.mean(rsh["ms"])) * 1e-3) / 1e12}
+    if want("batched_star_tree_instances"):
         rec["batched_star_tree_instances"] = batch_block(woi, torch, W, ev, args.extra_steps)
+    if want("ellipsoid_tree_3d_vr"):
         p4, x4 = W.ellipsoid_tree_3d()
         rec["ellipsoid_tree_3d_vr"] = config_block(
             woi, torch, ev, "unit ball, spheres 0.6 > 0.3, 10 ellipsoids (semi-axes 0.03-0.08), sigma 10^U(log .5, "
             "log 50), real SH l <= 4 data; 16384 points; VR, W = 1e5 walkers, M = 6", p4, x4, 100000, 6, 1, 64,
             args.extra_steps)
+    if want("nested_spheres_6d"):
         p5, x5 = W.nested_spheres_6d()
         rec["nested_spheres_6d"] = config_block(
             woi, torch, ev, "unit 6-ball, spheres 0.7 > 0.35, sigma (1, 5, 0.2), c + lambda x1/|x| data; 1024 points; "
             "W = 1e6, M = 8", p5, x5, 1000000, 8, 0, 4, args.extra_steps)
+    if want("point_charge_ellipsoids"):
         # three nested ellipsoids around the potential |x|^(2-m) of a point charge, m = 3..6
         # (1e4 points; M = m + 2 as the paper walks them; W = 2e5 keeps the run short, the rates
         # do not depend on W)
@@ -416,12 +429,14 @@ def main():
                 woi, torch, ev, f"{m}D: 3 nested ellipsoids (centres 1.3/1.4/1.6 e1), sigma (1.1, 1.3, 0.9), data "
                 f"from u = |x|^(2-m); 10000 points; W = 2e5, M = {m + 2}", pm, xm, 200000, m + 2, 0, 32,
                 args.extra_steps)
+    if want("mesh_tree_3d"):
         # triangle-mesh interfaces (BVH line/ray hits over 1280 triangles per mesh)
         p6, x6 = W.mesh_tree_3d()
         rec["mesh_tree_3d"] = config_block(
             woi, torch, ev, "3D: jittered icosphere (R 1, 1280 triangles) around a jittered icosphere (R 0.45, 1280 "
             "triangles) and a sphere; sigma (1, 4, 0.5); quadratic direction-polynomial data; 4096 points; W = 2e4, "
             "M = 4", p6, x6, 20000, 4, 0, 16, args.extra_steps)
+    if want("naive_markov_trees"):
         rec["naive_markov_trees"] = naive_block(woi, torch, ev, prob, pts, args.extra_steps)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(prob_desc, pts_np, args.walks, M, args.cpu_seconds)
