@@ -142,8 +142,9 @@ woi_status woi_problem_get_info(const woi_problem *p, woi_problem_info *out);
  * both the same expectation).  A tree has sum_{i=0}^{M} N^{i+1} interface points, drawn with the
  * transitions of Eq. naive_woi_p; node (h_0..h_i) draws from its own counter, so a branch is
  * reused by all its extensions.  For NAIVE, walks = trees per point (walk_offset = first tree);
- * it requires FP64, batch_share = 1 and instance = 0 (WOI_E_UNSUPPORTED otherwise) and
- * (N + 1)^(M + 1) <= 2^31 (WOI_E_INVALID_ARG); schedule_mode and block_size are ignored. */
+ * it requires batch_share = 1 and instance = 0 (WOI_E_UNSUPPORTED otherwise) and
+ * (N + 1)^(M + 1) <= 2^31 (WOI_E_INVALID_ARG); FP32 walks keep FP64 tree sums; schedule_mode and
+ * block_size are ignored. */
 typedef enum { WOI_EST_PLAIN = 0, WOI_EST_VR = 1, WOI_EST_NAIVE = 2 } woi_estimator;
 typedef enum { WOI_PREC_FP64 = 0, WOI_PREC_FP32 = 1 } woi_precision;
 typedef enum { WOI_SCHED_PER_GROUP = 0, WOI_SCHED_SHARED = 1 } woi_schedule_mode;
@@ -180,8 +181,8 @@ woi_status woi_workspace_size(const woi_problem *p, int64_t P, const woi_query *
  *             [5] search node tests (polyline blocks, mesh BVH nodes), [6] segment or triangle
  *             tests, [7] uniform ("other") transitions
  * Errors: INVALID_ARG (sizes, NULL, VR with odd walks, naive with (N+1)^(M+1) > 2^31),
- *         UNSUPPORTED (VR in dim > 3 or with meshes; naive with FP32, batch_share > 1 or
- *         instance != 0), OOM (workspace), DEVICE. */
+ *         UNSUPPORTED (VR in dim > 3 or with meshes; naive with batch_share > 1 or instance != 0),
+ *         OOM (workspace), DEVICE. */
 woi_status woi_estimate(const woi_problem *p, const double *points, int64_t P, const woi_query *q,
                         double *mean, double *se, double *grad, double *grad_se,
                         void *workspace, size_t workspace_bytes, uint64_t *counters, void *stream);

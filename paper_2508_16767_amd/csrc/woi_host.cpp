@@ -1266,7 +1266,6 @@ woi_status check_query_impl(const woi_problem* p, int64_t P, const woi_query* q)
     }
     if (q->batch_share < 1) return fail(WOI_E_INVALID_ARG, "batch_share must be >= 1");
     if (q->estimator == WOI_EST_NAIVE) {
-        if (q->precision != WOI_PREC_FP64) return fail(WOI_E_UNSUPPORTED, "the naive estimator runs in FP64 only");
         if (q->batch_share != 1) return fail(WOI_E_UNSUPPORTED, "the naive estimator needs batch_share = 1");
         if (q->instance != 0) return fail(WOI_E_UNSUPPORTED, "the naive estimator needs instance = 0");
         if (std::pow(p->H.N + 1.0, q->M + 1.0) > 2147483648.0)
@@ -1415,7 +1414,7 @@ woi_status estimate_naive(const woi_problem* p, const double* points, int64_t P,
     kp.counters = counters;
     if (q->event_begin && hipEventRecord(static_cast<hipEvent_t>(q->event_begin), s) != hipSuccess)
         return fail(WOI_E_DEVICE, "hipEventRecord(begin) failed");
-    hipError_t e = woi::launch_naive(kp, pl.np, p->H.m, dim3(pl.gx, pl.chunks), s);
+    hipError_t e = woi::launch_naive(kp, pl.np, p->H.m, q->precision == WOI_PREC_FP32, dim3(pl.gx, pl.chunks), s);
     if (e != hipSuccess) return fail(WOI_E_DEVICE, "naive launch failed: %s", hipGetErrorString(e));
     if (q->event_end && hipEventRecord(static_cast<hipEvent_t>(q->event_end), s) != hipSuccess)
         return fail(WOI_E_DEVICE, "hipEventRecord(end) failed");
@@ -1599,7 +1598,8 @@ woi_status woi_trace(const woi_problem* p, const double* points, int64_t P, cons
         woi::KParams kp = naive_params(p, points, P, &qq, n_samples, pl);
         kp.traceF = F;
         kp.traceG = G;
-        hipError_t e = woi::launch_naive(kp, pl.np, p->H.m, dim3(pl.gx, pl.chunks), static_cast<hipStream_t>(stream));
+        hipError_t e = woi::launch_naive(kp, pl.np, p->H.m, q->precision == WOI_PREC_FP32, dim3(pl.gx, pl.chunks),
+                                         static_cast<hipStream_t>(stream));
         if (e != hipSuccess) return fail(WOI_E_DEVICE, "naive launch failed: %s", hipGetErrorString(e));
         return WOI_OK;
     }

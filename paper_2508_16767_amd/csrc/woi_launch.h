@@ -83,13 +83,13 @@ hipError_t launch_walk(const KParams& kp, int dim, bool vr, bool fp32, unsigned 
 hipError_t launch_reduce(const RParams& rp, hipStream_t s);
 
 // Naive estimator (Markov trees): wave = (point, chunk of samples_per_thread trees), lane = leaf;
-// grid = (ceil(P / 4), chunks), 256 threads.  FP64; partials and trace values as launch_walk
-// (K = 1, one value per tree).
+// grid = (ceil(P / 4), chunks), 256 threads.  FP64 or FP32 walks (FP64 tree sums); partials and
+// trace values as launch_walk (K = 1, one value per tree).
 struct NParams {
     uint32_t leaves;               // N^(M+1) leaves per tree
     uint32_t span0;                // N^M: leaves under one root
 };
-hipError_t launch_naive(const KParams& kp, const NParams& np, int dim, dim3 grid, hipStream_t s);
+hipError_t launch_naive(const KParams& kp, const NParams& np, int dim, bool fp32, dim3 grid, hipStream_t s);
 
 // ----------------------------------------------------------------------------- batches
 // Many instances in one persistent launch.  A work item is (instance, tile of 64 points,

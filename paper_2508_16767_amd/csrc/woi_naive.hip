@@ -27,10 +27,10 @@ __device__ __forceinline__ void add_counts(Counts& a, const Counts& b) {
     a.zero += b.zero; a.nodes += b.nodes; a.segs += b.segs; a.other += b.other;
 }
 
-// LDS: in 3D, the mesh-capable instantiation (nothing is staged in LDS by this kernel).
-template <int D, bool LDS, bool COUNT>
+// R: FP64, or FP32 walks (each lane's sums in FP32, the tree's lane sum and the moments in
+// FP64).  LDS: in 3D, the mesh-capable instantiation (nothing is staged in LDS by this kernel).
+template <typename R, int D, bool LDS, bool COUNT>
 __global__ __launch_bounds__(256) void naive_kernel(KParams kp, NParams np) {
-    using R = double;
     const DevProblem* __restrict__ dp = kp.dp;
     const R* __restrict__ pay = Pay<R>::base(dp);
     const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -48,9 +48,9 @@ __global__ __launch_bounds__(256) void naive_kernel(KParams kp, NParams np) {
     Counts cnt{0, 0, 0, 0, 0, 0, 0, 0};
     for (uint64_t s = s0; s < s1; ++s) {
         const uint32_t w = (uint32_t)(kp.first_sample + s);
-        R F = 0, G[D];
+        R Fl = 0, Gl[D];
 #pragma unroll
-        for (int i = 0; i < D; ++i) G[i] = 0;
+        for (int i = 0; i < D; ++i) Gl[i] = 0;
         for (uint32_t leaf = lane; leaf < np.leaves; leaf += 64) {
             uint32_t span = np.span0, id = 0;
             int hp = 0, seg = 0;
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void naive_kernel(KParams kp, NParams np) {
                         alive = false;   // no hit within the attempt cap: the subtree contributes nothing
                     } else {
                         T *= tf;
-                        A *= g->alpha;
+                        A *= (R)g->alpha;
 #pragma unroll
                         for (int j = 0; j < D; ++j) y[j] = yn[j];
                         seg = segn;
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void naive_kernel(KParams kp, NParams np) {
                 }
                 if (counted) {
                     if (alive) {
-                        add_term<R, D>(dp, xh, xl, y, (i == M ? R(0.5) : R(1)) * A * Q * T, F, G, c);
+                        add_term<R, D>(dp, xh, xl, y, (i == M ? R(0.5) : R(1)) * A * Q * T, Fl, Gl, c);
                         c.steps++;
                     }
                     if constexpr (COUNT) add_counts(cnt, c);
@@ -101,7 +101,10 @@ __global__ __launch_bounds__(256) void naive_kernel(KParams kp, NParams np) {
                 span /= N;
             }
         }
-        // the tree's value: lanes summed in a fixed butterfly (every lane ends with the same sum)
+        // the tree's value: lanes summed in FP64 in a fixed butterfly (every lane ends with the same sum)
+        double F = (double)Fl, G[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) G[i] = (double)Gl[i];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             F += __shfl_xor(F, o, 64);
@@ -136,29 +139,31 @@ __global__ __launch_bounds__(256) void naive_kernel(KParams kp, NParams np) {
     }
 }
 
-template <int D, bool LDS, bool COUNT>
+template <typename R, int D, bool LDS, bool COUNT>
 static hipError_t launch_naive_t(const KParams& kp, const NParams& np, dim3 grid, hipStream_t s) {
-    hipLaunchKernelGGL((naive_kernel<D, LDS, COUNT>), grid, dim3(256), 0, s, kp, np);
+    hipLaunchKernelGGL((naive_kernel<R, D, LDS, COUNT>), grid, dim3(256), 0, s, kp, np);
     return hipGetLastError();
 }
 
-template <bool COUNT>
+template <typename R, bool COUNT>
 static hipError_t launch_naive_c(const KParams& kp, const NParams& np, int dim, dim3 grid, hipStream_t s) {
-    if (dim == 3 && kp.mesh) return launch_naive_t<3, true, COUNT>(kp, np, grid, s);
+    if (dim == 3 && kp.mesh) return launch_naive_t<R, 3, true, COUNT>(kp, np, grid, s);
     switch (dim) {
-        case 2: return launch_naive_t<2, false, COUNT>(kp, np, grid, s);
-        case 3: return launch_naive_t<3, false, COUNT>(kp, np, grid, s);
-        case 4: return launch_naive_t<4, false, COUNT>(kp, np, grid, s);
-        case 5: return launch_naive_t<5, false, COUNT>(kp, np, grid, s);
-        case 6: return launch_naive_t<6, false, COUNT>(kp, np, grid, s);
-        case 7: return launch_naive_t<7, false, COUNT>(kp, np, grid, s);
-        case 8: return launch_naive_t<8, false, COUNT>(kp, np, grid, s);
+        case 2: return launch_naive_t<R, 2, false, COUNT>(kp, np, grid, s);
+        case 3: return launch_naive_t<R, 3, false, COUNT>(kp, np, grid, s);
+        case 4: return launch_naive_t<R, 4, false, COUNT>(kp, np, grid, s);
+        case 5: return launch_naive_t<R, 5, false, COUNT>(kp, np, grid, s);
+        case 6: return launch_naive_t<R, 6, false, COUNT>(kp, np, grid, s);
+        case 7: return launch_naive_t<R, 7, false, COUNT>(kp, np, grid, s);
+        case 8: return launch_naive_t<R, 8, false, COUNT>(kp, np, grid, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_naive(const KParams& kp, const NParams& np, int dim, dim3 grid, hipStream_t s) {
-    return kp.counters ? launch_naive_c<true>(kp, np, dim, grid, s) : launch_naive_c<false>(kp, np, dim, grid, s);
+hipError_t launch_naive(const KParams& kp, const NParams& np, int dim, bool fp32, dim3 grid, hipStream_t s) {
+    if (fp32)
+        return kp.counters ? launch_naive_c<float, true>(kp, np, dim, grid, s) : launch_naive_c<float, false>(kp, np, dim, grid, s);
+    return kp.counters ? launch_naive_c<double, true>(kp, np, dim, grid, s) : launch_naive_c<double, false>(kp, np, dim, grid, s);
 }
 
 }  // namespace woi

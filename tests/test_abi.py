@@ -98,15 +98,15 @@ def test_query_validation_without_gpu(woi):
         with pytest.raises(woi.WoiError):
             woi.workspace_size(prob, 16, q)
     assert woi.workspace_size(prob, 64, woi.make_query(10000, 4)) > 0
-    # naive Markov trees: FP64, batch_share 1, instance 0 and (N + 1)^(M + 1) <= 2^31
-    for q, st in ((woi.make_query(100, 4, estimator=woi.NAIVE, precision=woi.FP32), "WOI_E_UNSUPPORTED"),
-                  (woi.make_query(100, 4, estimator=woi.NAIVE, batch_share=2), "WOI_E_UNSUPPORTED"),
+    # naive Markov trees: batch_share 1, instance 0 and (N + 1)^(M + 1) <= 2^31
+    for q, st in ((woi.make_query(100, 4, estimator=woi.NAIVE, batch_share=2), "WOI_E_UNSUPPORTED"),
                   (woi.make_query(100, 4, estimator=woi.NAIVE, instance=1), "WOI_E_UNSUPPORTED"),
                   (woi.make_query(100, 19, estimator=woi.NAIVE), "WOI_E_INVALID_ARG")):
         with pytest.raises(woi.WoiError) as e:
             woi.workspace_size(prob, 16, q)
         assert e.value.status == st
     assert woi.workspace_size(prob, 64, woi.make_query(1000, 18, estimator=woi.NAIVE)) > 0   # 3^19 ids fit
+    assert woi.workspace_size(prob, 64, woi.make_query(1000, 4, estimator=woi.NAIVE, precision=woi.FP32)) > 0
 
 
 @pytest.mark.parametrize("make", [lambda: W.concentric_disk_2d()[0], lambda: W.star_tree_2d(n_points=8)[0], lambda: W.nested_spheres_6d()[0],

@@ -133,10 +133,37 @@ def test_naive_full_size_sampled():
     assert np.max(np.abs(mean[idx] - mo) / so) < 0.5
 
 
+def test_naive_fp32_paired_with_fp64():
+    """FP32 walks on the FP64 trees' streams: per-tree values differ only by rounding (a rare
+    FP32 flip of a discrete choice aside), the means by a small fraction of the SE; the FP32
+    mean matches the exact u_M."""
+    p, xs = W.concentric_disk_2d()
+    gp = woi.Problem(p)
+    pts = xs[::4]
+    F64, _, _ = woi.trace(gp, pts, 2000, 3, seed=6, estimator=woi.NAIVE)
+    F32, _, _ = woi.trace(gp, pts, 2000, 3, seed=6, estimator=woi.NAIVE, precision=woi.FP32)
+    F64, F32 = _np(F64)[..., 0], _np(F32)[..., 0]
+    rms = np.sqrt(np.mean(F64 ** 2))
+    close = np.abs(F32 - F64) <= 1e-3 * np.maximum(np.abs(F64), rms)
+    assert close.mean() > 0.99
+    se = F64.std(1, ddof=1) / np.sqrt(F64.shape[1])
+    assert np.all(np.abs(F32.mean(1) - F64.mean(1)) < 0.05 * se)
+    from test_oracle_pins import _star_tree, STAR_PTS
+    ps, _, _ = _star_tree()
+    gs = woi.Problem(ps)
+    m64, s64, _, _ = [_np(a) for a in woi.estimate(gs, STAR_PTS, 4000, 2, seed=8, estimator=woi.NAIVE)]
+    m32, _, _, _ = [_np(a) for a in woi.estimate(gs, STAR_PTS, 4000, 2, seed=8, estimator=woi.NAIVE, precision=woi.FP32)]
+    assert np.all(np.abs(m32 - m64) < 0.1 * s64), (m32 - m64) / s64
+    H, gH = CF.harmonic_2d(1, "cos")
+    mean, se32, _, _ = [_np(t) for t in woi.estimate(gp, xs, 50000, 3, seed=9, estimator=woi.NAIVE, precision=woi.FP32)]
+    ref = np.array([CF.concentric_uM([1, .5], [10, 1], [1, 1], 1, 2, 3, x, H, gH)[0] for x in xs])
+    assert np.max(np.abs((mean - ref) / se32)) < 4.5
+
+
 def test_naive_rejections():
     p, xs = W.concentric_disk_2d()
     gp = woi.Problem(p)
-    for kw in ({"precision": woi.FP32}, {"batch_share": 2}, {"instance": 3}):
+    for kw in ({"batch_share": 2}, {"instance": 3}):
         with pytest.raises(woi.WoiError, match="UNSUPPORTED"):
             woi.estimate(gp, xs, 100, 2, estimator=woi.NAIVE, **kw)
     with pytest.raises(woi.WoiError, match="INVALID_ARG"):    # (N + 1)^(M + 1) = 3^20 > 2^31
