@@ -1,28 +1,29 @@
 #!/usr/bin/env python3
 """Walk-on-Interfaces benchmark on one MI355X.
 
-Headline workload (the 2D star tree): unit disk containing 3 nested star
-interfaces r0 (1 + 0.2 cos k t) with (r0, k) = (0.7, 3), (0.4, 5), (0.2, 7) as 2048-vertex
-polylines and 5 circular inclusions (N = 9 regions, depth 3), sigma = 10^U(-1, 2), 5-mode
-random Fourier flux data with zero mean; 4096 evaluation points (25 % within 1e-3 of an
-interface); W = 1e5 walkers per point, M = 4; values and gradients.
+Headline workload (the batched uneven 2D instances): 512 independent problems, each the unit
+disk with 1-16 circle or star interfaces (stars r0 (1 + 0.2 cos k t) as 512-vertex polylines) in
+a random nesting tree, sigma = 10^U(-1, 3), 5-mode random Fourier flux data with zero mean,
+P = 2^U(4, 10) points and W = 10^U(3, 6) walkers per point, M = 4.  One step = the whole batch
+estimated once (values and gradients of every point), inputs resident in HBM, as ONE persistent
+graph launch (queue reset, persistent walk kernel, reduction) with FP32 walks and FP64
+per-point sums; the same batch in FP64 gives the equal-standard-error comparison and the paired
+FP32 - FP64 difference on identical random streams.
 
-One step = one full estimate of all points, inputs resident in HBM.  The headline path is
-FP32-batched: FP32 walks with FP64 per-point sums and the wave-uniform shared schedule, run
-as one persistent batched graph launch (queue reset, persistent walk kernel, reduction);
-the FP64 plain path (the per-point walk kernel in FP64) gives the equal-standard-error
-comparison, and the FP32 per-point kernel is reported beside it.  Beside it the line reports, at their full sizes: the star tree
-with shared trajectories (B = 16 <= 0.5 % of the points, Sec. 4.6), the 512-instance batch
-(one persistent graph launch), 3D spheres + ellipsoids with the variance-reduced estimator,
-and the 6D nested spheres; each with its FP64 plain comparison at equal SE and the paired
-FP32 - FP64 difference on identical random streams.  Prints one JSON line.
+Beside it, one compact record per configuration ("configs", printed last): the concentric
+disk (FP64 plain, W = 1e4), the 2D star tree (FP32 batched / per point / VR / shared
+trajectories against FP64 plain), the 3D sphere + ellipsoid tree (VR), the 6D nested spheres,
+the point-charge ellipsoids (3-6D), the triangle-mesh tree and the naive Markov trees; each with
+its FP32-vs-FP64 decision-flip rate on identical streams.  Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
 import ctypes
 import json
+import math
 import os
+import platform
 import sys
 import time
 
@@ -31,21 +32,31 @@ sys.path.insert(0, ROOT)
 
 METRIC = "walk-steps/s and eval-points/s at fixed std. error, FP32-batched vs FP64 plain"
 
-# Algorithmic FP work per event of the 2D walk kernel (counted from the kernel source; a
+# Algorithmic FP work per event of the 2D walk kernels (counted from the kernel source; a
 # transcendental counts as one flop, an FMA as two, compares and integer work count zero).
 FLOPS_PER_WALKER_STEP = 29      # Phi + grad Phi + accumulation (19) and the Q/T/sign update (10)
 FLOPS_PER_OTHER = 18            # uniform re-sample + |K*| |dOmega| factor
 FLOPS_PER_NODE_TEST = 4         # distance of a block end vertex from the line (two FMAs)
 FLOPS_PER_SEGMENT_TEST = 4      # distance of the segment end vertex (crossings add ~10, rare)
 FLOPS_PER_WALKER = 57           # step-0 datum b(y_0) (5-mode Fourier) and Q_0
-PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 (packed) peak
-# HBM bytes per launch of the timed FP32 walk kernel at W = 1e5, from the FETCH_SIZE and
-# WRITE_SIZE passes in profiles/headline_kernels_star_tree_2d_counters.md, scaled by what the same
-# counters read for a 1 GiB device copy.  None whenever the kernel has changed since those
-# passes were taken.
-TRAFFIC_BYTES = 858 * 1024 * 2.0 + 49152 * 1024 * 1.0
-# The same for the persistent batch kernel of the headline graph.
-BATCH_TRAFFIC_BYTES = 1790 * 1024 * 2.0 + 249172 * 1024 * 1.0
+PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 peak (packed FMA)
+# HBM bytes per launch of the headline batch kernel (512 instances), from the FETCH_SIZE and
+# WRITE_SIZE passes summarised in profiles/, each scaled by what the same counter reads for a
+# 1 GiB device copy.  None whenever the kernel has changed since those passes were taken.
+BATCH_TRAFFIC_BYTES = None
+
+
+def sig(x, n=4):
+    """Round every float of a nested record to n significant digits (keeps the line short)."""
+    if isinstance(x, float):
+        if not math.isfinite(x) or x == 0.0:
+            return x
+        return round(x, n - 1 - int(math.floor(math.log10(abs(x)))))
+    if isinstance(x, dict):
+        return {k: sig(v, n) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [sig(v, n) for v in x]
+    return x
 
 
 def eval_flops_per_pair(m):
@@ -76,9 +87,9 @@ class HipEvents:
         return t.value
 
 
-def flops_of(counts):
+def flops_of(counts, M=4):
     walker_steps, other, nodes, segs = counts[0], counts[7], counts[5], counts[6]
-    walkers = walker_steps / 5.0
+    walkers = walker_steps / (M + 1.0)
     return (FLOPS_PER_WALKER_STEP * walker_steps + FLOPS_PER_OTHER * other + FLOPS_PER_NODE_TEST * nodes +
             FLOPS_PER_SEGMENT_TEST * segs + FLOPS_PER_WALKER * walkers)
 
@@ -136,10 +147,10 @@ class BatchPath:
     (fill, persistent walk kernel, reduction) with the tuned launch shape.  Step k replays
     the cached graph with seed seed0 + k (the library refreshes its seed table first)."""
 
-    def __init__(self, woi, torch, prob, pts, walks, M, precision, seed0=1, counters=None):
+    def __init__(self, woi, torch, prob, pts, walks, M, precision, seed0=1, counters=None, estimator=0):
         self.torch, self.seed0 = torch, seed0
         self.b = woi.Batch([dict(problem=prob, points=pts, walks=walks, M=M, seed=seed0, precision=precision,
-                                 schedule_mode=woi.SCHED_SHARED)], counters=counters)
+                                 estimator=estimator, schedule_mode=woi.SCHED_SHARED)], counters=counters)
         self.first = None
 
     def __call__(self, k, events=None):
@@ -166,8 +177,24 @@ def paired(r32, r64):
     return {"mean_z": float(np.mean(z)), "mean_abs_z": float(np.mean(np.abs(z))), "max_abs_z": float(np.max(np.abs(z)))}
 
 
-def config_block(woi, torch, ev, name, prob_desc, pts_np, walks, M, estimator, B, steps):
-    """Per-point FP32 and FP64 and shared-trajectory FP32 for one configuration."""
+def flips(woi, torch, prob, pts, n, M, estimator=0, instance=0):
+    """FP32 against FP64 walks on identical streams (shared schedule): the fraction of walkers
+    whose decision words (region, case, q, pick, sign, attempts) differ in some step, and the
+    FP64 rechecks per walker-step of the FP32 walks."""
+    import numpy as np
+    kw = dict(seed=31, estimator=estimator, schedule_mode=woi.SCHED_SHARED, instance=instance)
+    _, _, t64 = woi.trace(prob, pts, n, M, precision=woi.FP64, **kw)
+    _, _, t32 = woi.trace(prob, pts, n, M, precision=woi.FP32, **kw)
+    c = woi.new_counters()
+    woi.estimate(prob, pts, n * (2 if estimator == woi.VR else 1), M, precision=woi.FP32, counters=c, **kw)
+    same = torch.all(t64 == t32, dim=-1).cpu().numpy()
+    cn = c.cpu().numpy().astype(float)
+    return {"walkers": int(same.size), "flip_rate": float(1.0 - same.mean()),
+            "fp64_rechecks_per_walker_step": float(cn[8] / max(cn[0], 1.0))}
+
+
+def config_block(woi, torch, ev, prob_desc, pts_np, walks, M, estimator, B, steps, flip_pts=64, flip_walks=2000):
+    """FP32 per point, FP64 plain and FP32 shared trajectories for one configuration."""
     import numpy as np
     prob = woi.Problem(prob_desc)
     woi._lib.woi_problem_upload(prob.handle)
@@ -182,111 +209,165 @@ def config_block(woi, torch, ev, name, prob_desc, pts_np, walks, M, estimator, B
     t64 = fixed_se(r64, eps)
     pairs = P * (walks // K) * K * (M + 1)
     ev_fl = pairs * eval_flops_per_pair(m) / (float(np.mean(rsh["ms"])) * 1e-3) / 1e12
+    z = paired(r32, r64)
+    fl = flips(woi, torch, prob, pts[:flip_pts], flip_walks, M, estimator)
     return {
-        "workload": name, "points": P, "walkers": walks, "M": M, "estimator": "VR" if estimator else "plain",
-        "fixed_se": eps,
-        "fp32_per_point": {"walk_steps_per_s": point_steps / r32["wall"], "ms_per_step": r32["wall"] * 1e3,
-                           "speedup_vs_fp64_plain_fixed_se": t64 / fixed_se(r32, eps)},
-        "fp64_plain": {"walk_steps_per_s": point_steps / r64["wall"], "ms_per_step": r64["wall"] * 1e3,
-                       "eval_points_per_s_fixed_se": P / t64},
-        "fp32_shared_trajectories": {"batch_share": B, "walk_steps_per_s": point_steps / rsh["wall"],
-                                     "ms_per_step": rsh["wall"] * 1e3,
-                                     "eval_points_per_s_fixed_se": P / fixed_se(rsh, eps),
-                                     "speedup_vs_fp64_plain_fixed_se": t64 / fixed_se(rsh, eps),
-                                     "pair_eval_tflops_over_traj_plus_eval": ev_fl},
-        "fp32_vs_fp64_paired_z": paired(r32, r64),
+        "points": P, "W": walks, "M": M, "estimator": "VR" if estimator else "plain",
+        "fp32_ms": r32["wall"] * 1e3, "fp32_walk_steps_per_s": point_steps / r32["wall"],
+        "fp64_ms": r64["wall"] * 1e3, "fp64_points_per_s_fixed_se": P / t64,
+        "fp32_speedup_fixed_se": t64 / fixed_se(r32, eps),
+        "shared": {"B": B, "ms": rsh["wall"] * 1e3, "walk_steps_per_s": point_steps / rsh["wall"],
+                   "points_per_s_fixed_se": P / fixed_se(rsh, eps), "speedup_fixed_se": t64 / fixed_se(rsh, eps),
+                   "pair_tflops": ev_fl},
+        "paired_z": [z["mean_abs_z"], z["max_abs_z"]], "flip_rate": fl["flip_rate"],
+        "fp64_rechecks_per_step": fl["fp64_rechecks_per_walker_step"],
     }
 
 
-def naive_block(woi, torch, ev, prob, pts, steps):
+def disk_block(woi, torch, W, ev, steps):
+    """Concentric disk (sigma 10 around 1, b = cos theta on both): 64 polar-grid points, W = 1e4,
+    FP64 plain at M = 4, 8, 12, and FP32 at M = 4."""
+    import numpy as np
+    p, xs = W.concentric_disk_2d()
+    prob = woi.Problem(p)
+    woi._lib.woi_problem_upload(prob.handle)
+    pts = torch.tensor(xs, dtype=torch.float64, device="cuda")
+    out = {"points": len(xs), "W": 10000, "estimator": "plain"}
+    for M in (4, 8, 12):
+        r = Path(woi, torch, prob, pts, 10000, M, woi.FP64).run(ev, steps, 1)
+        out[f"fp64_M{M}_ms"] = r["wall"] * 1e3
+        out[f"fp64_M{M}_walk_steps_per_s"] = len(xs) * 10000 * (M + 1) / r["wall"]
+    r32 = Path(woi, torch, prob, pts, 10000, 4, woi.FP32).run(ev, steps, 1)
+    out["fp32_M4_ms"] = r32["wall"] * 1e3
+    fl = flips(woi, torch, prob, pts, 4000, 4)
+    out["flip_rate"] = fl["flip_rate"]
+    out["fp64_rechecks_per_step"] = fl["fp64_rechecks_per_walker_step"]
+    return out
+
+
+def star_tree_block(woi, torch, W, ev, steps, walks):
+    """2D star tree: FP32 batched (one-item batch graph), FP32 per point, FP64 plain, VR (FP32 and
+    FP64) and shared trajectories (B = 16 <= 0.5 % of the points, Sec. 4.6)."""
+    import numpy as np
+    prob_desc, pts_np = W.star_tree_2d()
+    M = 4
+    prob = woi.Problem(prob_desc)
+    woi._lib.woi_problem_upload(prob.handle)
+    pts = torch.tensor(pts_np, dtype=torch.float64, device="cuda")
+    P = pts.shape[0]
+    steps_all = P * walks * (M + 1)
+    cnt = woi.new_counters()
+    BatchPath(woi, torch, prob, pts, walks, M, woi.FP32, seed0=999, counters=cnt)(0)
+    c32 = cnt.cpu().numpy().astype(float)
+    rb = BatchPath(woi, torch, prob, pts, walks, M, woi.FP32).run(ev, steps, 1)
+    r64 = Path(woi, torch, prob, pts, walks, M, woi.FP64).run(ev, 1, 1)
+    rpp = Path(woi, torch, prob, pts, walks, M, woi.FP32).run(ev, steps, 1)
+    rvr = Path(woi, torch, prob, pts, walks, M, woi.FP32, woi.VR).run(ev, steps, 1)
+    rvr64 = Path(woi, torch, prob, pts, walks, M, woi.FP64, woi.VR).run(ev, 1, 0)
+    rsh = Path(woi, torch, prob, pts, walks, M, woi.FP32, 0, 16).run(ev, steps, 1)
+    eps = float(np.median(r64["se"]))
+    t64 = fixed_se(r64, eps)
+    kms = float(np.mean(rb["ms"]))
+    ach = flops_of(c32, M) / (kms * 1e-3) / 1e12
+    z = paired(rb, r64)
+    zvr = paired(rvr, rvr64)
+    fl = flips(woi, torch, prob, pts[::64], 2000, M)
+    flv = flips(woi, torch, prob, pts[::64], 1000, M, woi.VR)
+    return {
+        "points": P, "W": walks, "M": M,
+        "fp32_batched_ms": rb["wall"] * 1e3, "fp32_batched_walk_steps_per_s": c32[0] / rb["wall"],
+        "fp32_batched_frac": ach / PEAK_FP32_TFLOPS, "fp32_batched_speedup_fixed_se": t64 / fixed_se(rb, eps),
+        "fp32_per_point_ms": rpp["wall"] * 1e3,
+        "fp64_ms": r64["wall"] * 1e3, "fp64_points_per_s_fixed_se": P / t64,
+        "vr_fp32_ms": rvr["wall"] * 1e3, "vr_fp64_ms": rvr64["wall"] * 1e3,
+        "vr_fp32_speedup_fixed_se": t64 / fixed_se(rvr, eps),
+        "shared": {"B": 16, "ms": rsh["wall"] * 1e3, "walk_steps_per_s": steps_all / rsh["wall"],
+                   "speedup_fixed_se": t64 / fixed_se(rsh, eps),
+                   "pair_tflops": steps_all * eval_flops_per_pair(2) / (float(np.mean(rsh["ms"])) * 1e-3) / 1e12},
+        "paired_z": [z["mean_abs_z"], z["max_abs_z"]], "vr_paired_z": [zvr["mean_abs_z"], zvr["max_abs_z"]],
+        "flip_rate": fl["flip_rate"], "vr_flip_rate": flv["flip_rate"],
+        "fp64_rechecks_per_step": fl["fp64_rechecks_per_walker_step"],
+    }
+
+
+def naive_block(woi, torch, W, ev, steps):
     """Naive Markov-tree estimator (FP64) against the scheduled FP64 estimator on the star tree
     (N = 9), M = 1..3: per tree sum_{i=0}^{M} 9^{i+1} interface points, against M + 1 per
     scheduled walker.  Cost at the same standard error, and the two means in combined SEs
     (Theorem 2: same expectation)."""
     import numpy as np
+    prob_desc, pts_np = W.star_tree_2d()
+    prob = woi.Problem(prob_desc)
+    pts = torch.tensor(pts_np, dtype=torch.float64, device="cuda")
     P = pts.shape[0]
     N = prob.N
-    out = {"workload": "star tree 2D (N = 9: unit disk, 3 nested 2048-segment stars, 5 circles), 4096 points",
-           "M": {}}
+    out = {}
     for M, trees in ((1, 400), (2, 100), (3, 12)):
         nodes = sum(N ** (i + 1) for i in range(M + 1))
         rn = Path(woi, torch, prob, pts, trees, M, woi.FP64, woi.NAIVE).run(ev, steps, 1)
         rs = Path(woi, torch, prob, pts, 100000, M, woi.FP64).run(ev, 1, 1)
         eps = float(np.median(rs["se"]))
         z = (rn["mean"] - rs["mean"]) / np.sqrt(rn["se"] ** 2 + rs["se"] ** 2)
-        out["M"][str(M)] = {
-            "trees_per_point": trees, "tree_points": nodes, "lane_node_draws_per_tree": (M + 1) * N ** (M + 1),
-            "ms_per_step": rn["wall"] * 1e3, "kernel_ms": float(np.mean(rn["ms"])),
-            "tree_points_per_s": P * trees * nodes / rn["wall"],
-            "eval_points_per_s_fixed_se": P / fixed_se(rn, eps),
-            "scheduled_fp64_eval_points_per_s_fixed_se": P / fixed_se(rs, eps),
-            "scheduled_speedup_fixed_se": fixed_se(rn, eps) / fixed_se(rs, eps),
-            "naive_vs_scheduled_z": {"mean_abs": float(np.mean(np.abs(z))), "max_abs": float(np.max(np.abs(z)))}}
+        out[f"M{M}"] = {"trees": trees, "ms": rn["wall"] * 1e3, "tree_points_per_s": P * trees * nodes / rn["wall"],
+                        "scheduled_speedup_fixed_se": fixed_se(rn, eps) / fixed_se(rs, eps),
+                        "z_mean_abs": float(np.mean(np.abs(z)))}
     return out
 
 
-def run_batch(woi, torch, W, precision, steps, warmup, ev):
-    """The 512-instance 2D batch in one persistent graph launch (tuned launch shape).  An
-    untimed graph of the counting kernel gives the event counts; the timed graph replays
-    the non-counting kernel (same seed: the whole batch is recomputed every replay)."""
-    inst = W.star_tree_instances_2d()
-    probs = [woi.Problem(p) for p, _, _ in inst]
+def run_instances(woi, torch, inst, probs, precision, steps, warmup, ev, counters=None):
+    """The 512-instance 2D batch in one persistent graph launch (tuned launch shape); the timed
+    graph replays the whole batch (same seed: every replay recomputes it)."""
     entries = [dict(problem=g, points=x, walks=w, M=4, seed=4242, precision=precision, schedule_mode=woi.SCHED_SHARED,
                     instance=i) for i, (g, (_, x, w)) in enumerate(zip(probs, inst))]
-    cnt = woi.new_counters()
-    woi.Batch(entries, counters=cnt).run()
-    b = woi.Batch(entries)
+    b = woi.Batch(entries, counters=counters)
+    if counters is not None:
+        b.run()
+        return None
     wall, ms = timed(torch, ev, lambda k, e: b.run(events=e), steps, warmup)
-    counts = cnt.cpu().numpy().astype(float)
     se = [o[1].cpu().numpy() for o in b.outputs]
     mean = [o[0].cpu().numpy() for o in b.outputs]
-    return {"wall": wall, "ms": ms, "counts": counts, "se": se, "mean": mean,
-            "points": sum(x.shape[0] for _, x, _ in inst), "walkers": sum(x.shape[0] * w for _, x, w in inst)}
+    return {"wall": wall, "ms": ms, "se": se, "mean": mean}
 
 
-def batch_block(woi, torch, W, ev, steps):
-    import numpy as np
-    b32 = run_batch(woi, torch, W, woi.FP32, steps, 1, ev)
-    b64 = run_batch(woi, torch, W, woi.FP64, 1, 0, ev)
-    # fixed SE per instance: median SE of the FP64 batch, time rescaled by the mean SE^2 ratio
-    bt32 = b32["wall"] * np.mean([np.mean(a ** 2) / np.median(c) ** 2 for a, c in zip(b32["se"], b64["se"])])
-    bt64 = b64["wall"] * np.mean([np.mean(c ** 2) / np.median(c) ** 2 for c in b64["se"]])
-    z = np.concatenate([(a - c) / s for a, c, s in zip(b32["mean"], b64["mean"], b64["se"])])
-    kms = float(np.mean(b32["ms"]))
-    bfl = flops_of(b32["counts"])
-    return {
-        "workload": "512 independent 2D instances: 1-16 circle/512-vertex star interfaces in random nesting trees, "
-                    "sigma 10^U(-1,3), P = 2^U(4,10), W = 10^U(3,6), M = 4; one persistent graph launch",
-        "points": b32["points"], "walkers": b32["walkers"],
-        "walk_steps_per_s": b32["counts"][0] / b32["wall"], "ms_per_step": b32["wall"] * 1e3, "graph_ms": kms,
-        "fp64_walk_steps_per_s": b64["counts"][0] / b64["wall"], "fp64_ms_per_step": b64["wall"] * 1e3,
-        "speedup_fp32_vs_fp64_fixed_se": bt64 / bt32,
-        "fp32_vs_fp64_paired_z": {"mean_z": float(np.mean(z)), "mean_abs_z": float(np.mean(np.abs(z))),
-                                  "max_abs_z": float(np.max(np.abs(z)))},
-        "roofline": {"bound": "alu", "achieved": bfl / (kms * 1e-3) / 1e12, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": bfl / (kms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, "traffic": None,
-                     "kernel": "batch_kernel<float, 2, false, false, WV, true> + fill + reduce (graph)",
-                     "counts_per_launch": {n: float(v) for n, v in zip(woi.COUNTER_NAMES, b32["counts"])}}}
-
-
-def cpu_baseline(prob, pts, walks, M, budget_s):
+def cpu_baseline(inst, budget_s):
+    """The FP64 oracle on the host cores over a fixed spread of the batch's instances, every point
+    of each, with W scaled down by one factor so that the run takes about budget_s seconds."""
     import numpy as np
     from oracle import oracle as O
-    threads = min(16, os.cpu_count() or 1)
-    op = O.OracleProblem(prob)
-    idx = np.linspace(0, len(pts) - 1, 64).astype(int)
+    ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    threads = min(16, ncpu)   # the CPU share of one GPU on the benchmark box
+    model = platform.processor() or ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    idx = np.linspace(0, len(inst) - 1, 32).round().astype(int)
+    ops = {int(i): O.OracleProblem(inst[i][0]) for i in idx}
+    # probe: the same instances at W = 64
     t = time.perf_counter()
-    _, _, _, _, c = O.estimate(op, pts[idx], 2000, M, seed=5, schedule_mode=1, threads=threads, groups=idx)
-    rate = c["walk_steps"] / (time.perf_counter() - t)
-    # points spread over the set, each with the full W, sized to the time budget
-    n_pts = int(max(threads, min(len(pts), budget_s * rate / (walks * (M + 1)))))
-    idx = np.linspace(0, len(pts) - 1, n_pts).astype(int)
+    steps = 0
+    for i in idx[:8]:
+        _, _, _, _, c = O.estimate(ops[int(i)], inst[i][1], 64, 4, seed=5, schedule_mode=1, threads=threads,
+                                   instance=int(i))
+        steps += c["walk_steps"]
+    rate = steps / (time.perf_counter() - t)
+    full = sum(len(inst[i][1]) * inst[i][2] * 5 for i in idx)
+    f = min(1.0, budget_s * rate / full)
     t = time.perf_counter()
-    _, _, _, _, c = O.estimate(op, pts[idx], walks, M, seed=6, schedule_mode=1, threads=threads, groups=idx)
+    steps = 0
+    for i in idx:
+        w = max(2, int(round(inst[i][2] * f)))
+        _, _, _, _, c = O.estimate(ops[int(i)], inst[i][1], w, 4, seed=6, schedule_mode=1, threads=threads,
+                                   instance=int(i))
+        steps += c["walk_steps"]
     dt = time.perf_counter() - t
-    return {"value": c["walk_steps"] / dt, "unit": "walk-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n_pts} of the 4096 points spread over the set, W = {walks} walkers each, FP64 oracle, "
-                      f"{c['walk_steps']} walker-steps in {dt:.1f} s"}
+    return {"value": steps / dt, "unit": "walk-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"32 of the 512 instances (every 16th), all their points, each W scaled by {f:.3g}; "
+                      f"FP64 oracle, {steps} walker-steps in {dt:.1f} s; host: {ncpu} CPUs available, "
+                      f"{os.cpu_count()} online, {model}"}
 
 
 def main():
@@ -294,17 +375,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--walks", type=int, default=100000)
-    ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--no-extra", action="store_true",
-                    help="measure only the headline path (skip shared trajectories, the instance batch, 3D and 6D)")
+    ap.add_argument("--no-extra", action="store_true", help="measure only the headline batch")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison of the headline batch")
     ap.add_argument("--extra-steps", type=int, default=2, help="timed steps of the other configurations")
     ap.add_argument("--blocks", default="all",
-                    help="comma-separated other configurations to run (shared_trajectories, batched_star_tree_instances, "
-                         "ellipsoid_tree_3d_vr, nested_spheres_6d, point_charge_ellipsoids, mesh_tree_3d, "
+                    help="comma-separated configurations to run besides the headline (disk_2d, star_tree_2d, "
+                         "ellipsoid_tree_3d_vr, spheres_6d, point_charge_ellipsoids, mesh_tree_3d, "
                          "naive_markov_trees), default all")
     ap.add_argument("--cpu-seconds", type=float, default=25.0)
+    ap.add_argument("--detail", default="", help="also write the full record to this JSON file")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after the run, copy this many bytes device-to-device three times (a plain copy "
                          "kernel of known size, to scale the FETCH_SIZE / WRITE_SIZE counters)")
@@ -322,125 +402,104 @@ def main():
 
     torch.cuda.set_device(0)
     ev = HipEvents()
-    prob_desc, pts_np = W.star_tree_2d()
-    M = 4
-    prob = woi.Problem(prob_desc)
-    woi._lib.woi_problem_upload(prob.handle)
-    pts = torch.tensor(pts_np, dtype=torch.float64, device="cuda")
-    P = pts.shape[0]
 
-    # headline: FP32 walks through the persistent batched graph; an untimed graph of the
-    # counting kernel on the same workload gives the event counts
+    # ---- headline: the 512 instances, FP32 walks, one persistent graph launch
+    inst = W.star_tree_instances_2d()
+    probs = [woi.Problem(p) for p, _, _ in inst]
     cnt = woi.new_counters()
-    BatchPath(woi, torch, prob, pts, args.walks, M, woi.FP32, seed0=999, counters=cnt)(0)
-    c32 = cnt.cpu().numpy().astype(float)
-    r32 = BatchPath(woi, torch, prob, pts, args.walks, M, woi.FP32).run(ev, args.steps, args.warmup)
-    # FP64 plain: the per-point walk kernel in FP64
-    p64 = Path(woi, torch, prob, pts, args.walks, M, woi.FP64)
-    c64 = p64.counts()
-    r64 = p64.run(ev, args.fp64_steps, min(args.warmup, 1))
-    # FP32 per-point walk kernel (same samples, one launch per estimate)
-    pp = Path(woi, torch, prob, pts, args.walks, M, woi.FP32)
-    cpp = pp.counts()
-    rpp = pp.run(ev, args.steps, args.warmup)
-
-    eps = float(np.median(r64["se"]))                  # fixed SE: median per-point SE of FP64 plain
-    t32_eps, t64_eps = fixed_se(r32, eps), fixed_se(r64, eps)
-    kern_ms = float(np.mean(r32["ms"]))
-    flops = flops_of(c32)
-    achieved = flops / (kern_ms * 1e-3) / 1e12
-    kern64_ms = float(np.mean(r64["ms"]))
-    kpp_ms = float(np.mean(rpp["ms"]))
+    run_instances(woi, torch, inst, probs, woi.FP32, 0, 0, ev, counters=cnt)      # counting graph (untimed)
+    counts = cnt.cpu().numpy().astype(float)
+    b32 = run_instances(woi, torch, inst, probs, woi.FP32, args.steps, args.warmup, ev)
+    kms = float(np.mean(b32["ms"]))
+    flops = flops_of(counts)
+    achieved = flops / (kms * 1e-3) / 1e12
+    n_points = sum(x.shape[0] for _, x, _ in inst)
     rec = {
         "metric": METRIC,
-        "value": c32[0] / r32["wall"],
+        "value": counts[0] / b32["wall"],
         "unit": "walk-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r32["wall"] * 1e3,
+        "ms_per_step": b32["wall"] * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "2D tree: unit disk, 3 nested 2048-vertex star polylines (k=3,5,7) + 5 circles, "
-                               "sigma 10^U(-1,2), 5-mode Fourier jump data; 4096 points (25% within 1e-3 of an "
-                               "interface); W=1e5 walkers, M=4; values + gradients",
-                   "points": P, "walkers": args.walks, "M": M, "estimator": "plain", "schedule": "shared",
-                   "precision": "FP32 walks, FP64 per-point sums",
-                   "path": "persistent batched graph launch (woi_estimate_batch, one instance, tuned shape)"},
-        "eval_points_per_s_fixed_se": P / t32_eps,
-        "fixed_se": eps,
-        "fp64_plain": {"walk_steps_per_s": c64[0] / r64["wall"], "ms_per_step": r64["wall"] * 1e3,
-                       "eval_points_per_s_fixed_se": P / t64_eps, "walk_kernel_ms": kern64_ms,
-                       "fp64_tflops": flops_of(c64) / (kern64_ms * 1e-3) / 1e12},
-        "speedup_fp32_vs_fp64_fixed_se": t64_eps / t32_eps,
-        "fp32_vs_fp64_paired_z": paired(r32, r64),
-        "graph_ms": kern_ms,
-        "fp32_per_point": {"walk_steps_per_s": cpp[0] / rpp["wall"], "ms_per_step": rpp["wall"] * 1e3,
-                           "walk_kernel_ms": kpp_ms, "speedup_vs_fp64_plain_fixed_se": t64_eps / fixed_se(rpp, eps),
-                           "tflops": flops_of(cpp) / (kpp_ms * 1e-3) / 1e12,
-                           "traffic": TRAFFIC_BYTES if args.walks == 100000 else None},
+        "config": {"workload": "batched uneven 2D instances: 512 problems, each the unit disk with 1-16 circle / "
+                               "512-vertex star interfaces in a random nesting tree, sigma 10^U(-1,3), 5-mode Fourier "
+                               "flux data; P = 2^U(4,10) points, W = 10^U(3,6) walkers, M = 4; values + gradients",
+                   "instances": len(inst), "points": n_points, "walker_steps": counts[0],
+                   "precision": "FP32 walks, FP64 per-point sums", "schedule": "shared",
+                   "path": "one persistent graph launch (woi_estimate_batch: queue reset, batch_kernel, reduction)"},
+        "graph_ms": kms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": BATCH_TRAFFIC_BYTES if args.walks == 100000 else None,
-                     "kernel": "batch_kernel<float, 2, false, false, WV, true> (FP32, 2D, plain, LDS-staged polylines; "
-                               "time over the whole graph: fill + persistent kernel + reduction)",
-                     "flops_per_launch": flops,
-                     "counts_per_launch": {n: float(v) for n, v in zip(woi.COUNTER_NAMES, c32)}},
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": BATCH_TRAFFIC_BYTES,
+                     "kernel": "batch_kernel<float, 2, false, false, WV, true> (time: the whole graph)",
+                     "flops_per_launch": flops},
     }
+    if not args.no_fp64:
+        b64 = run_instances(woi, torch, inst, probs, woi.FP64, 1, 0, ev)
+        # fixed SE per instance: median SE of the FP64 batch, time rescaled by the mean SE^2 ratio
+        bt32 = b32["wall"] * np.mean([np.mean(a ** 2) / np.median(c) ** 2 for a, c in zip(b32["se"], b64["se"])])
+        bt64 = b64["wall"] * np.mean([np.mean(c ** 2) / np.median(c) ** 2 for c in b64["se"]])
+        z = np.concatenate([(a - c) / s for a, c, s in zip(b32["mean"], b64["mean"], b64["se"])])
+        rec["eval_points_per_s_fixed_se"] = n_points / bt32
+        rec["fp64_batch"] = {"ms_per_step": b64["wall"] * 1e3, "walk_steps_per_s": counts[0] / b64["wall"],
+                             "eval_points_per_s_fixed_se": n_points / bt64}
+        rec["speedup_fp32_vs_fp64_fixed_se"] = bt64 / bt32
+        rec["fp32_vs_fp64_paired_z"] = {"mean_z": float(np.mean(z)), "mean_abs_z": float(np.mean(np.abs(z))),
+                                        "max_abs_z": float(np.max(np.abs(z)))}
+    sel = np.linspace(0, len(inst) - 1, 16).round().astype(int)
+    fr = [flips(woi, torch, probs[i], inst[i][1][:64], 500, 4, instance=int(i)) for i in sel]
+    rec["flips"] = {"instances": 16, "walkers": sum(f["walkers"] for f in fr),
+                    "flip_rate": float(np.average([f["flip_rate"] for f in fr], weights=[f["walkers"] for f in fr])),
+                    "fp64_rechecks_per_walker_step": float(counts[8] / max(counts[0], 1.0))}
+    rec["counts_per_launch"] = {n: float(v) for n, v in zip(woi.COUNTER_NAMES, counts)}
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
+
     blocks = set(args.blocks.split(",")) if args.blocks != "all" else None
 
     def want(name):
         return not args.no_extra and (blocks is None or name in blocks)
 
-    B = 16                                              # <= 0.5 % of the 4096 points
-    if want("shared_trajectories"):
-        rsh = Path(woi, torch, prob, pts, args.walks, M, woi.FP32, 0, B).run(ev, args.steps, args.warmup)
-        pairs = P * args.walks * (M + 1)
-        rec["shared_trajectories"] = {
-            "batch_share": B, "walk_steps_per_s": pairs / rsh["wall"], "ms_per_step": rsh["wall"] * 1e3,
-            "traj_plus_eval_ms": float(np.mean(rsh["ms"])),
-            "eval_points_per_s_fixed_se": P / fixed_se(rsh, eps),
-            "speedup_vs_fp64_plain_fixed_se": t64_eps / fixed_se(rsh, eps),
-            "pair_eval_tflops_over_traj_plus_eval":
-                pairs * eval_flops_per_pair(2) / (float(np.mean(rsh["ms"])) * 1e-3) / 1e12}
-    if want("batched_star_tree_instances"):
-        rec["batched_star_tree_instances"] = batch_block(woi, torch, W, ev, args.extra_steps)
+    cfg = {}
+    es = args.extra_steps
+    if want("disk_2d"):
+        cfg["disk_2d"] = disk_block(woi, torch, W, ev, es)
+    if want("star_tree_2d"):
+        cfg["star_tree_2d"] = star_tree_block(woi, torch, W, ev, es, 100000)
     if want("ellipsoid_tree_3d_vr"):
         p4, x4 = W.ellipsoid_tree_3d()
-        rec["ellipsoid_tree_3d_vr"] = config_block(
-            woi, torch, ev, "unit ball, spheres 0.6 > 0.3, 10 ellipsoids (semi-axes 0.03-0.08), sigma 10^U(log .5, "
-            "log 50), real SH l <= 4 data; 16384 points; VR, W = 1e5 walkers, M = 6", p4, x4, 100000, 6, 1, 64,
-            args.extra_steps)
-    if want("nested_spheres_6d"):
+        cfg["ellipsoid_tree_3d_vr"] = config_block(woi, torch, ev, p4, x4, 100000, 6, 1, 64, es)
+    if want("spheres_6d"):
         p5, x5 = W.nested_spheres_6d()
-        rec["nested_spheres_6d"] = config_block(
-            woi, torch, ev, "unit 6-ball, spheres 0.7 > 0.35, sigma (1, 5, 0.2), c + lambda x1/|x| data; 1024 points; "
-            "W = 1e6, M = 8", p5, x5, 1000000, 8, 0, 4, args.extra_steps)
+        cfg["spheres_6d"] = config_block(woi, torch, ev, p5, x5, 1000000, 8, 0, 4, es, flip_walks=1000)
     if want("point_charge_ellipsoids"):
         # three nested ellipsoids around the potential |x|^(2-m) of a point charge, m = 3..6
-        # (1e4 points; M = m + 2 as the paper walks them; W = 2e5 keeps the run short, the rates
-        # do not depend on W)
-        rec["point_charge_ellipsoids"] = {}
+        # (1e4 points; M = m + 2 as the paper walks them; W = 2e5: the rates do not depend on W)
         for m in (3, 4, 5, 6):
             pm, xm = W.point_charge_ellipsoids(m)
-            rec["point_charge_ellipsoids"][f"{m}d"] = config_block(
-                woi, torch, ev, f"{m}D: 3 nested ellipsoids (centres 1.3/1.4/1.6 e1), sigma (1.1, 1.3, 0.9), data "
-                f"from u = |x|^(2-m); 10000 points; W = 2e5, M = {m + 2}", pm, xm, 200000, m + 2, 0, 32,
-                args.extra_steps)
+            cfg[f"point_charge_{m}d"] = config_block(woi, torch, ev, pm, xm, 200000, m + 2, 0, 32, es, flip_walks=500)
     if want("mesh_tree_3d"):
-        # triangle-mesh interfaces (BVH line/ray hits over 1280 triangles per mesh)
         p6, x6 = W.mesh_tree_3d()
-        rec["mesh_tree_3d"] = config_block(
-            woi, torch, ev, "3D: jittered icosphere (R 1, 1280 triangles) around a jittered icosphere (R 0.45, 1280 "
-            "triangles) and a sphere; sigma (1, 4, 0.5); quadratic direction-polynomial data; 4096 points; W = 2e4, "
-            "M = 4", p6, x6, 20000, 4, 0, 16, args.extra_steps)
+        cfg["mesh_tree_3d"] = config_block(woi, torch, ev, p6, x6, 20000, 4, 0, 16, es, flip_walks=500)
     if want("naive_markov_trees"):
-        rec["naive_markov_trees"] = naive_block(woi, torch, ev, prob, pts, args.extra_steps)
-    if not args.no_cpu:
-        rec["cpu_baseline"] = cpu_baseline(prob_desc, pts_np, args.walks, M, args.cpu_seconds)
-    print(json.dumps(rec), flush=True)
+        cfg["naive_markov_trees"] = naive_block(woi, torch, W, ev, es)
+    headline_cfg = {"instances_2d": {
+        "ms": rec["ms_per_step"], "walk_steps_per_s": rec["value"], "frac": rec["roofline"]["frac"],
+        "speedup_fixed_se": rec.get("speedup_fp32_vs_fp64_fixed_se"),
+        "paired_z": ([rec["fp32_vs_fp64_paired_z"]["mean_abs_z"], rec["fp32_vs_fp64_paired_z"]["max_abs_z"]]
+                     if "fp32_vs_fp64_paired_z" in rec else None),
+        "flip_rate": rec["flips"]["flip_rate"]}}
+    rec["configs"] = {**headline_cfg, **cfg}
+    rec = sig(rec)
+    if args.detail:
+        with open(args.detail, "w") as f:
+            json.dump(rec, f, indent=1)
+    print(json.dumps(rec, separators=(",", ":")), flush=True)
     if args.copy_bytes:
         src = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -18,6 +18,9 @@
  *     streams of the device they were created on.
  *   - Region 0 is the root: its interface is the outer boundary dOmega (Neumann data
  *     b_1 in the paper's 1-based numbering); every other region i has parent[i] < i.
+ *   - Deliberately absent: host-array outputs (results stay in device memory; copying them
+ *     to the host is the caller's, on its own stream) and cancellation (every call only
+ *     enqueues bounded work; a caller stops by enqueuing no more).
  */
 #ifndef WOI_H
 #define WOI_H
@@ -32,7 +35,8 @@ extern "C" {
 #define WOI_MAX_DIM 8
 #define WOI_MAX_REGIONS 32
 #define WOI_MAX_M 32
-#define WOI_COUNTERS 8
+#define WOI_COUNTERS 9
+#define WOI_NAIVE_MAX_LEAVES (1 << 24)
 
 typedef enum {
     WOI_OK = 0,
@@ -143,7 +147,8 @@ woi_status woi_problem_get_info(const woi_problem *p, woi_problem_info *out);
  * transitions of Eq. naive_woi_p; node (h_0..h_i) draws from its own counter, so a branch is
  * reused by all its extensions.  For NAIVE, walks = trees per point (walk_offset = first tree);
  * it requires batch_share = 1 and instance = 0 (WOI_E_UNSUPPORTED otherwise) and
- * (N + 1)^(M + 1) <= 2^31 (WOI_E_INVALID_ARG); FP32 walks keep FP64 tree sums; schedule_mode and
+ * (N + 1)^(M + 1) <= 2^31 and N^(M + 1) <= WOI_NAIVE_MAX_LEAVES leaves per tree, which bounds the
+ * work of one tree (WOI_E_INVALID_ARG otherwise); FP32 walks keep FP64 tree sums; schedule_mode and
  * block_size are ignored. */
 typedef enum { WOI_EST_PLAIN = 0, WOI_EST_VR = 1, WOI_EST_NAIVE = 2 } woi_estimator;
 typedef enum { WOI_PREC_FP64 = 0, WOI_PREC_FP32 = 1 } woi_precision;
@@ -179,7 +184,9 @@ woi_status woi_workspace_size(const woi_problem *p, int64_t P, const woi_query *
  *   counters: NULL or device uint64[WOI_COUNTERS] that the call adds to: [0] walker-steps,
  *             [1] redraws (q = 0), [2] rejections, [3] attempt-cap hits, [4] zero distances,
  *             [5] search node tests (polyline blocks, mesh BVH nodes), [6] segment or triangle
- *             tests, [7] uniform ("other") transitions
+ *             tests, [7] uniform ("other") transitions, [8] FP64 rechecks of FP32 decisions
+ *             (crossing and sign tests whose FP32 value fell in the rounding band; see
+ *             woi_stats)
  * Errors: INVALID_ARG (sizes, NULL, VR with odd walks, naive with (N+1)^(M+1) > 2^31),
  *         UNSUPPORTED (VR in dim > 3 or with meshes; naive with batch_share > 1 or instance != 0),
  *         OOM (workspace), DEVICE. */
@@ -187,8 +194,10 @@ woi_status woi_estimate(const woi_problem *p, const double *points, int64_t P, c
                         double *mean, double *se, double *grad, double *grad_se,
                         void *workspace, size_t workspace_bytes, uint64_t *counters, void *stream);
 
-/* Per-sample values for parity checks: samples [walk_offset, walk_offset + n_samples) of
- * every point.  F[(p*n + j)*K + k] = N * (walker k's sum), K = 1 (plain) or 2 (VR); for NAIVE,
+/* Per-sample values and per-step decisions of Alg. 2 / Alg. 3 (the scheduled interface, the
+ * transition case of Eq. naive_woi_p, the hit count q and the uniform pick among the hits of
+ * Sec. 4.2.3, and the sign of Eq. naive_woi_T), for parity checks: samples
+ * [walk_offset, walk_offset + n_samples) of every point.  F[(p*n + j)*K + k] = N * (walker k's sum), K = 1 (plain) or 2 (VR); for NAIVE,
  * F[p*n + j] = tree j's value and trace must be NULL (WOI_E_INVALID_ARG otherwise);
  * G[((p*n + j)*K + k)*dim + d]; trace[((p*n + j)*K + k)*(M+1) + i] = decision word
  * (bits 0-5 region, 6-7 case 0 first/1 same/2 descendant/3 other, 8-15 q,
@@ -202,8 +211,9 @@ woi_status woi_trace(const woi_problem *p, const double *points, int64_t P, cons
  * woi_estimate call up to the summation order of the per-point sums.
  *
  * Work: items (instance, tile of 64 points, chunk of samples), largest first, pulled by a
- * grid of resident workgroups from one atomic queue; each item writes its own partial
- * slots, and the reduction merges them in sample order (deterministic results).
+ * grid of resident workgroups from one atomic queue; the waves of a workgroup split an item,
+ * add their sums in wave order and write the item's one partial slot, and the reduction
+ * merges the slots in sample order (deterministic results).
  *
  * Requirements: all items share dim, estimator and precision; batch_share = 1; fewer than
  * 2^32 samples per point; samples_per_thread is ignored; block_size is the same for all
@@ -219,8 +229,9 @@ typedef struct {
     double *mean, *se, *grad, *grad_se;  /* device; grad/grad_se may be NULL            */
 } woi_batch_item;
 
-/* Device workspace (bytes) woi_estimate_batch needs: 256 bytes of queue head, then the
- * partial slots of the largest plan the tuner may choose.  Uploads the problems and
+/* Device workspace (bytes) woi_estimate_batch needs: 256 bytes of queue head, then one
+ * running-sum record per resident workgroup and the partial slots (one per item) of the
+ * largest plan the tuner may choose.  Uploads the problems and
  * queries the current device.  Errors: INVALID_ARG, UNSUPPORTED, DEVICE. */
 woi_status woi_batch_workspace_size(const woi_batch_item *items, int n, size_t *bytes);
 
@@ -240,6 +251,24 @@ woi_status woi_batch_workspace_size(const woi_batch_item *items, int n, size_t *
  * Errors: INVALID_ARG, UNSUPPORTED, OOM (workspace too small or plan allocation), DEVICE. */
 woi_status woi_estimate_batch(const woi_batch_item *items, int n, void *workspace, size_t workspace_bytes,
                               uint64_t *counters, void *stream);
+
+/* Statistics of one or more calls: the counter array they added to (see woi_estimate) and the
+ * time between the query's event_begin and event_end.
+ *   counters     device uint64[WOI_COUNTERS] (read with a synchronous copy) or NULL (zeros)
+ *   event_begin, event_end   hipEvent_t recorded by a call (query.event_begin / event_end), or
+ *                NULL: then seconds = -1.  Waits for event_end.
+ * walks = walker-steps / (M + 1) is left to the caller (steps per walker vary with M).
+ * Errors: INVALID_ARG (NULL out), DEVICE. */
+typedef struct {
+    uint64_t walker_steps, redraws, rejections, cap_hits, zero_distances;
+    uint64_t search_node_tests, segment_tests, other_transitions;
+    uint64_t fp64_fallbacks;  /* FP32 decisions recomputed in FP64 because their FP32 value
+                                 fell inside the rounding band (crossing parameters near the
+                                 self-hit threshold, near-zero vertex distances, near-tangent
+                                 discriminants and signs)                               */
+    double seconds;
+} woi_stats;
+woi_status woi_stats_read(const uint64_t *counters, void *event_begin, void *event_end, woi_stats *out);
 
 const char *woi_status_string(woi_status s);
 const char *woi_last_error(void);

@@ -32,7 +32,8 @@
 /* OR_PLANT selects a deliberately wrong variant, built only by the tests that show
    the pins reject it: 1 sign product from m = 0, 2 sign applied twice in the "other"
    transition, 3 no 1/2 weight on the last term, 4 K* with the normal at y_{i-1},
-   5 T without the intersection count q, 6 naive trees weighted by |alpha| instead of alpha. */
+   5 T without the intersection count q, 6 naive trees weighted by |alpha| instead of alpha,
+   7 the ellipsoid surface Jacobian of the VR half-measure quadrature without its square root. */
 #ifndef OR_PLANT
 #define OR_PLANT 0
 #endif
@@ -338,10 +339,12 @@ static int vr_attempt(const or_problem *pr, int h, int cls, words_t *w, double *
     return (beta_at(pr, h, y, *seg) >= 0) == (cls == 0);
 }
 
-/* ---- intersections: hits of the line/ray y + t d with interface g, in segment order */
+/* ---- intersections: hits of the line/ray y + t d with interface g, in segment order.
+   Returns the number q of hits; hits first .. first + cap - 1 (in that order) are stored. */
 typedef struct { double t; int seg; } hit_t;
 
-static int hits_of(const region_t *g, int m, const double *y, int yseg, const double *d, int ray, hit_t *out, int cap)
+static int hits_of(const region_t *g, int m, const double *y, int yseg, const double *d, int ray, hit_t *out,
+                   int first, int cap)
 {
     if (g->kind == OR_SPHERE || g->kind == OR_ELLIPSOID) {
         double yc[OR_MAX_DIM], Ad[OR_MAX_DIM], Ayc[OR_MAX_DIM];
@@ -357,16 +360,18 @@ static int hits_of(const region_t *g, int m, const double *y, int yseg, const do
             }
             a = dot(d, Ad, m); b = dot(d, Ayc, m); cc = dot(yc, Ayc, m) - 1;
         }
+        double t;
         if (!ray) { /* y on the quadric: the other root of t (a t + 2 b) = 0 */
-            double t = -2 * b / a;
+            t = -2 * b / a;
             if (t == 0) return 0;
-            out[0].t = t; out[0].seg = 0; return 1;
+        } else {
+            double disc = b * b - a * cc; /* origin strictly inside: cc < 0 */
+            if (disc < 0) return 0;
+            t = (-b + sqrt(disc)) / a;
+            if (!(t > 0)) return 0;
         }
-        double disc = b * b - a * cc; /* origin strictly inside: cc < 0 */
-        if (disc < 0) return 0;
-        double t = (-b + sqrt(disc)) / a;
-        if (!(t > 0)) return 0;
-        out[0].t = t; out[0].seg = 0; return 1;
+        if (first == 0 && cap > 0) { out[0].t = t; out[0].seg = 0; }
+        return 1;
     }
     int q = 0;
     if (g->kind == OR_MESH) {
@@ -387,10 +392,10 @@ static int hits_of(const region_t *g, int m, const double *y, int yseg, const do
             if (v < 0 || u + v > 1) continue;
             double t = (e2[0] * qv[0] + e2[1] * qv[1] + e2[2] * qv[2]) / det;
             if (ray ? !(t > 0) : fabs(t) <= 1e-12) continue;
-            if (q < cap) { out[q].t = t; out[q].seg = j; }
+            if (q >= first && q - first < cap) { out[q - first].t = t; out[q - first].seg = j; }
             q++;
         }
-        return q < cap ? q : cap;
+        return q;
     }
     for (int j = 0; j < g->nv; ++j) {
         if (!ray && j == yseg) continue;
@@ -403,10 +408,10 @@ static int hits_of(const region_t *g, int m, const double *y, int yseg, const do
         double s = (wx * d[1] - wy * d[0]) / den;
         if (s < 0 || s >= 1) continue;
         if (ray ? !(t > 0) : fabs(t) <= 1e-12) continue;   /* |t| <= 1e-12: y_{i-1} itself */
-        if (q < cap) { out[q].t = t; out[q].seg = j; }
+        if (q >= first && q - first < cap) { out[q - first].t = t; out[q - first].seg = j; }
         q++;
     }
-    return q < cap ? q : cap;
+    return q;
 }
 
 /* ---------------------------------------------------------------- Green's function */
@@ -477,20 +482,25 @@ static double transition(const or_problem *pr, int hprev, int h, words_t *w, con
             words_seek(w, (uint32_t)(att * nbl));
             unit_dir(m, w, d);
             double up = unif(words_next(w));
-            qn = hits_of(g, m, y, seg, d, rel == REL_DESC, hits, 512);
+            qn = hits_of(g, m, y, seg, d, rel == REL_DESC, hits, 0, 512);
             if (qn == 0) { cnt->redraws++; continue; }
             pick = (int)floor(up * qn);
             if (pick >= qn) pick = qn - 1;
+            const hit_t *hp = hits + pick;
+            if (pick >= 512) {   /* beyond the stored hits: find hit `pick` by a second scan */
+                hits_of(g, m, y, seg, d, rel == REL_DESC, hits, pick, 1);
+                hp = hits;
+            }
             if (g->kind == OR_POLYLINE) {
-                int j = hits[pick].seg;
+                int j = hp->seg;
                 const double *a = g->v + 2 * j, *b = g->v + 2 * ((j + 1) % g->nv);
                 double ex = b[0] - a[0], ey = b[1] - a[1];
                 double den = d[0] * ey - d[1] * ex;
                 double s = ((a[0] - y[0]) * d[1] - (a[1] - y[1]) * d[0]) / den;
                 yn[0] = a[0] + s * ex; yn[1] = a[1] + s * ey; *segn = j;
             } else {   /* quadric (seg 0) or mesh (the triangle hit) */
-                for (int j = 0; j < m; ++j) yn[j] = y[j] + hits[pick].t * d[j];
-                *segn = hits[pick].seg;
+                for (int j = 0; j < m; ++j) yn[j] = y[j] + hp->t * d[j];
+                *segn = hp->seg;
             }
             found = 1;
             break;
@@ -749,7 +759,8 @@ static void ring_point(const region_t *g, double th, double ph, double *y, doubl
         double uAu = 0;
         for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) uAu += u[i] * g->A[i * 3 + j] * u[j];
         for (int i = 0; i < 3; ++i) { double t = 0; for (int j = 0; j < 3; ++j) t += g->L[i * 3 + j] * u[j]; y[i] = g->c[i] + t; }
-        *J = g->detL * sqrt(uAu);
+        /* dA_y = det(A^{-1/2}) |A^{1/2} u| dA_u for y = c + A^{-1/2} u */
+        *J = g->detL * (OR_PLANT == 7 ? uAu : sqrt(uAu));
     }
 }
 
@@ -969,6 +980,8 @@ int or_problem_create(const or_problem_in *in, or_problem **out)
     /* VR halves */
     pr->vr_ok = m <= 3;
     for (int i = 0; i < N; ++i) if (pr->r[i].kind == OR_MESH) pr->vr_ok = 0;   /* no VR halves on meshes */
+    /* 2D halves are arclength intervals, built for circles and polylines only */
+    for (int i = 0; i < N; ++i) if (m == 2 && pr->r[i].kind == OR_ELLIPSOID) pr->vr_ok = 0;
     for (int i = 0; i < N; ++i) {
         region_t *g = &pr->r[i];
         if (!pr->vr_ok) {

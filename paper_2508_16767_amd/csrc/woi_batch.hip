@@ -5,9 +5,11 @@
 // a woi_estimate call with the same query.  What differs is the work distribution:
 // uneven instances (N, P, W all vary) are cut into items (instance, 64-point tile,
 // chunk of samples) listed largest-first, and a grid of resident workgroups pulls items
-// from one atomic queue head until the list is exhausted.  Each item's results go to
-// its own partial slots, and the reduction merges them in sample order, so the result
-// does not depend on which workgroup ran which item.
+// from one atomic queue head until the list is exhausted.  The waves of a workgroup split
+// an item's samples; their per-lane sums are added in wave order through the workgroup's
+// own record in global memory (L2-resident, reused item after item) and written to the
+// item's one partial slot, and the reduction merges the slots in chunk order, so the
+// result does not depend on which workgroup ran which item.
 #include "woi_walk.h"
 
 namespace woi {
@@ -18,7 +20,7 @@ __global__ __launch_bounds__(64 * WV) void batch_kernel(BParams bp) {
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     constexpr int K = VR ? 2 : 1;
     uint32_t staged = 0xFFFFFFFFu;   // instance whose polylines are in LDS (workgroup-uniform)
-    Counts tot{0, 0, 0, 0, 0, 0, 0, 0};
+    Counts tot{0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(bp.head, 1u);
         __syncthreads();
@@ -57,7 +59,7 @@ __global__ __launch_bounds__(64 * WV) void batch_kernel(BParams bp) {
         double S1 = 0, S2 = 0, G1[D], G2[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) { G1[i] = 0; G2[i] = 0; }
-        Counts cnt{0, 0, 0, 0, 0, 0, 0, 0};
+        Counts cnt{0, 0, 0, 0, 0, 0, 0, 0, 0};
         for (uint32_t s = s0; s < s1; ++s) {
             const uint32_t w = (uint32_t)(in.first_sample + s);
             double F = 0, Gs[D];
@@ -76,22 +78,43 @@ __global__ __launch_bounds__(64 * WV) void batch_kernel(BParams bp) {
 #pragma unroll
             for (int i = 0; i < D; ++i) { G1[i] += Gs[i]; G2[i] += Gs[i] * Gs[i]; }
         }
-        if (active) {
-            const uint64_t slot = in.slot0 + ((uint64_t)item.tile * in.n_chunks + item.chunk) * WV + wv;
-            double* o = bp.partials + (slot * 64 + lane) * (2 + 2 * D);
-            o[0] = S1; o[1] = S2;
+        // the waves' sums, added in wave order: wave r adds its own to the running record of
+        // waves 0..r-1; the last wave writes the item's slot (fields of one lane 64 apart)
+        {
+            constexpr int NF = 2 + 2 * D;
+            double v[NF];
+            v[0] = S1; v[1] = S2;
 #pragma unroll
-            for (int i = 0; i < D; ++i) { o[2 + i] = G1[i]; o[2 + D + i] = G2[i]; }
+            for (int i = 0; i < D; ++i) { v[2 + i] = G1[i]; v[2 + D + i] = G2[i]; }
+            double* acc = bp.wg_sums + (size_t)blockIdx.x * 64 * NF + lane;
+            const uint64_t slot = in.slot0 + (uint64_t)item.tile * in.n_chunks + item.chunk;
+            double* o = bp.partials + slot * 64 * NF + lane;
+            for (int r = 0; r < WV; ++r) {
+                if (wv == r) {
+                    if (r > 0) {
+#pragma unroll
+                        for (int f = 0; f < NF; ++f) v[f] = acc[64 * f] + v[f];
+                    }
+                    if (r < WV - 1) {
+#pragma unroll
+                        for (int f = 0; f < NF; ++f) acc[64 * f] = v[f];
+                    } else if (active) {
+#pragma unroll
+                        for (int f = 0; f < NF; ++f) o[64 * f] = v[f];
+                    }
+                }
+                if (r < WV - 1) __syncthreads();
+            }
         }
         if (COUNT && active) {   // idle lanes of a ragged tile walk too, but are not counted
             tot.steps += cnt.steps; tot.redraws += cnt.redraws; tot.rejections += cnt.rejections;
             tot.caps += cnt.caps; tot.zero += cnt.zero; tot.nodes += cnt.nodes; tot.segs += cnt.segs;
-            tot.other += cnt.other;
+            tot.other += cnt.other; tot.fb += cnt.fb;
         }
     }
     if constexpr (COUNT) {
         const uint32_t v[WOI_COUNTERS] = {tot.steps, tot.redraws, tot.rejections, tot.caps,
-                                          tot.zero, tot.nodes, tot.segs, tot.other};
+                                          tot.zero, tot.nodes, tot.segs, tot.other, tot.fb};
 #pragma unroll
         for (int i = 0; i < WOI_COUNTERS; ++i) {
             const uint64_t s = wave_sum((uint64_t)v[i]);
@@ -100,11 +123,13 @@ __global__ __launch_bounds__(64 * WV) void batch_kernel(BParams bp) {
     }
 }
 
-// One thread per (instance, point) of the flattened point list: merge the point's partial
-// slots in chunk order, and within a chunk in wave order (= sample order).
-__global__ void batch_reduce_kernel(BRParams rp) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= rp.n_points) return;
+// One wave per (instance, point) of the flattened point list: lane l merges the point's
+// chunk slots l, l + 64, ... in order, then the lanes' triples are combined in a fixed
+// butterfly.  Deterministic.
+__global__ __launch_bounds__(256) void batch_reduce_kernel(BRParams rp) {
+    const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (q >= rp.n_points) return;   // wave-uniform
     int lo = 0, hi = rp.n_inst - 1;           // last instance with out0 <= q
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -113,20 +138,22 @@ __global__ void batch_reduce_kernel(BRParams rp) {
     }
     const BInst& in = rp.inst[lo];
     const int64_t p = q - in.out0;
-    const int D = rp.dim, W = 2 + 2 * D, WV = rp.waves;
-    const uint64_t tile = (uint64_t)(p >> 6), lane = (uint64_t)(p & 63);
+    const int D = rp.dim, W = 2 + 2 * D;
+    const uint64_t tile = (uint64_t)(p >> 6), pl = (uint64_t)(p & 63);
     Moments f{0, 0, 0}, g[WOI_MAX_DIM];
     for (int i = 0; i < D; ++i) g[i] = Moments{0, 0, 0};
-    for (uint32_t c = 0; c < in.n_chunks; ++c) {
-        const uint32_t a = rp.ctab[in.c0 + c], len = rp.ctab[in.c0 + c + 1] - a;
-        for (int w = 0; w < WV; ++w) {
-            const uint32_t s0 = (uint32_t)(((uint64_t)len * w) / WV), s1 = (uint32_t)(((uint64_t)len * (w + 1)) / WV);
-            if (s1 == s0) continue;
-            const uint64_t slot = in.slot0 + (tile * in.n_chunks + c) * WV + w;
-            merge_partial(f, g, D, (double)(s1 - s0), rp.partials + (slot * 64 + lane) * W);
-        }
+    for (uint32_t c = (uint32_t)lane; c < in.n_chunks; c += 64) {
+        const uint32_t len = rp.ctab[in.c0 + c + 1] - rp.ctab[in.c0 + c];
+        const double* o = rp.partials + (in.slot0 + tile * in.n_chunks + c) * 64 * W + pl;
+        double r[2 + 2 * WOI_MAX_DIM];
+        for (int k = 0; k < W; ++k) r[k] = o[64 * k];
+        merge_partial(f, g, D, (double)len, r);
     }
-    store_moments(f, g, D, p, in.mean, in.se, in.grad, in.grad_se);
+    for (int o = 1; o < 64; o <<= 1) {
+        f.combine(shfl_xor_moments(f, o));
+        for (int i = 0; i < D; ++i) g[i].combine(shfl_xor_moments(g[i], o));
+    }
+    if (lane == 0) store_moments(f, g, D, p, in.mean, in.se, in.grad, in.grad_se);
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t n, uint32_t v) {
@@ -202,8 +229,7 @@ int batch_blocks_per_cu(int dim, bool vr, bool fp32, int waves, unsigned smem) {
 }
 
 hipError_t launch_batch_reduce(const BRParams& rp, hipStream_t s) {
-    const int bs = 256;
-    hipLaunchKernelGGL(batch_reduce_kernel, dim3((unsigned)((rp.n_points + bs - 1) / bs)), dim3(bs), 0, s, rp);
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3((unsigned)((rp.n_points + 3) / 4)), dim3(256), 0, s, rp);
     return hipGetLastError();
 }
 

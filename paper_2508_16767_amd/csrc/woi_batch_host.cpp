@@ -2,6 +2,10 @@
 // the launch-shape autotuner and the cached HIP graph (queue reset, persistent walk kernel,
 // reduction).
 //
+// Partial sums.  The waves of the workgroup that runs an item add their per-lane sums in wave
+// order (through the workgroup's record in the workspace) and write one slot per item, so the
+// partial traffic is (2 + 2 dim) doubles per (tile lane, chunk), whatever the launch shape.
+//
 // Plan.  Instance i has T_i = ceil(P_i / 64) tiles and S_i samples (walkers, or walker
 // pairs for VR).  A model cost e_i per sample and lane, (M_i + 1) K (1 + 3 f_i) with f_i the
 // schedule mass on polylines (Theorem 2: H ~ |alpha| / ||alpha||_1), converts samples into
@@ -63,7 +67,11 @@ struct Plan {
     std::vector<uint32_t> ctab;
     uint64_t n_slots = 0;
     int64_t n_points = 0;
-    size_t partial_bytes(int dim) const { return (size_t)n_slots * 64 * (2 + 2 * dim) * sizeof(double); }
+    // workspace after the queue head: the workgroups' running sums, then the partial slots
+    size_t wg_bytes(int dim) const { return ((size_t)grid * 64 * (2 + 2 * dim) * sizeof(double) + 255) & ~size_t(255); }
+    size_t partial_bytes(int dim) const {
+        return wg_bytes(dim) + (size_t)n_slots * 64 * (2 + 2 * dim) * sizeof(double);
+    }
     size_t table_bytes() const {   // [BInst][BItem][ctab][pad to 8][seeds]
         const size_t a = inst.size() * sizeof(woi::BInst) + items.size() * sizeof(woi::BItem) + ctab.size() * sizeof(uint32_t);
         return ((a + 7) & ~size_t(7)) + inst.size() * sizeof(uint64_t);
@@ -180,7 +188,7 @@ Plan make_plan(const woi_batch_item* items, const Spec& sp, Tune t, unsigned gri
         b.shared_sched = it.query.schedule_mode == WOI_SCHED_SHARED;
         b.instance = it.query.instance;
         b.lds = sp.smem ? (uint32_t)sp.ref[i].host->lds_bytes : 0u;
-        pl.n_slots += tiles * b.n_chunks * (uint64_t)t.waves;
+        pl.n_slots += tiles * b.n_chunks;
         out0 += it.P;
         for (uint64_t tile = 0; tile < tiles; ++tile)
             for (uint32_t k = 0; k < b.n_chunks; ++k) {
@@ -258,7 +266,7 @@ std::vector<uint64_t> seeds_of(const woi_batch_item* items, int n) {
     return s;
 }
 
-woi::BParams batch_params(const Plan& pl, const DevTables& t, void* ws, uint64_t* counters) {
+woi::BParams batch_params(const Plan& pl, const DevTables& t, void* ws, uint64_t* counters, int dim) {
     woi::BParams bp{};
     bp.inst = t.inst;
     bp.items = t.items;
@@ -266,7 +274,8 @@ woi::BParams batch_params(const Plan& pl, const DevTables& t, void* ws, uint64_t
     bp.seeds = t.seeds;
     bp.n_items = (uint32_t)pl.items.size();
     bp.head = static_cast<uint32_t*>(ws);
-    bp.partials = reinterpret_cast<double*>(static_cast<char*>(ws) + kHead);
+    bp.wg_sums = reinterpret_cast<double*>(static_cast<char*>(ws) + kHead);
+    bp.partials = reinterpret_cast<double*>(static_cast<char*>(ws) + kHead + pl.wg_bytes(dim));
     bp.counters = counters;
     return bp;
 }
@@ -300,7 +309,7 @@ woi_status autotune(const woi_batch_item* items, const Spec& sp, const Device& d
         DevTables t;
         st = upload(plans[c], seeds_of(items, sp.n), tbuf, t);
         if (st != WOI_OK) break;
-        const woi::BParams bp = batch_params(plans[c], t, ws, nullptr);
+        const woi::BParams bp = batch_params(plans[c], t, ws, nullptr, sp.dim);
         float ms = 0;
         for (int rep = 0; rep < 2 && st == WOI_OK; ++rep) {   // the first run loads the code object
             hipError_t e = woi::launch_fill_u32(bp.head, 1, 0, d.capture);
@@ -411,7 +420,7 @@ woi_status build_entry(const woi_batch_item* items, const Spec& sp, Device& d, v
         if (hipEventCreateWithFlags(&e.copied[b], hipEventDisableTiming) != hipSuccess)
             return set_error(WOI_E_DEVICE, "hipEventCreate failed");
     }
-    const woi::BParams bp = batch_params(e.plan, e.tab, ws, counters);
+    const woi::BParams bp = batch_params(e.plan, e.tab, ws, counters, sp.dim);
     woi::BRParams rp{};
     rp.inst = e.tab.inst;
     rp.ctab = e.tab.ctab;
@@ -419,7 +428,6 @@ woi_status build_entry(const woi_batch_item* items, const Spec& sp, Device& d, v
     rp.n_inst = sp.n;
     rp.n_points = e.plan.n_points;
     rp.dim = sp.dim;
-    rp.waves = e.plan.t.waves;
     // set the kernels' LDS limits before capturing
     if (woi::batch_blocks_per_cu(sp.dim, sp.vr, sp.f32, e.plan.t.waves, sp.smem) <= 0)
         return set_error(WOI_E_DEVICE, "batch kernel cannot be resident");

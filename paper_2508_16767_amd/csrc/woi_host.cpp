@@ -1271,6 +1271,9 @@ woi_status check_query_impl(const woi_problem* p, int64_t P, const woi_query* q)
         if (std::pow(p->H.N + 1.0, q->M + 1.0) > 2147483648.0)
             return fail(WOI_E_INVALID_ARG, "naive estimator: (N + 1)^(M + 1) = %.3g exceeds 2^31 tree-node ids",
                         std::pow(p->H.N + 1.0, q->M + 1.0));
+        if (std::pow((double)p->H.N, q->M + 1.0) > (double)WOI_NAIVE_MAX_LEAVES)
+            return fail(WOI_E_INVALID_ARG, "naive estimator: N^(M + 1) = %.3g leaves per tree exceed %d",
+                        std::pow((double)p->H.N, q->M + 1.0), WOI_NAIVE_MAX_LEAVES);
     }
     if (q->instance >= (1u << 24)) return fail(WOI_E_INVALID_ARG, "instance must be < 2^24");
     const uint64_t ns = q->estimator == WOI_EST_VR ? q->walks / 2 : q->walks;
@@ -1580,6 +1583,32 @@ woi_status woi_estimate(const woi_problem* p, const double* points, int64_t P, c
     rp.grad_se = grad_se;
     e = woi::launch_reduce(rp, s);
     if (e != hipSuccess) return fail(WOI_E_DEVICE, "reduce launch failed: %s", hipGetErrorString(e));
+    return WOI_OK;
+}
+
+woi_status woi_stats_read(const uint64_t* counters, void* event_begin, void* event_end, woi_stats* out) {
+    if (!out) return fail(WOI_E_INVALID_ARG, "NULL stats");
+    uint64_t c[WOI_COUNTERS] = {0};
+    if (counters && hipMemcpy(c, counters, sizeof c, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(WOI_E_DEVICE, "hipMemcpy of the counters failed");
+    out->walker_steps = c[0];
+    out->redraws = c[1];
+    out->rejections = c[2];
+    out->cap_hits = c[3];
+    out->zero_distances = c[4];
+    out->search_node_tests = c[5];
+    out->segment_tests = c[6];
+    out->other_transitions = c[7];
+    out->fp64_fallbacks = c[8];
+    out->seconds = -1.0;
+    if (event_begin && event_end) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(static_cast<hipEvent_t>(event_end)) != hipSuccess ||
+            hipEventElapsedTime(&ms, static_cast<hipEvent_t>(event_begin), static_cast<hipEvent_t>(event_end)) !=
+                hipSuccess)
+            return fail(WOI_E_DEVICE, "hipEventElapsedTime failed");
+        out->seconds = 1e-3 * (double)ms;
+    }
     return WOI_OK;
 }
 

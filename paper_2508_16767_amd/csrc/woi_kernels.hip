@@ -26,7 +26,7 @@ __global__ __launch_bounds__(LDS ? 512 : 256) void walk_kernel(KParams kp) {
     double S1 = 0, S2 = 0, G1[D], G2[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) { G1[i] = 0; G2[i] = 0; }
-    Counts cnt{0, 0, 0, 0, 0, 0, 0, 0};
+    Counts cnt{0, 0, 0, 0, 0, 0, 0, 0, 0};
     constexpr int K = VR ? 2 : 1;
     for (uint64_t s = s0; s < s1; ++s) {
         const uint32_t w = (uint32_t)(kp.first_sample + s);
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(LDS ? 512 : 256) void walk_kernel(KParams kp) {
     }
     if constexpr (COUNT) {
         const uint32_t v[WOI_COUNTERS] = {cnt.steps, cnt.redraws, cnt.rejections, cnt.caps,
-                                          cnt.zero, cnt.nodes, cnt.segs, cnt.other};
+                                          cnt.zero, cnt.nodes, cnt.segs, cnt.other, cnt.fb};
 #pragma unroll
         for (int i = 0; i < WOI_COUNTERS; ++i) {
             const uint64_t s = wave_sum(active ? (uint64_t)v[i] : 0);
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(LDS ? 512 : 256) void traj_kernel(KParams kp, TPara
     R* planes = static_cast<R*>(tp.traj);
     const uint64_t first = ((uint64_t)blockIdx.y * (blockDim.x / lg) + row) * tp.spt;
     const uint32_t s0 = (uint32_t)min(first, (uint64_t)tp.ns), s1 = (uint32_t)min(first + tp.spt, (uint64_t)tp.ns);
-    Counts cnt{0, 0, 0, 0, 0, 0, 0, 0};
+    Counts cnt{0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (uint32_t s = s0; s < s1; ++s) {
         const uint32_t w = (uint32_t)(kp.first_sample + tp.chunk_first + s);
         Start<R, D> st2[2];

@@ -94,8 +94,9 @@ hipError_t launch_naive(const KParams& kp, const NParams& np, int dim, bool fp32
 // ----------------------------------------------------------------------------- batches
 // Many instances in one persistent launch.  A work item is (instance, tile of 64 points,
 // chunk of samples); the workgroup that pulls it splits the chunk's samples evenly over
-// its WV waves, and wave w writes partial slot slot0 + (tile * n_chunks + chunk) * WV + w
-// (64 lanes x (2 + 2 dim) doubles).  Chunk k of an instance covers samples
+// its WV waves, adds their sums in wave order through its record wg_sums[blockIdx.x] and
+// writes partial slot slot0 + tile * n_chunks + chunk (64 lanes x (2 + 2 dim) doubles,
+// field f of lane l at f * 64 + l).  Chunk k of an instance covers samples
 // [ctab[c0 + k], ctab[c0 + k + 1]) counted from first_sample; every tile of the instance
 // has the same chunks.
 struct BInst {
@@ -123,6 +124,7 @@ struct BParams {
     const uint64_t* seeds;     // Philox key of every instance (refreshed before each launch)
     uint32_t n_items;
     uint32_t* head;            // queue head, zeroed before the launch
+    double* wg_sums;           // [grid][2 + 2 dim][64]: each workgroup's running sum of its waves
     double* partials;
     uint64_t* counters;
 };
@@ -133,7 +135,7 @@ struct BRParams {
     const double* partials;
     int n_inst;
     int64_t n_points;          // total points over all instances
-    int dim, waves;
+    int dim;
 };
 
 // Persistent walk kernel: grid = resident workgroups, 64 * waves threads each (waves 4 or 8).

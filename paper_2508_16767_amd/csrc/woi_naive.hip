@@ -24,11 +24,11 @@ constexpr uint32_t NAIVE_TAG = 0x80000000u;
 
 __device__ __forceinline__ void add_counts(Counts& a, const Counts& b) {
     a.steps += b.steps; a.redraws += b.redraws; a.rejections += b.rejections; a.caps += b.caps;
-    a.zero += b.zero; a.nodes += b.nodes; a.segs += b.segs; a.other += b.other;
+    a.zero += b.zero; a.nodes += b.nodes; a.segs += b.segs; a.other += b.other; a.fb += b.fb;
 }
 
-// R: FP64, or FP32 walks (each lane's sums in FP32, the tree's lane sum and the moments in
-// FP64).  LDS: in 3D, the mesh-capable instantiation (nothing is staged in LDS by this kernel).
+// R: FP64, or FP32 walks (each node's term c Phi, c grad Phi in FP32, converted to FP64 before it
+// joins the lane's sum; the tree's lane sum and the moments in FP64).  LDS: in 3D, the mesh-capable instantiation (nothing is staged in LDS by this kernel).
 template <typename R, int D, bool LDS, bool COUNT>
 __global__ __launch_bounds__(256) void naive_kernel(KParams kp, NParams np) {
     const DevProblem* __restrict__ dp = kp.dp;
@@ -45,10 +45,10 @@ __global__ __launch_bounds__(256) void naive_kernel(KParams kp, NParams np) {
     double S1 = 0, S2 = 0, G1[D], G2[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) { G1[i] = 0; G2[i] = 0; }
-    Counts cnt{0, 0, 0, 0, 0, 0, 0, 0};
+    Counts cnt{0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (uint64_t s = s0; s < s1; ++s) {
         const uint32_t w = (uint32_t)(kp.first_sample + s);
-        R Fl = 0, Gl[D];
+        double Fl = 0, Gl[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) Gl[i] = 0;
         for (uint32_t leaf = lane; leaf < np.leaves; leaf += 64) {
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void naive_kernel(KParams kp, NParams np) {
                 id = id * (N + 1) + (uint32_t)(h + 1);
                 const Stream st{kp.k0, kp.k1, w, (uint32_t)p, NAIVE_TAG | id};
                 const DevRegion* g = &dp->reg[h];
-                Counts c{0, 0, 0, 0, 0, 0, 0, 0};
+                Counts c{0, 0, 0, 0, 0, 0, 0, 0, 0};
                 bool alive = true;
                 if (i == 0) {   // y_0 uniform on dOmega_{h0}: Q = beta(y_0) |dOmega_{h0}|
                     int att;
@@ -91,7 +91,13 @@ __global__ __launch_bounds__(256) void naive_kernel(KParams kp, NParams np) {
                 }
                 if (counted) {
                     if (alive) {
-                        add_term<R, D>(dp, xh, xl, y, (i == M ? R(0.5) : R(1)) * A * Q * T, Fl, Gl, c);
+                        R Fn = 0, Gn[D];
+#pragma unroll
+                        for (int j = 0; j < D; ++j) Gn[j] = 0;
+                        add_term<R, D>(dp, xh, xl, y, (i == M ? R(0.5) : R(1)) * A * Q * T, Fn, Gn, c);
+                        Fl += (double)Fn;
+#pragma unroll
+                        for (int j = 0; j < D; ++j) Gl[j] += (double)Gn[j];
                         c.steps++;
                     }
                     if constexpr (COUNT) add_counts(cnt, c);
@@ -102,9 +108,9 @@ __global__ __launch_bounds__(256) void naive_kernel(KParams kp, NParams np) {
             }
         }
         // the tree's value: lanes summed in FP64 in a fixed butterfly (every lane ends with the same sum)
-        double F = (double)Fl, G[D];
+        double F = Fl, G[D];
 #pragma unroll
-        for (int i = 0; i < D; ++i) G[i] = (double)Gl[i];
+        for (int i = 0; i < D; ++i) G[i] = Gl[i];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             F += __shfl_xor(F, o, 64);
@@ -130,7 +136,7 @@ __global__ __launch_bounds__(256) void naive_kernel(KParams kp, NParams np) {
     }
     if constexpr (COUNT) {
         const uint32_t v[WOI_COUNTERS] = {cnt.steps, cnt.redraws, cnt.rejections, cnt.caps,
-                                          cnt.zero, cnt.nodes, cnt.segs, cnt.other};
+                                          cnt.zero, cnt.nodes, cnt.segs, cnt.other, cnt.fb};
 #pragma unroll
         for (int i = 0; i < WOI_COUNTERS; ++i) {
             const uint64_t t = wave_sum((uint64_t)v[i]);

@@ -149,7 +149,7 @@ template <> struct Pay<float> {
 };
 
 struct Counts {
-    uint32_t steps, redraws, rejections, caps, zero, nodes, segs, other;
+    uint32_t steps, redraws, rejections, caps, zero, nodes, segs, other, fb;
 };
 
 // Polyline tables staged by the workgroup (FP32 vertices, FP16 block bounds).

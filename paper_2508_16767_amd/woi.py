@@ -16,12 +16,12 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libwoi.so")
 
-MAX_DIM, MAX_REGIONS, MAX_M, N_COUNTERS = 8, 32, 32, 8
+MAX_DIM, MAX_REGIONS, MAX_M, N_COUNTERS = 8, 32, 32, 9
 PLAIN, VR, NAIVE = 0, 1, 2   # estimators: Alg. 2, Alg. 3, naive Markov trees (Sec. 4.2)
 FP64, FP32 = 0, 1
 SCHED_PER_GROUP, SCHED_SHARED = 0, 1
 COUNTER_NAMES = ("walker_steps", "redraws", "rejections", "cap_hits", "zero_distance", "node_tests",
-                 "segment_tests", "other_transitions")
+                 "segment_tests", "other_transitions", "fp64_fallbacks")
 
 
 class WoiError(RuntimeError):
@@ -67,8 +67,14 @@ class _BatchItem(C.Structure):
                 ("mean", C.c_void_p), ("se", C.c_void_p), ("grad", C.c_void_p), ("grad_se", C.c_void_p)]
 
 
+class Stats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in ("walker_steps", "redraws", "rejections", "cap_hits", "zero_distances",
+                                          "search_node_tests", "segment_tests", "other_transitions",
+                                          "fp64_fallbacks")] + [("seconds", C.c_double)]
+
+
 EXPORTS = ("woi_problem_create", "woi_problem_upload", "woi_problem_destroy", "woi_problem_get_info", "woi_workspace_size",
-           "woi_estimate", "woi_trace", "woi_batch_workspace_size", "woi_estimate_batch",
+           "woi_estimate", "woi_trace", "woi_batch_workspace_size", "woi_estimate_batch", "woi_stats_read",
            "woi_status_string", "woi_last_error")
 
 
@@ -88,6 +94,7 @@ def _load():
     lib.woi_batch_workspace_size.argtypes = [C.POINTER(_BatchItem), C.c_int, C.POINTER(C.c_size_t)]
     lib.woi_estimate_batch.argtypes = [C.POINTER(_BatchItem), C.c_int, C.c_void_p, C.c_size_t, C.c_void_p,
                                        C.c_void_p]
+    lib.woi_stats_read.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Stats)]
     lib.woi_status_string.restype = C.c_char_p
     lib.woi_status_string.argtypes = [C.c_int]
     lib.woi_last_error.restype = C.c_char_p
@@ -309,3 +316,14 @@ def estimate_batch(entries, block_size=0, counters=None):
 
 def new_counters(device="cuda"):
     return torch.zeros(N_COUNTERS, dtype=torch.int64, device=device)
+
+
+def stats(counters=None, events=None):
+    """woi_stats_read: the counters (a new_counters() tensor) and the seconds between two events
+    recorded by a call (-1 without events), as a dict."""
+    st = Stats()
+    ev = events if events is not None else (None, None)
+    _check(_lib.woi_stats_read(C.c_void_p(counters.data_ptr()) if counters is not None else None,
+                               C.c_void_p(ev[0]) if ev[0] else None, C.c_void_p(ev[1]) if ev[1] else None,
+                               C.byref(st)))
+    return {f: getattr(st, f) for f, _ in Stats._fields_}

@@ -101,11 +101,22 @@ def test_query_validation_without_gpu(woi):
     # naive Markov trees: batch_share 1, instance 0 and (N + 1)^(M + 1) <= 2^31
     for q, st in ((woi.make_query(100, 4, estimator=woi.NAIVE, batch_share=2), "WOI_E_UNSUPPORTED"),
                   (woi.make_query(100, 4, estimator=woi.NAIVE, instance=1), "WOI_E_UNSUPPORTED"),
-                  (woi.make_query(100, 19, estimator=woi.NAIVE), "WOI_E_INVALID_ARG")):
+                  (woi.make_query(100, 19, estimator=woi.NAIVE), "WOI_E_INVALID_ARG"),
+                  (woi.make_query(100, 24, estimator=woi.NAIVE), "WOI_E_INVALID_ARG")):
         with pytest.raises(woi.WoiError) as e:
             woi.workspace_size(prob, 16, q)
         assert e.value.status == st
     assert woi.workspace_size(prob, 64, woi.make_query(1000, 18, estimator=woi.NAIVE)) > 0   # 3^19 ids fit
+    # work bound: N^(M + 1) <= 2^24 leaves per tree (N = 9: M = 6 fits, M = 8 has ids but 9^9 leaves)
+    star = woi.Problem(W.star_tree_2d(n_points=8)[0])
+    assert woi.workspace_size(star, 64, woi.make_query(10, 6, estimator=woi.NAIVE)) > 0
+    with pytest.raises(woi.WoiError) as e:
+        woi.workspace_size(star, 64, woi.make_query(10, 8, estimator=woi.NAIVE))
+    assert e.value.status == "WOI_E_INVALID_ARG" and "leaves" in str(e.value)
+    # 2D ellipses are refused at compile time (the oracle's plain 2D ellipse is a pin only)
+    with pytest.raises(woi.WoiError) as e:
+        woi.Problem(W.single_ellipsoid_linear(2, [0.9, 0.5])[0])
+    assert e.value.status == "WOI_E_UNSUPPORTED" and "ellipse" in str(e.value)
     assert woi.workspace_size(prob, 64, woi.make_query(1000, 4, estimator=woi.NAIVE, precision=woi.FP32)) > 0
 
 
@@ -127,6 +138,13 @@ def test_host_compile_matches_oracle(woi, oracle_mod, make):
         assert np.allclose(a["area_minus"], b["area_minus"], rtol=1e-6, atol=1e-12 * scale)
     else:
         assert np.all(np.isnan(a["area_plus"]))
+
+
+def test_stats_without_counters_or_events(woi):
+    """woi_stats_read with neither counters nor events touches no device: zeros, seconds = -1."""
+    st = woi.stats()
+    assert all(st[k] == 0 for k in st if k != "seconds") and st["seconds"] == -1.0
+    assert len(woi.COUNTER_NAMES) == woi.N_COUNTERS == 9
 
 
 def test_batch_validation_without_gpu(woi):

@@ -160,6 +160,32 @@ def test_naive_fp32_paired_with_fp64():
     assert np.max(np.abs((mean - ref) / se32)) < 4.5
 
 
+def _naive_cases():
+    from test_oracle_pins import _star_tree, STAR_PTS
+    ps, _, _ = _star_tree()
+    pm, xm = W.mesh_tree_3d(n_points=6, subdiv=2)
+    return [("sphere_3d", W.zheng_ex3_3d(), W.ball_points(np.random.default_rng(3), 6, 3, 0.9), 3, 600),
+            ("mesh_3d", pm, xm, 2, 400),
+            ("star_tree_M3", ps, STAR_PTS, 3, 200)]
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_naive_fp32_paired_with_fp64_3d_mesh_star(case):
+    """FP32 naive walks (FP32 node terms taken to FP64 before they are summed) against FP64 trees on
+    identical node-keyed streams: a 3D sphere pair, triangle meshes, and the star tree at M = 3
+    (about 340 signed terms per tree)."""
+    name, p, pts, M, trees = _naive_cases()[case]
+    gp = woi.Problem(p)
+    F64, _, _ = woi.trace(gp, pts, trees, M, seed=12, estimator=woi.NAIVE)
+    F32, _, _ = woi.trace(gp, pts, trees, M, seed=12, estimator=woi.NAIVE, precision=woi.FP32)
+    F64, F32 = _np(F64)[..., 0], _np(F32)[..., 0]
+    rms = np.sqrt(np.mean(F64 ** 2))
+    close = np.abs(F32 - F64) <= 1e-3 * np.maximum(np.abs(F64), rms)
+    assert close.mean() > 0.98, name
+    se = F64.std(1, ddof=1) / np.sqrt(F64.shape[1])
+    assert np.all(np.abs(F32.mean(1) - F64.mean(1)) < 0.25 * se), (name, (F32.mean(1) - F64.mean(1)) / se)
+
+
 def test_naive_rejections():
     p, xs = W.concentric_disk_2d()
     gp = woi.Problem(p)

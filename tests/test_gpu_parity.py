@@ -258,11 +258,19 @@ def test_counters_and_errors():
     p, xs = W.concentric_disk_2d()
     gp = woi.Problem(p)
     c = woi.new_counters()
-    woi.estimate(gp, xs, 1000, 4, seed=2, counters=c)
+    hip = __import__("ctypes").CDLL("libamdhip64.so")
+    evs = []
+    for _ in range(2):
+        e = __import__("ctypes").c_void_p()
+        assert hip.hipEventCreate(__import__("ctypes").byref(e)) == 0
+        evs.append(e.value)
+    woi.estimate(gp, xs, 1000, 4, seed=2, counters=c, events=tuple(evs))
+    st = woi.stats(c, tuple(evs))                           # woi_stats_read: counters and seconds
     torch.cuda.synchronize()
     c = _np(c)
     assert c[0] == len(xs) * 1000 * 5
     assert c[3] == 0
+    assert st["walker_steps"] == c[0] and st["fp64_fallbacks"] == 0 and 0 < st["seconds"] < 10
     with pytest.raises(woi.WoiError):
         woi.estimate(gp, xs, 1001, 4, estimator=woi.VR)     # odd walker count for VR
     with pytest.raises(woi.WoiError):

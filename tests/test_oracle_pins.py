@@ -116,6 +116,61 @@ def test_vr_half_measures(oracle_mod):
     assert np.allclose(info["area_plus"], info["area"] / 2, rtol=1e-12)
 
 
+def test_vr_half_measures_ellipsoid_odd_data(oracle_mod):
+    """Variance reduction on an ellipsoid (Sec. 4.4): flux data n . g of a uniform field are odd
+    under y -> 2c - y, which maps the ellipsoid onto itself with the same surface element, so
+    {beta >= 0} and {beta < 0} are exact halves; their sum is Legendre's area.  The halves come
+    from the oracle's ring quadrature (ellipsoid Jacobian, sign breakpoints), not from its area
+    rule."""
+    for axes, direction in (([0.9, 0.6, 0.4], 0), ([0.5, 0.8, 0.3], 2)):
+        p, _, _ = W.single_ellipsoid_linear(3, axes, direction=direction)
+        info = oracle_mod.OracleProblem(p).info()
+        area = CF.ellipsoid3_area(*axes)
+        assert info["area_plus"][0] == pytest.approx(area / 2, rel=1e-8)
+        assert info["area_minus"][0] == pytest.approx(area / 2, rel=1e-8)
+
+
+def test_vr_half_measures_ellipsoid_uneven_split(oracle_mod):
+    """An uneven split: b = 0.35 + e . v in the direction e = (y - c)/|y - c| about a centre off
+    the ellipsoid's own.  The fraction of the surface with b >= 0, counted on the oracle's uniform
+    surface samples (pinned separately by the slab-area test), times Legendre's area, must match
+    the quadrature's |dOmega^+| within Monte Carlo error, and |dOmega^+| + |dOmega^-| = area."""
+    axes = [0.9, 0.6, 0.4]
+    p0, A, Q = W.single_ellipsoid_linear(3, axes, direction=0)
+    v = np.array([0.3, -0.8, 0.5])
+    c = np.array([0.1, 0.05, -0.02])
+    terms = {(0, 0, 0): 0.35, (1, 0, 0): v[0], (0, 1, 0): v[1], (0, 0, 1): v[2]}
+    p = W.Problem(3, [-1], [1.0], p0.shapes, [W.dirpoly(c, terms)], 2, "ellipsoid-uneven")
+    op = oracle_mod.OracleProblem(p)
+    info = op.info()
+    area = CF.ellipsoid3_area(*axes)
+    assert info["area_plus"][0] + info["area_minus"][0] == pytest.approx(area, rel=1e-8)
+    y = op.sample_surface(0, 17, 400000)
+    e = (y - c) / np.linalg.norm(y - c, axis=1, keepdims=True)
+    frac = np.mean(0.35 + e @ v >= 0)
+    assert 0.55 < frac < 0.9                                  # genuinely uneven
+    sd = np.sqrt(frac * (1 - frac) / len(y))
+    assert abs(info["area_plus"][0] / area - frac) < 5 * sd
+
+
+def test_ellipsoid_depolarization_gradient_vr(oracle_mod):
+    """The variance-reduced estimator (Alg. 3) on a 3D ellipsoid has the same exact gradient as
+    the plain one: first points on {beta >= 0} / {beta < 0} by sign rejection, weighted by the
+    half-measures.  (In 2D the halves are arclength intervals of circles and polylines: VR on an
+    ellipse is refused.)"""
+    dim, axes = 3, [0.9, 0.6, 0.4]
+    p2, _, _ = W.single_ellipsoid_linear(2, [0.9, 0.5], direction=0)
+    with pytest.raises(ValueError):
+        oracle_mod.estimate(oracle_mod.OracleProblem(p2), np.zeros((1, 2)), 100, 1, estimator=1)
+    p, A, Q = W.single_ellipsoid_linear(dim, axes, direction=0)
+    op = oracle_mod.OracleProblem(p)
+    pts = np.random.default_rng(0).standard_normal((3, dim)) * 0.1
+    for M in (1, 3):
+        _, _, g, gse, _ = oracle_mod.estimate(op, pts, 100000, M, seed=19, estimator=1)
+        gref = CF.ellipsoid_grad_uM(axes, Q, 0, M)
+        assert np.max(np.abs(_z(g, gref[None, :], gse))) < ZMAX
+
+
 def test_uniform_surface_samples(oracle_mod):
     """Uniform sampling on an ellipsoid: area fraction of a slab {|n1| < 0.5} matches quadrature,
     and on a polyline the arclength histogram is flat."""
@@ -396,7 +451,7 @@ def test_shared_trajectories_batch(oracle_mod):
 
 
 # ----------------------------------------------------------------------------- planted mistakes
-@pytest.mark.parametrize("plant", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("plant", [1, 2, 3, 4, 5, 6, 7])
 def test_pins_reject_planted_mistakes(oracle_mod, tmp_path, plant):
     """Each plausible mistake, planted in a copy of the oracle, fails one of the pins above."""
     libv = oracle_mod.load(oracle_mod.build_variant(plant, str(tmp_path)))
@@ -414,6 +469,14 @@ def test_pins_reject_planted_mistakes(oracle_mod, tmp_path, plant):
         ref = [CF.concentric_uM(*CFG1, 1, 2, 1, x, H, gH)[0] for x in pts]
         mean, se, _, _, _ = oracle_mod.estimate(op, pts, 100000, 1, seed=4, estimator=oracle_mod.NAIVE)
         z = _z(mean, ref, se)
+    elif plant == 7:  # wrong ellipsoid Jacobian in the VR half-measures: the VR gradient is off
+        axes = [0.9, 0.6, 0.4]
+        p, A, Q = W.single_ellipsoid_linear(3, axes, direction=0)
+        op = oracle_mod.OracleProblem(p, library=libv)
+        pts = np.random.default_rng(0).standard_normal((3, 3)) * 0.1
+        _, _, g, gse, _ = oracle_mod.estimate(op, pts, 100000, 1, seed=19, estimator=1)
+        z = _z(g, CF.ellipsoid_grad_uM(axes, Q, 0, 1)[None, :], gse).ravel()
+        assert op.info()["area_plus"][0] != pytest.approx(CF.ellipsoid3_area(*axes) / 2, rel=1e-3)
     elif plant == 4:  # normal at the wrong end of K* matters for the "other" transition
         p = W.concentric(2, [1.0, 0.5], [1.0, 3.0], [W.fourier([0, 0], 0, [0.5], [1.0]), W.fourier([0, 0], 0, [1.0], [0.0])])
         op = oracle_mod.OracleProblem(p, library=libv)
