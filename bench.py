@@ -46,6 +46,11 @@ PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 peak (packed FMA)
 BATCH_TRAFFIC_BYTES = None
 
 
+def log(msg):
+    """Progress of the run on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def sig(x, n=4):
     """Round every float of a nested record to n significant digits (keeps the line short)."""
     if isinstance(x, float):
@@ -409,7 +414,9 @@ def main():
     cnt = woi.new_counters()
     run_instances(woi, torch, inst, probs, woi.FP32, 0, 0, ev, counters=cnt)      # counting graph (untimed)
     counts = cnt.cpu().numpy().astype(float)
+    log("headline: counting graph done")
     b32 = run_instances(woi, torch, inst, probs, woi.FP32, args.steps, args.warmup, ev)
+    log(f"headline: FP32 batch {b32['wall'] * 1e3:.1f} ms per step")
     kms = float(np.mean(b32["ms"]))
     flops = flops_of(counts)
     achieved = flops / (kms * 1e-3) / 1e12
@@ -441,6 +448,7 @@ def main():
     }
     if not args.no_fp64:
         b64 = run_instances(woi, torch, inst, probs, woi.FP64, 1, 0, ev)
+        log(f"headline: FP64 batch {b64['wall'] * 1e3:.1f} ms")
         # fixed SE per instance: median SE of the FP64 batch, time rescaled by the mean SE^2 ratio
         bt32 = b32["wall"] * np.mean([np.mean(a ** 2) / np.median(c) ** 2 for a, c in zip(b32["se"], b64["se"])])
         bt64 = b64["wall"] * np.mean([np.mean(c ** 2) / np.median(c) ** 2 for c in b64["se"]])
@@ -457,8 +465,10 @@ def main():
                     "flip_rate": float(np.average([f["flip_rate"] for f in fr], weights=[f["walkers"] for f in fr])),
                     "fp64_rechecks_per_walker_step": float(counts[8] / max(counts[0], 1.0))}
     rec["counts_per_launch"] = {n: float(v) for n, v in zip(woi.COUNTER_NAMES, counts)}
+    log("headline: flip rates done")
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
+        log("cpu baseline done")
 
     blocks = set(args.blocks.split(",")) if args.blocks != "all" else None
 
@@ -469,25 +479,32 @@ def main():
     es = args.extra_steps
     if want("disk_2d"):
         cfg["disk_2d"] = disk_block(woi, torch, W, ev, es)
+        log("disk_2d done")
     if want("star_tree_2d"):
         cfg["star_tree_2d"] = star_tree_block(woi, torch, W, ev, es, 100000)
+        log("star_tree_2d done")
     if want("ellipsoid_tree_3d_vr"):
         p4, x4 = W.ellipsoid_tree_3d()
         cfg["ellipsoid_tree_3d_vr"] = config_block(woi, torch, ev, p4, x4, 100000, 6, 1, 64, es)
+        log("ellipsoid_tree_3d_vr done")
     if want("spheres_6d"):
         p5, x5 = W.nested_spheres_6d()
         cfg["spheres_6d"] = config_block(woi, torch, ev, p5, x5, 1000000, 8, 0, 4, es, flip_walks=1000)
+        log("spheres_6d done")
     if want("point_charge_ellipsoids"):
         # three nested ellipsoids around the potential |x|^(2-m) of a point charge, m = 3..6
         # (1e4 points; M = m + 2 as the paper walks them; W = 2e5: the rates do not depend on W)
         for m in (3, 4, 5, 6):
             pm, xm = W.point_charge_ellipsoids(m)
             cfg[f"point_charge_{m}d"] = config_block(woi, torch, ev, pm, xm, 200000, m + 2, 0, 32, es, flip_walks=500)
+            log(f"point_charge_{m}d done")
     if want("mesh_tree_3d"):
         p6, x6 = W.mesh_tree_3d()
         cfg["mesh_tree_3d"] = config_block(woi, torch, ev, p6, x6, 20000, 4, 0, 16, es, flip_walks=500)
+        log("mesh_tree_3d done")
     if want("naive_markov_trees"):
         cfg["naive_markov_trees"] = naive_block(woi, torch, W, ev, es)
+    log("configurations done: " + ", ".join(cfg))
     headline_cfg = {"instances_2d": {
         "ms": rec["ms_per_step"], "walk_steps_per_s": rec["value"], "frac": rec["roofline"]["frac"],
         "speedup_fixed_se": rec.get("speedup_fp32_vs_fp64_fixed_se"),

@@ -15,7 +15,7 @@
 namespace woi {
 
 template <typename R, int D, bool VR, bool COUNT, int WV, bool LDS>
-__global__ __launch_bounds__(64 * WV) void batch_kernel(BParams bp) {
+__global__ __launch_bounds__(64 * WV, (walk_waves_per_simd<R, D>())) void batch_kernel(BParams bp) {
     __shared__ uint32_t s_item;
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     constexpr int K = VR ? 2 : 1;

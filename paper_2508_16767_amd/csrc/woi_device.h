@@ -32,7 +32,7 @@ constexpr int DK_DIRPOLY_HORNER = 16;
 //   for every level l >= 1 and aligned block b (vertices [b 2^l, min((b+1) 2^l, nv)]),
 //   bnd[(N2 >> l) + b] bounds the distance of the block's vertices from its chord (heap
 //   layout, N2 = nv rounded up to a power of two, entry 0 unused); the segments (level 0)
-//   follow as bnd[N2 + j] = 0, so block (j, l) sits at (N2 + j) >> l at every level; the
+//   follow as bnd[N2 + j] = hband_f, so block (j, l) sits at (N2 + j) >> l at every level; the
 //   walk starts at level top.  The FP32 vertex copy is padded with v[nv] up to N2 + 1
 //   entries (a block [j, j + 2^l] past nv then ends on v[nv], the end of its chord).  Guide table (int payload): gd[k] = largest j with
 //   cum[j] <= k L / nv.
@@ -52,6 +52,7 @@ struct DevRegion {
     double alpha, sgn, s, area, meas[2], total;
     double gscale;             // polyline: nv / total length (guide-table index scale)
     float alpha_f, sgn_f, s_f, area_f, meas_f[2], total_f, gscale_f;
+    float hband_f;             // polyline: |signed distance| below which FP32 walks decide a crossing in FP64
 };
 
 // Largest LDS staging area per workgroup: two 512-thread workgroups per CU share its
@@ -61,7 +62,9 @@ constexpr int LDS_BUDGET_MAX = 80 * 1024 - 256;
 struct DevProblem {
     int dim, N, vr_ok, lds_bytes;             // lds_bytes: LDS needed to stage every polyline (0: none)
     double alpha_l1, unit_area, phi_c;        // |S^{m-1}|, Phi prefactor (m >= 3)
-    float alpha_l1_f, unit_area_f, phi_c_f, pad1;
+    float alpha_l1_f, unit_area_f, phi_c_f;
+    float sign_band_f;                        // FP32 walks: |(y_i - y_{i-1}) . n(y_i)| at or below it is
+                                              // inside the dot product's rounding band (sign from FP64)
     double cdf[WOI_MAX_REGIONS];              // schedule CDF over |alpha| / ||alpha||_1
     unsigned char rel[WOI_MAX_REGIONS][WOI_MAX_REGIONS];
     // start of the inverse-CDF search for u in [k/64, (k+1)/64): the search's result at

@@ -823,8 +823,10 @@ double seg_dist(const double* p, const double* a, const double* b) {
 // Block bounds of the polyline search: every vertex of the aligned block
 // [b 2^l, min((b+1) 2^l, n)] lies within bnd of the block's chord segment, so its signed
 // distance to any line lies within [min(h_first, h_last) - bnd, max(...) + bnd].
-// Inflated to stay conservative under FP32 rounding.  The segments themselves (level 0, a
-// block whose chord is the segment) follow at N2 + j with bound 0.
+// Inflated by `pad` to stay conservative under FP32 rounding.  The segments themselves
+// (level 0, a block whose chord is the segment) follow at N2 + j with the segment band: FP32
+// signed distances too close to zero to be trusted (the FP32 walk queues such a segment and
+// decides it in FP64; the FP64 walk decides every segment exactly).
 // DIRPOLY data in dimension 2 or 3 as a dense triangular coefficient table c[i][j](k) over
 // total degree <= n, in the order a nested Horner evaluation reads it (i, j, k descending):
 // b = sum_i e0^i sum_j e1^j sum_k e2^k c_ijk.  Declined (false) when the table would be
@@ -854,16 +856,31 @@ bool dirpoly_dense(const HostRegion& g, int m, std::vector<double>& dense, int& 
     return true;
 }
 
+double polyline_band(const HostRegion& g) {
+    double scale = 0;
+    for (double x : g.v) scale = std::max(scale, std::fabs(x));
+    return 4e-6 * (1.0 + scale);
+}
+
+// |signed distance| of a vertex from a line below which an FP32 walk's sign is not trusted:
+// 16 FP32 ulps of the coordinates (the FP32 distance is two FMAs on rounded coordinates, a few
+// ulps at most).
+double segment_band(const HostRegion& g) {
+    double scale = 0;
+    for (double x : g.v) scale = std::max(scale, std::fabs(x));
+    return 0x1p-20 * (1.0 + scale);
+}
+
 void block_bounds(const HostRegion& g, std::vector<float>& bnd, int& n2, int& top) {
     const int n = g.nv();
     n2 = 1;
     int L = 0;
     while (n2 < n) { n2 *= 2; ++L; }
     top = std::max(1, L - 3);   // first block: 1/8 of the polyline
-    double scale = 0;
-    for (double x : g.v) scale = std::max(scale, std::fabs(x));
-    const double pad = 4e-6 * (1.0 + scale);
+    const double pad = polyline_band(g);
     bnd.assign((size_t)n2 + n, 0.0f);
+    const double band = segment_band(g);
+    for (int j = 0; j < n; ++j) bnd[(size_t)n2 + j] = (float)band;
     for (int l = 1; l <= L; ++l) {
         const int base = n2 >> l;   // heap layout: level l occupies [n2 >> l, 2 (n2 >> l))
         for (int j0 = 0, blk = 0; j0 < n; j0 += 1 << l, ++blk) {
@@ -994,6 +1011,26 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
     hdr.alpha_l1_f = (float)hdr.alpha_l1;
     hdr.unit_area_f = (float)hdr.unit_area;
     hdr.phi_c_f = (float)hdr.phi_c;
+    // FP32 sign band: 2^-19 (32 FP32 ulps) of the largest coordinate magnitude on dOmega (every
+    // interface lies inside the root's)
+    {
+        const HostRegion& g = H.r[0];
+        double ext = 0;
+        if (g.kind == WOI_SHAPE_SPHERE || g.kind == WOI_SHAPE_ELLIPSOID) {
+            for (int i = 0; i < m; ++i) {
+                double half = g.R;
+                if (g.kind == WOI_SHAPE_ELLIPSOID) {   // extent along axis i: sqrt((A^-1)_ii), A^-1 = L L
+                    double s2 = 0;
+                    for (int j = 0; j < m; ++j) s2 += g.L[i * m + j] * g.L[i * m + j];
+                    half = std::sqrt(s2);
+                }
+                ext = std::max(ext, std::fabs(g.c[i]) + half);
+            }
+        }
+        for (double x : g.v) ext = std::max(ext, std::fabs(x));
+        for (double x : g.mv) ext = std::max(ext, std::fabs(x));
+        hdr.sign_band_f = (float)(0x1p-19 * std::max(1.0, ext));
+    }
     double acc = 0;
     for (int i = 0; i < N; ++i) {
         acc += std::fabs(H.r[i].alpha);
@@ -1081,6 +1118,7 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
             block_bounds(g, bnd, r.n2, r.top);
             r.bnd = (int)p32.size();
             p32.insert(p32.end(), bnd.begin(), bnd.end());
+            r.hband_f = (float)segment_band(g);
             r.guide = (int)pi.size();
             for (int k = 0; k < n; ++k) {
                 const double s0 = g.cum[n] * k / n;
@@ -1282,7 +1320,8 @@ woi_status check_query_impl(const woi_problem* p, int64_t P, const woi_query* q)
     return WOI_OK;
 }
 
-Plan make_plan(const woi_problem* p, int64_t P, const woi_query* q, uint64_t n_samples) {
+// max_chunks > 0 caps the number of partial slots (a fixed-size partial buffer).
+Plan make_plan(const woi_problem* p, int64_t P, const woi_query* q, uint64_t n_samples, uint64_t max_chunks = 0) {
     Plan pl;
     pl.n_samples = n_samples;
     pl.first = q->estimator == WOI_EST_VR ? q->walk_offset / 2 : q->walk_offset;
@@ -1302,6 +1341,10 @@ Plan make_plan(const woi_problem* p, int64_t P, const woi_query* q, uint64_t n_s
     }
     spt = std::min<uint64_t>(spt, n_samples);
     uint64_t chunks = (n_samples + spt - 1) / spt;
+    if (max_chunks > 0 && chunks > max_chunks) {
+        spt = (n_samples + max_chunks - 1) / max_chunks;
+        chunks = (n_samples + spt - 1) / spt;
+    }
     while (chunks > 65535) { spt *= 2; chunks = (n_samples + spt - 1) / spt; }
     pl.spt = (uint32_t)spt;
     pl.chunks = (int)chunks;
@@ -1438,6 +1481,51 @@ woi_status estimate_naive(const woi_problem* p, const double* points, int64_t P,
     return WOI_OK;
 }
 
+// The per-point path: walk kernel over (point tile, sample chunk), then the reduction of the
+// chunk partials (pl.chunks * P records of 2 + 2 dim doubles at `partials`).
+woi_status launch_per_point(const woi_problem* p, const double* points, int64_t P, const woi_query* q, const Plan& pl,
+                            double* mean, double* se, double* grad, double* grad_se, double* partials,
+                            uint64_t* counters, hipStream_t s) {
+    woi::KParams kp{};
+    kp.dp = static_cast<const DevProblem*>(p->dev);
+    kp.points = points;
+    kp.P = P;
+    kp.n_samples = pl.n_samples;
+    kp.first_sample = pl.first;
+    kp.samples_per_thread = pl.spt;
+    kp.k0 = (uint32_t)q->seed;
+    kp.k1 = (uint32_t)(q->seed >> 32);
+    kp.M = q->M;
+    kp.batch_share = q->batch_share;
+    kp.shared_sched = q->schedule_mode == WOI_SCHED_SHARED;
+    kp.mesh = has_mesh(p->H) ? 1 : 0;
+    kp.instance = q->instance;
+    kp.partials = partials;
+    kp.counters = counters;
+    if (q->event_begin && hipEventRecord(static_cast<hipEvent_t>(q->event_begin), s) != hipSuccess)
+        return fail(WOI_E_DEVICE, "hipEventRecord(begin) failed");
+    hipError_t e = woi::launch_walk(kp, p->H.m, q->estimator == WOI_EST_VR, q->precision == WOI_PREC_FP32, pl.lds,
+                                    dim3(pl.gx, pl.chunks), dim3(pl.block), s);
+    if (e != hipSuccess) return fail(WOI_E_DEVICE, "walk launch failed: %s", hipGetErrorString(e));
+    if (q->event_end && hipEventRecord(static_cast<hipEvent_t>(q->event_end), s) != hipSuccess)
+        return fail(WOI_E_DEVICE, "hipEventRecord(end) failed");
+    woi::RParams rp{};
+    rp.partials = partials;
+    rp.P = P;
+    rp.dim = p->H.m;
+    rp.n_chunks = pl.chunks;
+    rp.samples_per_thread = pl.spt;
+    rp.full = 0;
+    rp.tail = pl.n_samples;
+    rp.mean = mean;
+    rp.se = se;
+    rp.grad = grad;
+    rp.grad_se = grad_se;
+    e = woi::launch_reduce(rp, s);
+    if (e != hipSuccess) return fail(WOI_E_DEVICE, "reduce launch failed: %s", hipGetErrorString(e));
+    return WOI_OK;
+}
+
 // Shared trajectories: per chunk, generate the trajectories of every point group, then
 // evaluate them at the group's points; finally the deterministic per-point reduction.
 woi_status estimate_shared(const woi_problem* p, const double* points, int64_t P, const woi_query* q, uint64_t ns,
@@ -1545,45 +1633,8 @@ woi_status woi_estimate(const woi_problem* p, const double* points, int64_t P, c
     const size_t need = (size_t)pl.chunks * (size_t)P * (2 + 2 * p->H.m) * sizeof(double);
     if (!workspace || workspace_bytes < need)
         return fail(WOI_E_OOM, "workspace of %zu bytes is smaller than the %zu bytes needed", workspace_bytes, need);
-    woi::KParams kp{};
-    kp.dp = static_cast<const DevProblem*>(p->dev);
-    kp.points = points;
-    kp.P = P;
-    kp.n_samples = ns;
-    kp.first_sample = pl.first;
-    kp.samples_per_thread = pl.spt;
-    kp.k0 = (uint32_t)q->seed;
-    kp.k1 = (uint32_t)(q->seed >> 32);
-    kp.M = q->M;
-    kp.batch_share = q->batch_share;
-    kp.shared_sched = q->schedule_mode == WOI_SCHED_SHARED;
-    kp.mesh = has_mesh(p->H) ? 1 : 0;
-    kp.instance = q->instance;
-    kp.partials = static_cast<double*>(workspace);
-    kp.counters = counters;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    if (q->event_begin && hipEventRecord(static_cast<hipEvent_t>(q->event_begin), s) != hipSuccess)
-        return fail(WOI_E_DEVICE, "hipEventRecord(begin) failed");
-    hipError_t e = woi::launch_walk(kp, p->H.m, q->estimator == WOI_EST_VR, q->precision == WOI_PREC_FP32, pl.lds,
-                                    dim3(pl.gx, pl.chunks), dim3(pl.block), s);
-    if (e != hipSuccess) return fail(WOI_E_DEVICE, "walk launch failed: %s", hipGetErrorString(e));
-    if (q->event_end && hipEventRecord(static_cast<hipEvent_t>(q->event_end), s) != hipSuccess)
-        return fail(WOI_E_DEVICE, "hipEventRecord(end) failed");
-    woi::RParams rp{};
-    rp.partials = kp.partials;
-    rp.P = P;
-    rp.dim = p->H.m;
-    rp.n_chunks = pl.chunks;
-    rp.samples_per_thread = pl.spt;
-    rp.full = 0;
-    rp.tail = ns;
-    rp.mean = mean;
-    rp.se = se;
-    rp.grad = grad;
-    rp.grad_se = grad_se;
-    e = woi::launch_reduce(rp, s);
-    if (e != hipSuccess) return fail(WOI_E_DEVICE, "reduce launch failed: %s", hipGetErrorString(e));
-    return WOI_OK;
+    return launch_per_point(p, points, P, q, pl, mean, se, grad, grad_se, static_cast<double*>(workspace), counters,
+                            static_cast<hipStream_t>(stream));
 }
 
 woi_status woi_stats_read(const uint64_t* counters, void* event_begin, void* event_end, woi_stats* out) {
@@ -1672,6 +1723,7 @@ woi_status set_error(woi_status s, const char* fmt, ...) {
 }
 
 woi_status check_query(const woi_problem* p, int64_t P, const woi_query* q) { return check_query_impl(p, P, q); }
+
 bool problem_has_mesh(const woi_problem* p) { return p && has_mesh(p->H); }
 
 woi_status problem_ref(woi_problem* p, ProblemRef* out) {

@@ -10,7 +10,7 @@ namespace woi {
 // handles triangle-mesh interfaces (their tables stay in global memory), which the other 3D
 // kernels leave out so that quadric-only problems keep their register budget.
 template <typename R, int D, bool VR, bool COUNT, bool LDS>
-__global__ __launch_bounds__(LDS ? 512 : 256) void walk_kernel(KParams kp) {
+__global__ __launch_bounds__(LDS ? 512 : 256, (walk_waves_per_simd<R, D>())) void walk_kernel(KParams kp) {
     const DevProblem* __restrict__ dp = kp.dp;
     const R* __restrict__ pay = Pay<R>::base(dp);
     if constexpr (LDS && D == 2) stage_polylines(dp);
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(LDS ? 512 : 256) void walk_kernel(KParams kp) {
 // schedule the transition case and geometry record are wave-uniform.  The walker runs with its
 // polyline sampler out of line (INL = false): inlined here, ROCm 7.2 clang miscompiled it.
 template <typename R, int D, bool VR, bool LDS>
-__global__ __launch_bounds__(LDS ? 512 : 256) void traj_kernel(KParams kp, TParams tp) {
+__global__ __launch_bounds__(LDS ? 512 : 256, (walk_waves_per_simd<R, D>())) void traj_kernel(KParams kp, TParams tp) {
     const DevProblem* __restrict__ dp = kp.dp;
     const R* __restrict__ pay = Pay<R>::base(dp);
     if constexpr (LDS && D == 2) stage_polylines(dp);

@@ -30,7 +30,7 @@ __device__ __forceinline__ void add_counts(Counts& a, const Counts& b) {
 // R: FP64, or FP32 walks (each node's term c Phi, c grad Phi in FP32, converted to FP64 before it
 // joins the lane's sum; the tree's lane sum and the moments in FP64).  LDS: in 3D, the mesh-capable instantiation (nothing is staged in LDS by this kernel).
 template <typename R, int D, bool LDS, bool COUNT>
-__global__ __launch_bounds__(256) void naive_kernel(KParams kp, NParams np) {
+__global__ __launch_bounds__(256, (walk_waves_per_simd<R, D>())) void naive_kernel(KParams kp, NParams np) {
     const DevProblem* __restrict__ dp = kp.dp;
     const R* __restrict__ pay = Pay<R>::base(dp);
     const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);

@@ -102,7 +102,7 @@ template <> struct RO<float> {
     // a / b to about 2 ulp (hardware reciprocal), for the FP32 walks
     static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
     static __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
-    static constexpr float line_eps = 1e-5f;
+    static constexpr float line_eps = 1e-5f;   // FP32 line hits with |t| < POLY_T_BAND are decided in FP64
     static constexpr float ray_eps = 0.0f;
 };
 
@@ -164,6 +164,12 @@ __device__ __forceinline__ const R* poly_xy(const DevRegion& g, const R* __restr
 }
 
 constexpr int dir_words(int D) { return D == 2 ? 1 : (D == 3 ? 2 : 2 * ((D + 1) / 2)); }
+
+// Resident waves per SIMD that the FP32 walk kernels keep (the register budget they are
+// compiled to: 128 VGPRs for 4 waves): the FP64 recheck paths, rarely taken, would otherwise
+// raise the allocation and cost a wave per SIMD.  FP64 kernels are left to the compiler.
+template <typename R, int D>
+constexpr int walk_waves_per_simd() { return std::is_same<R, float>::value ? (D <= 4 ? 4 : D <= 6 ? 3 : 2) : 1; }
 
 // ----------------------------------------------------------------------------- directions
 // Uniform direction on S^{D-1} from the first dir_words(D) words.
@@ -551,6 +557,25 @@ constexpr int POLY_QUEUE = 8;
 
 constexpr bool COUNT_POLY = true;   // dead code unless the counting kernel reads the counters
 
+// FP32 walks: crossing parameters below this magnitude are decided in FP64 (polylines, meshes).
+constexpr float POLY_T_BAND = 1e-4f;
+// A line from y never counts a crossing this close to y (it is y itself, up to the FP32 state's
+// own rounding); the FP64 walk's threshold is RO<double>::line_eps.
+constexpr double LINE_EPS_F32_STATE = 1e-6;
+
+// FP64 decision of polyline segment j for an FP32 walker at y, direction d (both taken exactly
+// to FP64): the FP64 path's sign test on the FP64 vertices, then the crossing parameter.
+__device__ __forceinline__ bool poly_hit_fp64(const DevProblem* dp, const DevRegion& g, const float y[2], const float d[2],
+                                           int j, bool ray) {
+    const double* a = Pay<double>::base(dp) + g.g64 + 2 * j;
+    const double y0 = y[0], y1 = y[1], d0 = d[0], d1 = d[1];
+    const double ha = d0 * (a[1] - y1) - d1 * (a[0] - y0), hb = d0 * (a[3] - y1) - d1 * (a[2] - y0);
+    const bool cross = (hb != 0.0) & ((ha == 0.0) | ((ha > 0.0) != (hb > 0.0)));
+    const double ex = a[2] - a[0], ey = a[3] - a[1], den = d0 * ey - d1 * ex;
+    const double t = ((a[0] - y0) * ey - (a[1] - y1) * ex) / den;
+    return cross & (den != 0.0) & (ray ? (t > 0.0) : (fabs(t) > LINE_EPS_F32_STATE));
+}
+
 // The walk: calls cand(j) for every candidate segment j in increasing order, and stops
 // early when cand returns true.
 // Search modes: PS_RAY when every lane of the wave searches along a ray, else PS_ANY (each
@@ -610,15 +635,16 @@ __device__ __forceinline__ void poly_walk(const DevProblem* dp, const DevRegion&
         const float b = bound(jn >> lvl);
         // Every vertex of the block strictly on one side of the line: the end value nearer
         // zero, med3(h_j, h_e, 0) (zero when the signs differ), exceeds the bound in magnitude.
-        // For a segment (b = 0) this reads "both values nonzero, one sign".  A segment crosses
-        // when it is not skipped and its end value is nonzero: a zero start value belongs to
-        // this segment and a zero end value to the next.
+        // For a segment the bound is the FP32 rounding band: FP32 walks queue every segment
+        // that is not clearly on one side (a sign change, or an end value within the band) and
+        // decide it exactly after the walk (in FP64 when inside the band).
         bool skip = fabsf(__builtin_amdgcn_fmed3f(hj, he, 0.0f)) > b;
         if constexpr (RAY) skip |= !seg & (gj < -b) & (ge < -b);   // (fmaxf would add a NaN canonicalisation)
         bool cross;
         if constexpr (F32) {
-            cross = !(skip | (he == 0.0f));
-        } else {                                              // FP64 exact values at stride 1 only
+            cross = !skip;
+        } else {                                              // FP64 exact values at stride 1 only:
+            // a zero start value belongs to this segment, a zero end value to the next
             R ha = R(0), hb = R(0);
             if (seg) {
                 const R* a = v + 2 * (jn - n2);
@@ -649,13 +675,27 @@ __device__ __forceinline__ int poly_pick_t(const DevProblem* dp, const DevRegion
                                            int& jp, Counts& cnt) {
     const bool ray = MODE == PS_RAY || ray_lane;
     const R* __restrict__ v = poly_xy<R, LDS>(g, pay);
-    // crossing parameter test of candidate segment j (precision R)
+    // Exact test of candidate segment j: its ends on opposite sides of the line (a zero start
+    // value belongs to this segment, a zero end value to the next), and the crossing parameter
+    // passes the line / ray test.  FP32 walks decide in FP32 only when every quantity is clear
+    // of its rounding band, else from the FP64 vertices (counted as an FP64 recheck).
     auto hit = [&](int j) -> bool {
         const R* a = v + 2 * j;
         const R ex = a[2] - a[0], ey = a[3] - a[1];
         const R den = d[0] * ey - d[1] * ex;
         const R t = RO<R>::div((a[0] - y[0]) * ey - (a[1] - y[1]) * ex, den);
-        return (den != R(0)) & (ray ? (t > R(0)) : (fabs(t) > RO<R>::line_eps));
+        if constexpr (std::is_same<R, float>::value) {
+            // signed distances of the ends from the line: h_a = d x (a - y), h_b = h_a + d x e; with
+            // both clear of the band their signs are trusted (the walk's own values, computed
+            // differently, may sit on the other side of the band edge)
+            const float ha = d[0] * (a[1] - y[1]) - d[1] * (a[0] - y[0]), hb = ha + den;
+            const bool amb = (fminf(fabsf(ha), fabsf(hb)) <= g.hband_f) | (fabsf(t) < POLY_T_BAND);
+            if (!amb) return (ha * hb < 0.0f) & (!ray | (t > 0.0f));
+            cnt.fb++;
+            return poly_hit_fp64(dp, g, y, d, j, ray);
+        } else {
+            return (den != R(0)) & (ray ? (t > R(0)) : (fabs(t) > RO<R>::line_eps));
+        }
     };
     Queue16 cq{0u, 0u, 0u, 0u};
     int c = 0;
@@ -704,23 +744,51 @@ __device__ __forceinline__ int poly_pick(const DevProblem* dp, const DevRegion& 
 // Triangle mesh: hits of the line / ray y + t d in triangle order (Moller-Trumbore with the
 // closed barycentric bounds; a line skips the triangle of y and |t| <= eps, a ray keeps t > 0).
 // Returns q and, when q > 0, the parameter t and triangle of hit `pick` = min(floor(up q), q - 1).
+// Moller-Trumbore in precision Q for one triangle (a, e1 = b - a, e2 = c - a): barycentric u, v,
+// parameter t and the determinant.
+template <typename Q, typename P>
+__device__ __forceinline__ void moller_trumbore(const Q* a, const P* y, const P* d, Q& u, Q& v, Q& t, Q& det) {
+    const Q *e1 = a + 3, *e2 = a + 6;
+    const Q yq[3] = {(Q)y[0], (Q)y[1], (Q)y[2]}, dq[3] = {(Q)d[0], (Q)d[1], (Q)d[2]};
+    const Q sv[3] = {yq[0] - a[0], yq[1] - a[1], yq[2] - a[2]};
+    const Q pv[3] = {dq[1] * e2[2] - dq[2] * e2[1], dq[2] * e2[0] - dq[0] * e2[2], dq[0] * e2[1] - dq[1] * e2[0]};
+    det = e1[0] * pv[0] + e1[1] * pv[1] + e1[2] * pv[2];
+    u = RO<Q>::div(sv[0] * pv[0] + sv[1] * pv[1] + sv[2] * pv[2], det);
+    const Q qv[3] = {sv[1] * e1[2] - sv[2] * e1[1], sv[2] * e1[0] - sv[0] * e1[2], sv[0] * e1[1] - sv[1] * e1[0]};
+    v = RO<Q>::div(dq[0] * qv[0] + dq[1] * qv[1] + dq[2] * qv[2], det);
+    t = RO<Q>::div(e2[0] * qv[0] + e2[1] * qv[1] + e2[2] * qv[2], det);
+}
+
+// FP32 walks: a triangle test whose barycentric coordinates lie within this band of an edge,
+// or whose parameter lies within POLY_T_BAND of 0, is decided in FP64.
+constexpr float MESH_UV_BAND = 2e-6f;
+
 template <typename R>
 struct MeshHit {
     const R* __restrict__ T;   // per triangle (a, b - a, c - a)
+    const double* __restrict__ T64;   // the same in FP64 (the FP64 recheck of FP32 walks)
     const R *y, *d;
     bool ray;
     int yseg;
+    Counts* cnt;
     __device__ __forceinline__ bool operator()(int j, R& t) const {
-        const R* a = T + 9 * j;
-        const R *e1 = a + 3, *e2 = a + 6;
-        const R sv[3] = {y[0] - a[0], y[1] - a[1], y[2] - a[2]};
-        const R pv[3] = {d[1] * e2[2] - d[2] * e2[1], d[2] * e2[0] - d[0] * e2[2], d[0] * e2[1] - d[1] * e2[0]};
-        const R det = e1[0] * pv[0] + e1[1] * pv[1] + e1[2] * pv[2];
-        const R u = RO<R>::div(sv[0] * pv[0] + sv[1] * pv[1] + sv[2] * pv[2], det);
-        const R qv[3] = {sv[1] * e1[2] - sv[2] * e1[1], sv[2] * e1[0] - sv[0] * e1[2], sv[0] * e1[1] - sv[1] * e1[0]};
-        const R v = RO<R>::div(d[0] * qv[0] + d[1] * qv[1] + d[2] * qv[2], det);
-        t = RO<R>::div(e2[0] * qv[0] + e2[1] * qv[1] + e2[2] * qv[2], det);
-        return (ray | (j != yseg)) & (det != R(0)) & (u >= R(0)) & (u <= R(1)) & (v >= R(0)) & (u + v <= R(1)) &
+        if (!ray & (j == yseg)) return false;
+        R u, v, det;
+        moller_trumbore<R, R>(T + 9 * j, y, d, u, v, t, det);
+        if constexpr (std::is_same<R, float>::value) {
+            const float w = 1.0f - u - v;
+            const bool amb = (fminf(fminf(fabsf(u), fabsf(v)), fminf(fabsf(w), fminf(fabsf(1.0f - u), fabsf(1.0f - v)))) <
+                              MESH_UV_BAND) | (fabsf(t) < POLY_T_BAND) | (det == 0.0f);
+            if (amb) {
+                cnt->fb++;
+                double u6, v6, t6, det6;
+                moller_trumbore<double, float>(T64 + 9 * j, y, d, u6, v6, t6, det6);
+                t = (float)t6;
+                return (det6 != 0.0) & (u6 >= 0.0) & (u6 <= 1.0) & (v6 >= 0.0) & (u6 + v6 <= 1.0) &
+                       (ray ? (t6 > 0.0) : (fabs(t6) > LINE_EPS_F32_STATE));
+            }
+        }
+        return (det != R(0)) & (u >= R(0)) & (u <= R(1)) & (v >= R(0)) & (u + v <= R(1)) &
                (ray ? (t > R(0)) : (fabs(t) > RO<R>::line_eps));
     }
 };
@@ -766,7 +834,7 @@ template <typename R>
 __device__ __forceinline__ int mesh_pick(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
                                          const R y[3], const R d[3], bool ray, int yseg, R up, int& pick, R& tp,
                                          int& jp, Counts& cnt) {
-    const MeshHit<R> hit{pay + Pay<R>::g(g), y, d, ray, yseg};
+    const MeshHit<R> hit{pay + Pay<R>::g(g), Pay<double>::base(dp) + g.g64, y, d, ray, yseg, &cnt};
     const int n = g.nv;
     const float* __restrict__ nodes = Pay<float>::base(dp) + g.bvh;
     const int* __restrict__ list = int_payload(dp) + g.bvhidx;
@@ -816,6 +884,42 @@ __device__ __forceinline__ int mesh_pick(const DevProblem* dp, const DevRegion& 
     tp = t;
     jp = jb;
     return q;
+}
+
+// ----------------------------------------------------------------------------- FP64 sign recheck
+// The sign factor of Eq. naive_woi_T in FP64 for an FP32 walker that moved from y to yn on
+// interface g (segment or triangle seg), used when the FP32 dot product lies inside its rounding
+// band (|dn| <= DevProblem::sign_band_f).  Polylines and meshes: (a - y) . n with a a vertex of
+// the segment / triangle and n its FP64 normal (yn - a is parallel to the segment / triangle).
+// A line or ray on a quadric: +1, the exact sign -- the far end of a chord of the convex quadric
+// through y has (yn - y) . A (yn - c) = t (b + t a), which is 2 b^2 / a for the line's other
+// root t = -2 b / a and t sqrt(b^2 - a cc) > 0 for a ray from inside.  A uniform point on a
+// quadric: (yn - y) . n(yn) in FP64.
+template <int D, bool LDS>
+__device__ __forceinline__ float sign_fp64(const DevProblem* dp, const DevRegion& g, int rel, const float y[D],
+                                        const float yn[D], int seg) {
+    const double* p64 = Pay<double>::base(dp);
+    double s = 0;
+    if (g.kind == WOI_SHAPE_POLYLINE2D) {
+        if constexpr (D == 2) {
+            const double *a = p64 + g.g64 + 2 * seg, *n = p64 + g.nrm64 + 2 * seg;
+            s = (a[0] - (double)y[0]) * n[0] + (a[1] - (double)y[1]) * n[1];
+        }
+    } else if (D == 3 && LDS && g.kind == WOI_SHAPE_MESH3D) {
+        const double *a = p64 + g.g64 + 9 * seg, *n = p64 + g.nrm64 + 3 * seg;
+#pragma unroll
+        for (int k = 0; k < D && k < 3; ++k) s += (a[k] - (double)y[k]) * n[k];
+    } else if (rel == REL_OTHER) {
+        double yn6[D], n6[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) yn6[j] = yn[j];
+        normal_at<double, D, LDS>(g, p64, yn6, seg, n6);
+#pragma unroll
+        for (int j = 0; j < D; ++j) s += (yn6[j] - (double)y[j]) * n6[j];
+    } else {
+        s = 1.0;
+    }
+    return s < 0.0 ? -1.0f : 1.0f;
 }
 
 // ----------------------------------------------------------------------------- accumulation
@@ -928,6 +1032,12 @@ __device__ __forceinline__ R transition(const DevProblem* __restrict__ dp, const
     R dn = 0;
 #pragma unroll
     for (int j = 0; j < D; ++j) dn += (yn[j] - y[j]) * nn[j];
+    if constexpr (std::is_same<R, float>::value) {
+        if (fabsf(dn) <= dp->sign_band_f) {   // inside the FP32 rounding band: the sign from FP64
+            cnt.fb++;
+            dn = sign_fp64<D, LDS>(dp, *g, rel, y, yn, segn);
+        }
+    }
     return dn < R(0) ? -(R)qn : (R)qn;
 }
 

@@ -84,6 +84,7 @@ def _load():
     lib = C.CDLL(LIB_PATH)
     lib.woi_problem_create.argtypes = [C.POINTER(_Desc), C.POINTER(C.c_void_p)]
     lib.woi_problem_destroy.argtypes = [C.c_void_p]
+    lib.woi_problem_upload.argtypes = [C.c_void_p]
     lib.woi_problem_destroy.restype = None
     lib.woi_problem_get_info.argtypes = [C.c_void_p, C.POINTER(_Info)]
     lib.woi_workspace_size.argtypes = [C.c_void_p, C.c_int64, C.POINTER(Query), C.POINTER(C.c_size_t)]
@@ -241,6 +242,11 @@ def estimate(problem, points, walks, M, seed=0, estimator=PLAIN, precision=FP64,
                              C.c_void_p(workspace.data_ptr()), workspace.numel(),
                              C.c_void_p(counters.data_ptr()) if counters is not None else None, _stream()))
     return mean, se, g, gse
+
+
+def upload(problem):
+    """woi_problem_upload: copy the compiled problem to the current device now."""
+    _check(_lib.woi_problem_upload(problem.handle))
 
 
 def trace(problem, points, n_samples, M, seed=0, estimator=PLAIN, precision=FP64, schedule_mode=SCHED_PER_GROUP,

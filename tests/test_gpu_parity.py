@@ -220,19 +220,36 @@ def test_estimate_six_ball_exact_expectation_fp32():
 
 
 def test_fp32_paired_with_fp64():
-    """FP32 walks against FP64 walks on identical streams: most decisions agree, the
-    paired difference is far below the statistical error, and its mean is consistent with 0."""
+    """FP32 walks against FP64 walks on identical streams: at least 99.9 % of the walkers take
+    the same decisions (the FP32 decisions inside their rounding band are taken again in FP64),
+    the paired difference is far below the statistical error, and its mean is consistent with 0."""
     p, xs = W.star_tree_2d(n_points=64)
     gp = woi.Problem(p)
     F64, _, T64 = woi.trace(gp, xs, 2000, 4, seed=9, schedule_mode=1)
     F32, _, T32 = woi.trace(gp, xs, 2000, 4, seed=9, precision=woi.FP32, schedule_mode=1)
     F64, F32 = _np(F64)[..., 0], _np(F32)[..., 0]
     same = np.all(_np(T64) == _np(T32), axis=-1)[..., 0]
-    assert same.mean() > 0.99
+    assert same.mean() > 0.999
     d = (F32 - F64)[same]
     sd = F64.std()
     assert np.median(np.abs(d)) < 1e-4 * sd
     assert abs(d.mean()) < 4 * d.std() / np.sqrt(d.size) + 1e-6 * sd
+
+
+def test_fp32_chord_signs_rechecked_in_fp64():
+    """On concentric circles every FP32-vs-FP64 decision flip was the sign of a near-tangent
+    chord (its dot product 2 b^2 / R below the FP32 rounding of about 1e-7): with the FP64
+    recheck of signs inside the band, no walker flips, and the rechecks are counted."""
+    p, xs = W.concentric_disk_2d()
+    gp = woi.Problem(p)
+    _, _, T64 = woi.trace(gp, xs, 4000, 4, seed=31, schedule_mode=1)
+    _, _, T32 = woi.trace(gp, xs, 4000, 4, seed=31, precision=woi.FP32, schedule_mode=1)
+    flips = int((~np.all(_np(T64) == _np(T32), axis=-1)).sum())
+    c = woi.new_counters()
+    woi.estimate(gp, xs, 4000, 4, seed=31, precision=woi.FP32, schedule_mode=1, counters=c)
+    c = _np(c)
+    assert flips == 0, flips
+    assert 0 < c[8] < 1e-2 * c[0]
 
 
 # ----------------------------------------------------------------------------- edge cases
