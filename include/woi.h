@@ -194,6 +194,22 @@ woi_status woi_estimate(const woi_problem *p, const double *points, int64_t P, c
                         double *mean, double *se, double *grad, double *grad_se,
                         void *workspace, size_t workspace_bytes, uint64_t *counters, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): woi_estimate without a workspace.  The partial sums go
+ * to a library-owned device array of WOI_NOALLOC_SCRATCH_BYTES (16 MiB, one per device, held
+ * until the process ends); the sample chunks are capped so that they fit, which bounds P at
+ * WOI_NOALLOC_SCRATCH_BYTES / ((2 + 2 dim) 8) points per call (349525 in 2D).  The call makes no
+ * allocation: the problem must already be on the current device (woi_problem_upload).
+ * Plain and VR estimators with batch_share = 1 only.  Results equal woi_estimate's up to the
+ * summation order of the chunk sums.  All calls on one device share the array: calls that
+ * overlap on a device race (order them on one stream).
+ * Errors: INVALID_ARG (as woi_estimate; problem not uploaded; P too large), UNSUPPORTED (naive
+ * estimator, batch_share > 1), DEVICE. */
+#define WOI_NOALLOC_SCRATCH_BYTES (16u << 20)
+woi_status woi_estimate_noalloc(const woi_problem *p, const double *points, int64_t P, const woi_query *q,
+                                double *mean, double *se, double *grad, double *grad_se,
+                                uint64_t *counters, void *stream);
+
 /* Per-sample values and per-step decisions of Alg. 2 / Alg. 3 (the scheduled interface, the
  * transition case of Eq. naive_woi_p, the hit count q and the uniform pick among the hits of
  * Sec. 4.2.3, and the sign of Eq. naive_woi_T), for parity checks: samples

@@ -1724,6 +1724,35 @@ woi_status set_error(woi_status s, const char* fmt, ...) {
 
 woi_status check_query(const woi_problem* p, int64_t P, const woi_query* q) { return check_query_impl(p, P, q); }
 
+woi_status estimate_into(const woi_problem* p, const double* points, int64_t P, const woi_query* q, double* mean,
+                         double* se, double* grad, double* grad_se, double* partials, size_t partial_bytes,
+                         uint64_t* counters, void* stream) {
+    woi_status st = check_query_impl(p, P, q);
+    if (st != WOI_OK) return st;
+    if (!points || !mean || !se) return fail(WOI_E_INVALID_ARG, "NULL points/mean/se");
+    if (q->estimator == WOI_EST_NAIVE || q->batch_share != 1)
+        return fail(WOI_E_UNSUPPORTED, "the allocation-free path takes the plain and VR estimators with batch_share 1");
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(WOI_E_DEVICE, "no HIP device");
+    {
+        std::lock_guard<std::mutex> lk(const_cast<woi_problem*>(p)->mu);
+        if (!p->dev) return fail(WOI_E_INVALID_ARG, "the problem is not on a device: call woi_problem_upload first");
+        if (p->device != cur)
+            return fail(WOI_E_INVALID_ARG, "problem lives on device %d, current device is %d", p->device, cur);
+    }
+    const size_t rec = (size_t)P * (2 + 2 * p->H.m) * sizeof(double);   // one chunk of partials
+    const uint64_t max_chunks = partial_bytes / rec;
+    if (max_chunks < 1)
+        return fail(WOI_E_INVALID_ARG, "%lld points need %zu bytes of partial sums, more than the %zu available",
+                    (long long)P, rec, partial_bytes);
+    const uint64_t ns = q->estimator == WOI_EST_VR ? q->walks / 2 : q->walks;
+    const Plan pl = make_plan(p, P, q, ns, max_chunks);
+    if ((uint64_t)pl.chunks > max_chunks)
+        return fail(WOI_E_INVALID_ARG, "%llu samples need %d partial slots, more than the %llu that fit",
+                    (unsigned long long)ns, pl.chunks, (unsigned long long)max_chunks);
+    return launch_per_point(p, points, P, q, pl, mean, se, grad, grad_se, partials, counters,
+                            static_cast<hipStream_t>(stream));
+}
 bool problem_has_mesh(const woi_problem* p) { return p && has_mesh(p->H); }
 
 woi_status problem_ref(woi_problem* p, ProblemRef* out) {

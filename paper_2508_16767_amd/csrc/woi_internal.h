@@ -12,6 +12,12 @@ namespace woi {
 woi_status set_error(woi_status s, const char* fmt, ...);
 // Validation of one query for P points (the checks woi_estimate makes).
 woi_status check_query(const woi_problem* p, int64_t P, const woi_query* q);
+// The per-point estimate (plain or VR, batch_share 1) with its partial sums in a caller-given
+// device buffer of partial_bytes bytes: the sample chunks are capped to fit it.  Allocates
+// nothing: the problem must already be on the current device (INVALID_ARG otherwise).
+woi_status estimate_into(const woi_problem* p, const double* points, int64_t P, const woi_query* q, double* mean,
+                         double* se, double* grad, double* grad_se, double* partials, size_t partial_bytes,
+                         uint64_t* counters, void* stream);
 // Whether any interface of the problem is a triangle mesh (host state only).
 bool problem_has_mesh(const woi_problem* p);
 

@@ -74,7 +74,8 @@ class Stats(C.Structure):
 
 
 EXPORTS = ("woi_problem_create", "woi_problem_upload", "woi_problem_destroy", "woi_problem_get_info", "woi_workspace_size",
-           "woi_estimate", "woi_trace", "woi_batch_workspace_size", "woi_estimate_batch", "woi_stats_read",
+           "woi_estimate", "woi_estimate_noalloc", "woi_trace", "woi_batch_workspace_size", "woi_estimate_batch",
+           "woi_stats_read",
            "woi_status_string", "woi_last_error")
 
 
@@ -90,6 +91,8 @@ def _load():
     lib.woi_workspace_size.argtypes = [C.c_void_p, C.c_int64, C.POINTER(Query), C.POINTER(C.c_size_t)]
     lib.woi_estimate.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(Query), C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]
+    lib.woi_estimate_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(Query), C.c_void_p,
+                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.woi_trace.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(Query), C.c_uint64, C.c_void_p,
                               C.c_void_p, C.c_void_p, C.c_void_p]
     lib.woi_batch_workspace_size.argtypes = [C.POINTER(_BatchItem), C.c_int, C.POINTER(C.c_size_t)]
@@ -241,6 +244,25 @@ def estimate(problem, points, walks, M, seed=0, estimator=PLAIN, precision=FP64,
                              C.c_void_p(se.data_ptr()), C.c_void_p(g.data_ptr()), C.c_void_p(gse.data_ptr()),
                              C.c_void_p(workspace.data_ptr()), workspace.numel(),
                              C.c_void_p(counters.data_ptr()) if counters is not None else None, _stream()))
+    return mean, se, g, gse
+
+
+def estimate_noalloc(problem, points, walks, M, seed=0, estimator=PLAIN, precision=FP64,
+                     schedule_mode=SCHED_PER_GROUP, walk_offset=0, instance=0, counters=None, out=None):
+    """woi_estimate_noalloc: the per-point estimate with the library's own fixed partial-sum
+    array (no workspace; the problem must be uploaded first).  Returns (mean, se, grad, grad_se)."""
+    x = _points(points, problem.dim)
+    P = x.shape[0]
+    q = make_query(walks, M, seed, estimator, precision, schedule_mode, 1, walk_offset, instance)
+    if out is None:
+        out = (torch.empty(P, dtype=torch.float64, device=x.device), torch.empty(P, dtype=torch.float64, device=x.device),
+               torch.empty(P, problem.dim, dtype=torch.float64, device=x.device),
+               torch.empty(P, problem.dim, dtype=torch.float64, device=x.device))
+    mean, se, g, gse = out
+    _check(_lib.woi_estimate_noalloc(problem.handle, C.c_void_p(x.data_ptr()), P, C.byref(q),
+                                     C.c_void_p(mean.data_ptr()), C.c_void_p(se.data_ptr()), C.c_void_p(g.data_ptr()),
+                                     C.c_void_p(gse.data_ptr()),
+                                     C.c_void_p(counters.data_ptr()) if counters is not None else None, _stream()))
     return mean, se, g, gse
 
 
