@@ -484,6 +484,86 @@ __device__ __forceinline__ bool vr_attempt(const DevProblem* dp, const DevRegion
     }
 }
 
+// ---- wave-cooperative rejection sampling
+// Lane l needs the first attempt a >= 0 whose proposal try_at(c0_l, c1_l, a, y, seg) accepts,
+// or the proposal of attempt WOI_ATTEMPT_CAP - 1 when none does (rejection sampling on an
+// ellipsoid, or on a half {beta >= 0} / {beta < 0}).  Every proposal is a function of the lane's
+// stream words (c0, c1) and a alone, so after each lane's own attempt 0 the whole wave serves the
+// lanes still pending: with np pending, the lane of rank r among them gets its next 64 / np
+// attempts from the lanes r, r + np, r + 2 np, ... and takes the first accepted one in attempt
+// order.  Points, attempt numbers and rejection / cap counts are those of each lane's sequential
+// loop; a wave waits for about two rounds instead of its unluckiest lane.  Requires all 64 lanes
+// active on the same interface (a shared schedule); try_at must hold no wave-wide operation.
+// Returns the attempt taken (WOI_ATTEMPT_CAP on a cap hit).
+template <typename R, int D, class Try>
+__device__ __forceinline__ int coop_first_accept(const Try& try_at, uint32_t c0, uint32_t c1, R y[D], int& seg,
+                                                 Counts& cnt) {
+    int att = 0, next = 1;
+    bool pend = !try_at(c0, c1, 0, y, seg);
+    if (pend) cnt.rejections++;
+    uint64_t pm = __ballot(pend);
+    const int lane = (int)__lane_id();
+    const uint64_t below = (1ull << lane) - 1ull;
+    while (pm) {
+        const int np = __popcll(pm), per = 64 / np;
+        // lane id of every pending rank (ds_permute by a permutation of the lanes: pending lanes to
+        // their rank, the others after them in lane order)
+        const int rk = __popcll(pm & below);
+        const int dst = pend ? rk : np + (lane - rk);
+        const int who = __builtin_amdgcn_ds_permute(dst << 2, lane);
+        // this lane evaluates attempt next_t + k of the pending lane t of rank r = lane mod np
+        const int r = lane % np, k = lane / np;
+        const int t = __shfl(who, r);
+        const uint32_t tc0 = __shfl(c0, t), tc1 = __shfl(c1, t);
+        const int a = __shfl(next, t) + k;
+        R yc[D];
+        int sc = 0;
+        bool okc = false, fin = false;
+#pragma unroll
+        for (int j = 0; j < D; ++j) yc[j] = R(0);
+        if ((k < per) & (a < WOI_ATTEMPT_CAP)) {
+            okc = try_at(tc0, tc1, a, yc, sc);
+            fin = okc | (a == WOI_ATTEMPT_CAP - 1);
+        }
+        const uint64_t fm = __ballot(fin);
+        // pending lanes: the first finished helper in attempt order
+        int h = lane, kk = 0;
+        bool got = false;
+        if (pend) {
+            for (kk = 0; kk < per && next + kk < WOI_ATTEMPT_CAP; ++kk)
+                if ((fm >> (rk + kk * np)) & 1ull) { got = true; break; }
+            if (got) h = rk + kk * np;
+        }
+        R yh[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) yh[j] = __shfl(yc[j], h);
+        const int sh = __shfl(sc, h);
+        const bool okh = __shfl((int)okc, h) != 0;
+        if (pend) {
+            if (got) {
+#pragma unroll
+                for (int j = 0; j < D; ++j) y[j] = yh[j];
+                seg = sh;
+                cnt.rejections += (uint32_t)kk + (okh ? 0u : 1u);
+                if (okh) att = next + kk;
+                else { att = WOI_ATTEMPT_CAP; cnt.caps++; }
+                pend = false;
+            } else {
+                cnt.rejections += (uint32_t)kk;
+                next += per;
+            }
+        }
+        pm = __ballot(pend);
+    }
+    return att;
+}
+
+// Whether the wave may sample cooperatively: a shared schedule (the same interface in every
+// lane) and all 64 lanes active.
+__device__ __forceinline__ bool wave_full(bool shared_sched) {
+    return shared_sched && __builtin_amdgcn_read_exec() == ~0ull;
+}
+
 // ---- line / ray intersections
 // Quadric (sphere, ellipsoid): returns q in {0, 1} and t.
 template <typename R, int D>
@@ -961,20 +1041,30 @@ __device__ __forceinline__ uint32_t trace_word(int h, int cs, int q, int pick, i
 // ancestor) with a uniform pick among its q hits.  Returns T's factor
 // q sign((y_i - y_{i-1}) . n(y_i)) (Eq. naive_woi_T), or 0 when no line or ray hit turned up
 // within WOI_ATTEMPT_CAP draws (the walk stops there).  Draws come from st at `step`.
+// coop: the wave shares the interface (shared schedule) -- rejection sampling on an ellipsoid is
+// then done cooperatively (same points and counts).
 template <typename R, int D, bool LDS, bool INL = true>
 __device__ __forceinline__ R transition(const DevProblem* __restrict__ dp, const R* __restrict__ pay,
                                         const DevRegion* g, int rel, const Stream& st, uint32_t step,
                                         const R y[D], int seg, R yn[D], int& segn, R& Q, int& qn, int& pick,
-                                        int& att, Counts& cnt, const uint32_t* pre = nullptr) {
+                                        int& att, Counts& cnt, const uint32_t* pre = nullptr, bool coop = false) {
     R nn[D];
     segn = 0; qn = 1; pick = 0;
     if (rel == REL_OTHER) {
         cnt.other++;
-        for (att = 0; att < WOI_ATTEMPT_CAP; ++att) {
-            if (surf_attempt<R, D, LDS, INL>(dp, *g, pay, st, step, att, yn, segn, pre)) break;
-            cnt.rejections++;
+        if (D == 3 && g->kind == WOI_SHAPE_ELLIPSOID && wave_full(coop)) {
+            auto try_at = [&](uint32_t c0, uint32_t c1, int a, R yy[D], int& sg) -> bool {
+                const Stream s2{st.k0, st.k1, c0, c1, st.c2};
+                return surf_attempt<R, D, LDS, INL>(dp, *g, pay, s2, step, a, yy, sg);
+            };
+            att = coop_first_accept<R, D>(try_at, st.c0, st.c1, yn, segn, cnt);
+        } else {
+            for (att = 0; att < WOI_ATTEMPT_CAP; ++att) {
+                if (surf_attempt<R, D, LDS, INL>(dp, *g, pay, st, step, att, yn, segn, pre)) break;
+                cnt.rejections++;
+            }
+            if (att == WOI_ATTEMPT_CAP) cnt.caps++;
         }
-        if (att == WOI_ATTEMPT_CAP) cnt.caps++;
         normal_at<R, D, LDS>(*g, pay, yn, segn, nn);
         R dn = 0, r2 = 0;
 #pragma unroll
@@ -1124,6 +1214,19 @@ __device__ __forceinline__ void vr_starts(const DevProblem* __restrict__ dp, con
     s[0].seg = s[1].seg = 0;
 #pragma unroll
     for (int i = 0; i < D; ++i) { s[0].y[i] = R(0); s[1].y[i] = R(0); }
+    if (D == 3 && wave_full(kp.shared_sched)) {   // the same interface in every lane: cooperative
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            if (!(k ? need1 : need0)) continue;     // wave-uniform (the measures are the interface's)
+            const Stream& sk = k ? st1 : st0;
+            auto try_at = [&](uint32_t c0, uint32_t c1, int a, R yy[D], int& sg) -> bool {
+                const Stream s2{sk.k0, sk.k1, c0, c1, sk.c2};
+                return vr_attempt<R, D, LDS, INL>(dp, g, pay, k, s2, a, yy, sg);
+            };
+            s[k].att = coop_first_accept<R, D>(try_at, sk.c0, sk.c1, s[k].y, s[k].seg, cnt);
+        }
+        return;
+    }
     while (need0 || need1) {
         const int k = need0 ? 0 : 1;
         const int att = k ? s[1].att : s[0].att;
@@ -1184,14 +1287,22 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
         seg = pre->seg;
         att = pre->att;
     } else {
-        for (att = 0; att < WOI_ATTEMPT_CAP; ++att) {
-            bool ok;
-            if constexpr (VR) ok = vr_attempt<R, D, LDS, INL>(dp, *g, pay, k, st, att, y, seg);
-            else ok = surf_attempt<R, D, LDS, INL>(dp, *g, pay, st, 0, att, y, seg);
-            if (ok) break;
-            cnt.rejections++;
+        if (!VR && D == 3 && g->kind == WOI_SHAPE_ELLIPSOID && wave_full(kp.shared_sched)) {
+            auto try_at = [&](uint32_t c0, uint32_t c1, int a, R yy[D], int& sg) -> bool {
+                const Stream s2{st.k0, st.k1, c0, c1, st.c2};
+                return surf_attempt<R, D, LDS, INL>(dp, *g, pay, s2, 0, a, yy, sg);
+            };
+            att = coop_first_accept<R, D>(try_at, st.c0, st.c1, y, seg, cnt);
+        } else {
+            for (att = 0; att < WOI_ATTEMPT_CAP; ++att) {
+                bool ok;
+                if constexpr (VR) ok = vr_attempt<R, D, LDS, INL>(dp, *g, pay, k, st, att, y, seg);
+                else ok = surf_attempt<R, D, LDS, INL>(dp, *g, pay, st, 0, att, y, seg);
+                if (ok) break;
+                cnt.rejections++;
+            }
+            if (att == WOI_ATTEMPT_CAP) cnt.caps++;
         }
-        if (att == WOI_ATTEMPT_CAP) cnt.caps++;
     }
     R Q = Pay<R>::s(*g) * data_b<R, D, LDS>(dp, *g, pay, y, seg) * meas, T = 1;
     sink.add(0, (M == 0 ? R(0.5) : R(1)) * Q * T, y, cnt);
@@ -1224,7 +1335,7 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
             pre[1] = (i & 1) ? pb.y : pb.w;
         }
         const R tf = transition<R, D, LDS, INL>(dp, pay, g, rel, st, (uint32_t)i, y, seg, yn, segn, Q, qn, pick, att,
-                                                cnt, D == 2 ? pre : nullptr);
+                                                cnt, D == 2 ? pre : nullptr, kp.shared_sched != 0);
         if (tf == R(0)) {   // no hit after the attempt cap: the walker stops here
             if (tr) for (int j = i; j <= M; ++j) tr[j] = trace_word(h, rel, 0, 0, 0, att);
             break;

@@ -155,9 +155,23 @@ def test_walk_parity_star_tree_2d_small():
 
 
 def test_walk_parity_ellipsoids_vr_3d():
+    """Per-point schedules (every lane samples on its own), and the shared schedule, where a wave
+    samples one ellipsoid or VR half cooperatively: identical points, attempts and counts."""
     p, xs = W.ellipsoid_tree_3d(n_points=24)
     walk_parity(p, xs, 300, 6, estimator=1, flip_budget=1e-4)
     walk_parity(p, xs[:8], 300, 4, estimator=0, sched=1, flip_budget=1e-4)
+    walk_parity(p, xs[:16], 300, 6, estimator=1, sched=1, flip_budget=1e-4)
+    # rejection counts: the cooperative loop counts what the sequential loop counts
+    gp = woi.Problem(p)
+    c1, c2 = woi.new_counters(), woi.new_counters()
+    woi.estimate(gp, xs, 2000, 6, seed=5, estimator=woi.VR, precision=woi.FP32, schedule_mode=1, counters=c1)
+    woi.estimate(gp, xs, 2000, 6, seed=5, estimator=woi.VR, precision=woi.FP32, schedule_mode=0, counters=c2)
+    c1 = _np(c1)
+    assert c1[2] > 0 and c1[3] == 0
+    o = O.estimate(O.OracleProblem(p), xs[:4], 2000, 6, seed=5, estimator=1, schedule_mode=1, groups=np.arange(4))[4]
+    g1 = woi.new_counters()
+    woi.estimate(gp, xs[:4], 2000, 6, seed=5, estimator=woi.VR, schedule_mode=1, counters=g1)
+    assert int(_np(g1)[2]) == o["rejections"]
 
 
 @pytest.mark.parametrize("dim,axes", [(3, [0.9, 0.6, 0.4]), (4, [0.8, 0.6, 0.5, 0.4])])
