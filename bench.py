@@ -152,10 +152,11 @@ class BatchPath:
     (fill, persistent walk kernel, reduction) with the tuned launch shape.  Step k replays
     the cached graph with seed seed0 + k (the library refreshes its seed table first)."""
 
-    def __init__(self, woi, torch, prob, pts, walks, M, precision, seed0=1, counters=None, estimator=0):
+    def __init__(self, woi, torch, prob, pts, walks, M, precision, seed0=1, counters=None, estimator=0, B=1):
         self.torch, self.seed0 = torch, seed0
         self.b = woi.Batch([dict(problem=prob, points=pts, walks=walks, M=M, seed=seed0, precision=precision,
-                                 estimator=estimator, schedule_mode=woi.SCHED_SHARED)], counters=counters)
+                                 estimator=estimator, schedule_mode=woi.SCHED_SHARED, batch_share=B)],
+                           counters=counters)
         self.first = None
 
     def __call__(self, k, events=None):
@@ -209,7 +210,7 @@ def config_block(woi, torch, ev, prob_desc, pts_np, walks, M, estimator, B, step
     point_steps = P * walks * (M + 1)                           # (point, walker, step) contributions
     r32 = Path(woi, torch, prob, pts, walks, M, woi.FP32, estimator).run(ev, steps, 1)
     r64 = Path(woi, torch, prob, pts, walks, M, woi.FP64, estimator).run(ev, 1, 0)
-    rsh = Path(woi, torch, prob, pts, walks, M, woi.FP32, estimator, B).run(ev, steps, 1)
+    rsh = BatchPath(woi, torch, prob, pts, walks, M, woi.FP32, estimator=estimator, B=B).run(ev, steps, 1)
     eps = float(np.median(r64["se"]))
     t64 = fixed_se(r64, eps)
     pairs = P * (walks // K) * K * (M + 1)
@@ -269,7 +270,7 @@ def star_tree_block(woi, torch, W, ev, steps, walks):
     rpp = Path(woi, torch, prob, pts, walks, M, woi.FP32).run(ev, steps, 1)
     rvr = Path(woi, torch, prob, pts, walks, M, woi.FP32, woi.VR).run(ev, steps, 1)
     rvr64 = Path(woi, torch, prob, pts, walks, M, woi.FP64, woi.VR).run(ev, 1, 0)
-    rsh = Path(woi, torch, prob, pts, walks, M, woi.FP32, 0, 16).run(ev, steps, 1)
+    rsh = BatchPath(woi, torch, prob, pts, walks, M, woi.FP32, B=16).run(ev, steps, 1)
     eps = float(np.median(r64["se"]))
     t64 = fixed_se(r64, eps)
     kms = float(np.mean(rb["ms"]))
@@ -319,11 +320,13 @@ def naive_block(woi, torch, W, ev, steps):
     return out
 
 
-def run_instances(woi, torch, inst, probs, precision, steps, warmup, ev, counters=None):
+def run_instances(woi, torch, inst, probs, precision, steps, warmup, ev, counters=None, shared=False):
     """The 512-instance 2D batch in one persistent graph launch (tuned launch shape); the timed
-    graph replays the whole batch (same seed: every replay recomputes it)."""
+    graph replays the whole batch (same seed: every replay recomputes it).  shared: every instance
+    takes shared trajectories with B = floor(0.5 % of its points) (Sec. 4.6), B = 1 below 400 points."""
     entries = [dict(problem=g, points=x, walks=w, M=4, seed=4242, precision=precision, schedule_mode=woi.SCHED_SHARED,
-                    instance=i) for i, (g, (_, x, w)) in enumerate(zip(probs, inst))]
+                    instance=i, batch_share=max(1, int(0.005 * len(x))) if shared else 1)
+               for i, (g, (_, x, w)) in enumerate(zip(probs, inst))]
     b = woi.Batch(entries, counters=counters)
     if counters is not None:
         b.run()
@@ -459,6 +462,16 @@ def main():
         rec["speedup_fp32_vs_fp64_fixed_se"] = bt64 / bt32
         rec["fp32_vs_fp64_paired_z"] = {"mean_z": float(np.mean(z)), "mean_abs_z": float(np.mean(np.abs(z))),
                                         "max_abs_z": float(np.max(np.abs(z)))}
+    # the same batch with shared trajectories where the paper's batch size allows it (B <= 0.5 % of P)
+    if not args.no_extra:
+        bsh = run_instances(woi, torch, inst, probs, woi.FP32, args.extra_steps, 1, ev, shared=True)
+        rec["shared_trajectories_b_0p5pct"] = {
+            "ms_per_step": bsh["wall"] * 1e3, "walk_steps_per_s": counts[0] / bsh["wall"],
+            "instances_shared": int(sum(1 for _, x, _ in inst if int(0.005 * len(x)) > 1))}
+        if "fp64_batch" in rec:
+            bts = bsh["wall"] * np.mean([np.mean(a ** 2) / np.median(c) ** 2 for a, c in zip(bsh["se"], b64["se"])])
+            rec["shared_trajectories_b_0p5pct"]["speedup_vs_fp64_fixed_se"] = bt64 / bts
+        log(f"headline: shared-trajectory batch {bsh['wall'] * 1e3:.1f} ms")
     sel = np.linspace(0, len(inst) - 1, 16).round().astype(int)
     fr = [flips(woi, torch, probs[i], inst[i][1][:64], 500, 4, instance=int(i)) for i in sel]
     rec["flips"] = {"instances": 16, "walkers": sum(f["walkers"] for f in fr),

@@ -231,9 +231,13 @@ woi_status woi_trace(const woi_problem *p, const double *points, int64_t P, cons
  * add their sums in wave order and write the item's one partial slot, and the reduction
  * merges the slots in sample order (deterministic results).
  *
- * Requirements: all items share dim, estimator and precision; batch_share = 1; fewer than
- * 2^32 samples per point; samples_per_thread is ignored; block_size is the same for all
- * items: 0 (tuned) or 256 / 512 (64 x waves per workgroup).  Per-item arrays are host
+ * Items with batch_share = 1 run in the persistent kernel; items with batch_share B > 1 (shared
+ * trajectories, Sec. 4.6: points with equal p / B share every trajectory) run in the same graph
+ * after it, each as the trajectory-generation and evaluation launches of woi_estimate with that
+ * query, so their results equal woi_estimate's exactly.  Triangle meshes only in the latter.
+ * Requirements: all items share dim, estimator and precision; fewer than 2^32 samples per
+ * point; samples_per_thread is ignored; block_size is the same for all items: 0 (tuned) or
+ * 256 / 512 (64 x waves per workgroup).  Per-item arrays are host
  * arrays of length n; the pointers inside are device pointers.
  * Events: items[0].query.event_begin / event_end, if set, are recorded on `stream` around
  * the graph launch. */
@@ -246,8 +250,9 @@ typedef struct {
 } woi_batch_item;
 
 /* Device workspace (bytes) woi_estimate_batch needs: 256 bytes of queue head, then one
- * running-sum record per resident workgroup and the partial slots (one per item) of the
- * largest plan the tuner may choose.  Uploads the problems and
+ * running-sum record per resident workgroup and the partial slots (one per work item) of the
+ * largest plan the tuner may choose, then the largest shared-trajectory item's workspace
+ * (woi_workspace_size of its query; the shared items run one after another).  Uploads the problems and
  * queries the current device.  Errors: INVALID_ARG, UNSUPPORTED, DEVICE. */
 woi_status woi_batch_workspace_size(const woi_batch_item *items, int n, size_t *bytes);
 

@@ -72,9 +72,9 @@ struct Plan {
     size_t partial_bytes(int dim) const {
         return wg_bytes(dim) + (size_t)n_slots * 64 * (2 + 2 * dim) * sizeof(double);
     }
-    size_t table_bytes() const {   // [BInst][BItem][ctab][pad to 8][seeds]
+    size_t table_bytes(size_t n_seeds) const {   // [BInst][BItem][ctab][pad to 8][seeds]
         const size_t a = inst.size() * sizeof(woi::BInst) + items.size() * sizeof(woi::BItem) + ctab.size() * sizeof(uint32_t);
-        return ((a + 7) & ~size_t(7)) + inst.size() * sizeof(uint64_t);
+        return ((a + 7) & ~size_t(7)) + n_seeds * sizeof(uint64_t);
     }
 };
 
@@ -90,12 +90,11 @@ woi_status validate(const woi_batch_item* items, int n, Spec& sp) {
         woi_status st = woi::check_query(it.problem, it.P, &it.query);
         if (st != WOI_OK) return set_error(st, "item %d: %s", i, woi_last_error());
         if (!it.points || !it.mean || !it.se) return set_error(WOI_E_INVALID_ARG, "item %d: NULL points/mean/se", i);
-        if (it.query.batch_share != 1)
-            return set_error(WOI_E_UNSUPPORTED, "item %d: batched estimation needs batch_share = 1", i);
         if (it.query.estimator == WOI_EST_NAIVE)
             return set_error(WOI_E_UNSUPPORTED, "item %d: batched estimation does not take the naive estimator", i);
-        if (woi::problem_has_mesh(it.problem))
-            return set_error(WOI_E_UNSUPPORTED, "item %d: batched estimation does not take triangle meshes", i);
+        if (woi::problem_has_mesh(it.problem) && it.query.batch_share == 1)
+            return set_error(WOI_E_UNSUPPORTED,
+                             "item %d: the persistent kernel does not take triangle meshes (batch_share > 1 does)", i);
         const bool vr = it.query.estimator == WOI_EST_VR, f32 = it.query.precision == WOI_PREC_FP32;
         if (i == 0) { sp.vr = vr; sp.f32 = f32; }
         if (vr != sp.vr || f32 != sp.f32)
@@ -252,18 +251,45 @@ woi_status upload(const Plan& pl, const std::vector<uint64_t>& seeds, void* buf,
     t.ctab = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(t.items) + pl.items.size() * sizeof(woi::BItem));
     const size_t a = reinterpret_cast<char*>(t.ctab + pl.ctab.size()) - b;
     t.seeds = reinterpret_cast<uint64_t*>(b + ((a + 7) & ~size_t(7)));
-    if (hipMemcpy(t.inst, pl.inst.data(), pl.inst.size() * sizeof(woi::BInst), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(t.items, pl.items.data(), pl.items.size() * sizeof(woi::BItem), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(t.ctab, pl.ctab.data(), pl.ctab.size() * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(t.seeds, seeds.data(), seeds.size() * sizeof(uint64_t), hipMemcpyHostToDevice) != hipSuccess)
+    auto put = [](void* dst, const void* src, size_t bytes) {
+        return bytes == 0 || hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    if (!put(t.inst, pl.inst.data(), pl.inst.size() * sizeof(woi::BInst)) ||
+        !put(t.items, pl.items.data(), pl.items.size() * sizeof(woi::BItem)) ||
+        !put(t.ctab, pl.ctab.data(), pl.ctab.size() * sizeof(uint32_t)) ||
+        !put(t.seeds, seeds.data(), seeds.size() * sizeof(uint64_t)))
         return set_error(WOI_E_DEVICE, "plan upload failed");
     return WOI_OK;
 }
 
-std::vector<uint64_t> seeds_of(const woi_batch_item* items, int n) {
-    std::vector<uint64_t> s((size_t)n);
-    for (int i = 0; i < n; ++i) s[i] = items[i].query.seed;
+// Items of a batch by path: `one` (batch_share 1) run in the persistent kernel, `shared` (batch_share
+// > 1) as shared-trajectory launches after it.  `order` lists the item indices in the order of the
+// device seed table: the persistent kernel's instances first, then the shared items.
+struct Split {
+    std::vector<woi_batch_item> one;
+    std::vector<int> shared, order;
+};
+
+Split split_items(const woi_batch_item* items, int n) {
+    Split sp;
+    for (int i = 0; i < n; ++i)
+        if (items[i].query.batch_share == 1) { sp.one.push_back(items[i]); sp.order.push_back(i); }
+    for (int i = 0; i < n; ++i)
+        if (items[i].query.batch_share > 1) { sp.shared.push_back(i); sp.order.push_back(i); }
+    return sp;
+}
+
+std::vector<uint64_t> seeds_of(const woi_batch_item* items, const std::vector<int>& order) {
+    std::vector<uint64_t> s(order.size());
+    for (size_t i = 0; i < order.size(); ++i) s[i] = items[order[i]].query.seed;
     return s;
+}
+
+// Workspace of the shared items (run one after another): the largest one's.
+size_t shared_bytes(const woi_batch_item* items, const Split& sl) {
+    size_t b = 0;
+    for (int i : sl.shared) b = std::max(b, woi::shared_workspace_bytes(items[i].problem, items[i].P, &items[i].query));
+    return (b + 255) & ~size_t(255);
 }
 
 woi::BParams batch_params(const Plan& pl, const DevTables& t, void* ws, uint64_t* counters, int dim) {
@@ -292,7 +318,7 @@ woi_status autotune(const woi_batch_item* items, const Spec& sp, const Device& d
     size_t tab = 0, part = 0;
     for (const Tune& t : kCandidates) {
         plans.push_back(make_plan(items, sp, t, grid_for(sp, d, t.waves), scale));
-        tab = std::max(tab, plans.back().table_bytes());
+        tab = std::max(tab, plans.back().table_bytes((size_t)sp.n));
         part = std::max(part, plans.back().partial_bytes(sp.dim));
     }
     void *tbuf = nullptr, *ws = nullptr;
@@ -307,7 +333,9 @@ woi_status autotune(const woi_batch_item* items, const Spec& sp, const Device& d
     float best_ms = 0;
     for (size_t c = 0; c < plans.size() && st == WOI_OK; ++c) {
         DevTables t;
-        st = upload(plans[c], seeds_of(items, sp.n), tbuf, t);
+        std::vector<int> ident((size_t)sp.n);
+        std::iota(ident.begin(), ident.end(), 0);
+        st = upload(plans[c], seeds_of(items, ident), tbuf, t);
         if (st != WOI_OK) break;
         const woi::BParams bp = batch_params(plans[c], t, ws, nullptr, sp.dim);
         float ms = 0;
@@ -341,6 +369,7 @@ struct Entry {
     // Seeds are not part of the graph: the device seed table is refreshed on the caller's
     // stream before a launch whose seeds differ, from one of two pinned staging buffers
     // (each reused only after the copy that last read it has completed).
+    std::vector<int> order;               // item of every seed-table entry (Split::order)
     std::vector<uint64_t> seeds;          // what the device table holds once queued copies land
     uint64_t* pinned[2] = {nullptr, nullptr};
     hipEvent_t copied[2] = {nullptr, nullptr};
@@ -402,17 +431,34 @@ woi_status choose_plan(const woi_batch_item* items, const Spec& sp, const Device
     return WOI_OK;
 }
 
-woi_status build_entry(const woi_batch_item* items, const Spec& sp, Device& d, void* ws, size_t ws_bytes,
+// Validated spec of the persistent kernel's items (batch_share 1).
+woi_status spec_of(const std::vector<woi_batch_item>& one, Spec& sp1) {
+    woi_status st = validate(one.data(), (int)one.size(), sp1);
+    if (st == WOI_OK) st = resolve(one.data(), sp1);
+    return st;
+}
+
+woi_status build_entry(const woi_batch_item* items, int n, const Spec& sp, Device& d, void* ws, size_t ws_bytes,
                        uint64_t* counters, hipStream_t caller, Entry& e) {
-    woi_status st = choose_plan(items, sp, d, caller, e.plan);
-    if (st != WOI_OK) return st;
-    e.need = kHead + e.plan.partial_bytes(sp.dim);
+    const Split sl = split_items(items, n);
+    const int n1 = (int)sl.one.size();
+    Spec sp1;
+    if (n1) {
+        woi_status st = spec_of(sl.one, sp1);
+        if (st == WOI_OK) st = choose_plan(sl.one.data(), sp1, d, caller, e.plan);
+        if (st != WOI_OK) return st;
+    }
+    const size_t part = n1 ? ((e.plan.partial_bytes(sp.dim) + 255) & ~size_t(255)) : 0;
+    const size_t shb = shared_bytes(items, sl);
+    char* const wsc = static_cast<char*>(ws);
+    e.need = kHead + part + shb;
     if (!ws || ws_bytes < e.need)
         return set_error(WOI_E_OOM, "workspace of %zu bytes is smaller than the %zu bytes needed", ws_bytes, e.need);
-    if (hipMalloc(&e.tab.buf, e.plan.table_bytes()) != hipSuccess)
-        return set_error(WOI_E_OOM, "hipMalloc(%zu) for the work items failed", e.plan.table_bytes());
-    e.seeds = seeds_of(items, sp.n);
-    st = upload(e.plan, e.seeds, e.tab.buf, e.tab);
+    if (hipMalloc(&e.tab.buf, e.plan.table_bytes((size_t)n)) != hipSuccess)
+        return set_error(WOI_E_OOM, "hipMalloc(%zu) for the work items failed", e.plan.table_bytes((size_t)n));
+    e.order = sl.order;
+    e.seeds = seeds_of(items, e.order);
+    woi_status st = upload(e.plan, e.seeds, e.tab.buf, e.tab);
     if (st != WOI_OK) return st;
     for (int b = 0; b < 2; ++b) {
         if (hipHostMalloc(reinterpret_cast<void**>(&e.pinned[b]), e.seeds.size() * sizeof(uint64_t)) != hipSuccess)
@@ -425,19 +471,31 @@ woi_status build_entry(const woi_batch_item* items, const Spec& sp, Device& d, v
     rp.inst = e.tab.inst;
     rp.ctab = e.tab.ctab;
     rp.partials = bp.partials;
-    rp.n_inst = sp.n;
+    rp.n_inst = n1;
     rp.n_points = e.plan.n_points;
     rp.dim = sp.dim;
     // set the kernels' LDS limits before capturing
-    if (woi::batch_blocks_per_cu(sp.dim, sp.vr, sp.f32, e.plan.t.waves, sp.smem) <= 0)
+    if (n1 && woi::batch_blocks_per_cu(sp.dim, sp1.vr, sp1.f32, e.plan.t.waves, sp1.smem) <= 0)
         return set_error(WOI_E_DEVICE, "batch kernel cannot be resident");
     if (hipStreamBeginCapture(d.capture, hipStreamCaptureModeRelaxed) != hipSuccess)
         return set_error(WOI_E_DEVICE, "hipStreamBeginCapture failed");
-    hipError_t err = woi::launch_fill_u32(bp.head, 1, 0, d.capture);
-    if (err == hipSuccess)
-        err = woi::launch_batch(bp, sp.dim, sp.vr, sp.f32, e.plan.t.waves, e.plan.grid, sp.smem, d.capture);
-    if (err == hipSuccess) err = woi::launch_batch_reduce(rp, d.capture);
+    hipError_t err = hipSuccess;
+    if (n1) {
+        err = woi::launch_fill_u32(bp.head, 1, 0, d.capture);
+        if (err == hipSuccess)
+            err = woi::launch_batch(bp, sp.dim, sp1.vr, sp1.f32, e.plan.t.waves, e.plan.grid, sp1.smem, d.capture);
+        if (err == hipSuccess) err = woi::launch_batch_reduce(rp, d.capture);
+    }
+    // shared-trajectory items, one after another in the workspace after the persistent kernel's
+    for (size_t j = 0; j < sl.shared.size() && err == hipSuccess && st == WOI_OK; ++j) {
+        const woi_batch_item& it = items[sl.shared[j]];
+        woi_query q = it.query;
+        q.event_begin = q.event_end = nullptr;
+        st = woi::enqueue_shared(it.problem, it.points, it.P, &q, it.mean, it.se, it.grad, it.grad_se,
+                                 wsc + kHead + part, shb, counters, e.tab.seeds + n1 + j, d.capture);
+    }
     const hipError_t ec = hipStreamEndCapture(d.capture, &e.graph);
+    if (st != WOI_OK) return st;
     if (err != hipSuccess || ec != hipSuccess)
         return set_error(WOI_E_DEVICE, "graph capture failed: %s", hipGetErrorString(err != hipSuccess ? err : ec));
     if (hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0) != hipSuccess)
@@ -459,16 +517,22 @@ woi_status woi_batch_workspace_size(const woi_batch_item* items, int n, size_t* 
     Device* d = nullptr;
     st = device_info(d);
     if (st != WOI_OK) return st;
-    // the largest over the shapes the tuner may pick (or the one given)
-    size_t need = 0;
-    const int bs = items[0].query.block_size;
-    for (const Tune& t : kCandidates) {
-        if (bs && t.waves != bs / 64) continue;
-        if (bs && t.grain != kDefault.grain) continue;
-        const Plan pl = make_plan(items, sp, t, grid_for(sp, *d, t.waves), 1.0);
-        need = std::max(need, kHead + pl.partial_bytes(sp.dim));
+    // the largest over the shapes the tuner may pick (or the one given), then the shared items'
+    const Split sl = split_items(items, n);
+    size_t part = 0;
+    if (!sl.one.empty()) {
+        Spec sp1;
+        st = spec_of(sl.one, sp1);
+        if (st != WOI_OK) return st;
+        const int bs = items[0].query.block_size;
+        for (const Tune& t : kCandidates) {
+            if (bs && t.waves != bs / 64) continue;
+            if (bs && t.grain != kDefault.grain) continue;
+            const Plan pl = make_plan(sl.one.data(), sp1, t, grid_for(sp1, *d, t.waves), 1.0);
+            part = std::max(part, (pl.partial_bytes(sp.dim) + 255) & ~size_t(255));
+        }
     }
-    *bytes = need;
+    *bytes = kHead + part + shared_bytes(items, sl);
     return WOI_OK;
 }
 
@@ -497,7 +561,7 @@ woi_status woi_estimate_batch(const woi_batch_item* items, int n, void* workspac
         auto fresh = std::make_unique<Entry>();
         fresh->key = key;
         fresh->device = dev;
-        st = build_entry(items, sp, *d, workspace, workspace_bytes, counters, static_cast<hipStream_t>(stream), *fresh);
+        st = build_entry(items, n, sp, *d, workspace, workspace_bytes, counters, static_cast<hipStream_t>(stream), *fresh);
         if (st != WOI_OK) return st;
         g_cache.push_front(std::move(fresh));
         while (g_cache.size() > kCacheSize) g_cache.pop_back();
@@ -506,7 +570,7 @@ woi_status woi_estimate_batch(const woi_batch_item* items, int n, void* workspac
     if (workspace_bytes < e->need)
         return set_error(WOI_E_OOM, "workspace of %zu bytes is smaller than the %zu bytes needed", workspace_bytes, e->need);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    std::vector<uint64_t> seeds = seeds_of(items, n);
+    std::vector<uint64_t> seeds = seeds_of(items, e->order);
     if (seeds != e->seeds) {   // new seeds: refresh the device table on the caller's stream
         const int b = e->next;
         if (hipEventSynchronize(e->copied[b]) != hipSuccess) return set_error(WOI_E_DEVICE, "hipEventSynchronize failed");

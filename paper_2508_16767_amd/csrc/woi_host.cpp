@@ -1530,7 +1530,8 @@ woi_status launch_per_point(const woi_problem* p, const double* points, int64_t 
 // evaluate them at the group's points; finally the deterministic per-point reduction.
 woi_status estimate_shared(const woi_problem* p, const double* points, int64_t P, const woi_query* q, uint64_t ns,
                            double* mean, double* se, double* grad, double* grad_se, void* workspace,
-                           size_t workspace_bytes, uint64_t* counters, hipStream_t s) {
+                           size_t workspace_bytes, uint64_t* counters, hipStream_t s,
+                           const uint64_t* seed_tab = nullptr) {
     const SharedPlan sp = make_shared_plan(p, P, q, ns);
     if (!workspace || workspace_bytes < sp.traj_bytes + sp.part_bytes)
         return fail(WOI_E_OOM, "workspace of %zu bytes is smaller than the %zu bytes needed", workspace_bytes,
@@ -1552,6 +1553,7 @@ woi_status estimate_shared(const woi_problem* p, const double* points, int64_t P
     kp.instance = q->instance;
     kp.partials = reinterpret_cast<double*>(static_cast<char*>(workspace) + sp.traj_bytes);
     kp.counters = counters;
+    kp.seed_tab = seed_tab;
     woi::TParams tp{};
     tp.traj = workspace;
     tp.plane = sp.plane;
@@ -1723,6 +1725,20 @@ woi_status set_error(woi_status s, const char* fmt, ...) {
 }
 
 woi_status check_query(const woi_problem* p, int64_t P, const woi_query* q) { return check_query_impl(p, P, q); }
+
+size_t shared_workspace_bytes(const woi_problem* p, int64_t P, const woi_query* q) {
+    const uint64_t ns = q->estimator == WOI_EST_VR ? q->walks / 2 : q->walks;
+    const SharedPlan sp = make_shared_plan(p, P, q, ns);
+    return sp.traj_bytes + sp.part_bytes;
+}
+
+woi_status enqueue_shared(const woi_problem* p, const double* points, int64_t P, const woi_query* q, double* mean,
+                          double* se, double* grad, double* grad_se, void* workspace, size_t workspace_bytes,
+                          uint64_t* counters, const uint64_t* seed_tab, void* stream) {
+    const uint64_t ns = q->estimator == WOI_EST_VR ? q->walks / 2 : q->walks;
+    return estimate_shared(p, points, P, q, ns, mean, se, grad, grad_se, workspace, workspace_bytes, counters,
+                           static_cast<hipStream_t>(stream), seed_tab);
+}
 
 woi_status estimate_into(const woi_problem* p, const double* points, int64_t P, const woi_query* q, double* mean,
                          double* se, double* grad, double* grad_se, double* partials, size_t partial_bytes,

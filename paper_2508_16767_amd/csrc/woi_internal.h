@@ -18,6 +18,13 @@ woi_status check_query(const woi_problem* p, int64_t P, const woi_query* q);
 woi_status estimate_into(const woi_problem* p, const double* points, int64_t P, const woi_query* q, double* mean,
                          double* se, double* grad, double* grad_se, double* partials, size_t partial_bytes,
                          uint64_t* counters, void* stream);
+// Shared trajectories (batch_share > 1) of one validated query on an uploaded problem: per chunk
+// the trajectory and evaluation launches, then the reduction, enqueued on `stream`.  seed_tab:
+// device address of the Philox key (a cached graph refreshes it), or null for q->seed.
+size_t shared_workspace_bytes(const woi_problem* p, int64_t P, const woi_query* q);
+woi_status enqueue_shared(const woi_problem* p, const double* points, int64_t P, const woi_query* q, double* mean,
+                          double* se, double* grad, double* grad_se, void* workspace, size_t workspace_bytes,
+                          uint64_t* counters, const uint64_t* seed_tab, void* stream);
 // Whether any interface of the problem is a triangle mesh (host state only).
 bool problem_has_mesh(const woi_problem* p);
 

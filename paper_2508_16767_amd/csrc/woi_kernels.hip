@@ -83,7 +83,13 @@ __global__ __launch_bounds__(LDS ? 512 : 256, (walk_waves_per_simd<R, D>())) voi
 // schedule the transition case and geometry record are wave-uniform.  The walker runs with its
 // polyline sampler out of line (INL = false): inlined here, ROCm 7.2 clang miscompiled it.
 template <typename R, int D, bool VR, bool LDS>
-__global__ __launch_bounds__(LDS ? 512 : 256, (walk_waves_per_simd<R, D>())) void traj_kernel(KParams kp, TParams tp) {
+__global__ __launch_bounds__(LDS ? 512 : 256, (walk_waves_per_simd<R, D>())) void traj_kernel(KParams kq, TParams tp) {
+    KParams kp = kq;
+    if (kq.seed_tab) {   // the key of a cached batch graph, refreshed before each launch
+        const uint64_t key = *kq.seed_tab;
+        kp.k0 = (uint32_t)key;
+        kp.k1 = (uint32_t)(key >> 32);
+    }
     const DevProblem* __restrict__ dp = kp.dp;
     const R* __restrict__ pay = Pay<R>::base(dp);
     if constexpr (LDS && D == 2) stage_polylines(dp);

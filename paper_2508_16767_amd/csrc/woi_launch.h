@@ -24,6 +24,8 @@ struct KParams {
     int mesh;                      // 3D problem with triangle-mesh interfaces: the mesh-capable kernels
     uint32_t instance;
     double* partials;              // [chunks][P][2 + 2 dim] or null
+    const uint64_t* seed_tab;      // trajectory generation: the Philox key read from here (device) when
+                                   // not null, else k0, k1 (a cached graph whose seed may change)
     double* traceF;                // per-walker values (trace mode) or null
     double* traceG;
     uint32_t* trace;

@@ -294,7 +294,7 @@ def trace(problem, points, n_samples, M, seed=0, estimator=PLAIN, precision=FP64
 class Batch:
     """Instances estimated together by woi_estimate_batch (one persistent launch, replayed
     as a cached HIP graph).  `entries` is a list of dicts with keys problem, points, walks,
-    M and optionally seed, estimator, precision, schedule_mode, walk_offset, instance.  The
+    M and optionally seed, estimator, precision, schedule_mode, batch_share, walk_offset, instance.  The
     object keeps the points, the outputs and the workspace alive: the graph reads and
     writes them on every run()."""
 
@@ -311,8 +311,8 @@ class Batch:
                    torch.empty(P, prob.dim, dtype=torch.float64, device=x.device),
                    torch.empty(P, prob.dim, dtype=torch.float64, device=x.device))
             q = make_query(e["walks"], e["M"], e.get("seed", 0), e.get("estimator", PLAIN), e.get("precision", FP64),
-                           e.get("schedule_mode", SCHED_SHARED), 1, e.get("walk_offset", 0), e.get("instance", 0),
-                           0, block_size)
+                           e.get("schedule_mode", SCHED_SHARED), e.get("batch_share", 1), e.get("walk_offset", 0),
+                           e.get("instance", 0), 0, block_size)
             it = self.items[i]
             it.problem, it.points, it.P, it.query = prob.handle, x.data_ptr(), P, q
             it.mean, it.se, it.grad, it.grad_se = (t.data_ptr() for t in out)

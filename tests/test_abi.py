@@ -171,7 +171,7 @@ def test_batch_validation_without_gpu(woi):
     assert status(items(q), n=0) == "WOI_E_INVALID_ARG"                                  # empty batch
     assert status(items(q, woi.make_query(100, 4, precision=woi.FP32))) == "WOI_E_INVALID_ARG"   # mixed precision
     assert status(items(q, woi.make_query(100, 4, estimator=woi.VR))) == "WOI_E_INVALID_ARG"     # mixed estimator
-    assert status(items(woi.make_query(100, 4, batch_share=4))) == "WOI_E_UNSUPPORTED"   # shared trajectories
+    assert status(items(woi.make_query(100, 4, batch_share=0))) == "WOI_E_INVALID_ARG"   # batch_share < 1
     assert status(items(woi.make_query(100, 4, block_size=128))) == "WOI_E_INVALID_ARG"  # launch shape
     assert status(items(q, woi.make_query(100, 4, block_size=256))) == "WOI_E_INVALID_ARG"
     assert status(items(woi.make_query(100, 99))) == "WOI_E_INVALID_ARG"                 # M above the maximum

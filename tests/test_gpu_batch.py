@@ -192,3 +192,35 @@ def test_batch_seed_change_reuses_graph():
         ref = woi.estimate(g, x, w, 4, seed=4, schedule_mode=woi.SCHED_SHARED, instance=i)
         _close_to_rounding([_np(t) for t in r4[i]], [_np(t) for t in ref], w)
         assert not np.allclose(_np(r4[i][0]), _np(r3[i][0]))
+
+
+@pytest.mark.parametrize("precision", [woi.FP64, woi.FP32])
+def test_batch_with_shared_trajectory_items(precision):
+    """Items with batch_share B > 1 run in the same graph as the persistent kernel's items, as
+    woi_estimate's shared-trajectory launches with the same keys: their results equal
+    woi_estimate's exactly, before and after a seed change on a replay of the cached graph; the
+    persistent kernel's items keep matching theirs to rounding."""
+    inst = _small_instances(n=6)
+    probs = [woi.Problem(p) for p, _, _ in inst]
+    ents = _entries(inst, probs, precision)
+    for i, B in ((1, 4), (3, 2), (4, 8)):                 # three shared items among per-point ones
+        ents[i]["batch_share"] = B
+    b = woi.Batch(ents)
+    for seed in (11, 23):
+        outs = b.run(seed=seed)
+        for i, e in enumerate(ents):
+            ref = woi.estimate(e["problem"], e["points"], e["walks"], e["M"], seed=seed, precision=precision,
+                               schedule_mode=woi.SCHED_SHARED, batch_share=e.get("batch_share", 1), instance=i)
+            got = [_np(t) for t in outs[i]]
+            ref = [_np(t) for t in ref]
+            if e.get("batch_share", 1) > 1:
+                for g, r in zip(got, ref):
+                    assert np.array_equal(g, r), (i, seed)
+            elif precision == woi.FP64:
+                _close_to_rounding(got, ref, e["walks"])
+    # the shared items against the oracle on the same streams (B > 1 keys: group = p / B)
+    if precision == woi.FP64:
+        i = 4
+        p, x, w = inst[i]
+        mo, so, _, _, _ = O.estimate(O.OracleProblem(p), x, w, 4, seed=23, schedule_mode=1, batch_share=8, instance=i)
+        assert np.allclose(_np(b.outputs[i][0]), mo, rtol=1e-9, atol=1e-9 * so.max())
