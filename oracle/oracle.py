@@ -92,6 +92,9 @@ def _declare(_lib):
                                         C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(_Counters)]
     _lib.or_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
     _lib.or_sample_surface.argtypes = [C.c_void_p, C.c_int, C.c_uint64, C.c_uint64, C.POINTER(C.c_double)]
+    _lib.or_training_points.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_int, C.POINTER(C.c_double), C.c_int64,
+                                        C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double), C.POINTER(C.c_int64)]
 
 
 def _p(a, ct):
@@ -180,6 +183,24 @@ class OracleProblem:
         y = np.zeros((n, self.dim))
         self.lib.or_sample_surface(self.h, region, seed, n, _p(y, C.c_double))
         return y
+
+    def training_points(self, grid_n, margin=0.0, bc_n=0):
+        """Surrogate training data (Sec. 5): interior grid points, boundary points, normals and
+        b_1 / sigma_1 targets."""
+        n_in, n_bc = C.c_int64(), C.c_int64()
+        rc = self.lib.or_training_points(self.h, grid_n, margin, 0, None, 0, C.byref(n_in), None, None, None,
+                                         C.byref(n_bc))
+        if rc != 0:
+            raise ValueError(f"oracle training points failed: {rc}")
+        nb = (bc_n if self.dim == 2 else 2 * bc_n * bc_n) if bc_n else 0
+        x = np.zeros((max(n_in.value, 1), self.dim)); yb = np.zeros((max(nb, 1), self.dim))
+        nrm = np.zeros((max(nb, 1), self.dim)); fl = np.zeros(max(nb, 1))
+        rc = self.lib.or_training_points(self.h, grid_n, margin, bc_n, _p(x, C.c_double), n_in.value, C.byref(n_in),
+                                         _p(yb, C.c_double) if nb else None, _p(nrm, C.c_double), _p(fl, C.c_double),
+                                         C.byref(n_bc))
+        if rc != 0:
+            raise ValueError(f"oracle training points failed: {rc}")
+        return x[:n_in.value], yb[:nb], nrm[:nb], fl[:nb]
 
 
 PLAIN, VR, NAIVE = 0, 1, 2   # estimators: Alg. 2, Alg. 3, the naive Markov-tree estimator (Sec. 4.2)

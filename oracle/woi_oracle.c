@@ -1027,6 +1027,166 @@ int or_problem_info(const or_problem *pr, double *alpha, double *beta_scale, dou
     return OR_OK;
 }
 
+/* ---------------------------------------------------------------- surrogate training points */
+/* Training data of the neural-network surrogate (Sec. 5, Eq. MLP_loss).  Interior points: the
+   cell centres x_d = lo_d + (i_d + 1/2) (hi_d - lo_d) / n of an n^m grid over the bounding box of
+   dOmega (row-major, last coordinate fastest) that lie strictly inside dOmega and, when
+   margin > 0, farther than `margin` from every interface (sphere: ||x - c| - R|; ellipsoid: the
+   first-order level-set distance |q - 1| / |grad q|, q = (x - c)^T A (x - c); polyline: the
+   distance to its nearest segment).  Boundary points: uniform in the angular coordinates of
+   dOmega -- 2D: theta_k = 2 pi k / n_bc, the point of dOmega in direction theta_k from its centre
+   (circle) or from the vertex mean (polyline: the farthest crossing of that ray); 3D: polar
+   angles pi (i + 1/2) / n_bc and azimuths pi j / n_bc (2 n_bc of them) mapped through the
+   sphere or ellipsoid parametrisation -- with the outward unit normal and the normal-derivative
+   target b_1 / sigma_1 of the Neumann condition sigma_1 d_n u = b_1 (Eq. interface_problem). */
+static int training_box(const or_problem *pr, double *lo, double *hi)
+{
+    const region_t *g = &pr->r[0];
+    const int m = pr->m;
+    if (g->kind == OR_SPHERE || g->kind == OR_ELLIPSOID) {
+        for (int d = 0; d < m; ++d) {
+            double half = g->R;
+            if (g->kind == OR_ELLIPSOID) {   /* extent along axis d: sqrt((A^-1)_dd), A^-1 = L L */
+                double s2 = 0;
+                for (int j = 0; j < m; ++j) s2 += g->L[d * m + j] * g->L[d * m + j];
+                half = sqrt(s2);
+            }
+            lo[d] = g->c[d] - half; hi[d] = g->c[d] + half;
+        }
+        return OR_OK;
+    }
+    if (g->kind == OR_POLYLINE) {
+        lo[0] = hi[0] = g->v[0]; lo[1] = hi[1] = g->v[1];
+        for (int j = 1; j < g->nv; ++j)
+            for (int d = 0; d < 2; ++d) {
+                if (g->v[2 * j + d] < lo[d]) lo[d] = g->v[2 * j + d];
+                if (g->v[2 * j + d] > hi[d]) hi[d] = g->v[2 * j + d];
+            }
+        return OR_OK;
+    }
+    return OR_EUNSUP;
+}
+
+static int inside_region(const region_t *g, int m, const double *x)
+{
+    if (g->kind == OR_SPHERE) {
+        double r2 = 0; for (int i = 0; i < m; ++i) r2 += (x[i] - g->c[i]) * (x[i] - g->c[i]);
+        return r2 < g->R * g->R;
+    }
+    if (g->kind == OR_ELLIPSOID) {
+        double q = 0;
+        for (int i = 0; i < m; ++i) for (int j = 0; j < m; ++j) q += (x[i] - g->c[i]) * g->A[i * m + j] * (x[j] - g->c[j]);
+        return q < 1.0;
+    }
+    /* polyline: crossing number of the ray x + t e_1, t > 0 */
+    int in = 0;
+    for (int j = 0; j < g->nv; ++j) {
+        const double *a = g->v + 2 * j, *b = g->v + 2 * ((j + 1) % g->nv);
+        if ((a[1] > x[1]) != (b[1] > x[1])) {
+            double xi = a[0] + (x[1] - a[1]) / (b[1] - a[1]) * (b[0] - a[0]);
+            if (x[0] < xi) in = !in;
+        }
+    }
+    return in;
+}
+
+static double distance_to_region(const region_t *g, int m, const double *x)
+{
+    if (g->kind == OR_SPHERE) {
+        double r2 = 0; for (int i = 0; i < m; ++i) r2 += (x[i] - g->c[i]) * (x[i] - g->c[i]);
+        return fabs(sqrt(r2) - g->R);
+    }
+    if (g->kind == OR_ELLIPSOID) {
+        double q = 0, gn = 0;
+        for (int i = 0; i < m; ++i) {
+            double t = 0; for (int j = 0; j < m; ++j) t += g->A[i * m + j] * (x[j] - g->c[j]);
+            q += (x[i] - g->c[i]) * t; gn += t * t;
+        }
+        return fabs(q - 1.0) / (2.0 * sqrt(gn));
+    }
+    double best = INFINITY;
+    for (int j = 0; j < g->nv; ++j) {
+        const double *a = g->v + 2 * j, *b = g->v + 2 * ((j + 1) % g->nv);
+        double ex = b[0] - a[0], ey = b[1] - a[1], l2 = ex * ex + ey * ey;
+        double s = ((x[0] - a[0]) * ex + (x[1] - a[1]) * ey) / l2;
+        s = s < 0 ? 0 : (s > 1 ? 1 : s);
+        double dx = x[0] - (a[0] + s * ex), dy = x[1] - (a[1] + s * ey), dd = sqrt(dx * dx + dy * dy);
+        if (dd < best) best = dd;
+    }
+    return best;
+}
+
+int or_training_points(const or_problem *pr, int grid_n, double margin, int bc_n, double *interior, int64_t cap,
+                       int64_t *n_interior, double *bc_points, double *bc_normals, double *bc_flux, int64_t *n_bc)
+{
+    const int m = pr->m;
+    if (grid_n < 1 || bc_n < 0 || (m != 2 && m != 3 && bc_n > 0)) return OR_EINVAL;
+    for (int i = 0; i < pr->N; ++i) if (pr->r[i].kind == OR_MESH) return OR_EUNSUP;
+    double lo[OR_MAX_DIM], hi[OR_MAX_DIM], step[OR_MAX_DIM];
+    int rc = training_box(pr, lo, hi);
+    if (rc) return rc;
+    for (int d = 0; d < m; ++d) step[d] = (hi[d] - lo[d]) / grid_n;
+    uint64_t nodes = 1;
+    for (int d = 0; d < m; ++d) nodes *= (uint64_t)grid_n;
+    int64_t count = 0;
+    for (uint64_t k = 0; k < nodes; ++k) {
+        double x[OR_MAX_DIM];
+        uint64_t r = k;
+        for (int d = m - 1; d >= 0; --d) { x[d] = lo[d] + ((double)(r % (uint64_t)grid_n) + 0.5) * step[d]; r /= (uint64_t)grid_n; }
+        if (!inside_region(&pr->r[0], m, x)) continue;
+        int keep = 1;
+        if (margin > 0)
+            for (int i = 0; i < pr->N && keep; ++i) keep = distance_to_region(&pr->r[i], m, x) > margin;
+        if (!keep) continue;
+        if (count < cap) memcpy(interior + (size_t)count * m, x, sizeof(double) * m);
+        ++count;
+    }
+    *n_interior = count;
+    /* boundary */
+    const region_t *g = &pr->r[0];
+    int64_t nb = m == 2 ? bc_n : 2 * (int64_t)bc_n * bc_n;
+    if (n_bc) *n_bc = nb;
+    if (!bc_points || bc_n == 0) return OR_OK;
+    const double sigma1 = pr->sigma[0];
+    for (int64_t k = 0; k < nb; ++k) {
+        double y[3] = {0, 0, 0}, n[3] = {0, 0, 0};
+        int seg = 0;
+        if (m == 2) {
+            const double th = 2 * OR_PI * (double)k / bc_n, d[2] = {cos(th), sin(th)};
+            if (g->kind == OR_SPHERE) {
+                for (int i = 0; i < 2; ++i) y[i] = g->c[i] + g->R * d[i];
+            } else {   /* polyline: farthest crossing of the ray from the vertex mean */
+                double z[2] = {0, 0}, tbest = -1;
+                for (int j = 0; j < g->nv; ++j) { z[0] += g->v[2 * j] / g->nv; z[1] += g->v[2 * j + 1] / g->nv; }
+                for (int j = 0; j < g->nv; ++j) {
+                    const double *a = g->v + 2 * j, *b = g->v + 2 * ((j + 1) % g->nv);
+                    double ex = b[0] - a[0], ey = b[1] - a[1], den = d[0] * ey - d[1] * ex;
+                    if (den == 0) continue;
+                    double t = ((a[0] - z[0]) * ey - (a[1] - z[1]) * ex) / den;
+                    double sp = ((a[0] - z[0]) * d[1] - (a[1] - z[1]) * d[0]) / den;
+                    if (sp < 0 || sp >= 1 || !(t > 0) || t <= tbest) continue;
+                    tbest = t; seg = j;
+                    y[0] = a[0] + sp * ex; y[1] = a[1] + sp * ey;
+                }
+                if (tbest < 0) return OR_EGEOM;
+            }
+        } else {
+            const int64_t i = k / (2 * bc_n), j = k % (2 * bc_n);
+            const double th = OR_PI * ((double)i + 0.5) / bc_n, ph = OR_PI * (double)j / bc_n;
+            const double u[3] = {sin(th) * cos(ph), sin(th) * sin(ph), cos(th)};
+            if (g->kind == OR_SPHERE) {
+                for (int a = 0; a < 3; ++a) y[a] = g->c[a] + g->R * u[a];
+            } else {
+                for (int a = 0; a < 3; ++a) { double t = 0; for (int b = 0; b < 3; ++b) t += g->L[a * 3 + b] * u[b]; y[a] = g->c[a] + t; }
+            }
+        }
+        normal_at(g, m, y, seg, n);
+        for (int a = 0; a < m; ++a) { bc_points[k * m + a] = y[a]; bc_normals[k * m + a] = n[a]; }
+        bc_flux[k] = data_b(g, m, y, seg) / sigma1;
+    }
+    return OR_OK;
+}
+
 int or_sample_surface(const or_problem *pr, int h, uint64_t seed, uint64_t n, double *y)
 {
     if (h < 0 || h >= pr->N) return OR_EINVAL;

@@ -98,6 +98,11 @@ int  or_estimate_groups(const or_problem *p, const double *x, int64_t P, const o
                         int n_threads, double *mean, double *se, double *grad, double *grad_se, or_counters *cnt);
 /* Philox4x32-10 block, exported for the known-answer test. */
 void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* Training data of the neural-network surrogate (Sec. 5, Eq. MLP_loss): the interior grid nodes
+   inside dOmega clear of the interfaces by `margin` (count in *n_interior, the first `cap`
+   written), and 2D n_bc / 3D 2 n_bc^2 boundary points with outward normals and b_1 / sigma_1. */
+int  or_training_points(const or_problem *p, int grid_n, double margin, int bc_n, double *interior, int64_t cap,
+                        int64_t *n_interior, double *bc_points, double *bc_normals, double *bc_flux, int64_t *n_bc);
 /* Uniform point on interface `region` from one attempt's words (for histogram tests). */
 int  or_sample_surface(const or_problem *p, int region, uint64_t seed, uint64_t n, double *y);
 

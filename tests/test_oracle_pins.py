@@ -594,3 +594,69 @@ def test_nested_meshes_match_concentric_spheres(oracle_mod):
         u, gu = CF.concentric_uM([1.0, 0.5], sig, lam, 1, 3, M, xk, H, gH)
         assert abs(mean[k] - u) < ZMAX * se[k]
         assert np.max(np.abs((g[k] - gu) / gse[k])) < ZMAX
+
+
+# ----------------------------------------------------------------------------- surrogate training data
+def test_training_grid_counts_lattice_points(oracle_mod):
+    """Interior training points of the surrogate (Sec. 5): on the unit disk a grid of n = 2k + 1
+    cells per axis has its centres at 2 (a, b) / (2k + 1), a, b in -k..k, so the nodes inside are
+    the integer pairs with a^2 + b^2 <= k (k + 1) (counted here over the integers); with a margin,
+    the nodes within it of the circles r = 1 and r = 0.5 are dropped."""
+    p, _ = W.concentric_disk_2d()
+    op = oracle_mod.OracleProblem(p)
+    for k in (1, 2, 5, 13, 30):
+        x, _, _, _ = op.training_points(2 * k + 1)
+        a = np.arange(-k, k + 1)
+        count = int(((a[:, None] ** 2 + a[None, :] ** 2) <= k * (k + 1)).sum())
+        assert len(x) == count, (k, len(x), count)
+        assert np.allclose(x * (2 * k + 1) / 2, np.round(x * (2 * k + 1) / 2), atol=1e-12)
+    x, _, _, _ = op.training_points(61, margin=0.1)
+    a = np.arange(-30, 31) * 2 / 61
+    X, Y = np.meshgrid(a, a, indexing="ij")
+    r = np.hypot(X, Y)
+    keep = (r < 1) & (np.abs(r - 1) > 0.1) & (np.abs(r - 0.5) > 0.1)
+    assert len(x) == int(keep.sum())
+    assert np.allclose(x, np.stack([X[keep], Y[keep]], 1), atol=1e-14)   # row-major, last coordinate fastest
+
+
+def test_training_grid_polyline_inside(oracle_mod):
+    """A non-convex L-shaped polyline: its 8 x 8 cell centres (box [0, 2]^2) are inside unless both
+    coordinates exceed 1: 48 nodes."""
+    L = W.Shape(W.POLYLINE, np.array([0.6, 0.6]), 0.0, None,
+                np.array([[0, 0], [2, 0], [2, 1], [1, 1], [1, 2], [0, 2]], dtype=np.float64))
+    p = W.Problem(2, [-1], [1.0], [L], [W.zero_data(2)], 2, "L-shape")
+    x, _, _, _ = oracle_mod.OracleProblem(p).training_points(8)
+    assert len(x) == 48 and not np.any((x[:, 0] > 1) & (x[:, 1] > 1))
+
+
+def test_training_boundary_samples(oracle_mod):
+    """Boundary training points (Sec. 5, Eq. MLP_loss): uniform angles on dOmega with the outward
+    normal and the normal-derivative target b_1 / sigma_1.  Circle: b = cos(theta), sigma_1 = 10;
+    sphere: b = 5 x_1 / |x|; ellipsoid: on (y - c)^T A (y - c) = 1 with n = A y / |A y| and the
+    uniform-field flux b = sigma n_1; star polyline: on the polyline, in the sampled direction from
+    its vertex mean."""
+    p, _ = W.concentric_disk_2d()
+    _, y, n, f = oracle_mod.OracleProblem(p).training_points(5, bc_n=64)
+    th = 2 * np.pi * np.arange(64) / 64
+    assert np.allclose(y, np.stack([np.cos(th), np.sin(th)], 1), atol=1e-14) and np.allclose(n, y, atol=1e-14)
+    assert np.allclose(f, np.cos(th) / 10.0, atol=1e-14)
+    _, y, n, f = oracle_mod.OracleProblem(W.zheng_ex3_3d()).training_points(3, bc_n=6)
+    assert len(y) == 72 and np.allclose(np.linalg.norm(y, axis=1), 1.0) and np.allclose(n, y)
+    assert np.allclose(f, 5.0 * y[:, 0] / 1.0)
+    pe, A, Q = W.single_ellipsoid_linear(3, [0.9, 0.6, 0.4], sigma=2.0)
+    _, y, n, f = oracle_mod.OracleProblem(pe).training_points(3, bc_n=5)
+    assert np.allclose(np.einsum("ij,jk,ik->i", y, A, y), 1.0, atol=1e-12)
+    Ay = y @ A
+    assert np.allclose(n, Ay / np.linalg.norm(Ay, axis=1, keepdims=True), atol=1e-12)
+    assert np.allclose(f, n[:, 0], atol=1e-12)                         # b = sigma n . e_1, target b / sigma
+    star = W.star_polyline([0.05, -0.02], 0.5, 0.2, 5, 512, phase=0.3)
+    ps = W.Problem(2, [-1], [1.0], [star], [W.zero_data(2)], 2, "star")
+    _, y, n, f = oracle_mod.OracleProblem(ps).training_points(3, bc_n=40)
+    z = star.vertices.mean(0)
+    th = 2 * np.pi * np.arange(40) / 40
+    d = (y - z) / np.linalg.norm(y - z, axis=1, keepdims=True)
+    assert np.allclose(d, np.stack([np.cos(th), np.sin(th)], 1), atol=1e-12)
+    v, w = star.vertices, np.roll(star.vertices, -1, 0)
+    e = w - v
+    dist = [np.min(np.abs(e[:, 0] * (q - v)[:, 1] - e[:, 1] * (q - v)[:, 0]) / np.linalg.norm(e, axis=1)) for q in y]
+    assert np.max(dist) < 1e-13 and np.all(f == 0.0)
