@@ -320,6 +320,33 @@ def naive_block(woi, torch, W, ev, steps):
     return out
 
 
+def training_block(woi, torch, W, ev, steps):
+    """Training data of the neural-network surrogate (Sec. 5, Eq. MLP_loss) for the paper's Example 3
+    set-ups: interior grid points inside dOmega (2D: 100^2 grid, about the paper's 7845 points; 3D:
+    25^3, about its 8326) with the WoI estimate (value, SE, gradient; W = 1e5, M = 4 / 6, FP32 walks)
+    at each, and boundary points with normals and b_1 / sigma_1 targets (2D: 500; 3D: 51 x 102).
+    Points/s of the whole generation, and at the fixed SE of the FP64 path."""
+    import numpy as np
+    out = {}
+    for name, prob_desc, grid_n, bc_n, M in (("ex3_2d", W.bower_ex3_2d(), 100, 500, 4),
+                                             ("ex3_3d", W.zheng_ex3_3d(), 25, 51, 6)):
+        gp = woi.Problem(prob_desc)
+        woi._lib.woi_problem_upload(gp.handle)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, yb, nb, fb, cnt = woi.training_points(gp, grid_n, bc_n=bc_n)
+        t_pts = time.perf_counter() - t0
+        r32 = Path(woi, torch, gp, x, 100000, M, woi.FP32).run(ev, steps, 1)
+        r64 = Path(woi, torch, gp, x, 100000, M, woi.FP64).run(ev, 1, 0)
+        eps = float(np.median(r64["se"]))
+        out[name] = {"interior_points": cnt, "boundary_points": int(yb.shape[0]), "points_ms": t_pts * 1e3,
+                     "fp32_estimate_ms": r32["wall"] * 1e3, "fp64_estimate_ms": r64["wall"] * 1e3,
+                     "points_per_s": cnt / (t_pts + r32["wall"]),
+                     "points_per_s_fixed_se": cnt / (t_pts + fixed_se(r32, eps)),
+                     "fp64_points_per_s_fixed_se": cnt / (t_pts + fixed_se(r64, eps))}
+    return out
+
+
 def run_instances(woi, torch, inst, probs, precision, steps, warmup, ev, counters=None, shared=False):
     """The 512-instance 2D batch in one persistent graph launch (tuned launch shape); the timed
     graph replays the whole batch (same seed: every replay recomputes it).  shared: every instance
@@ -390,7 +417,7 @@ def main():
     ap.add_argument("--blocks", default="all",
                     help="comma-separated configurations to run besides the headline (disk_2d, star_tree_2d, "
                          "ellipsoid_tree_3d_vr, spheres_6d, point_charge_ellipsoids, mesh_tree_3d, "
-                         "naive_markov_trees), default all")
+                         "naive_markov_trees, surrogate_training_data), default all")
     ap.add_argument("--cpu-seconds", type=float, default=25.0)
     ap.add_argument("--detail", default="", help="also write the full record to this JSON file")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -517,6 +544,9 @@ def main():
         log("mesh_tree_3d done")
     if want("naive_markov_trees"):
         cfg["naive_markov_trees"] = naive_block(woi, torch, W, ev, es)
+    if want("surrogate_training_data"):
+        cfg["surrogate_training_data"] = training_block(woi, torch, W, ev, es)
+        log("surrogate_training_data done")
     log("configurations done: " + ", ".join(cfg))
     headline_cfg = {"instances_2d": {
         "ms": rec["ms_per_step"], "walk_steps_per_s": rec["value"], "frac": rec["roofline"]["frac"],

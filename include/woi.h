@@ -273,6 +273,32 @@ woi_status woi_batch_workspace_size(const woi_batch_item *items, int n, size_t *
 woi_status woi_estimate_batch(const woi_batch_item *items, int n, void *workspace, size_t workspace_bytes,
                               uint64_t *counters, void *stream);
 
+/* Training data of the neural-network surrogate of Sec. 5 (Eq. MLP_loss: a mean squared misfit to
+ * the WoI estimates at interior points plus one to the Neumann data at boundary points).
+ *   interior: cell centres x_d = lo_d + (i_d + 1/2)(hi_d - lo_d) / grid_n of a grid_n^dim grid over
+ *     the bounding box of dOmega, in row-major order (last coordinate fastest), strictly inside
+ *     dOmega and, when margin > 0, farther than `margin` from every interface (sphere: distance;
+ *     ellipsoid: first-order level-set distance |q - 1| / |grad q|; polyline: distance to the
+ *     nearest segment).  The first `cap` are written to interior [cap*dim] (device); the count of
+ *     all of them to *n_interior (host).  Estimate u, its SE and grad u there with woi_estimate.
+ *   boundary (bc_n > 0, dim 2 or 3): n_bc = bc_n (2D: angles 2 pi k / bc_n about the circle's
+ *     centre, or the polyline's vertex mean -- the farthest crossing of that ray) or 2 bc_n^2 (3D:
+ *     polar angles pi (i + 1/2) / bc_n, azimuths pi j / bc_n, through the sphere or ellipsoid
+ *     parametrisation) points bc_points [n_bc*dim], outward unit normals bc_normals [n_bc*dim] and
+ *     targets bc_flux [n_bc] = b_1 / sigma_1, the normal derivative the Neumann condition
+ *     sigma_1 d_n u = b_1 prescribes (device arrays; *n_bc, host, may be NULL).
+ * Synchronizes `stream` (the interior count is copied to the host); allocates 8 bytes of device
+ * memory per call.  Errors: INVALID_ARG (sizes, NULL, grid_n^dim > 1e10), UNSUPPORTED (triangle
+ * meshes; boundary points for dim > 3), DEVICE, OOM. */
+typedef struct {
+    int grid_n;               /* grid nodes per axis (>= 1)                            */
+    int bc_n;                 /* boundary resolution (0: no boundary points)          */
+    double margin;            /* minimum distance of interior points from interfaces  */
+} woi_training_spec;
+woi_status woi_training_points(const woi_problem *p, const woi_training_spec *spec, double *interior, int64_t cap,
+                               int64_t *n_interior, double *bc_points, double *bc_normals, double *bc_flux,
+                               int64_t *n_bc, void *stream);
+
 /* Statistics of one or more calls: the counter array they added to (see woi_estimate) and the
  * time between the query's event_begin and event_end.
  *   counters     device uint64[WOI_COUNTERS] (read with a synchronous copy) or NULL (zeros)

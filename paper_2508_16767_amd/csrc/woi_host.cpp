@@ -1665,6 +1665,66 @@ woi_status woi_stats_read(const uint64_t* counters, void* event_begin, void* eve
     return WOI_OK;
 }
 
+woi_status woi_training_points(const woi_problem* p, const woi_training_spec* spec, double* interior, int64_t cap,
+                               int64_t* n_interior, double* bc_points, double* bc_normals, double* bc_flux,
+                               int64_t* n_bc, void* stream) {
+    if (!p || !spec || !n_interior || cap < 0 || (cap > 0 && !interior))
+        return fail(WOI_E_INVALID_ARG, "NULL problem, spec or count, or no interior array for cap > 0");
+    const Host& H = p->H;
+    const int m = H.m;
+    if (spec->grid_n < 1 || spec->bc_n < 0 || !(spec->margin >= 0))
+        return fail(WOI_E_INVALID_ARG, "grid_n must be >= 1, bc_n >= 0, margin >= 0");
+    if (spec->bc_n > 0 && m != 2 && m != 3) return fail(WOI_E_UNSUPPORTED, "boundary samples need dim 2 or 3");
+    if (spec->bc_n > 0 && (!bc_points || !bc_normals || !bc_flux)) return fail(WOI_E_INVALID_ARG, "NULL boundary arrays");
+    if (has_mesh(H)) return fail(WOI_E_UNSUPPORTED, "training points are not built for triangle meshes");
+    if (std::pow((double)spec->grid_n, (double)m) > 1e10) return fail(WOI_E_INVALID_ARG, "grid_n^dim exceeds 1e10 nodes");
+    woi_status st = woi_problem_upload(const_cast<woi_problem*>(p));
+    if (st != WOI_OK) return st;
+    woi::TrainParams tp{};
+    tp.dp = static_cast<const DevProblem*>(p->dev);
+    tp.n = spec->grid_n;
+    const HostRegion& g = H.r[0];
+    for (int d = 0; d < m; ++d) {
+        double lo = 0, hi = 0;
+        if (g.kind == WOI_SHAPE_SPHERE || g.kind == WOI_SHAPE_ELLIPSOID) {
+            double half = g.R;
+            if (g.kind == WOI_SHAPE_ELLIPSOID) {   // extent along axis d: sqrt((A^-1)_dd), A^-1 = L L
+                double s2 = 0;
+                for (int j = 0; j < m; ++j) s2 += g.L[d * m + j] * g.L[d * m + j];
+                half = std::sqrt(s2);
+            }
+            lo = g.c[d] - half;
+            hi = g.c[d] + half;
+        } else {
+            lo = hi = g.v[d];
+            for (int j = 0; j < g.nv(); ++j) { lo = std::min(lo, g.v[2 * j + d]); hi = std::max(hi, g.v[2 * j + d]); }
+        }
+        tp.lo[d] = lo;
+        tp.step[d] = (hi - lo) / spec->grid_n;
+    }
+    tp.margin = spec->margin;
+    tp.nodes = 1;
+    for (int d = 0; d < m; ++d) tp.nodes *= (uint64_t)spec->grid_n;
+    tp.out = interior;
+    tp.cap = cap;
+    tp.bc_n = spec->bc_n;
+    tp.n_bc = spec->bc_n == 0 ? 0 : (m == 2 ? spec->bc_n : 2 * (int64_t)spec->bc_n * spec->bc_n);
+    tp.bc_points = bc_points;
+    tp.bc_normals = bc_normals;
+    tp.bc_flux = bc_flux;
+    if (n_bc) *n_bc = tp.n_bc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int64_t* dcount = nullptr;
+    if (hipMalloc(&dcount, sizeof(int64_t)) != hipSuccess) return fail(WOI_E_OOM, "hipMalloc(8) failed");
+    tp.count = dcount;
+    hipError_t e = woi::launch_training(tp, m, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(n_interior, dcount, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(dcount);
+    if (e != hipSuccess) return fail(WOI_E_DEVICE, "training points: %s", hipGetErrorString(e));
+    return WOI_OK;
+}
+
 woi_status woi_trace(const woi_problem* p, const double* points, int64_t P, const woi_query* q, uint64_t n_samples,
                      double* F, double* G, uint32_t* trace, void* stream) {
     woi_query qq = *q;

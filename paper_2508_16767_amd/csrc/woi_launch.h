@@ -93,6 +93,26 @@ struct NParams {
 };
 hipError_t launch_naive(const KParams& kp, const NParams& np, int dim, bool fp32, dim3 grid, hipStream_t s);
 
+// ----------------------------------------------------------------------------- surrogate training data
+// Interior nodes x_d = lo_d + (i_d + 1/2) step_d of an n^dim grid (last coordinate fastest) inside
+// region 0 and farther than `margin` from every interface (when margin > 0), written in grid order
+// to `out` (the first `cap`; the total to *count, device); boundary nodes k < n_bc (2D: angle
+// 2 pi k / bc_n; 3D: bc_n polar x 2 bc_n azimuthal angles) with normals and b_1 / sigma_1.
+struct TrainParams {
+    const DevProblem* dp;
+    int n;
+    double lo[WOI_MAX_DIM], step[WOI_MAX_DIM];
+    double margin;
+    uint64_t nodes;
+    double* out;
+    int64_t cap;
+    int64_t* count;
+    int bc_n;
+    int64_t n_bc;
+    double *bc_points, *bc_normals, *bc_flux;
+};
+hipError_t launch_training(const TrainParams& tp, int dim, hipStream_t s);
+
 // ----------------------------------------------------------------------------- batches
 // Many instances in one persistent launch.  A work item is (instance, tile of 64 points,
 // chunk of samples); the workgroup that pulls it splits the chunk's samples evenly over

@@ -67,6 +67,10 @@ class _BatchItem(C.Structure):
                 ("mean", C.c_void_p), ("se", C.c_void_p), ("grad", C.c_void_p), ("grad_se", C.c_void_p)]
 
 
+class _TrainSpec(C.Structure):
+    _fields_ = [("grid_n", C.c_int), ("bc_n", C.c_int), ("margin", C.c_double)]
+
+
 class Stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("walker_steps", "redraws", "rejections", "cap_hits", "zero_distances",
                                           "search_node_tests", "segment_tests", "other_transitions",
@@ -75,7 +79,7 @@ class Stats(C.Structure):
 
 EXPORTS = ("woi_problem_create", "woi_problem_upload", "woi_problem_destroy", "woi_problem_get_info", "woi_workspace_size",
            "woi_estimate", "woi_estimate_noalloc", "woi_trace", "woi_batch_workspace_size", "woi_estimate_batch",
-           "woi_stats_read",
+           "woi_stats_read", "woi_training_points",
            "woi_status_string", "woi_last_error")
 
 
@@ -99,6 +103,9 @@ def _load():
     lib.woi_estimate_batch.argtypes = [C.POINTER(_BatchItem), C.c_int, C.c_void_p, C.c_size_t, C.c_void_p,
                                        C.c_void_p]
     lib.woi_stats_read.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Stats)]
+    lib.woi_training_points.argtypes = [C.c_void_p, C.POINTER(_TrainSpec), C.c_void_p, C.c_int64,
+                                        C.POINTER(C.c_int64), C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.POINTER(C.c_int64), C.c_void_p]
     lib.woi_status_string.restype = C.c_char_p
     lib.woi_status_string.argtypes = [C.c_int]
     lib.woi_last_error.restype = C.c_char_p
@@ -340,6 +347,28 @@ class Batch:
 def estimate_batch(entries, block_size=0, counters=None):
     """One batched estimate of every entry (see Batch)."""
     return Batch(entries, block_size, counters).run()
+
+
+def training_points(problem, grid_n, margin=0.0, bc_n=0, cap=None):
+    """woi_training_points: surrogate training data of Sec. 5 on the device -- interior grid points
+    inside dOmega (clear of the interfaces by `margin`), and boundary points, outward normals and
+    b_1 / sigma_1 targets.  Returns (interior [n, dim], bc_points, bc_normals, bc_flux) tensors."""
+    m = problem.dim
+    spec = _TrainSpec(int(grid_n), int(bc_n), float(margin))
+    if cap is None:
+        cap = 1
+        for _ in range(m):
+            cap *= int(grid_n)
+    nb = (bc_n if m == 2 else 2 * bc_n * bc_n) if bc_n else 0
+    x = torch.empty(max(cap, 1), m, dtype=torch.float64, device="cuda")
+    yb = torch.empty(max(nb, 1), m, dtype=torch.float64, device="cuda")
+    nr = torch.empty(max(nb, 1), m, dtype=torch.float64, device="cuda")
+    fl = torch.empty(max(nb, 1), dtype=torch.float64, device="cuda")
+    n_in, n_bc = C.c_int64(), C.c_int64()
+    _check(_lib.woi_training_points(problem.handle, C.byref(spec), C.c_void_p(x.data_ptr()), int(cap), C.byref(n_in),
+                                    C.c_void_p(yb.data_ptr()) if nb else None, C.c_void_p(nr.data_ptr()) if nb else None,
+                                    C.c_void_p(fl.data_ptr()) if nb else None, C.byref(n_bc), _stream()))
+    return x[:min(n_in.value, cap)], yb[:nb], nr[:nb], fl[:nb], n_in.value
 
 
 def new_counters(device="cuda"):
