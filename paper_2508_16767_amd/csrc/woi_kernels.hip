@@ -80,8 +80,7 @@ __global__ __launch_bounds__(LDS ? 512 : 256, (walk_waves_per_simd<R, D>())) voi
 // Generation: lane = point group.  A workgroup row of tp.lg lanes (a multiple of 64, so a
 // wave never leaves its row) walks one run of tp.spt consecutive samples; a workgroup holds
 // blockDim.x / tp.lg rows.  All lanes of a wave share the walk index, so with the shared
-// schedule the transition case and geometry record are wave-uniform.  The walker runs with its
-// polyline sampler out of line (INL = false): inlined here, ROCm 7.2 clang miscompiled it.
+// schedule the transition case and geometry record are wave-uniform.
 template <typename R, int D, bool VR, bool LDS>
 __global__ __launch_bounds__(LDS ? 512 : 256, (walk_waves_per_simd<R, D>())) void traj_kernel(KParams kq, TParams tp) {
     KParams kp = kq;
@@ -106,7 +105,7 @@ __global__ __launch_bounds__(LDS ? 512 : 256, (walk_waves_per_simd<R, D>())) voi
     for (uint32_t s = s0; s < s1; ++s) {
         const uint32_t w = (uint32_t)(kp.first_sample + tp.chunk_first + s);
         Start<R, D> st2[2];
-        if constexpr (VR) vr_starts<R, D, LDS, false>(dp, pay, kp, w, (uint32_t)gc, first_region(dp, kp, w, (uint32_t)gc), st2, cnt);
+        if constexpr (VR) vr_starts<R, D, LDS>(dp, pay, kp, w, (uint32_t)gc, first_region(dp, kp, w, (uint32_t)gc), st2, cnt);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             StoreSink<R, D> sink;
@@ -115,8 +114,8 @@ __global__ __launch_bounds__(LDS ? 512 : 256, (walk_waves_per_simd<R, D>())) voi
             sink.ng = tp.ng;
             sink.M = kp.M;
             sink.on = active;
-            walker<R, D, VR, LDS, StoreSink<R, D>, false>(dp, pay, kp, w, (uint32_t)gc, k, sink, nullptr, cnt,
-                                                          VR ? &st2[k] : nullptr);
+            walker<R, D, VR, LDS, StoreSink<R, D>>(dp, pay, kp, w, (uint32_t)gc, k, sink, nullptr, cnt,
+                                                   VR ? &st2[k] : nullptr);
         }
     }
 }

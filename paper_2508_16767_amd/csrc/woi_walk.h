@@ -326,13 +326,10 @@ __device__ __forceinline__ const int* int_payload(const DevProblem* dp) {
 }
 
 // Point at arclength s on a polyline: the segment is the largest j with cum[j] <= s, found
-// from the guide table entry for s in O(1) expected probes.  Inlined in the walk, batch and
-// naive kernels; the trajectory-generation kernel calls it out of line: inlined there at
-// -O2/-O3 (ROCm 7.2 clang) it produced points off the polyline in "other" transitions, while
-// -O1, an out-of-line call, and the other kernels were exact; the shared-trajectory parity
-// tests check this path.
+// from the guide table entry for s in O(1) expected probes (inlined in every kernel: no call
+// frame, no scratch).
 template <typename R, int D, bool LDS>
-__device__ __forceinline__ bool polyline_at_body(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay, R s,
+__device__ __forceinline__ bool polyline_at(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay, R s,
                                             R y[D], int& seg) {
     if constexpr (D == 2) {
         // FP32: cum and 1/len interleaved (stride 2); FP64: cum, and len in its own table
@@ -353,20 +350,6 @@ __device__ __forceinline__ bool polyline_at_body(const DevProblem* dp, const Dev
         seg = j;
     }
     return true;
-}
-
-template <typename R, int D, bool LDS>
-__device__ __noinline__ bool polyline_at_call(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay, R s,
-                                                 R y[D], int& seg) {
-    return polyline_at_body<R, D, LDS>(dp, g, pay, s, y, seg);
-}
-
-// INL: inline the sampler (every kernel but the trajectory generation, which passes false).
-template <typename R, int D, bool LDS, bool INL>
-__device__ __forceinline__ bool polyline_at(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay, R s,
-                                            R y[D], int& seg) {
-    if constexpr (INL) return polyline_at_body<R, D, LDS>(dp, g, pay, s, y, seg);
-    else return polyline_at_call<R, D, LDS>(dp, g, pay, s, y, seg);
 }
 
 template <typename R, int D>
@@ -391,7 +374,7 @@ __device__ __forceinline__ int mesh_triangle(const DevProblem* dp, const DevRegi
     return j;
 }
 
-template <typename R, int D, bool LDS, bool INL = true>
+template <typename R, int D, bool LDS>
 __device__ __forceinline__ bool surf_attempt(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
                                              const Stream& st, uint32_t step, int att, R y[D], int& seg,
                                              const uint32_t* pre = nullptr) {
@@ -411,7 +394,7 @@ __device__ __forceinline__ bool surf_attempt(const DevProblem* dp, const DevRegi
     }
     if (g.kind == WOI_SHAPE_POLYLINE2D) {
         Words<1> W; W.take(st, step, (uint32_t)att, pre);
-        return polyline_at<R, D, LDS, INL>(dp, g, pay, RO<R>::u(W.w[0]) * Pay<R>::total(g), y, seg);
+        return polyline_at<R, D, LDS>(dp, g, pay, RO<R>::u(W.w[0]) * Pay<R>::total(g), y, seg);
     }
     const R* q = pay + Pay<R>::g(g);
     if (g.kind == WOI_SHAPE_SPHERE) {
@@ -442,11 +425,11 @@ __device__ __forceinline__ bool surf_attempt(const DevProblem* dp, const DevRegi
 }
 
 // point at arclength s on a closed 2D curve (circle or polyline)
-template <typename R, int D, bool LDS, bool INL = true>
+template <typename R, int D, bool LDS>
 __device__ __forceinline__ void curve_at(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay, R s,
                                          R y[D], int& seg) {
     if constexpr (D == 2) {
-        if (g.kind == WOI_SHAPE_POLYLINE2D) { polyline_at<R, D, LDS, INL>(dp, g, pay, s, y, seg); return; }
+        if (g.kind == WOI_SHAPE_POLYLINE2D) { polyline_at<R, D, LDS>(dp, g, pay, s, y, seg); return; }
         const R* q = pay + Pay<R>::g(g);
         R sn, cs;
         RO<R>::sc2pi(s / (R(2) * R(3.14159265358979323846) * q[2]), sn, cs);
@@ -455,7 +438,7 @@ __device__ __forceinline__ void curve_at(const DevProblem* dp, const DevRegion& 
 }
 
 // one attempt of a uniform sample on the VR half `cls` of region h
-template <typename R, int D, bool LDS, bool INL = true>
+template <typename R, int D, bool LDS>
 __device__ __forceinline__ bool vr_attempt(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
                                            int cls, const Stream& st, int att, R y[D], int& seg) {
     if constexpr (D == 2) {
@@ -469,17 +452,17 @@ __device__ __forceinline__ bool vr_attempt(const DevProblem* dp, const DevRegion
             if (c == cls) {
                 const R l = end - start;
                 if (t < acc + l || p == g.nbrk) {
-                    curve_at<R, D, LDS, INL>(dp, g, pay, fmin(start + (t - acc), end), y, seg);
+                    curve_at<R, D, LDS>(dp, g, pay, fmin(start + (t - acc), end), y, seg);
                     return true;
                 }
                 acc += l;
             }
             start = end; c ^= 1;
         }
-        curve_at<R, D, LDS, INL>(dp, g, pay, start, y, seg);
+        curve_at<R, D, LDS>(dp, g, pay, start, y, seg);
         return true;
     } else {
-        if (!surf_attempt<R, D, LDS, INL>(dp, g, pay, st, 0, att, y, seg)) return false;
+        if (!surf_attempt<R, D, LDS>(dp, g, pay, st, 0, att, y, seg)) return false;
         return (Pay<R>::s(g) * data_b<R, D, LDS>(dp, g, pay, y, seg) >= R(0)) == (cls == 0);
     }
 }
@@ -1043,7 +1026,7 @@ __device__ __forceinline__ uint32_t trace_word(int h, int cs, int q, int pick, i
 // within WOI_ATTEMPT_CAP draws (the walk stops there).  Draws come from st at `step`.
 // coop: the wave shares the interface (shared schedule) -- rejection sampling on an ellipsoid is
 // then done cooperatively (same points and counts).
-template <typename R, int D, bool LDS, bool INL = true>
+template <typename R, int D, bool LDS>
 __device__ __forceinline__ R transition(const DevProblem* __restrict__ dp, const R* __restrict__ pay,
                                         const DevRegion* g, int rel, const Stream& st, uint32_t step,
                                         const R y[D], int seg, R yn[D], int& segn, R& Q, int& qn, int& pick,
@@ -1055,12 +1038,12 @@ __device__ __forceinline__ R transition(const DevProblem* __restrict__ dp, const
         if (D == 3 && g->kind == WOI_SHAPE_ELLIPSOID && wave_full(coop)) {
             auto try_at = [&](uint32_t c0, uint32_t c1, int a, R yy[D], int& sg) -> bool {
                 const Stream s2{st.k0, st.k1, c0, c1, st.c2};
-                return surf_attempt<R, D, LDS, INL>(dp, *g, pay, s2, step, a, yy, sg);
+                return surf_attempt<R, D, LDS>(dp, *g, pay, s2, step, a, yy, sg);
             };
             att = coop_first_accept<R, D>(try_at, st.c0, st.c1, yn, segn, cnt);
         } else {
             for (att = 0; att < WOI_ATTEMPT_CAP; ++att) {
-                if (surf_attempt<R, D, LDS, INL>(dp, *g, pay, st, step, att, yn, segn, pre)) break;
+                if (surf_attempt<R, D, LDS>(dp, *g, pay, st, step, att, yn, segn, pre)) break;
                 cnt.rejections++;
             }
             if (att == WOI_ATTEMPT_CAP) cnt.caps++;
@@ -1201,7 +1184,7 @@ __device__ __forceinline__ int first_region(const DevProblem* __restrict__ dp, c
 // per walker.  Walker k keeps its own stream and attempt count, so the points, attempt counts
 // and cap rule (after WOI_ATTEMPT_CAP attempts the last proposal is kept) are exactly those
 // of drawing the walkers one after the other.  A walker whose half is empty draws nothing.
-template <typename R, int D, bool LDS, bool INL = true>
+template <typename R, int D, bool LDS>
 __device__ __forceinline__ void vr_starts(const DevProblem* __restrict__ dp, const R* __restrict__ pay,
                                           const KParams& kp, uint32_t w, uint32_t group, int h, Start<R, D> s[2],
                                           Counts& cnt) {
@@ -1221,7 +1204,7 @@ __device__ __forceinline__ void vr_starts(const DevProblem* __restrict__ dp, con
             const Stream& sk = k ? st1 : st0;
             auto try_at = [&](uint32_t c0, uint32_t c1, int a, R yy[D], int& sg) -> bool {
                 const Stream s2{sk.k0, sk.k1, c0, c1, sk.c2};
-                return vr_attempt<R, D, LDS, INL>(dp, g, pay, k, s2, a, yy, sg);
+                return vr_attempt<R, D, LDS>(dp, g, pay, k, s2, a, yy, sg);
             };
             s[k].att = coop_first_accept<R, D>(try_at, sk.c0, sk.c1, s[k].y, s[k].seg, cnt);
         }
@@ -1232,7 +1215,7 @@ __device__ __forceinline__ void vr_starts(const DevProblem* __restrict__ dp, con
         const int att = k ? s[1].att : s[0].att;
         R y[D];
         int seg = 0;
-        const bool ok = vr_attempt<R, D, LDS, INL>(dp, g, pay, k, k ? st1 : st0, att, y, seg);
+        const bool ok = vr_attempt<R, D, LDS>(dp, g, pay, k, k ? st1 : st0, att, y, seg);
         if (!ok) cnt.rejections++;
         const bool done = ok || att + 1 == WOI_ATTEMPT_CAP;
         if (!ok && done) cnt.caps++;
@@ -1249,7 +1232,7 @@ __device__ __forceinline__ void vr_starts(const DevProblem* __restrict__ dp, con
 // Walker k of sample `w`: emits c_i and y_i, i = 0..M, to the sink (the accumulating sink
 // forms sum_i c_i Phi(x, y_i) and sum_i c_i grad_x Phi; the caller multiplies by N).
 // pre: the walker's first point drawn beforehand (VR, see vr_starts), or null.
-template <typename R, int D, bool VR, bool LDS, class Sink, bool INL = true>
+template <typename R, int D, bool VR, bool LDS, class Sink>
 __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const R* __restrict__ pay,
                                        const KParams& kp, uint32_t w, uint32_t group, int k, Sink& sink,
                                        uint32_t* __restrict__ tr, Counts& cnt, const Start<R, D>* pre = nullptr) {
@@ -1290,14 +1273,14 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
         if (!VR && D == 3 && g->kind == WOI_SHAPE_ELLIPSOID && wave_full(kp.shared_sched)) {
             auto try_at = [&](uint32_t c0, uint32_t c1, int a, R yy[D], int& sg) -> bool {
                 const Stream s2{st.k0, st.k1, c0, c1, st.c2};
-                return surf_attempt<R, D, LDS, INL>(dp, *g, pay, s2, 0, a, yy, sg);
+                return surf_attempt<R, D, LDS>(dp, *g, pay, s2, 0, a, yy, sg);
             };
             att = coop_first_accept<R, D>(try_at, st.c0, st.c1, y, seg, cnt);
         } else {
             for (att = 0; att < WOI_ATTEMPT_CAP; ++att) {
                 bool ok;
-                if constexpr (VR) ok = vr_attempt<R, D, LDS, INL>(dp, *g, pay, k, st, att, y, seg);
-                else ok = surf_attempt<R, D, LDS, INL>(dp, *g, pay, st, 0, att, y, seg);
+                if constexpr (VR) ok = vr_attempt<R, D, LDS>(dp, *g, pay, k, st, att, y, seg);
+                else ok = surf_attempt<R, D, LDS>(dp, *g, pay, st, 0, att, y, seg);
                 if (ok) break;
                 cnt.rejections++;
             }
@@ -1334,7 +1317,7 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
             pre[0] = (i & 1) ? pb.x : pb.z;
             pre[1] = (i & 1) ? pb.y : pb.w;
         }
-        const R tf = transition<R, D, LDS, INL>(dp, pay, g, rel, st, (uint32_t)i, y, seg, yn, segn, Q, qn, pick, att,
+        const R tf = transition<R, D, LDS>(dp, pay, g, rel, st, (uint32_t)i, y, seg, yn, segn, Q, qn, pick, att,
                                                 cnt, D == 2 ? pre : nullptr, kp.shared_sched != 0);
         if (tf == R(0)) {   // no hit after the attempt cap: the walker stops here
             if (tr) for (int j = i; j <= M; ++j) tr[j] = trace_word(h, rel, 0, 0, 0, att);
