@@ -749,10 +749,11 @@ void flux_integrals(Host& H) {
 
 // Bounding-volume hierarchy over a mesh's triangles: median split of the centroids along the
 // longest axis of their box, leaves of at most 4 triangles, nodes in depth-first order with the
-// index of the node after each subtree.  Node: box min, box max (widened outward by a relative
-// 1e-5 of the mesh size plus FP32 rounding), skip index, 8 * leaf list start + triangle count
+// index of the node after each subtree.  Node: box min, box max (widened outward by 1e-5 of the
+// larger of the mesh's size and coordinates and the root extent `ext`, which bounds the walker
+// positions the FP32 slab tests subtract, plus FP32 rounding), skip index, 8 * leaf list start + triangle count
 // (-1 for inner nodes).
-void mesh_bvh(const HostRegion& g, std::vector<float>& nodes, std::vector<int32_t>& list) {
+void mesh_bvh(const HostRegion& g, double ext, std::vector<float>& nodes, std::vector<int32_t>& list) {
     const int nt = g.ntri();
     std::vector<int> ids(nt);
     std::iota(ids.begin(), ids.end(), 0);
@@ -770,7 +771,7 @@ void mesh_bvh(const HostRegion& g, std::vector<float>& nodes, std::vector<int32_
             cen[3 * j + k] = c;
         }
     const double pad = 1e-5 * std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], std::fabs(lo[0]), std::fabs(hi[0]),
-                                        std::fabs(lo[1]), std::fabs(hi[1]), std::fabs(lo[2]), std::fabs(hi[2])});
+                                        std::fabs(lo[1]), std::fabs(hi[1]), std::fabs(lo[2]), std::fabs(hi[2]), ext});
     nodes.clear();
     list.clear();
     std::function<void(int, int)> build = [&](int a, int b) {   // triangles ids[a, b)
@@ -856,30 +857,31 @@ bool dirpoly_dense(const HostRegion& g, int m, std::vector<double>& dense, int& 
     return true;
 }
 
-double polyline_band(const HostRegion& g) {
+// Coordinate magnitude that the FP32 rounding bands scale with: 1 + the polyline's own, or the
+// magnitude of the walker positions if larger (every interface lies inside the root's, so
+// `ext`, the root's extent, bounds them).
+double band_scale(const HostRegion& g, double ext) {
     double scale = 0;
     for (double x : g.v) scale = std::max(scale, std::fabs(x));
-    return 4e-6 * (1.0 + scale);
+    return std::max(1.0 + scale, ext);
 }
+
+double polyline_band(const HostRegion& g, double ext) { return 4e-6 * band_scale(g, ext); }
 
 // |signed distance| of a vertex from a line below which an FP32 walk's sign is not trusted:
 // 16 FP32 ulps of the coordinates (the FP32 distance is two FMAs on rounded coordinates, a few
 // ulps at most).
-double segment_band(const HostRegion& g) {
-    double scale = 0;
-    for (double x : g.v) scale = std::max(scale, std::fabs(x));
-    return 0x1p-20 * (1.0 + scale);
-}
+double segment_band(const HostRegion& g, double ext) { return 0x1p-20 * band_scale(g, ext); }
 
-void block_bounds(const HostRegion& g, std::vector<float>& bnd, int& n2, int& top) {
+void block_bounds(const HostRegion& g, double ext, std::vector<float>& bnd, int& n2, int& top) {
     const int n = g.nv();
     n2 = 1;
     int L = 0;
     while (n2 < n) { n2 *= 2; ++L; }
     top = std::max(1, L - 3);   // first block: 1/8 of the polyline
-    const double pad = polyline_band(g);
+    const double pad = polyline_band(g, ext);
     bnd.assign((size_t)n2 + n, 0.0f);
-    const double band = segment_band(g);
+    const double band = segment_band(g, ext);
     for (int j = 0; j < n; ++j) bnd[(size_t)n2 + j] = (float)band;
     for (int l = 1; l <= L; ++l) {
         const int base = n2 >> l;   // heap layout: level l occupies [n2 >> l, 2 (n2 >> l))
@@ -1012,7 +1014,8 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
     hdr.unit_area_f = (float)hdr.unit_area;
     hdr.phi_c_f = (float)hdr.phi_c;
     // FP32 sign band: 2^-19 (32 FP32 ulps) of the largest coordinate magnitude on dOmega (every
-    // interface lies inside the root's)
+    // interface lies inside the root's); root_ext also scales the polyline bands and mesh boxes
+    double root_ext = 0;
     {
         const HostRegion& g = H.r[0];
         double ext = 0;
@@ -1030,6 +1033,7 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
         for (double x : g.v) ext = std::max(ext, std::fabs(x));
         for (double x : g.mv) ext = std::max(ext, std::fabs(x));
         hdr.sign_band_f = (float)(0x1p-19 * std::max(1.0, ext));
+        root_ext = ext;
     }
     double acc = 0;
     for (int i = 0; i < N; ++i) {
@@ -1115,10 +1119,10 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
             r.nrm64 = put64(nrm.data(), nrm.size());
             r.nrm32 = put32(nrm.data(), nrm.size());
             std::vector<float> bnd;
-            block_bounds(g, bnd, r.n2, r.top);
+            block_bounds(g, root_ext, bnd, r.n2, r.top);
             r.bnd = (int)p32.size();
             p32.insert(p32.end(), bnd.begin(), bnd.end());
-            r.hband_f = (float)segment_band(g);
+            r.hband_f = (float)segment_band(g, root_ext);
             r.guide = (int)pi.size();
             for (int k = 0; k < n; ++k) {
                 const double s0 = g.cum[n] * k / n;
@@ -1131,7 +1135,7 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
             r.nrm32 = put32(g.tn.data(), g.tn.size());
             std::vector<float> nodes;
             std::vector<int32_t> list;
-            mesh_bvh(g, nodes, list);
+            mesh_bvh(g, root_ext, nodes, list);
             r.bvh = (int)p32.size();
             r.nbvh = (int)(nodes.size() / 8);
             p32.insert(p32.end(), nodes.begin(), nodes.end());

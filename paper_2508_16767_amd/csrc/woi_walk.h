@@ -644,15 +644,15 @@ __device__ __forceinline__ bool poly_hit_fp64(const DevProblem* dp, const DevReg
 // Search modes: PS_RAY when every lane of the wave searches along a ray, else PS_ANY (each
 // lane's `ray` flag decides).  The ray mode also skips blocks behind the ray's origin: every
 // vertex v of a block has d.(v - y) <= max(g_j, g_e) + bound (the bound holds in every
-// direction), and a crossing point z with t = d.(z - y) <= 0 is no ray hit; segments are left
-// to the exact test.  Mixed waves gain nothing from it (a wave waits for its slowest lane), so
-// PS_ANY keeps the plain walk.
+// direction), and a crossing point z with t = d.(z - y) <= 0 is no ray hit.  For a segment the
+// bound is the FP32 rounding band, which covers the error of the FP32 g values, so a segment
+// skipped this way has t < 0 in exact arithmetic too (the exact test would reject it).  Mixed
+// waves gain nothing from it (a wave waits for its slowest lane), so PS_ANY keeps the plain walk.
 enum : int { PS_ANY = 0, PS_RAY = 1 };
 
 template <typename R, bool LDS, int MODE, class Cand>
 __device__ __forceinline__ void poly_walk(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
-                                          const R y[2], const R d[2], bool ray_lane, int yseg, Counts& cnt,
-                                          Cand cand) {
+                                          const R y[2], const R d[2], bool ray_lane, Counts& cnt, Cand cand) {
     constexpr bool RAY = MODE == PS_RAY;    // the walk keeps the ray parameters
     const bool ray = RAY || ray_lane;
     constexpr bool F32 = std::is_same<R, float>::value;
@@ -671,7 +671,7 @@ __device__ __forceinline__ void poly_walk(const DevProblem* dp, const DevRegion&
     // jn >> lvl, segments included (their bound is 0), and ctz(jn) is the highest level a
     // block starting at j may take.  The walk starts with the block [0, 2^top] and after
     // each skipped block takes the largest aligned block that follows.
-    const int jend = n2 + n, ysn = ray ? -1 : n2 + yseg;   // a line excludes the segment of y
+    const int jend = n2 + n;
     // h of vertex jn - n2; the LDS byte offset of vertex 0 less 8 n2, in wrapping 32-bit
     // arithmetic, makes the address one shift-add of jn
     const uint32_t vbase = (uint32_t)g.lds_v - 8u * (uint32_t)n2;
@@ -702,7 +702,7 @@ __device__ __forceinline__ void poly_walk(const DevProblem* dp, const DevRegion&
         // that is not clearly on one side (a sign change, or an end value within the band) and
         // decide it exactly after the walk (in FP64 when inside the band).
         bool skip = fabsf(__builtin_amdgcn_fmed3f(hj, he, 0.0f)) > b;
-        if constexpr (RAY) skip |= !seg & (gj < -b) & (ge < -b);   // (fmaxf would add a NaN canonicalisation)
+        if constexpr (RAY) skip |= (gj < -b) & (ge < -b);   // (fmaxf would add a NaN canonicalisation)
         bool cross;
         if constexpr (F32) {
             cross = !skip;
@@ -716,7 +716,7 @@ __device__ __forceinline__ void poly_walk(const DevProblem* dp, const DevRegion&
             }
             cross = (hb != R(0)) & ((ha == R(0)) | ((ha > R(0)) != (hb > R(0))));
         }
-        if (seg & cross & (RAY || jn != ysn)) {   // a ray excludes no segment
+        if (seg & cross) {
             if (cand(jn - n2)) return;
         }
         if (COUNT_POLY) { cnt.nodes += seg ? 0 : 1; cnt.segs += seg ? 1 : 0; }
@@ -743,6 +743,7 @@ __device__ __forceinline__ int poly_pick_t(const DevProblem* dp, const DevRegion
     // passes the line / ray test.  FP32 walks decide in FP32 only when every quantity is clear
     // of its rounding band, else from the FP64 vertices (counted as an FP64 recheck).
     auto hit = [&](int j) -> bool {
+        if (!ray & (j == yseg)) return false;   // a line excludes the segment of y (the walk queues it)
         const R* a = v + 2 * j;
         const R ex = a[2] - a[0], ey = a[3] - a[1];
         const R den = d[0] * ey - d[1] * ex;
@@ -762,7 +763,7 @@ __device__ __forceinline__ int poly_pick_t(const DevProblem* dp, const DevRegion
     };
     Queue16 cq{0u, 0u, 0u, 0u};
     int c = 0;
-    poly_walk<R, LDS, MODE>(dp, g, pay, y, d, ray, yseg, cnt, [&](int j) -> bool {
+    poly_walk<R, LDS, MODE>(dp, g, pay, y, d, ray, cnt, [&](int j) -> bool {
         cq.push((uint32_t)j);
         ++c;
         return false;
@@ -781,11 +782,11 @@ __device__ __forceinline__ int poly_pick_t(const DevProblem* dp, const DevRegion
         }
         return q;
     }
-    poly_walk<R, LDS, MODE>(dp, g, pay, y, d, ray, yseg, cnt, [&](int j) -> bool { q += hit(j) ? 1 : 0; return false; });
+    poly_walk<R, LDS, MODE>(dp, g, pay, y, d, ray, cnt, [&](int j) -> bool { q += hit(j) ? 1 : 0; return false; });
     if (q > 0) {
         pick = min((int)(up * (R)q), q - 1);
         int k = 0;
-        poly_walk<R, LDS, MODE>(dp, g, pay, y, d, ray, yseg, cnt, [&](int j) -> bool {
+        poly_walk<R, LDS, MODE>(dp, g, pay, y, d, ray, cnt, [&](int j) -> bool {
             if (!hit(j)) return false;
             jp = j;
             return k++ == pick;
