@@ -10,7 +10,9 @@ graph launch (queue reset, persistent walk kernel, reduction) with FP32 walks an
 per-point sums; the same batch in FP64 gives the equal-standard-error comparison and the paired
 FP32 - FP64 difference on identical random streams.
 
-Beside it, one compact record per configuration ("configs", printed last): the concentric
+Beside it, one record per configuration ("configs") and, as the last key, a compact
+"summary" of every configuration's ms per step, roofline fraction, speed-up at equal SE, paired
+z and flip rate: the concentric
 disk (FP64 plain, W = 1e4), the 2D star tree (FP32 batched / per point / VR / shared
 trajectories against FP64 plain), the 3D sphere + ellipsoid tree (VR), the 6D nested spheres,
 the point-charge ellipsoids (3-6D), the triangle-mesh tree and the naive Markov trees; each with
@@ -218,7 +220,6 @@ def config_block(woi, torch, ev, prob_desc, pts_np, walks, M, estimator, B, step
     z = paired(r32, r64)
     fl = flips(woi, torch, prob, pts[:flip_pts], flip_walks, M, estimator)
     return {
-        "points": P, "W": walks, "M": M, "estimator": "VR" if estimator else "plain",
         "fp32_ms": r32["wall"] * 1e3, "fp32_walk_steps_per_s": point_steps / r32["wall"],
         "fp64_ms": r64["wall"] * 1e3, "fp64_points_per_s_fixed_se": P / t64,
         "fp32_speedup_fixed_se": t64 / fixed_se(r32, eps),
@@ -238,7 +239,7 @@ def disk_block(woi, torch, W, ev, steps):
     prob = woi.Problem(p)
     woi._lib.woi_problem_upload(prob.handle)
     pts = torch.tensor(xs, dtype=torch.float64, device="cuda")
-    out = {"points": len(xs), "W": 10000, "estimator": "plain"}
+    out = {}
     for M in (4, 8, 12):
         r = Path(woi, torch, prob, pts, 10000, M, woi.FP64).run(ev, steps, 1)
         out[f"fp64_M{M}_ms"] = r["wall"] * 1e3
@@ -280,7 +281,6 @@ def star_tree_block(woi, torch, W, ev, steps, walks):
     fl = flips(woi, torch, prob, pts[::64], 2000, M)
     flv = flips(woi, torch, prob, pts[::64], 1000, M, woi.VR)
     return {
-        "points": P, "W": walks, "M": M,
         "fp32_batched_ms": rb["wall"] * 1e3, "fp32_batched_walk_steps_per_s": c32[0] / rb["wall"],
         "fp32_batched_frac": ach / PEAK_FP32_TFLOPS, "fp32_batched_speedup_fixed_se": t64 / fixed_se(rb, eps),
         "fp32_per_point_ms": rpp["wall"] * 1e3,
@@ -344,6 +344,56 @@ def training_block(woi, torch, W, ev, steps):
                      "points_per_s": cnt / (t_pts + r32["wall"]),
                      "points_per_s_fixed_se": cnt / (t_pts + fixed_se(r32, eps)),
                      "fp64_points_per_s_fixed_se": cnt / (t_pts + fixed_se(r64, eps))}
+    return out
+
+
+def summary(rec):
+    """The last key of the line, short enough for a log tail: per configuration and path, ms per
+    step, the roofline fraction where its flops are counted (2D walks; shared-trajectory pairs),
+    the speed-up over FP64 plain at equal SE, FP32-vs-FP64 paired mean |z| and the decision-flip
+    rate."""
+    out = {}
+
+    def put(key, ms, frac=None, x=None, z=None, flip=None):
+        e = {"ms": ms}
+        for k, v in (("frac", frac), ("x_fp64", x), ("z", z), ("flip", flip)):
+            if v is not None:
+                e[k] = v
+        out[key] = e
+
+    c = rec.get("configs", {})
+    h = c.get("instances_2d", {})
+    put("c3_batch", h.get("ms"), h.get("frac"), h.get("speedup_fixed_se"), (h.get("paired_z") or [None])[0],
+        h.get("flip_rate"))
+    sh = rec.get("shared_trajectories_b_0p5pct")
+    if sh:
+        put("c3_shared", sh["ms_per_step"], x=sh.get("speedup_vs_fp64_fixed_se"))
+    d = c.get("disk_2d")
+    if d:
+        put("c1_fp64_M4", d["fp64_M4_ms"], flip=d["flip_rate"])
+    t = c.get("star_tree_2d")
+    if t:
+        put("c2_batch", t["fp32_batched_ms"], t["fp32_batched_frac"], t["fp32_batched_speedup_fixed_se"],
+            t["paired_z"][0], t["flip_rate"])
+        put("c2_vr", t["vr_fp32_ms"], x=t["vr_fp32_speedup_fixed_se"], z=t["vr_paired_z"][0], flip=t["vr_flip_rate"])
+        put("c2_shared", t["shared"]["ms"], t["shared"]["pair_tflops"] / PEAK_FP32_TFLOPS, t["shared"]["speedup_fixed_se"])
+    for key, name in (("c4_vr", "ellipsoid_tree_3d_vr"), ("c5_6d", "spheres_6d"), ("pc3", "point_charge_3d"),
+                      ("pc4", "point_charge_4d"), ("pc5", "point_charge_5d"), ("pc6", "point_charge_6d"),
+                      ("mesh", "mesh_tree_3d")):
+        b = c.get(name)
+        if b:
+            put(key, b["fp32_ms"], x=b["fp32_speedup_fixed_se"], z=b["paired_z"][0], flip=b["flip_rate"])
+            put(key + "_shared", b["shared"]["ms"], b["shared"]["pair_tflops"] / PEAK_FP32_TFLOPS,
+                b["shared"]["speedup_fixed_se"])
+    n = c.get("naive_markov_trees")
+    if n:
+        for M in (1, 2, 3):
+            if f"M{M}" in n:
+                put(f"naive_M{M}", n[f"M{M}"]["ms"], x=1.0 / n[f"M{M}"]["scheduled_speedup_fixed_se"])
+    tr = c.get("surrogate_training_data")
+    if tr:
+        for k, v in tr.items():
+            put("train_" + k, v["points_ms"] + v["fp32_estimate_ms"], x=v["points_per_s_fixed_se"] / v["fp64_points_per_s_fixed_se"])
     return out
 
 
@@ -555,6 +605,8 @@ def main():
                      if "fp32_vs_fp64_paired_z" in rec else None),
         "flip_rate": rec["flips"]["flip_rate"]}}
     rec["configs"] = {**headline_cfg, **cfg}
+    rec["summary"] = summary(rec)
+    rec["configs"], rec["summary"] = sig(rec["configs"], 3), sig(rec["summary"], 3)
     rec = sig(rec)
     if args.detail:
         with open(args.detail, "w") as f:

@@ -249,9 +249,9 @@ typedef struct {
     double *mean, *se, *grad, *grad_se;  /* device; grad/grad_se may be NULL            */
 } woi_batch_item;
 
-/* Device workspace (bytes) woi_estimate_batch needs: 256 bytes of queue head, then the
- * partial slots (one per work item) of the largest plan the tuner may choose, then the
- * largest shared-trajectory item's workspace
+/* Device workspace (bytes) woi_estimate_batch needs: 256 bytes of queue head, then one
+ * running-sum record per resident workgroup and the partial slots (one per work item) of the
+ * largest plan the tuner may choose, then the largest shared-trajectory item's workspace
  * (woi_workspace_size of its query; the shared items run one after another).  Uploads the problems and
  * queries the current device.  Errors: INVALID_ARG, UNSUPPORTED, DEVICE. */
 woi_status woi_batch_workspace_size(const woi_batch_item *items, int n, size_t *bytes);

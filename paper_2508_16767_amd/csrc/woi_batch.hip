@@ -6,8 +6,10 @@
 // uneven instances (N, P, W all vary) are cut into items (instance, 64-point tile,
 // chunk of samples) listed largest-first, and a grid of resident workgroups pulls items
 // from one atomic queue head until the list is exhausted.  The waves of a workgroup split
-// an item's samples; their per-lane sums are added in wave order through 64 doubles of LDS,
-// one field at a time, and written to the item's one partial slot, and the reduction merges
+// an item's samples; their per-lane sums are added in wave order through the workgroup's
+// own record in global memory (L2-resident, reused item after item; one turn per wave, each
+// adding every field, where the few hundred bytes of LDS the staged polylines leave would
+// need a turn per field) and written to the item's one partial slot, and the reduction merges
 // the slots in chunk order, so the result does not depend on which workgroup ran which item.
 #include "woi_walk.h"
 
@@ -16,7 +18,6 @@ namespace woi {
 template <typename R, int D, bool VR, bool COUNT, int WV, bool LDS>
 __global__ __launch_bounds__(64 * WV, (walk_waves_per_simd<R, D>())) void batch_kernel(BParams bp) {
     __shared__ uint32_t s_item;
-    __shared__ double s_acc[64];     // running sum of one field over waves 0..r-1
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     constexpr int K = VR ? 2 : 1;
     uint32_t staged = 0xFFFFFFFFu;   // instance whose polylines are in LDS (workgroup-uniform)
@@ -78,28 +79,32 @@ __global__ __launch_bounds__(64 * WV, (walk_waves_per_simd<R, D>())) void batch_
 #pragma unroll
             for (int i = 0; i < D; ++i) { G1[i] += Gs[i]; G2[i] += Gs[i] * Gs[i]; }
         }
-        // the waves' sums, added in wave order, field by field: wave r adds its own to the
-        // running sum of waves 0..r-1 in s_acc; the last wave writes the item's slot (fields of
-        // one lane 64 apart).  The barrier after each wave's turn also keeps the next field's
-        // first write behind the last wave's read.
+        // the waves' sums, added in wave order: wave r adds its own to the running record of
+        // waves 0..r-1; the last wave writes the item's slot (fields of one lane 64 apart)
         {
             constexpr int NF = 2 + 2 * D;
             double v[NF];
             v[0] = S1; v[1] = S2;
 #pragma unroll
             for (int i = 0; i < D; ++i) { v[2 + i] = G1[i]; v[2 + D + i] = G2[i]; }
+            double* acc = bp.wg_sums + (size_t)blockIdx.x * 64 * NF + lane;
             const uint64_t slot = in.slot0 + (uint64_t)item.tile * in.n_chunks + item.chunk;
             double* o = bp.partials + slot * 64 * NF + lane;
+            for (int r = 0; r < WV; ++r) {
+                if (wv == r) {
+                    if (r > 0) {
 #pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                for (int r = 0; r < WV; ++r) {
-                    if (wv == r) {
-                        const double x = r > 0 ? s_acc[lane] + v[f] : v[f];
-                        if (r < WV - 1) s_acc[lane] = x;
-                        else if (active) o[64 * f] = x;
+                        for (int f = 0; f < NF; ++f) v[f] = acc[64 * f] + v[f];
                     }
-                    __syncthreads();
+                    if (r < WV - 1) {
+#pragma unroll
+                        for (int f = 0; f < NF; ++f) acc[64 * f] = v[f];
+                    } else if (active) {
+#pragma unroll
+                        for (int f = 0; f < NF; ++f) o[64 * f] = v[f];
+                    }
                 }
+                if (r < WV - 1) __syncthreads();
             }
         }
         if (COUNT && active) {   // idle lanes of a ragged tile walk too, but are not counted

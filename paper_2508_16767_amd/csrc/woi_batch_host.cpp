@@ -3,8 +3,8 @@
 // reduction).
 //
 // Partial sums.  The waves of the workgroup that runs an item add their per-lane sums in wave
-// order (through LDS) and write one slot per item, so the partial traffic is (2 + 2 dim)
-// doubles per (tile lane, chunk), whatever the launch shape.
+// order (through the workgroup's record in the workspace) and write one slot per item, so the
+// partial traffic is (2 + 2 dim) doubles per (tile lane, chunk), whatever the launch shape.
 //
 // Plan.  Instance i has T_i = ceil(P_i / 64) tiles and S_i samples (walkers, or walker
 // pairs for VR).  A model cost e_i per sample and lane, (M_i + 1) K (1 + 3 f_i) with f_i the
@@ -67,8 +67,11 @@ struct Plan {
     std::vector<uint32_t> ctab;
     uint64_t n_slots = 0;
     int64_t n_points = 0;
-    // workspace after the queue head: the partial slots
-    size_t partial_bytes(int dim) const { return (size_t)n_slots * 64 * (2 + 2 * dim) * sizeof(double); }
+    // workspace after the queue head: the workgroups' running sums, then the partial slots
+    size_t wg_bytes(int dim) const { return ((size_t)grid * 64 * (2 + 2 * dim) * sizeof(double) + 255) & ~size_t(255); }
+    size_t partial_bytes(int dim) const {
+        return wg_bytes(dim) + (size_t)n_slots * 64 * (2 + 2 * dim) * sizeof(double);
+    }
     size_t table_bytes(size_t n_seeds) const {   // [BInst][BItem][ctab][pad to 8][seeds]
         const size_t a = inst.size() * sizeof(woi::BInst) + items.size() * sizeof(woi::BItem) + ctab.size() * sizeof(uint32_t);
         return ((a + 7) & ~size_t(7)) + n_seeds * sizeof(uint64_t);
@@ -289,7 +292,7 @@ size_t shared_bytes(const woi_batch_item* items, const Split& sl) {
     return (b + 255) & ~size_t(255);
 }
 
-woi::BParams batch_params(const Plan& pl, const DevTables& t, void* ws, uint64_t* counters) {
+woi::BParams batch_params(const Plan& pl, const DevTables& t, void* ws, uint64_t* counters, int dim) {
     woi::BParams bp{};
     bp.inst = t.inst;
     bp.items = t.items;
@@ -297,7 +300,8 @@ woi::BParams batch_params(const Plan& pl, const DevTables& t, void* ws, uint64_t
     bp.seeds = t.seeds;
     bp.n_items = (uint32_t)pl.items.size();
     bp.head = static_cast<uint32_t*>(ws);
-    bp.partials = reinterpret_cast<double*>(static_cast<char*>(ws) + kHead);
+    bp.wg_sums = reinterpret_cast<double*>(static_cast<char*>(ws) + kHead);
+    bp.partials = reinterpret_cast<double*>(static_cast<char*>(ws) + kHead + pl.wg_bytes(dim));
     bp.counters = counters;
     return bp;
 }
@@ -333,7 +337,7 @@ woi_status autotune(const woi_batch_item* items, const Spec& sp, const Device& d
         std::iota(ident.begin(), ident.end(), 0);
         st = upload(plans[c], seeds_of(items, ident), tbuf, t);
         if (st != WOI_OK) break;
-        const woi::BParams bp = batch_params(plans[c], t, ws, nullptr);
+        const woi::BParams bp = batch_params(plans[c], t, ws, nullptr, sp.dim);
         float ms = 0;
         for (int rep = 0; rep < 2 && st == WOI_OK; ++rep) {   // the first run loads the code object
             hipError_t e = woi::launch_fill_u32(bp.head, 1, 0, d.capture);
@@ -462,7 +466,7 @@ woi_status build_entry(const woi_batch_item* items, int n, const Spec& sp, Devic
         if (hipEventCreateWithFlags(&e.copied[b], hipEventDisableTiming) != hipSuccess)
             return set_error(WOI_E_DEVICE, "hipEventCreate failed");
     }
-    const woi::BParams bp = batch_params(e.plan, e.tab, ws, counters);
+    const woi::BParams bp = batch_params(e.plan, e.tab, ws, counters, sp.dim);
     woi::BRParams rp{};
     rp.inst = e.tab.inst;
     rp.ctab = e.tab.ctab;

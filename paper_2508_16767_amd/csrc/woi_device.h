@@ -56,9 +56,8 @@ struct DevRegion {
 };
 
 // Largest LDS staging area per workgroup: two 512-thread workgroups per CU share its
-// 160 KB of LDS on gfx950 (1 KB left for a kernel's own static LDS: the batch kernel's
-// queue slot and its 512-byte wave-merge buffer).
-constexpr int LDS_BUDGET_MAX = 80 * 1024 - 1024;
+// 160 KB of LDS on gfx950 (256 bytes left for a kernel's own static LDS).
+constexpr int LDS_BUDGET_MAX = 80 * 1024 - 256;
 
 struct DevProblem {
     int dim, N, vr_ok, lds_bytes;             // lds_bytes: LDS needed to stage every polyline (0: none)

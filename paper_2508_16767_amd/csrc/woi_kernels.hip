@@ -190,24 +190,25 @@ __global__ __launch_bounds__(256) void eval_kernel(KParams kp, TParams tp) {
             R dv[D], r2 = 0;
 #pragma unroll
             for (int d = 0; d < D; ++d) { dv[d] = (xh[d] - q[2 + d]) + xl[d]; r2 += dv[d] * dv[d]; }
-            const bool nz = r2 > R(0);                  // |x - y| = 0: the term is skipped
-            R tf, tg;
+            // |x - y| = 0: the term is skipped (its kernel powers are taken as 0, one select)
+            const bool nz = r2 > R(0);
+            R tg;
             if constexpr (D == 2) {
-                tf = q[0] * LnK<R>::lnk(r2);
-                tg = q[1] * RO<R>::rcp(r2);
+                const R lg = nz ? LnK<R>::lnk(r2) : R(0), rc = nz ? RO<R>::rcp(r2) : R(0);
+                Fk = fma(q[0], lg, Fk);
+                tg = q[1] * rc;
             } else {
-                const R ir = RO<R>::rsq(r2);
-                R ir2 = ir * ir, pw = R(1);
+                const R ir = nz ? RO<R>::rsq(r2) : R(0);
+                const R ir2 = ir * ir;
+                R pw = R(1);
 #pragma unroll
                 for (int i = 0; i < (D - 2) / 2; ++i) pw *= ir2;
                 if constexpr (D % 2) pw *= ir;          // r^{2-m}
-                tf = q[0] * pw;
+                Fk = fma(q[0], pw, Fk);
                 tg = q[1] * pw * ir2;
             }
-            Fk += nz ? tf : R(0);
-            tg = nz ? tg : R(0);
 #pragma unroll
-            for (int d = 0; d < D; ++d) Gk[d] += tg * dv[d];
+            for (int d = 0; d < D; ++d) Gk[d] = fma(tg, dv[d], Gk[d]);
             if (++step == M1) {                         // walker done (uniform branch)
                 step = 0;
                 F += (double)Fk;

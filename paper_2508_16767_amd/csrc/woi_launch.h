@@ -116,7 +116,8 @@ hipError_t launch_training(const TrainParams& tp, int dim, hipStream_t s);
 // ----------------------------------------------------------------------------- batches
 // Many instances in one persistent launch.  A work item is (instance, tile of 64 points,
 // chunk of samples); the workgroup that pulls it splits the chunk's samples evenly over
-// its WV waves, adds their sums in wave order (through LDS) and writes partial slot slot0 + tile * n_chunks + chunk (64 lanes x (2 + 2 dim) doubles,
+// its WV waves, adds their sums in wave order through its record wg_sums[blockIdx.x] and
+// writes partial slot slot0 + tile * n_chunks + chunk (64 lanes x (2 + 2 dim) doubles,
 // field f of lane l at f * 64 + l).  Chunk k of an instance covers samples
 // [ctab[c0 + k], ctab[c0 + k + 1]) counted from first_sample; every tile of the instance
 // has the same chunks.
@@ -145,6 +146,7 @@ struct BParams {
     const uint64_t* seeds;     // Philox key of every instance (refreshed before each launch)
     uint32_t n_items;
     uint32_t* head;            // queue head, zeroed before the launch
+    double* wg_sums;           // [grid][2 + 2 dim][64]: each workgroup's running sum of its waves
     double* partials;
     uint64_t* counters;
 };
