@@ -955,13 +955,11 @@ __device__ __forceinline__ int mesh_pick(const DevProblem* dp, const DevRegion& 
 // interface g (segment or triangle seg), used when the FP32 dot product lies inside its rounding
 // band (|dn| <= DevProblem::sign_band_f).  Polylines and meshes: (a - y) . n with a a vertex of
 // the segment / triangle and n its FP64 normal (yn - a is parallel to the segment / triangle).
-// A line or ray on a quadric: +1, the exact sign -- the far end of a chord of the convex quadric
-// through y has (yn - y) . A (yn - c) = t (b + t a), which is 2 b^2 / a for the line's other
-// root t = -2 b / a and t sqrt(b^2 - a cc) > 0 for a ray from inside.  A uniform point on a
-// quadric: (yn - y) . n(yn) in FP64.
+// A uniform point on a quadric: (yn - y) . n(yn) in FP64.  (A line or ray on a quadric never
+// gets here: its sign is + exactly, see transition.)
 template <int D, bool LDS>
-__device__ __forceinline__ float sign_fp64(const DevProblem* dp, const DevRegion& g, int rel, const float y[D],
-                                        const float yn[D], int seg) {
+__device__ __forceinline__ float sign_fp64(const DevProblem* dp, const DevRegion& g, const float y[D], const float yn[D],
+                                        int seg) {
     const double* p64 = Pay<double>::base(dp);
     double s = 0;
     if (g.kind == WOI_SHAPE_POLYLINE2D) {
@@ -973,15 +971,13 @@ __device__ __forceinline__ float sign_fp64(const DevProblem* dp, const DevRegion
         const double *a = p64 + g.g64 + 9 * seg, *n = p64 + g.nrm64 + 3 * seg;
 #pragma unroll
         for (int k = 0; k < D && k < 3; ++k) s += (a[k] - (double)y[k]) * n[k];
-    } else if (rel == REL_OTHER) {
+    } else {
         double yn6[D], n6[D];
 #pragma unroll
         for (int j = 0; j < D; ++j) yn6[j] = yn[j];
         normal_at<double, D, LDS>(g, p64, yn6, seg, n6);
 #pragma unroll
         for (int j = 0; j < D; ++j) s += (yn6[j] - (double)y[j]) * n6[j];
-    } else {
-        s = 1.0;
     }
     return s < 0.0 ? -1.0f : 1.0f;
 }
@@ -1101,6 +1097,13 @@ __device__ __forceinline__ R transition(const DevProblem* __restrict__ dp, const
         }
         if (!found) { cnt.caps++; return R(0); }
         if (!ray) Q *= R(0.5);
+        // A line or ray on a quadric (convex): the sign is + exactly -- the far end of a chord
+        // through y has (yn - y) . A (yn - c) = t (b + t a), which is 2 b^2 / a for the line's
+        // other root t = -2 b / a and t sqrt(b^2 - a cc) > 0 for a ray from inside.  FP32 walks
+        // take it without the dot product (which they could only confirm or, inside its rounding
+        // band, recheck to +); FP64 walks form it as the oracle does.
+        if constexpr (std::is_same<R, float>::value)
+            if (g->kind == WOI_SHAPE_SPHERE || g->kind == WOI_SHAPE_ELLIPSOID) return (R)qn;
         normal_at<R, D, LDS>(*g, pay, yn, segn, nn);
     }
     R dn = 0;
@@ -1109,7 +1112,7 @@ __device__ __forceinline__ R transition(const DevProblem* __restrict__ dp, const
     if constexpr (std::is_same<R, float>::value) {
         if (fabsf(dn) <= dp->sign_band_f) {   // inside the FP32 rounding band: the sign from FP64
             cnt.fb++;
-            dn = sign_fp64<D, LDS>(dp, *g, rel, y, yn, segn);
+            dn = sign_fp64<D, LDS>(dp, *g, y, yn, segn);
         }
     }
     return dn < R(0) ? -(R)qn : (R)qn;
