@@ -252,8 +252,10 @@ def test_fp32_paired_with_fp64():
 
 def test_fp32_chord_signs_rechecked_in_fp64():
     """On concentric circles every FP32-vs-FP64 decision flip was the sign of a near-tangent
-    chord (its dot product 2 b^2 / R below the FP32 rounding of about 1e-7): with the FP64
-    recheck of signs inside the band, no walker flips, and the rechecks are counted."""
+    chord (its dot product 2 b^2 / R below the FP32 rounding of about 1e-7).  FP32 walks take a
+    line's or ray's sign on a circle as + exactly (it is + for every chord), so no walker flips and
+    hardly any decision needs FP64; on the star tree the polyline crossings inside their rounding
+    band are decided in FP64, and counted."""
     p, xs = W.concentric_disk_2d()
     gp = woi.Problem(p)
     _, _, T64 = woi.trace(gp, xs, 4000, 4, seed=31, schedule_mode=1)
@@ -263,6 +265,11 @@ def test_fp32_chord_signs_rechecked_in_fp64():
     woi.estimate(gp, xs, 4000, 4, seed=31, precision=woi.FP32, schedule_mode=1, counters=c)
     c = _np(c)
     assert flips == 0, flips
+    assert c[8] <= 1e-3 * c[0]
+    ps, xss = W.star_tree_2d(n_points=64)
+    c = woi.new_counters()
+    woi.estimate(woi.Problem(ps), xss, 2000, 4, seed=31, precision=woi.FP32, schedule_mode=1, counters=c)
+    c = _np(c)
     assert 0 < c[8] < 1e-2 * c[0]
 
 
