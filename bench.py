@@ -45,7 +45,7 @@ PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 peak (packed FMA)
 # HBM bytes per launch of the headline batch kernel (512 instances), from the FETCH_SIZE and
 # WRITE_SIZE passes summarised in profiles/, each scaled by what the same counter reads for a
 # 1 GiB device copy.  None whenever the kernel has changed since those passes were taken.
-BATCH_TRAFFIC_BYTES = None
+BATCH_TRAFFIC_BYTES = 7.471e8   # FETCH 501.8 MB + WRITE 245.3 MB (profiles/batch_kernel_instances_2d_counters.md)
 
 
 def log(msg):
@@ -465,9 +465,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison of the headline batch")
     ap.add_argument("--extra-steps", type=int, default=2, help="timed steps of the other configurations")
     ap.add_argument("--blocks", default="all",
-                    help="comma-separated configurations to run besides the headline (disk_2d, star_tree_2d, "
-                         "ellipsoid_tree_3d_vr, spheres_6d, point_charge_ellipsoids, mesh_tree_3d, "
-                         "naive_markov_trees, surrogate_training_data), default all")
+                    help="comma-separated configurations to run besides the headline batch (instances_2d_shared: "
+                         "the same batch with shared trajectories; disk_2d, star_tree_2d, ellipsoid_tree_3d_vr, "
+                         "spheres_6d, point_charge_ellipsoids, mesh_tree_3d, naive_markov_trees, "
+                         "surrogate_training_data), default all")
     ap.add_argument("--cpu-seconds", type=float, default=25.0)
     ap.add_argument("--detail", default="", help="also write the full record to this JSON file")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -539,8 +540,13 @@ def main():
         rec["speedup_fp32_vs_fp64_fixed_se"] = bt64 / bt32
         rec["fp32_vs_fp64_paired_z"] = {"mean_z": float(np.mean(z)), "mean_abs_z": float(np.mean(np.abs(z))),
                                         "max_abs_z": float(np.max(np.abs(z)))}
+    blocks = set(args.blocks.split(",")) if args.blocks != "all" else None
+
+    def want(name):
+        return not args.no_extra and (blocks is None or name in blocks)
+
     # the same batch with shared trajectories where the paper's batch size allows it (B <= 0.5 % of P)
-    if not args.no_extra:
+    if want("instances_2d_shared"):
         bsh = run_instances(woi, torch, inst, probs, woi.FP32, args.extra_steps, 1, ev, shared=True)
         rec["shared_trajectories_b_0p5pct"] = {
             "ms_per_step": bsh["wall"] * 1e3, "walk_steps_per_s": counts[0] / bsh["wall"],
@@ -559,11 +565,6 @@ def main():
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
         log("cpu baseline done")
-
-    blocks = set(args.blocks.split(",")) if args.blocks != "all" else None
-
-    def want(name):
-        return not args.no_extra and (blocks is None or name in blocks)
 
     cfg = {}
     es = args.extra_steps
