@@ -476,7 +476,7 @@ def main():
                          "kernel of known size, to scale the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the walk ranges would shard with one all-reduce of per-point sums)", file=sys.stderr)
         sys.exit(2)
 

@@ -43,7 +43,7 @@ typedef enum {
     WOI_E_INVALID_ARG = -1,   /* bad pointer, size, dimension, query field            */
     WOI_E_GEOMETRY = -2,      /* not a tree, degenerate or non-nested shapes          */
     WOI_E_INCOMPATIBLE = -3,  /* flux data violate the compatibility condition        */
-    WOI_E_UNSUPPORTED = -4,   /* valid request this build does not implement          */
+    WOI_E_UNSUPPORTED = -4,   /* valid request the library does not implement         */
     WOI_E_DEVICE = -5,        /* a HIP call failed                                    */
     WOI_E_OOM = -6            /* device allocation or workspace too small             */
 } woi_status;

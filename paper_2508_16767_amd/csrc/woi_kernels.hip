@@ -264,16 +264,23 @@ __global__ __launch_bounds__(256) void reduce_kernel(RParams rp) {
 }
 
 // ----------------------------------------------------------------------------- launchers
+// Lets `fn` take lds_budget() bytes of dynamic LDS on the current device (once per device and
+// kernel; `done` is that kernel's per-device flag array).
+static hipError_t allow_lds(const void* fn, bool* done) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    if (done[dev]) return hipSuccess;
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_budget());
+    if (e == hipSuccess) done[dev] = true;
+    return e;
+}
+
 template <typename R, int D, bool VR, bool COUNT, bool LDS>
 static hipError_t launch_walk_t(const KParams& kp, dim3 grid, dim3 block, unsigned smem, hipStream_t s) {
     if constexpr (LDS && D == 2) {
-        static bool attr = false;
-        if (!attr) {
-            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&walk_kernel<R, D, VR, COUNT, LDS>),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_budget());
-            if (e != hipSuccess) return e;
-            attr = true;
-        }
+        static bool done[64] = {};
+        const hipError_t e = allow_lds(reinterpret_cast<const void*>(&walk_kernel<R, D, VR, COUNT, LDS>), done);
+        if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((walk_kernel<R, D, VR, COUNT, LDS>), grid, block, smem, s, kp);
     return hipGetLastError();
@@ -312,13 +319,9 @@ template <typename R, int D, bool VR, bool LDS>
 static hipError_t launch_traj_t(const KParams& kp, const TParams& tp, unsigned smem, hipStream_t s) {
     const int bs = LDS ? 512 : 256;
     if constexpr (LDS && D == 2) {
-        static bool attr = false;
-        if (!attr) {
-            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&traj_kernel<R, D, VR, LDS>),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_budget());
-            if (e != hipSuccess) return e;
-            attr = true;
-        }
+        static bool done[64] = {};
+        const hipError_t e = allow_lds(reinterpret_cast<const void*>(&traj_kernel<R, D, VR, LDS>), done);
+        if (e != hipSuccess) return e;
     }
     if (tp.lg < 64 || tp.lg % 64 || bs % tp.lg) return hipErrorInvalidValue;
     const unsigned rows = (unsigned)(bs / tp.lg), runs = (unsigned)((tp.ns + tp.spt - 1) / tp.spt);
