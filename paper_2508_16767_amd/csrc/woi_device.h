@@ -48,6 +48,8 @@ struct DevRegion {
     int d64, d32, dexp;        // data coefficients, DIRPOLY exponents (byte offset)
     int b64, b32, nbrk, class0;// VR (2D): sign breakpoints of beta along arclength
     int lds_v, lds_b;          // byte offsets of the LDS copies (FP32 vertices, FP16 bounds), -1 if none
+    int lds_c, lds_g;          // byte offsets of the LDS copies of the FP32 arclength CDF ((cum, 1/len)
+                               // pairs) and of the guide table, -1 if they stay in global memory
     int bvh, nbvh, bvhidx;     // mesh: float offset of the BVH nodes, node count, int offset of the leaf triangle lists
     double alpha, sgn, s, area, meas[2], total;
     double gscale;             // polyline: nv / total length (guide-table index scale)

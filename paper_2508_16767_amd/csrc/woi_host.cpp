@@ -1193,18 +1193,34 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
         r.total_f = (float)r.total;
     }
     // LDS staging layout: FP32 vertices (8 B each, n2 + 1, padded) and FP16 bounds (2 B
-    // each, n2 + n) of every polyline
+    // each, n2 + n) of every polyline, the tables of the block walk; then, if everything still
+    // fits the largest staging area, the FP32 arclength CDF ((cum, 1/len) pairs, 8 B each, n + 1)
+    // and the guide table (4 B each, n) of every polyline, the tables of uniform sampling
     {
         int off = 0;
         for (int i = 0; i < N; ++i) {
             DevRegion& r = hdr.reg[i];
-            r.lds_v = r.lds_b = -1;
+            r.lds_v = r.lds_b = r.lds_c = r.lds_g = -1;
             if (r.kind != WOI_SHAPE_POLYLINE2D) continue;
             r.lds_v = off;
             off += 8 * (r.n2 + 1);
             r.lds_b = off;
             off += 2 * (r.n2 + r.nv);
             off = (off + 15) & ~15;
+        }
+        int cdf = 0;
+        for (int i = 0; i < N; ++i)
+            if (hdr.reg[i].kind == WOI_SHAPE_POLYLINE2D) cdf += ((8 * (hdr.reg[i].nv + 1) + 4 * hdr.reg[i].nv) + 15) & ~15;
+        if (off > 0 && off + cdf <= woi::LDS_BUDGET_MAX) {
+            for (int i = 0; i < N; ++i) {
+                DevRegion& r = hdr.reg[i];
+                if (r.kind != WOI_SHAPE_POLYLINE2D) continue;
+                r.lds_c = off;
+                off += 8 * (r.nv + 1);
+                r.lds_g = off;
+                off += 4 * r.nv;
+                off = (off + 15) & ~15;
+            }
         }
         hdr.lds_bytes = off;   // staged only if the device's workgroup limit allows (decided at launch)
     }

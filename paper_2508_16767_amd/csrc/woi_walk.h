@@ -335,19 +335,25 @@ __device__ __forceinline__ bool polyline_at(const DevProblem* dp, const DevRegio
         // FP32: cum and 1/len interleaved (stride 2); FP64: cum, and len in its own table
         constexpr bool F32 = std::is_same<R, float>::value;
         constexpr int CS = F32 ? 2 : 1;
-        const R* cum = pay + Pay<R>::cum(g);
         const int n = g.nv;
         int k = (int)(s * Pay<R>::gscale(g));   // guide hint; the probes below find the exact j
         k = min(max(k, 0), n - 1);
-        int j = int_payload(dp)[g.guide + k];
-        while (j < n - 1 && cum[CS * (j + 1)] <= s) ++j;
-        while (j > 0 && cum[CS * j] > s) --j;
-        const R* v = poly_xy<R, LDS>(g, pay) + 2 * j;
-        R f;
-        if constexpr (F32) f = (s - cum[2 * j]) * cum[2 * j + 1];
-        else f = (s - cum[j]) / pay[Pay<R>::len(g) + j];
-        y[0] = v[0] + f * (v[2] - v[0]); y[1] = v[1] + f * (v[3] - v[1]);
-        seg = j;
+        auto locate = [&](const R* cum, const int* guide) {
+            int j = guide[k];
+            while (j < n - 1 && cum[CS * (j + 1)] <= s) ++j;
+            while (j > 0 && cum[CS * j] > s) --j;
+            const R* v = poly_xy<R, LDS>(g, pay) + 2 * j;
+            R f;
+            if constexpr (F32) f = (s - cum[2 * j]) * cum[2 * j + 1];
+            else f = (s - cum[j]) / pay[Pay<R>::len(g) + j];
+            y[0] = v[0] + f * (v[2] - v[0]); y[1] = v[1] + f * (v[3] - v[1]);
+            seg = j;
+        };
+        // the staged copies where the layout has them (region-uniform branch), else global memory
+        if (LDS && F32 && g.lds_c >= 0)
+            locate(reinterpret_cast<const R*>(woi_smem + g.lds_c), reinterpret_cast<const int*>(woi_smem + g.lds_g));
+        else
+            locate(pay + Pay<R>::cum(g), int_payload(dp) + g.guide);
     }
     return true;
 }
@@ -1356,7 +1362,8 @@ __device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
     return v;
 }
 
-// Stage every polyline's FP32 vertices and FP16 block bounds into LDS (LDS variant).
+// Stage every polyline's FP32 vertices and FP16 block bounds into LDS (LDS variant), and its
+// FP32 arclength CDF and guide table where the problem's layout gives them room.
 __device__ __forceinline__ void stage_polylines(const DevProblem* __restrict__ dp) {
     const float* __restrict__ f32 = Pay<float>::base(dp);
     for (int i = 0; i < dp->N; ++i) {
@@ -1367,6 +1374,13 @@ __device__ __forceinline__ void stage_polylines(const DevProblem* __restrict__ d
         for (int t = threadIdx.x; t <= g.n2; t += blockDim.x) dv[t] = sv[t];   // padded copy
         __half* db = reinterpret_cast<__half*>(woi_smem + g.lds_b);
         for (int t = threadIdx.x; t < g.n2 + g.nv; t += blockDim.x) db[t] = __float2half_ru(f32[g.bnd + t]);
+        if (g.lds_c < 0) continue;
+        float2* dc = reinterpret_cast<float2*>(woi_smem + g.lds_c);
+        const float2* sc = reinterpret_cast<const float2*>(f32 + g.cum32);
+        for (int t = threadIdx.x; t <= g.nv; t += blockDim.x) dc[t] = sc[t];
+        int* dg = reinterpret_cast<int*>(woi_smem + g.lds_g);
+        const int* sg = int_payload(dp) + g.guide;
+        for (int t = threadIdx.x; t < g.nv; t += blockDim.x) dg[t] = sg[t];
     }
     __syncthreads();
 }
