@@ -51,6 +51,7 @@ constexpr Tune kDefault{8, 8};
 struct Spec {
     int dim = 0;
     bool vr = false, f32 = false;
+    bool shared = true;                // every item takes the shared schedule
     int n = 0;
     std::vector<woi::ProblemRef> ref;
     std::vector<uint64_t> ns, first;   // samples per point, first sample index
@@ -97,6 +98,7 @@ woi_status validate(const woi_batch_item* items, int n, Spec& sp) {
                              "item %d: the persistent kernel does not take triangle meshes (batch_share > 1 does)", i);
         const bool vr = it.query.estimator == WOI_EST_VR, f32 = it.query.precision == WOI_PREC_FP32;
         if (i == 0) { sp.vr = vr; sp.f32 = f32; }
+        sp.shared = sp.shared && it.query.schedule_mode == WOI_SCHED_SHARED;
         if (vr != sp.vr || f32 != sp.f32)
             return set_error(WOI_E_INVALID_ARG, "item %d: every item needs the same estimator and precision", i);
         if (i > 0 && it.query.block_size != items[0].query.block_size)
@@ -230,7 +232,7 @@ woi_status device_info(Device*& out) {
 }
 
 unsigned grid_for(const Spec& sp, const Device& d, int waves) {
-    const int per_cu = woi::batch_blocks_per_cu(sp.dim, sp.vr, sp.f32, waves, sp.smem);
+    const int per_cu = woi::batch_blocks_per_cu(sp.dim, sp.vr, sp.f32, sp.shared, waves, sp.smem);
     return (unsigned)std::max(1, per_cu) * (unsigned)d.cus;
 }
 
@@ -342,7 +344,8 @@ woi_status autotune(const woi_batch_item* items, const Spec& sp, const Device& d
         for (int rep = 0; rep < 2 && st == WOI_OK; ++rep) {   // the first run loads the code object
             hipError_t e = woi::launch_fill_u32(bp.head, 1, 0, d.capture);
             if (e == hipSuccess) e = hipEventRecord(e0, d.capture);
-            if (e == hipSuccess) e = woi::launch_batch(bp, sp.dim, sp.vr, sp.f32, plans[c].t.waves, plans[c].grid, sp.smem, d.capture);
+            if (e == hipSuccess) e = woi::launch_batch(bp, sp.dim, sp.vr, sp.f32, sp.shared, plans[c].t.waves, plans[c].grid, sp.smem,
+                                                 d.capture);
             if (e == hipSuccess) e = hipEventRecord(e1, d.capture);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
@@ -475,7 +478,7 @@ woi_status build_entry(const woi_batch_item* items, int n, const Spec& sp, Devic
     rp.n_points = e.plan.n_points;
     rp.dim = sp.dim;
     // set the kernels' LDS limits before capturing
-    if (n1 && woi::batch_blocks_per_cu(sp.dim, sp1.vr, sp1.f32, e.plan.t.waves, sp1.smem) <= 0)
+    if (n1 && woi::batch_blocks_per_cu(sp.dim, sp1.vr, sp1.f32, sp1.shared, e.plan.t.waves, sp1.smem) <= 0)
         return set_error(WOI_E_DEVICE, "batch kernel cannot be resident");
     if (hipStreamBeginCapture(d.capture, hipStreamCaptureModeRelaxed) != hipSuccess)
         return set_error(WOI_E_DEVICE, "hipStreamBeginCapture failed");
@@ -483,7 +486,8 @@ woi_status build_entry(const woi_batch_item* items, int n, const Spec& sp, Devic
     if (n1) {
         err = woi::launch_fill_u32(bp.head, 1, 0, d.capture);
         if (err == hipSuccess)
-            err = woi::launch_batch(bp, sp.dim, sp1.vr, sp1.f32, e.plan.t.waves, e.plan.grid, sp1.smem, d.capture);
+            err = woi::launch_batch(bp, sp.dim, sp1.vr, sp1.f32, sp1.shared, e.plan.t.waves, e.plan.grid, sp1.smem,
+                                    d.capture);
         if (err == hipSuccess) err = woi::launch_batch_reduce(rp, d.capture);
     }
     // shared-trajectory items, one after another in the workspace after the persistent kernel's

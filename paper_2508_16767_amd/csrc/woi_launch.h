@@ -162,13 +162,14 @@ struct BRParams {
 
 // Persistent walk kernel: grid = resident workgroups, 64 * waves threads each (waves 4 or 8).
 // smem > 0: polyline tables are staged in LDS (dimension 2; every instance with polylines
-// then needs lds <= smem bytes).
-hipError_t launch_batch(const BParams& bp, int dim, bool vr, bool fp32, int waves, unsigned grid, unsigned smem,
-                        hipStream_t s);
+// then needs lds <= smem bytes).  shared: every instance takes the shared schedule (the
+// kernel is then compiled for it).
+hipError_t launch_batch(const BParams& bp, int dim, bool vr, bool fp32, bool shared, int waves, unsigned grid,
+                        unsigned smem, hipStream_t s);
 hipError_t launch_batch_reduce(const BRParams& rp, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s);
 // Resident workgroups per CU of the batch kernel for this configuration (0 on error).
-int batch_blocks_per_cu(int dim, bool vr, bool fp32, int waves, unsigned smem);
+int batch_blocks_per_cu(int dim, bool vr, bool fp32, bool shared, int waves, unsigned smem);
 // Bytes of LDS one workgroup may stage on the current device: the device's per-workgroup
 // limit, at most LDS_BUDGET_MAX.
 int lds_budget();

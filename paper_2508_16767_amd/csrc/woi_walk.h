@@ -1176,15 +1176,19 @@ struct Start {
 };
 
 // Region H_0 of sample w (Theorem 2: uniform over the regions); wave-uniform with the shared
-// schedule.  The walker draws it from the same counter.
+// schedule.  The walker draws it from the same counter.  SH: the shared schedule is known at
+// compile time (kp.shared_sched is then not read), so the compiler sees the schedule's region
+// indices as uniform.
+template <bool SH = false>
 __device__ __forceinline__ int first_region(const DevProblem* __restrict__ dp, const KParams& kp, uint32_t w,
                                             uint32_t group) {
+    const bool shared = SH || kp.shared_sched;
     const uint32_t inst = (kp.instance & 0xFFFFFFu) << 8;
-    const uint4 sb = kp.shared_sched ? philox(make_uint4(w, 0xFFFFFFFFu, inst, 0u), kp.k0, kp.k1)
-                                     : philox(make_uint4(w, group, inst, 0u), kp.k0, kp.k1);
+    const uint4 sb = shared ? philox(make_uint4(w, 0xFFFFFFFFu, inst, 0u), kp.k0, kp.k1)
+                            : philox(make_uint4(w, group, inst, 0u), kp.k0, kp.k1);
     const int t = (int)floor(RO<double>::u(sb.x) * dp->N);
     int h = t < dp->N ? t : dp->N - 1;
-    if (kp.shared_sched) h = __builtin_amdgcn_readfirstlane(h);
+    if (shared) h = __builtin_amdgcn_readfirstlane(h);
     return h;
 }
 
@@ -1194,7 +1198,7 @@ __device__ __forceinline__ int first_region(const DevProblem* __restrict__ dp, c
 // per walker.  Walker k keeps its own stream and attempt count, so the points, attempt counts
 // and cap rule (after WOI_ATTEMPT_CAP attempts the last proposal is kept) are exactly those
 // of drawing the walkers one after the other.  A walker whose half is empty draws nothing.
-template <typename R, int D, bool LDS>
+template <typename R, int D, bool LDS, bool SH = false>
 __device__ __forceinline__ void vr_starts(const DevProblem* __restrict__ dp, const R* __restrict__ pay,
                                           const KParams& kp, uint32_t w, uint32_t group, int h, Start<R, D> s[2],
                                           Counts& cnt) {
@@ -1207,7 +1211,7 @@ __device__ __forceinline__ void vr_starts(const DevProblem* __restrict__ dp, con
     s[0].seg = s[1].seg = 0;
 #pragma unroll
     for (int i = 0; i < D; ++i) { s[0].y[i] = R(0); s[1].y[i] = R(0); }
-    if (D == 3 && wave_full(kp.shared_sched)) {   // the same interface in every lane: cooperative
+    if (D == 3 && wave_full(SH || kp.shared_sched)) {   // the same interface in every lane: cooperative
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             if (!(k ? need1 : need0)) continue;     // wave-uniform (the measures are the interface's)
@@ -1241,17 +1245,19 @@ __device__ __forceinline__ void vr_starts(const DevProblem* __restrict__ dp, con
 
 // Walker k of sample `w`: emits c_i and y_i, i = 0..M, to the sink (the accumulating sink
 // forms sum_i c_i Phi(x, y_i) and sum_i c_i grad_x Phi; the caller multiplies by N).
-// pre: the walker's first point drawn beforehand (VR, see vr_starts), or null.
-template <typename R, int D, bool VR, bool LDS, class Sink>
+// pre: the walker's first point drawn beforehand (VR, see vr_starts), or null.  SH: see
+// first_region.
+template <typename R, int D, bool VR, bool LDS, class Sink, bool SH = false>
 __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const R* __restrict__ pay,
                                        const KParams& kp, uint32_t w, uint32_t group, int k, Sink& sink,
                                        uint32_t* __restrict__ tr, Counts& cnt, const Start<R, D>* pre = nullptr) {
     const int N = dp->N, M = kp.M;
+    const bool shared = SH || kp.shared_sched;
     const uint32_t inst = (kp.instance & 0xFFFFFFu) << 8;
     // Schedule words: counter (w, group or all-ones, instance, draw).  With the shared schedule
     // every input is wave-uniform and the block runs on the scalar unit.
     auto sched_block = [&](uint32_t draw) -> uint4 {
-        if (kp.shared_sched) return philox(make_uint4(w, 0xFFFFFFFFu, inst, draw), kp.k0, kp.k1);
+        if (shared) return philox(make_uint4(w, 0xFFFFFFFFu, inst, draw), kp.k0, kp.k1);
         return philox(make_uint4(w, group, inst, draw), kp.k0, kp.k1);
     };
     const Stream st{kp.k0, kp.k1, w, group, inst | ((uint32_t)k << 4) | 1u};
@@ -1263,7 +1269,7 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
     {
         int t = (int)floor(RO<double>::u(sb.x) * N);
         h = t < N ? t : N - 1;
-        if (kp.shared_sched) h = __builtin_amdgcn_readfirstlane(h);
+        if (shared) h = __builtin_amdgcn_readfirstlane(h);
     }
     const DevRegion* g = &dp->reg[h];
     const R meas = VR ? Pay<R>::meas(*g, k) : Pay<R>::area(*g);
@@ -1280,7 +1286,7 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
         seg = pre->seg;
         att = pre->att;
     } else {
-        if (!VR && D == 3 && g->kind == WOI_SHAPE_ELLIPSOID && wave_full(kp.shared_sched)) {
+        if (!VR && D == 3 && g->kind == WOI_SHAPE_ELLIPSOID && wave_full(shared)) {
             auto try_at = [&](uint32_t c0, uint32_t c1, int a, R yy[D], int& sg) -> bool {
                 const Stream s2{st.k0, st.k1, c0, c1, st.c2};
                 return surf_attempt<R, D, LDS>(dp, *g, pay, s2, 0, a, yy, sg);
@@ -1312,7 +1318,7 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
         // inverse CDF: the first region with uu < cdf, searched from the guide entry of uu
         int hn = dp->sguide[min((int)(uu * 64.0), 63)];
         while (hn < N - 1 && !(uu < dp->cdf[hn])) ++hn;
-        if (kp.shared_sched) hn = __builtin_amdgcn_readfirstlane(hn);
+        if (shared) hn = __builtin_amdgcn_readfirstlane(hn);
         const int rel = dp->rel[h][hn];
         h = hn;
         g = &dp->reg[h];
@@ -1328,7 +1334,7 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
             pre[1] = (i & 1) ? pb.y : pb.w;
         }
         const R tf = transition<R, D, LDS>(dp, pay, g, rel, st, (uint32_t)i, y, seg, yn, segn, Q, qn, pick, att,
-                                                cnt, D == 2 ? pre : nullptr, kp.shared_sched != 0);
+                                                cnt, D == 2 ? pre : nullptr, shared);
         if (tf == R(0)) {   // no hit after the attempt cap: the walker stops here
             if (tr) for (int j = i; j <= M; ++j) tr[j] = trace_word(h, rel, 0, 0, 0, att);
             break;

@@ -63,6 +63,31 @@ def test_batch_matches_per_instance_estimate(precision):
         _close_to_rounding([_np(t) for t in outs[i]], [_np(t) for t in ref], w)
 
 
+@pytest.mark.parametrize("mix", ["per_group", "mixed"])
+def test_batch_per_point_and_mixed_schedules(mix):
+    """A batch whose items do not all take the shared schedule runs the kernel built for any
+    schedule: every instance equals its own per-instance estimate (FP32 walks), and the FP64
+    per-point-schedule samples equal the oracle's."""
+    inst = _small_instances(n=6, seed=13)
+    probs = [woi.Problem(p) for p, _, _ in inst]
+    sched = [woi.SCHED_PER_GROUP if (mix == "per_group" or i % 2) else woi.SCHED_SHARED for i in range(len(inst))]
+    for precision in (woi.FP32, woi.FP64):
+        entries = _entries(inst, probs, precision=precision)
+        for e, s in zip(entries, sched):
+            e["schedule_mode"] = s
+        outs = woi.estimate_batch(entries)
+        for i, (g, (p, x, w)) in enumerate(zip(probs, inst)):
+            ref = woi.estimate(g, x, w, 4, seed=11, precision=precision, schedule_mode=sched[i], instance=i)
+            _close_to_rounding([_np(t) for t in outs[i]], [_np(t) for t in ref], w)
+    i = 1                                                   # per-point schedule in both mixes
+    p, x, w = inst[i]
+    mo, so, go, gso, _ = O.estimate(O.OracleProblem(p), x, w, 4, seed=11, schedule_mode=0, instance=i)
+    mg, sg, gg, _ = [_np(t) for t in outs[i]]
+    assert np.allclose(mg, mo, rtol=1e-9, atol=1e-9 * so.max())
+    assert np.allclose(sg, so, rtol=1e-7)
+    assert np.allclose(gg, go, rtol=1e-9, atol=1e-9 * gso.max())
+
+
 def test_batch_same_streams_match_oracle_fp64():
     inst = _small_instances(n=6, seed=9)
     probs = [woi.Problem(p) for p, _, _ in inst]
