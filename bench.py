@@ -45,7 +45,7 @@ PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 peak (packed FMA)
 # HBM bytes per launch of the headline batch kernel (512 instances), from the FETCH_SIZE and
 # WRITE_SIZE passes summarised in profiles/, each scaled by what the same counter reads for a
 # 1 GiB device copy.  None whenever the kernel has changed since those passes were taken.
-BATCH_TRAFFIC_BYTES = 7.471e8   # FETCH 501.8 MB + WRITE 245.3 MB (profiles/batch_kernel_instances_2d_counters.md)
+BATCH_TRAFFIC_BYTES = 4.468e8   # FETCH 390.1 MB + WRITE 56.7 MB (profiles/batch_kernel_instances_2d_counters.md)
 
 
 def log(msg):
@@ -524,7 +524,7 @@ def main():
         "graph_ms": kms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": BATCH_TRAFFIC_BYTES,
-                     "kernel": "batch_kernel<float, 2, false, false, WV, true> (time: the whole graph)",
+                     "kernel": "batch_kernel<float, 2, false, false, WV, true, true> (time: the whole graph)",
                      "flops_per_launch": flops},
     }
     if not args.no_fp64:
