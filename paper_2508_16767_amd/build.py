@@ -10,8 +10,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libwoi.so")
-SOURCES = ["woi_kernels.hip", "woi_batch.hip", "woi_batch_shared.hip", "woi_naive.hip", "woi_noalloc.hip", "woi_training.hip",
-           "woi_host.cpp", "woi_batch_host.cpp"]
+SOURCES = ["woi_kernels.hip", "woi_kernels_shared.hip", "woi_batch.hip", "woi_batch_shared.hip", "woi_naive.hip",
+           "woi_noalloc.hip", "woi_training.hip", "woi_host.cpp", "woi_batch_host.cpp"]
 ARCH = os.environ.get("WOI_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed FP32 instructions are disabled: hipcc -O3 would otherwise emit them
