@@ -60,7 +60,11 @@ hipError_t launch_batch(const BParams& bp, int dim, bool vr, bool fp32, bool sha
         if (e != hipSuccess) return e;
     }
     BParams arg = bp;
-    void* args[] = {&arg};
+    uint32_t* head = bp.head;
+    double* wg = bp.wg_sums;
+    double* part = bp.partials;
+    uint64_t* cnt = bp.counters;
+    void* args[] = {&arg, &head, &wg, &part, &cnt};
     return hipLaunchKernel(fn, dim3(grid), dim3(64 * waves), args, smem, s);
 }
 

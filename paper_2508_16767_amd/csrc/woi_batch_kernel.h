@@ -20,22 +20,26 @@
 namespace woi {
 
 // SH: every instance of the launch takes the shared schedule, known at compile time.
+// head, wg_sums, partials and counters are bp's, passed again as parameters the compiler may
+// take as unaliased: the problem tables are then read with scalar loads where uniform.
 template <typename R, int D, bool VR, bool COUNT, int WV, bool LDS, bool SH>
-__global__ __launch_bounds__(64 * WV, (walk_waves_per_simd<R, D>())) void batch_kernel(BParams bp) {
+__global__ __launch_bounds__(64 * WV, (walk_waves_per_simd<R, D>())) void batch_kernel(
+    BParams bp, uint32_t* __restrict__ head, double* __restrict__ wg_sums, double* __restrict__ partials,
+    uint64_t* __restrict__ counters) {
     __shared__ uint32_t s_item;
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     constexpr int K = VR ? 2 : 1;
     uint32_t staged = 0xFFFFFFFFu;   // instance whose polylines are in LDS (workgroup-uniform)
     Counts tot{0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(bp.head, 1u);
+        if (threadIdx.x == 0) s_item = atomicAdd(head, 1u);
         __syncthreads();
         const uint32_t it = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();             // every wave has read s_item (and left the previous item)
         if (it >= bp.n_items) break;
         const BItem item = bp.items[it];
         const BInst& in = bp.inst[item.inst];
-        const DevProblem* __restrict__ dp = in.dp;
+        const DevProblem* __restrict__ dp = uniform_global(in.dp);
         const R* __restrict__ pay = Pay<R>::base(dp);
         if constexpr (LDS) {
             if (in.lds && item.inst != staged) {
@@ -94,9 +98,9 @@ __global__ __launch_bounds__(64 * WV, (walk_waves_per_simd<R, D>())) void batch_
             v[0] = S1; v[1] = S2;
 #pragma unroll
             for (int i = 0; i < D; ++i) { v[2 + i] = G1[i]; v[2 + D + i] = G2[i]; }
-            double* acc = bp.wg_sums + (size_t)blockIdx.x * 64 * NF + lane;
+            double* acc = wg_sums + (size_t)blockIdx.x * 64 * NF + lane;
             const uint64_t slot = in.slot0 + (uint64_t)item.tile * in.n_chunks + item.chunk;
-            double* o = bp.partials + slot * 64 * NF + lane;
+            double* o = partials + slot * 64 * NF + lane;
             for (int r = 0; r < WV; ++r) {
                 if (wv == r) {
                     if (r > 0) {
@@ -126,7 +130,7 @@ __global__ __launch_bounds__(64 * WV, (walk_waves_per_simd<R, D>())) void batch_
 #pragma unroll
         for (int i = 0; i < WOI_COUNTERS; ++i) {
             const uint64_t s = wave_sum((uint64_t)v[i]);
-            if (lane == 0 && s) atomicAdd((unsigned long long*)&bp.counters[i], (unsigned long long)s);
+            if (lane == 0 && s) atomicAdd((unsigned long long*)&counters[i], (unsigned long long)s);
         }
     }
 }

@@ -44,6 +44,17 @@ __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
     return c;
 }
 
+// p, known to address global memory and to be the same in every lane, as the compiler should
+// see it: loads through the result are global-memory loads from a scalar base (scalar loads
+// where the address is uniform and no store of the kernel may alias them).
+template <typename T>
+__device__ __forceinline__ const T* uniform_global(const T* p) {
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    return (const T*)reinterpret_cast<const __attribute__((address_space(1))) T*>(((uint64_t)hi << 32) | lo);
+}
+
 struct Stream {
     uint32_t k0, k1, c0, c1, c2;
     __device__ __forceinline__ uint4 block(uint32_t step, uint32_t draw) const {
