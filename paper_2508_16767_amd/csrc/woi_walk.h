@@ -251,6 +251,23 @@ __device__ __forceinline__ void normal_at(const DevRegion& g, const R* __restric
     }
 }
 
+// Fourier series of a 2D datum in the direction e with NT modes (NT fixed: every coefficient is
+// loaded before the sum starts); the same sum as the general loop in data_b.
+template <typename R, int NT>
+__device__ __forceinline__ R fourier_fixed(const R* __restrict__ cf, const R e[2]) {
+    R c[2 * NT + 1];
+#pragma unroll
+    for (int k = 0; k <= 2 * NT; ++k) c[k] = cf[k];
+    R b = c[0], zr = 1, zi = 0;
+#pragma unroll
+    for (int k = 1; k <= NT; ++k) {
+        const R nr = zr * e[0] - zi * e[1], ni = zr * e[1] + zi * e[0];
+        zr = nr; zi = ni;
+        b += c[2 * k - 1] * zr + c[2 * k] * zi;
+    }
+    return b;
+}
+
 // b_i(y) (Eq. interface_problem data).
 template <typename R, int D, bool LDS = false>
 __device__ __forceinline__ R data_b(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
@@ -289,6 +306,15 @@ __device__ __forceinline__ R data_b(const DevProblem* dp, const DevRegion& g, co
 #pragma unroll
     for (int i = 0; i < D; ++i) e[i] *= ir;
     if (g.dkind == WOI_DATA_FOURIER2D) {
+        switch (g.nt) {   // the common mode counts, with their coefficients loaded up front
+            case 1: return fourier_fixed<R, 1>(cf, e);
+            case 2: return fourier_fixed<R, 2>(cf, e);
+            case 3: return fourier_fixed<R, 3>(cf, e);
+            case 4: return fourier_fixed<R, 4>(cf, e);
+            case 5: return fourier_fixed<R, 5>(cf, e);
+            case 6: return fourier_fixed<R, 6>(cf, e);
+            default: break;
+        }
         // cos(k th) + i sin(k th) = (e_x + i e_y)^k
         R b = cf[0], zr = 1, zi = 0;
         for (int k = 1; k <= g.nt; ++k) {
