@@ -68,6 +68,9 @@ struct DevProblem {
     float sign_band_f;                        // FP32 walks: |(y_i - y_{i-1}) . n(y_i)| at or below it is
                                               // inside the dot product's rounding band (sign from FP64)
     double cdf[WOI_MAX_REGIONS];              // schedule CDF over |alpha| / ||alpha||_1
+    // the CDF test on the 32-bit schedule word w itself: u(w) = (w + 1/2) 2^-32 < cdf[h] exactly
+    // when w < sthr[h] (sthr[h] = ceil(cdf[h] 2^32 - 1/2), at least 0, at most 2^32)
+    uint64_t sthr[WOI_MAX_REGIONS];
     unsigned char rel[WOI_MAX_REGIONS][WOI_MAX_REGIONS];
     // start of the inverse-CDF search for u in [k/64, (k+1)/64): the search's result at
     // u = k/64, so no region below it can be the result for a larger u

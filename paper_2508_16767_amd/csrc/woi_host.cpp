@@ -1039,6 +1039,9 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
     for (int i = 0; i < N; ++i) {
         acc += std::fabs(H.r[i].alpha);
         hdr.cdf[i] = acc / H.alpha_l1;
+        // cdf * 2^32 - 1/2 is exact in double (cdf <= 1), and so is its ceiling
+        const double x = std::ceil(std::ldexp(hdr.cdf[i], 32) - 0.5);
+        hdr.sthr[i] = x <= 0 ? 0ull : (uint64_t)x;
     }
     for (int k = 0; k < 64; ++k) {
         const double u = k / 64.0;

@@ -1212,6 +1212,12 @@ struct Start {
     int seg, att;
 };
 
+// floor(u(w) N) for u(w) = (w + 1/2) 2^-32: the FP64 product is exact (w + 1/2 has 33
+// significant bits, N at most 32), so it equals ((2w + 1) N) >> 33 in integers.
+__device__ __forceinline__ int region0(uint32_t w, int N) {
+    return (int)((((uint64_t)w << 1 | 1u) * (uint64_t)N) >> 33);
+}
+
 // Region H_0 of sample w (Theorem 2: uniform over the regions); wave-uniform with the shared
 // schedule.  The walker draws it from the same counter.  SH: the shared schedule is known at
 // compile time (kp.shared_sched is then not read), so the compiler sees the schedule's region
@@ -1223,7 +1229,7 @@ __device__ __forceinline__ int first_region(const DevProblem* __restrict__ dp, c
     const uint32_t inst = (kp.instance & 0xFFFFFFu) << 8;
     const uint4 sb = shared ? philox(make_uint4(w, 0xFFFFFFFFu, inst, 0u), kp.k0, kp.k1)
                             : philox(make_uint4(w, group, inst, 0u), kp.k0, kp.k1);
-    const int t = (int)floor(RO<double>::u(sb.x) * dp->N);
+    const int t = region0(sb.x, dp->N);
     int h = t < dp->N ? t : dp->N - 1;
     if (shared) h = __builtin_amdgcn_readfirstlane(h);
     return h;
@@ -1304,7 +1310,7 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
     uint4 sb = sched_block(0);
     int h;
     {
-        int t = (int)floor(RO<double>::u(sb.x) * N);
+        int t = region0(sb.x, N);
         h = t < N ? t : N - 1;
         if (shared) h = __builtin_amdgcn_readfirstlane(h);
     }
@@ -1351,10 +1357,10 @@ __device__ __forceinline__ void walker(const DevProblem* __restrict__ dp, const 
     for (int i = 1; i <= M; ++i) {
         if ((i & 3) == 0) sb = sched_block((uint32_t)(i >> 2));
         const uint32_t wv = (i & 3) == 0 ? sb.x : (i & 3) == 1 ? sb.y : (i & 3) == 2 ? sb.z : sb.w;
-        const double uu = RO<double>::u(wv);
-        // inverse CDF: the first region with uu < cdf, searched from the guide entry of uu
-        int hn = dp->sguide[min((int)(uu * 64.0), 63)];
-        while (hn < N - 1 && !(uu < dp->cdf[hn])) ++hn;
+        // inverse CDF: the first region with u(wv) < cdf, searched from the guide entry of u(wv)
+        // (floor(64 u(wv)) = wv >> 26; the CDF test in integers, see DevProblem::sthr)
+        int hn = dp->sguide[wv >> 26];
+        while (hn < N - 1 && !((uint64_t)wv < dp->sthr[hn])) ++hn;
         if (shared) hn = __builtin_amdgcn_readfirstlane(hn);
         const int rel = dp->rel[h][hn];
         h = hn;
