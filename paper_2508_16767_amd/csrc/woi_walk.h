@@ -268,6 +268,32 @@ __device__ __forceinline__ R fourier_fixed(const R* __restrict__ cf, const R e[2
     return b;
 }
 
+// Nested Horner sum of a 3D directional polynomial of degree NT over its dense triangular
+// coefficient table (NT fixed: every coefficient is loaded before the sum starts); the same sum
+// as the general loop in data_b.
+template <typename R, int NT>
+__device__ __forceinline__ R horner3_fixed(const R* __restrict__ cf, const R e[3]) {
+    constexpr int NC = (NT + 1) * (NT + 2) * (NT + 3) / 6;
+    R c[NC];
+#pragma unroll
+    for (int t = 0; t < NC; ++t) c[t] = cf[t];
+    int q = 0;
+    R b0 = 0;
+#pragma unroll
+    for (int i = NT; i >= 0; --i) {
+        R b1 = 0;
+#pragma unroll
+        for (int j = NT - i; j >= 0; --j) {
+            R b2 = 0;
+#pragma unroll
+            for (int k = NT - i - j; k >= 0; --k) b2 = b2 * e[2] + c[q++];
+            b1 = b1 * e[1] + b2;
+        }
+        b0 = b0 * e[0] + b1;
+    }
+    return b0;
+}
+
 // b_i(y) (Eq. interface_problem data).
 template <typename R, int D, bool LDS = false>
 __device__ __forceinline__ R data_b(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
@@ -326,6 +352,15 @@ __device__ __forceinline__ R data_b(const DevProblem* dp, const DevRegion& g, co
     }
     if constexpr (D <= 3) {
         if (g.dkind == DK_DIRPOLY_HORNER) {   // nested Horner over the dense triangular table
+            if constexpr (D == 3) {
+                switch (g.nt) {   // the common degrees, with their coefficients loaded up front
+                    case 1: return horner3_fixed<R, 1>(cf, e);
+                    case 2: return horner3_fixed<R, 2>(cf, e);
+                    case 3: return horner3_fixed<R, 3>(cf, e);
+                    case 4: return horner3_fixed<R, 4>(cf, e);
+                    default: break;
+                }
+            }
             const int n = g.nt;
             const R* q = cf;
             R b0 = 0;

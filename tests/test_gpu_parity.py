@@ -70,6 +70,25 @@ def test_walk_parity_concentric_2d(estimator, sched):
     walk_parity(p, xs[::4], 2000, 4, estimator=estimator, sched=sched)
 
 
+@pytest.mark.parametrize("sched", [0, 1])
+def test_walk_parity_fourier_mode_counts(sched):
+    """Fourier data with 2, 4, 6, 7 and 9 modes on five concentric circles: the sums the walker
+    unrolls (up to six modes) and its general loop, per walk in FP64; FP32 walks on the same
+    streams take the same decisions and differ from FP64 only at rounding level."""
+    rng = np.random.default_rng(12)
+    modes = (2, 4, 6, 7, 9)
+    data = [W.fourier([0, 0], 0.0, rng.normal(size=k), rng.normal(size=k)) for k in modes]
+    p = W.concentric(2, [1.0, 0.8, 0.6, 0.4, 0.2], [3.0, 1.0, 5.0, 0.5, 2.0], data)
+    xs = W.polar_grid_points(4, 4)
+    walk_parity(p, xs, 1000, 4, sched=sched)
+    gp = woi.Problem(p)
+    F64, _, T64 = woi.trace(gp, xs, 1000, 4, seed=3, schedule_mode=sched)
+    F32, _, T32 = woi.trace(gp, xs, 1000, 4, seed=3, precision=woi.FP32, schedule_mode=sched)
+    assert np.all(_np(T64) == _np(T32))
+    F64, F32 = _np(F64), _np(F32)
+    assert np.max(np.abs(F32 - F64)) < 1e-4 * np.abs(F64).max()
+
+
 def test_walk_parity_six_ball():
     p, xs = W.nested_spheres_6d()
     walk_parity(p, xs[:8], 1000, 8)
