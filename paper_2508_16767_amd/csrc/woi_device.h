@@ -45,7 +45,7 @@ struct DevRegion {
     int bnd;                   // float offset of the block bounds (N2 + nv entries)
     int n2, top;               // nv rounded up to a power of two, first walk level
     int guide;                 // int offset of the guide table (nv entries)
-    int d64, d32, dexp;        // data coefficients, DIRPOLY exponents (byte offset)
+    int d64, d32, dexp;        // data coefficients, DIRPOLY exponents (byte offset; 8 bytes per term)
     int b64, b32, nbrk, class0;// VR (2D): sign breakpoints of beta along arclength
     int lds_v, lds_b;          // byte offsets of the LDS copies (FP32 vertices, FP16 bounds), -1 if none
     int lds_c, lds_g;          // byte offsets of the LDS copies of the FP32 arclength CDF ((cum, 1/len)

@@ -1170,9 +1170,12 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
             r.d64 = put64(g.coef.data(), g.coef.size());
             r.d32 = put32(g.coef.data(), g.coef.size());
         }
-        if (!g.exps.empty()) {
+        if (!g.exps.empty()) {   // device form: one 8-byte word per term, exponent d in byte d
+            while (pb.size() % 8) pb.push_back(0);
             r.dexp = (int)pb.size();
-            pb.insert(pb.end(), g.exps.begin(), g.exps.end());
+            const size_t nt = g.exps.size() / m;
+            for (size_t t = 0; t < nt; ++t)
+                for (int d = 0; d < 8; ++d) pb.push_back(d < m ? g.exps[t * m + d] : 0);
         }
         if (!g.brk.empty()) {
             r.b64 = put64(g.brk.data(), g.brk.size());

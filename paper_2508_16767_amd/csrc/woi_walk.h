@@ -380,13 +380,15 @@ __device__ __forceinline__ R data_b(const DevProblem* dp, const DevRegion& g, co
             return b0;
         }
     }
-    const unsigned char* ex = reinterpret_cast<const unsigned char*>(dp) + dp->offb + g.dexp;
+    // term list: the exponents of term t are the bytes of one 8-byte word (dimension i in byte i)
+    const uint64_t* ex = reinterpret_cast<const uint64_t*>(reinterpret_cast<const char*>(dp) + dp->offb + g.dexp);
     R b = 0;
     for (int t = 0; t < g.nt; ++t) {
         R term = cf[t];
+        const uint64_t xb = ex[t];
 #pragma unroll
         for (int i = 0; i < D; ++i)
-            for (int p = 0; p < ex[t * D + i]; ++p) term *= e[i];
+            for (int p = (int)((xb >> (8 * i)) & 0xFFu); p > 0; --p) term *= e[i];
         b += term;
     }
     return b;
