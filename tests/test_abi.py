@@ -183,3 +183,24 @@ def test_batch_validation_without_gpu(woi):
     pm = woi.Problem(W.mesh_tree_3d(n_points=8, subdiv=1)[0])
     assert status(items(woi.make_query(100, 4), problems=[pm])) == "WOI_E_UNSUPPORTED"    # triangle meshes
     assert status(items(woi.make_query(100, 4, estimator=woi.NAIVE))) == "WOI_E_UNSUPPORTED"   # Markov trees
+
+
+def test_schedule_lookup_in_integers():
+    """The walkers decide the schedule on the 32-bit word w itself: with u(w) = (w + 1/2) 2^-32,
+    floor(64 u) = w >> 26, floor(u N) = ((2w + 1) N) >> 33, and u < c exactly when
+    w < ceil(c 2^32 - 1/2) (at least 0).  Checked here against the FP64 forms the oracle uses."""
+    import math
+    rng = np.random.default_rng(3)
+    w = np.concatenate([rng.integers(0, 2 ** 32, 200000, dtype=np.uint64),
+                        np.array([0, 1, 2 ** 26 - 1, 2 ** 26, 2 ** 31, 2 ** 32 - 1], dtype=np.uint64)])
+    u = (w.astype(np.float64) + 0.5) * 2.0 ** -32
+    assert np.array_equal(np.minimum((u * 64.0).astype(np.int64), 63), (w >> np.uint64(26)).astype(np.int64))
+    for n in range(1, 33):
+        h0 = (((w << np.uint64(1)) | np.uint64(1)) * np.uint64(n)) >> np.uint64(33)
+        assert np.array_equal(np.floor(u * n).astype(np.int64), h0.astype(np.int64))
+    for c in np.concatenate([rng.random(2000), [0.0, 1.0, 2.0 ** -33, 0.5, 1 - 2.0 ** -53]]):
+        thr = max(math.ceil(math.ldexp(float(c), 32) - 0.5), 0)
+        probe = [t for t in (thr - 2, thr - 1, thr, thr + 1) if 0 <= t < 2 ** 32]
+        probe += [int(t) for t in rng.integers(0, 2 ** 32, 8)]
+        for t in probe:
+            assert ((t + 0.5) * 2.0 ** -32 < c) == (t < thr)
