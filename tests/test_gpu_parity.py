@@ -356,10 +356,12 @@ def test_star_tree_2d_full_size_sampled():
 
 
 # ----------------------------------------------------------------------------- shared trajectories
+@pytest.mark.parametrize("sched", [1, 0])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_shared_trajectory_path(precision):
+def test_shared_trajectory_path(precision, sched):
     """batch_share B > 1 runs the generate-then-evaluate kernels; with the same keys they give the
-    per-point path's numbers (FP64: to rounding) and the oracle's (same streams)."""
+    per-point path's numbers (FP64: to rounding) and the oracle's (same streams), with the shared
+    schedule and with one schedule per group of B points."""
     from test_oracle_pins import STAR_PTS, _star_tree
     cases = [(W.concentric_disk_2d()[0], W.concentric_disk_2d()[1], 4, 0, 8), (_star_tree()[0], np.tile(STAR_PTS, (3, 1)), 3, 0, 6),
              (W.concentric_disk_2d()[0], W.concentric_disk_2d()[1], 3, 1, 4),
@@ -369,10 +371,10 @@ def test_shared_trajectory_path(precision):
         gp = woi.Problem(prob)
         walks = 6000
         sh = [_np(t) for t in woi.estimate(gp, pts, walks, M, seed=4, estimator=est, precision=precision,
-                                            schedule_mode=1, batch_share=B)]
+                                            schedule_mode=sched, batch_share=B)]
         # the per-point kernel computes the same keyed samples (trace path, B > 1)
         F, G, _ = woi.trace(gp, pts, walks // (2 if est else 1), M, seed=4, estimator=est, precision=precision,
-                            schedule_mode=1, batch_share=B)
+                            schedule_mode=sched, batch_share=B)
         Fs = _np(F).sum(-1)
         ref_mean = Fs.mean(1)
         ref_se = Fs.std(1, ddof=1) / np.sqrt(Fs.shape[1])
@@ -381,7 +383,7 @@ def test_shared_trajectory_path(precision):
         assert np.allclose(sh[1], ref_se, rtol=1e-6 if precision == 0 else 1e-4)
         if precision == 0:
             op = O.OracleProblem(prob)
-            mo, so, go, _, _ = O.estimate(op, pts, walks, M, seed=4, estimator=est, schedule_mode=1, batch_share=B)
+            mo, so, go, _, _ = O.estimate(op, pts, walks, M, seed=4, estimator=est, schedule_mode=sched, batch_share=B)
             assert np.allclose(sh[0], mo, rtol=1e-9, atol=1e-9 * so.max())
             assert np.allclose(sh[2], go, rtol=1e-9, atol=1e-9 * np.abs(go).max())
 
