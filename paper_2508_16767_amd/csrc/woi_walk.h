@@ -721,8 +721,8 @@ __device__ __forceinline__ bool poly_hit_fp64(const DevProblem* dp, const DevReg
 
 // The walk: calls cand(j) for every candidate segment j in increasing order, and stops
 // early when cand returns true.
-// Search modes: PS_RAY when every lane of the wave searches along a ray, else PS_ANY (each
-// lane's `ray` flag decides).  The ray mode also skips blocks behind the ray's origin: every
+// Search modes: PS_RAY when every lane of the wave searches along a ray, else PS_ANY (the plain
+// walk; each lane's line or ray applies in the exact test of the candidates).  The ray mode also skips blocks behind the ray's origin: every
 // vertex v of a block has d.(v - y) <= max(g_j, g_e) + bound (the bound holds in every
 // direction), and a crossing point z with t = d.(z - y) <= 0 is no ray hit.  For a segment the
 // bound is the FP32 rounding band, which covers the error of the FP32 g values, so a segment
@@ -732,9 +732,8 @@ enum : int { PS_ANY = 0, PS_RAY = 1 };
 
 template <typename R, bool LDS, int MODE, class Cand>
 __device__ __forceinline__ void poly_walk(const DevProblem* dp, const DevRegion& g, const R* __restrict__ pay,
-                                          const R y[2], const R d[2], bool ray_lane, Counts& cnt, Cand cand) {
+                                          const R y[2], const R d[2], Counts& cnt, Cand cand) {
     constexpr bool RAY = MODE == PS_RAY;    // the walk keeps the ray parameters
-    const bool ray = RAY || ray_lane;
     constexpr bool F32 = std::is_same<R, float>::value;
     const int n = g.nv, n2 = g.n2, top = g.top;
     // block tests run in FP32 on the staged (or global) FP32 copy; bounds absorb the rounding
@@ -843,7 +842,7 @@ __device__ __forceinline__ int poly_pick_t(const DevProblem* dp, const DevRegion
     };
     Queue16 cq{0u, 0u, 0u, 0u};
     int c = 0;
-    poly_walk<R, LDS, MODE>(dp, g, pay, y, d, ray, cnt, [&](int j) -> bool {
+    poly_walk<R, LDS, MODE>(dp, g, pay, y, d, cnt, [&](int j) -> bool {
         cq.push((uint32_t)j);
         ++c;
         return false;
@@ -862,11 +861,11 @@ __device__ __forceinline__ int poly_pick_t(const DevProblem* dp, const DevRegion
         }
         return q;
     }
-    poly_walk<R, LDS, MODE>(dp, g, pay, y, d, ray, cnt, [&](int j) -> bool { q += hit(j) ? 1 : 0; return false; });
+    poly_walk<R, LDS, MODE>(dp, g, pay, y, d, cnt, [&](int j) -> bool { q += hit(j) ? 1 : 0; return false; });
     if (q > 0) {
         pick = min((int)(up * (R)q), q - 1);
         int k = 0;
-        poly_walk<R, LDS, MODE>(dp, g, pay, y, d, ray, cnt, [&](int j) -> bool {
+        poly_walk<R, LDS, MODE>(dp, g, pay, y, d, cnt, [&](int j) -> bool {
             if (!hit(j)) return false;
             jp = j;
             return k++ == pick;
