@@ -107,7 +107,10 @@ template <> struct RO<float> {
     static __device__ __forceinline__ void sc2pi(float u, float& s, float& c) {
         s = __builtin_amdgcn_sinf(u); c = __builtin_amdgcn_cosf(u);
     }
-    static __device__ __forceinline__ float lg(float x) { return __logf(x); }
+    // natural log from the hardware log2 (one instruction; __logf adds ten for denormal inputs and
+    // an extended-precision ln 2).  FP32 walks take it of uniforms >= 2^-24 and of squared
+    // distances, whose reciprocal they also form: below FLT_MIN that overflows either way.
+    static __device__ __forceinline__ float lg(float x) { return __log2f(x) * 0.693147180559945309f; }
     static __device__ __forceinline__ float sq(float x) { return __builtin_sqrtf(x); }
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
     // a / b to about 2 ulp (hardware reciprocal), for the FP32 walks
