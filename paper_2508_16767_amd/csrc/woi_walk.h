@@ -111,7 +111,8 @@ template <> struct RO<float> {
     // an extended-precision ln 2).  FP32 walks take it of uniforms >= 2^-24 and of squared
     // distances, whose reciprocal they also form: below FLT_MIN that overflows either way.
     static __device__ __forceinline__ float lg(float x) { return __log2f(x) * 0.693147180559945309f; }
-    static __device__ __forceinline__ float sq(float x) { return __builtin_sqrtf(x); }
+    // hardware square root (about 1 ulp; sqrtf adds a correctly rounded refinement, 17 instructions)
+    static __device__ __forceinline__ float sq(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
     // a / b to about 2 ulp (hardware reciprocal), for the FP32 walks
     static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
@@ -319,7 +320,7 @@ __device__ __forceinline__ R data_b(const DevProblem* dp, const DevRegion& g, co
 #pragma unroll
         for (int i = 0; i < D / 2; ++i) rm *= r2;
         if constexpr (D % 2) rm *= RO<R>::sq(r2);
-        return cf[0] * dn / rm;
+        return RO<R>::div(cf[0] * dn, rm);
     }
     // direction-based data: e = (y - c)/|y - c|, c stored after the coefficients
     int ncoef = g.dkind == WOI_DATA_FOURIER2D ? 2 * g.nt + 1 : g.nt;
@@ -515,7 +516,7 @@ __device__ __forceinline__ void curve_at(const DevProblem* dp, const DevRegion& 
         if (g.kind == WOI_SHAPE_POLYLINE2D) { polyline_at<R, D, LDS>(dp, g, pay, s, y, seg); return; }
         const R* q = pay + Pay<R>::g(g);
         R sn, cs;
-        RO<R>::sc2pi(s / (R(2) * R(3.14159265358979323846) * q[2]), sn, cs);
+        RO<R>::sc2pi(RO<R>::div(s, R(2) * R(3.14159265358979323846) * q[2]), sn, cs);
         y[0] = q[0] + q[2] * cs; y[1] = q[1] + q[2] * sn; seg = 0;
     }
 }
