@@ -65,6 +65,7 @@ struct DevProblem {
     int dim, N, vr_ok, lds_bytes;             // lds_bytes: LDS needed to stage every polyline (0: none)
     double alpha_l1, unit_area, phi_c;        // |S^{m-1}|, Phi prefactor (m >= 3)
     float alpha_l1_f, unit_area_f, phi_c_f;
+    float inv_unit_area_f;                    // 1 / |S^{m-1}| in FP32 (the gradient terms' factor)
     float sign_band_f;                        // FP32 walks: |(y_i - y_{i-1}) . n(y_i)| at or below it is
                                               // inside the dot product's rounding band (sign from FP64)
     double cdf[WOI_MAX_REGIONS];              // schedule CDF over |alpha| / ||alpha||_1

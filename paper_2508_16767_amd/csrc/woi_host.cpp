@@ -1012,6 +1012,7 @@ woi_status woi_problem_create(const woi_problem_desc* d, woi_problem** out) {
     hdr.phi_c = m == 2 ? 1.0 / (2 * kPi) : 1.0 / ((m - 2) * hdr.unit_area);
     hdr.alpha_l1_f = (float)hdr.alpha_l1;
     hdr.unit_area_f = (float)hdr.unit_area;
+    hdr.inv_unit_area_f = (float)(1.0 / hdr.unit_area);
     hdr.phi_c_f = (float)hdr.phi_c;
     // FP32 sign band: 2^-19 (32 FP32 ulps) of the largest coordinate magnitude on dOmega (every
     // interface lies inside the root's); root_ext also scales the polyline bands and mesh boxes

@@ -1075,7 +1075,10 @@ __device__ __forceinline__ void add_term(const DevProblem* dp, const R xh[D], co
     if (r2 == R(0)) { cnt.zero++; return; }
     R phi, irm;   // Phi(x, y), |x - y|^{-m}
     if constexpr (D == 2) {
-        phi = -RO<R>::lg(r2) * R(0.0795774715459476678844418816863);   // 1/(4 pi)
+        if constexpr (std::is_same<R, float>::value)
+            phi = __log2f(r2) * -0.0551589000381629f;   // -ln 2 / (4 pi): -ln(r2) / (4 pi) from the hardware log2
+        else
+            phi = -RO<R>::lg(r2) * R(0.0795774715459476678844418816863);   // 1/(4 pi)
         irm = RO<R>::rcp(r2);
     } else {
         const R ir = RO<R>::rsq(r2);
@@ -1087,7 +1090,9 @@ __device__ __forceinline__ void add_term(const DevProblem* dp, const R xh[D], co
         irm = p * ir2;
     }
     F += c * phi;
-    const R gs = RO<R>::div(-c * irm, Pay<R>::ua(dp));
+    R gs;
+    if constexpr (std::is_same<R, float>::value) gs = -c * irm * dp->inv_unit_area_f;
+    else gs = RO<R>::div(-c * irm, Pay<R>::ua(dp));
 #pragma unroll
     for (int i = 0; i < D; ++i) G[i] += gs * d[i];
 }
