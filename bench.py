@@ -45,7 +45,7 @@ PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 peak (packed FMA)
 # HBM bytes per launch of the headline batch kernel (512 instances), from the FETCH_SIZE and
 # WRITE_SIZE passes summarised in profiles/, each scaled by what the same counter reads for a
 # 1 GiB device copy.  None whenever the kernel has changed since those passes were taken.
-BATCH_TRAFFIC_BYTES = 4.419e8   # FETCH 388.1 MB + WRITE 53.8 MB (profiles/batch_kernel_instances_2d_counters.md)
+BATCH_TRAFFIC_BYTES = 4.477e8   # FETCH 394.3 MB + WRITE 53.4 MB (profiles/batch_kernel_instances_2d_counters.md)
 
 
 def log(msg):
